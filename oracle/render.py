@@ -1,0 +1,145 @@
+"""Oracle: pixel-wise DP rendering (float64).  Test infrastructure only.
+
+Sec. 3.2 and Supplement S1.3: every output pixel is the all-in-focus image
+convolved with that pixel's own left and right PSF (a local, shift-variant
+convolution), the image edges are extended by replication, and the output
+stacks the left image's C channels before the right image's.  Following the
+corrected kernel orientation of S1.3 (the kernel is flipped before the
+unfolded patch is weighted), the operation is a true convolution with the
+output pixel's kernel:
+
+    out[n, s C + c, y, x] = sum_{i, j} K[n, y, x, c', s, i, j]
+                            * img[n, c, clamp(y + pad - i), clamp(x + pad - j)]
+
+with pad = (ks - 1) / 2, s = 0 (left) / 1 (right), clamp to [0, H-1] and
+[0, W-1], and c' = c for per-channel kernels or 0 for a kernel shared by
+all channels.  No normalisation happens inside.
+
+Kernel sources
+  dense : K given per pixel, [N][H][W][Cp][2][ks][ks];
+  bank  : K taken from a traced bank [F][Dn][L][2][ks][ks] of PSFs on radial
+          fields along +x, per pixel: nearest field radius (compared as the
+          exact integer R2 = (2x - W + 1)^2 + (2y - H + 1)^2 in half-pixel
+          units against precomputed squared midpoints), nearest inverse
+          depth (the float depth compared with the depths of the inverse-
+          depth midpoints), channel c -> wavelength slot lam_of_c[c]; pixels
+          left of the centre use the mirror image (columns flipped, left and
+          right swapped), pixels below it flip rows.  This lookup is an
+          approximation for pixels off the x axis (it ignores azimuth).
+"""
+
+import numpy as np
+
+
+def _shifted(img2d, di, dj):
+    """img2d[clamp(y + di), clamp(x + dj)] for every (y, x)."""
+    H, W = img2d.shape
+    rows = np.clip(np.arange(H) + di, 0, H - 1)
+    cols = np.clip(np.arange(W) + dj, 0, W - 1)
+    return img2d[rows][:, cols]
+
+
+def render_dense(img, K):
+    """img [N, C, H, W]; K [N, H, W, Cp, 2, ks, ks] -> out [N, 2C, H, W]."""
+    img = np.asarray(img, dtype=np.float64)
+    K = np.asarray(K, dtype=np.float64)
+    N, C, H, W = img.shape
+    Cp, ks = K.shape[3], K.shape[-1]
+    pad = (ks - 1) // 2
+    out = np.zeros((N, 2 * C, H, W))
+    for n in range(N):
+        for c in range(C):
+            cp = c if Cp == C else 0
+            for i in range(ks):
+                for j in range(ks):
+                    src = _shifted(img[n, c], pad - i, pad - j)
+                    for s in range(2):
+                        out[n, s * C + c] += K[n, :, :, cp, s, i, j] * src
+    return out
+
+
+def render_dense_adjoint(grad_out, K):
+    """Transpose of render_dense with respect to the image."""
+    g = np.asarray(grad_out, dtype=np.float64)
+    K = np.asarray(K, dtype=np.float64)
+    N, C2, H, W = g.shape
+    C = C2 // 2
+    Cp, ks = K.shape[3], K.shape[-1]
+    pad = (ks - 1) // 2
+    gin = np.zeros((N, C, H, W))
+    yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    for n in range(N):
+        for c in range(C):
+            cp = c if Cp == C else 0
+            for i in range(ks):
+                rows = np.clip(yy + pad - i, 0, H - 1)
+                for j in range(ks):
+                    cols = np.clip(xx + pad - j, 0, W - 1)
+                    contrib = sum(K[n, :, :, cp, s, i, j] * g[n, s * C + c]
+                                  for s in range(2))
+                    np.add.at(gin[n, c], (rows, cols), contrib)
+    return gin
+
+
+def bank_thresholds(field_radii, inv_depths, pitch):
+    """Squared-radius thresholds in half-pixel units (floored) and depth
+    thresholds for the nearest-entry bank lookup."""
+    r = np.asarray(field_radii, dtype=np.float64)
+    mid_r = 0.5 * (r[:-1] + r[1:])
+    t_r = np.floor((2.0 * mid_r / pitch) ** 2)
+    iv = np.asarray(inv_depths, dtype=np.float64)
+    mid_iv = 0.5 * (iv[:-1] + iv[1:])
+    t_z = 1.0 / mid_iv
+    return t_r, t_z
+
+
+def bank_lookup(H, W, depth, field_radii, inv_depths, pitch):
+    """Per pixel: field index, depth index, mirror-x flag, mirror-y flag.
+    depth is [H, W] (float32 values, compared exactly in float64)."""
+    t_r, t_z = bank_thresholds(field_radii, inv_depths, pitch)
+    yy, xx = np.meshgrid(np.arange(H, dtype=np.int64), np.arange(W, dtype=np.int64),
+                         indexing="ij")
+    X2 = 2 * xx - (W - 1)
+    Y2 = 2 * yy - (H - 1)
+    R2 = (X2 * X2 + Y2 * Y2).astype(np.float64)
+    fi = np.zeros((H, W), dtype=np.int64)
+    for t in t_r:
+        fi += (R2 > t)
+    z = np.asarray(depth, dtype=np.float64)
+    di = np.zeros((H, W), dtype=np.int64)
+    for t in t_z:
+        di += (z < t)
+    return fi, di, X2 < 0, Y2 < 0
+
+
+def dense_from_bank(bank, depth_maps, field_radii, inv_depths, lam_of_c, pitch):
+    """Expand a bank [F][Dn][L][2][ks][ks] to the dense per-pixel kernels
+    [N][H][W][C][2][ks][ks] chosen by the lookup rule above."""
+    bank = np.asarray(bank, dtype=np.float64)
+    N, H, W = depth_maps.shape
+    C = len(lam_of_c)
+    ks = bank.shape[-1]
+    K = np.zeros((N, H, W, C, 2, ks, ks))
+    for n in range(N):
+        fi, di, mx, my = bank_lookup(H, W, depth_maps[n], field_radii, inv_depths, pitch)
+        for y in range(H):
+            for x in range(W):
+                for c in range(C):
+                    k = bank[fi[y, x], di[y, x], lam_of_c[c]]
+                    if mx[y, x]:
+                        k = k[::-1, :, ::-1]     # swap L/R, flip columns
+                    if my[y, x]:
+                        k = k[:, ::-1, :]        # flip rows
+                    K[n, y, x, c] = k
+    return K
+
+
+def render_bank(img, bank, depth_maps, field_radii, inv_depths, lam_of_c, pitch):
+    K = dense_from_bank(bank, depth_maps, field_radii, inv_depths, lam_of_c, pitch)
+    return render_dense(img, K)
+
+
+def render_bank_adjoint(grad_out, bank, depth_maps, field_radii, inv_depths,
+                        lam_of_c, pitch):
+    K = dense_from_bank(bank, depth_maps, field_radii, inv_depths, lam_of_c, pitch)
+    return render_dense_adjoint(grad_out, K)

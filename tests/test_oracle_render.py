@@ -1,0 +1,117 @@
+"""Pins of the oracle's pixel-wise DP renderer (CPU only)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import render as R
+
+
+def _rand(shape, seed):
+    return np.random.default_rng(seed).uniform(0, 1, shape)
+
+
+def test_centred_delta_is_identity_and_offset_delta_shifts_with_replication():
+    N, C, H, W, ks = 1, 3, 9, 11, 5
+    img = _rand((N, C, H, W), 0)
+    K = np.zeros((N, H, W, 1, 2, ks, ks))
+    K[..., 0, 2, 2] = 1.0      # left: centred delta
+    K[..., 1, 2, 4] = 1.0      # right: delta two columns right of centre
+    out = R.render_dense(img, K)
+    assert np.allclose(out[:, :C], img, atol=0)
+    # tap (i, j) = (2, 4) reads img[y, clamp(x + 2 - 4)] = img[y, clamp(x - 2)]
+    cols = np.clip(np.arange(W) - 2, 0, W - 1)
+    assert np.allclose(out[:, C:], img[..., cols], atol=0)
+
+
+def test_constant_image_gives_kernel_sum():
+    N, C, H, W, ks = 2, 3, 7, 6, 5
+    K = _rand((N, H, W, C, 2, ks, ks), 1)
+    img = np.full((N, C, H, W), 0.75)
+    out = R.render_dense(img, K)
+    for s in range(2):
+        for c in range(C):
+            assert np.allclose(out[:, s * C + c], 0.75 * K[:, :, :, c, s].sum(axis=(-1, -2)))
+
+
+def test_matches_pure_python_loops():
+    N, C, H, W, ks = 1, 2, 6, 5, 3
+    img = _rand((N, C, H, W), 2)
+    K = _rand((N, H, W, C, 2, ks, ks), 3)
+    pad = ks // 2
+    ref = np.zeros((N, 2 * C, H, W))
+    for n in range(N):
+        for s in range(2):
+            for c in range(C):
+                for y in range(H):
+                    for x in range(W):
+                        acc = 0.0
+                        for i in range(ks):
+                            for j in range(ks):
+                                yy = min(max(y + pad - i, 0), H - 1)
+                                xx = min(max(x + pad - j, 0), W - 1)
+                                acc += K[n, y, x, c, s, i, j] * img[n, c, yy, xx]
+                        ref[n, s * C + c, y, x] = acc
+    assert np.allclose(R.render_dense(img, K), ref, atol=1e-14)
+
+
+def test_matches_torch_unfold_expression():
+    # library re-expression: replicate pad, unfold the ks x ks patches, weight
+    # each patch by the output pixel's kernel rotated by 180 degrees
+    N, C, H, W, ks = 2, 3, 10, 12, 5
+    img = _rand((N, C, H, W), 4)
+    K = _rand((N, H, W, C, 2, ks, ks), 5)
+    pad = ks // 2
+    t = torch.from_numpy(img)
+    patches = torch.nn.functional.unfold(
+        torch.nn.functional.pad(t, (pad, pad, pad, pad), mode="replicate"), ks)
+    patches = patches.view(N, C, ks * ks, H * W)                  # [N,C,T,P]
+    Kt = torch.from_numpy(K).flip(-1).flip(-2).reshape(N, H * W, C, 2, ks * ks)
+    outs = []
+    for s in range(2):
+        w = Kt[:, :, :, s, :].permute(0, 2, 3, 1)                 # [N,C,T,P]
+        outs.append((patches * w).sum(2).view(N, C, H, W))
+    ref = torch.cat(outs, 1).numpy()
+    assert np.allclose(R.render_dense(img, K), ref, atol=1e-13)
+
+
+def test_adjoint_dot_product():
+    N, C, H, W, ks = 1, 3, 9, 8, 5
+    img = _rand((N, C, H, W), 6)
+    g = _rand((N, 2 * C, H, W), 7)
+    for Cp in (1, C):
+        K = _rand((N, H, W, Cp, 2, ks, ks), 8)
+        lhs = np.sum(R.render_dense(img, K) * g)
+        rhs = np.sum(img * R.render_dense_adjoint(g, K))
+        assert lhs == pytest.approx(rhs, rel=1e-13)
+
+
+def test_bank_lookup_equals_nearest_search():
+    H, W, ps = 40, 56, 0.01
+    radii = np.linspace(0, 0.3, 7)
+    depths = 1.0 / np.linspace(1 / 5000.0, 1 / 500.0, 9)
+    rng = np.random.default_rng(9)
+    dmap = rng.uniform(500, 5000, (H, W)).astype(np.float32)
+    fi, di, mx, my = R.bank_lookup(H, W, dmap, radii, 1 / depths, ps)
+    yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    X = (xx - (W - 1) / 2) * ps
+    Y = (yy - (H - 1) / 2) * ps
+    rho = np.sqrt(X ** 2 + Y ** 2)
+    f_ref = np.argmin(np.abs(rho[..., None] - radii), axis=-1)
+    d_ref = np.argmin(np.abs(1.0 / dmap.astype(np.float64)[..., None] - 1 / depths), axis=-1)
+    assert np.mean(fi == f_ref) > 0.999
+    assert np.array_equal(di, d_ref)
+    assert np.array_equal(mx, X < 0) and np.array_equal(my, Y < 0)
+
+
+def test_bank_render_uses_mirror_rules():
+    # a bank whose PSFs are asymmetric deltas; a pixel left of the centre
+    # must see the column-flipped, side-swapped kernel
+    H, W, ks, ps = 5, 6, 3, 0.01
+    bank = np.zeros((2, 1, 1, 2, ks, ks))
+    bank[:, 0, 0, 0, 1, 2] = 1.0        # left side: tap to the right
+    bank[:, 0, 0, 1, 0, 1] = 1.0        # right side: tap upward
+    dmap = np.full((1, H, W), 1000.0)
+    K = R.dense_from_bank(bank, dmap, [0.0, 0.02], [1e-3], [0], ps)
+    assert K[0, 0, 0, 0, 1, 1, 0] == 1.0      # x<0,y<0: right <- flipped left
+    assert K[0, 0, 0, 0, 0, 2, 1] == 1.0      # left <- row-flipped right
+    assert K[0, 4, 5, 0, 0, 1, 2] == 1.0      # x>0,y>0: unchanged
