@@ -1,0 +1,244 @@
+/*
+ * sdirt.h -- C ABI of the MI355X (gfx950) dual-pixel PSF engine.
+ *
+ * The library implements the hot path of the ray-traced dual-pixel (DP)
+ * simulator of "Simulating Dual-Pixel Images From Ray Tracing For Depth
+ * Estimation" (He et al., ICCV 2025):
+ *   - Sec. 3.1: a ray set from an object point toward samples of the
+ *     entrance pupil, refracted through every lens surface by Snell's law
+ *     to the sensor; each landed ray split into the left or right
+ *     sub-pixel (microlens model, Eq. (1)/(2) with Eq. (S1) parameters, or
+ *     a smooth angular response) and accumulated into PSF_L / PSF_R,
+ *     Eq. (3);
+ *   - Sec. 3.2 and Supplement S1.3: the pixel-wise local convolution that
+ *     renders the left/right images from an all-in-focus image with each
+ *     pixel's own DP PSF;
+ *   - hand-written adjoints of both, and the PSF surrogate MLP of Sec. 3.2
+ *     and Supplement S1.4 with bf16 matrix-core kernels.
+ *
+ * Conventions shared by every entry point
+ *   - Lengths in millimetres, wavelengths in micrometres, z = 0 at the
+ *     first vertex, light toward +z, object depths measured from the first
+ *     vertex toward -z.
+ *   - Host structs (and the host arrays they point to) are read only during
+ *     the call.  Arrays documented as "device" are caller-owned device
+ *     buffers; the library keeps no pointer after returning.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *     asynchronous on that stream: it validates, precomputes on the host,
+ *     enqueues kernels and returns; it never synchronises.  The library has
+ *     no global mutable device state, so calls on different streams may
+ *     overlap.  Output buffers are cleared by the library's own kernels.
+ *   - Return value: SDIRT_OK (0) or a negative status.  Per-ray optical
+ *     failures (miss, clipping, total internal reflection, asphere root
+ *     failure, invalid direction) are not errors: they are counted in the
+ *     per-point statistics.
+ */
+#ifndef SDIRT_H
+#define SDIRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SDIRT_OK              0
+#define SDIRT_EINVAL         -1   /* bad argument: NULL, size, range, NaN  */
+#define SDIRT_EUNSUPPORTED   -2   /* valid but unsupported mode/dtype/size */
+#define SDIRT_ELAUNCH        -3   /* a HIP launch or runtime call failed   */
+#define SDIRT_ENODEVICE      -4   /* no HIP device available               */
+
+/* ---- limits ----------------------------------------------------------- */
+#define SDIRT_MAX_SURFACES    24  /* rows of the prescription incl. stop   */
+#define SDIRT_MAX_LAMBDAS      4  /* distinct wavelengths per call         */
+#define SDIRT_MAX_FIELDS      64  /* grid-mode fields                      */
+#define SDIRT_MAX_DEPTHS      64  /* grid-mode depths                      */
+#define SDIRT_MAX_KS         129  /* PSF window (odd)                      */
+#define SDIRT_MAX_BANK_F      64
+#define SDIRT_MAX_BANK_D      64
+
+/* ---- lens prescription (Table S1 / S2 columns) ------------------------ */
+enum { SDIRT_SPHERE = 0, SDIRT_PLANE = 1, SDIRT_STOP = 2, SDIRT_ASPHERE = 3,
+       SDIRT_IDEAL = 4 };
+enum { SDIRT_MAT_CAUCHY = 0,   /* n = p0 + p1 / lambda^2                  */
+       SDIRT_MAT_ABBE = 1 };   /* p0 = n_d, p1 = V_d (d/F/C-line Cauchy)  */
+
+typedef struct {
+    int    kind;           /* SDIRT_SPHERE ... SDIRT_IDEAL                  */
+    int    material;       /* model of the medium AFTER this surface        */
+    double mat_p0, mat_p1; /* its parameters (air: CAUCHY 1, 0)             */
+    double c;              /* curvature 1/R (1/mm); ignored for PLANE/STOP  */
+    double t;              /* axial distance to the next vertex (mm); for
+                              the last surface: sensor distance, used unless
+                              focus_depth > 0                               */
+    double semi_diameter;  /* clear semi-diameter (mm); the stop's radius   */
+    double conic;          /* k (ASPHERE)                                   */
+    double asph[5];        /* a4, a6, a8, a10, a12 (ASPHERE)                */
+    double focal;          /* IDEAL only: focal length (mm)                 */
+} sdirt_surface;
+
+typedef struct {
+    int n_surfaces;                  /* 1 .. SDIRT_MAX_SURFACES             */
+    int stop;                        /* index of the aperture stop          */
+    const sdirt_surface* surfaces;   /* host array [n_surfaces]             */
+    int    object_material;          /* medium before surface 0             */
+    double object_p0, object_p1;
+    double f_number;        /* > 0: stop resized so that the paraxial
+                               entrance pupil diameter is EFL / f_number   */
+    double focus_depth;     /* > 0: sensor at the paraxial image of the
+                               on-axis point at this depth                 */
+    double ref_wavelength;  /* wavelength of the stop / focus / chief-ray
+                               magnification computation (um, > 0)         */
+} sdirt_lens;
+
+/* First-order data resolved by the host (paraxial, at ref_wavelength). */
+typedef struct {
+    double efl;             /* effective focal length                      */
+    double bfd;             /* back focal distance (infinity focus)         */
+    double sensor_distance; /* last vertex -> sensor plane                  */
+    double stop_radius;     /* possibly resized by f_number                 */
+    double z_ep, rho_ep;    /* entrance pupil position / radius             */
+    double m_num;           /* chief-ray magnification m(d) = m_num/(z_ep+d) */
+    double sensor_z;        /* sensor plane z (from vertex 0)               */
+} sdirt_lens_info;
+
+/* ---- dual-pixel sensor (Sec. 3.1, Eq. (S1)) --------------------------- */
+enum { SDIRT_DP_SIGMOID = 0, SDIRT_DP_MICROLENS = 1 };
+
+typedef struct {
+    double pitch;          /* DP pixel size ps (mm)                         */
+    int    dp_mode;
+    double sigmoid_k;      /* left weight = logistic(k * sin(theta_x))     */
+    double ml_h, ml_f, ml_w, ml_r;  /* microlens model, units of pitch;
+                                       requires 0 <= h < f, w > 0, r > 0   */
+} sdirt_sensor;
+
+/* ---- PSF query -------------------------------------------------------- */
+enum { SDIRT_SPLAT_BOX = 0, SDIRT_SPLAT_TENT = 1 };
+enum { SDIRT_NORM_NONE = 0, SDIRT_NORM_SUM = 1, SDIRT_NORM_MAX = 2 };
+enum { SDIRT_F32 = 0, SDIRT_F64 = 1, SDIRT_BF16 = 2 };
+
+typedef struct {
+    /* Grid mode: P = F * D * L points, index q = (f * D + d) * L + l.      */
+    int n_fields, n_depths, n_wavelengths;
+    const double* fields;       /* host [F][2] image-plane (h_x, h_y), mm   */
+    const double* depths;       /* host [D] object depths (mm, > 0)         */
+    const double* wavelengths;  /* host [L] (um, > 0); also the slots of
+                                   list mode                               */
+    /* List mode (used when points != NULL): P = n_points arbitrary points. */
+    int n_points;
+    const double* points;       /* device [P][4]: h_x, h_y, depth, slot
+                                   (slot = index into wavelengths)          */
+    int rays_x, rays_y;         /* stratified pupil grid, rays = x * y      */
+    uint32_t seed;
+    int jitter;                 /* 0: cell centres                         */
+    int ks;                     /* odd window size                         */
+    int splat;                  /* SDIRT_SPLAT_*                           */
+    int normalize;              /* SDIRT_NORM_*                            */
+    int out_dtype;              /* SDIRT_F32 or SDIRT_F64                  */
+    int math;                   /* SDIRT_F64 (default) or SDIRT_F32 trace  */
+} sdirt_psf_query;
+
+/* Resolve stop size, sensor position and pupil on the host (no device
+ * work; usable without a GPU).  See Sec. 3.1 (entrance pupil) and Sec. 5.1
+ * (F-number, focus distance). */
+int sdirt_resolve_lens(const sdirt_lens* lens, sdirt_lens_info* out);
+
+/* Entrance pupil (z, radius) at a given wavelength with the resolved stop;
+ * host only. */
+int sdirt_pupil(const sdirt_lens* lens, double wavelength, double* z_ep,
+                double* rho_ep);
+
+/* Trace given rays surface by surface (Sec. 3.1; parity and debugging).
+ *   o, d      device [n][3] doubles: origin (global frame) and unit direction
+ *   hits_out  device [n][S+1][6] doubles: per surface the vertex-local hit
+ *             point (x, y, z) and the direction after the surface; entry S
+ *             is the sensor plane (x, y, 0, direction).
+ *   status    device [n] int: 0 alive, 1 miss, 2 clip, 3 TIR, 4 asphere
+ *             root failure, 5 invalid; first failure wins.
+ * math selects the arithmetic of the trace (SDIRT_F64 or SDIRT_F32). */
+int sdirt_trace_rays(const sdirt_lens* lens, double wavelength, int math,
+                     int n, const double* o, const double* d,
+                     double* hits_out, int* status_out, void* stream);
+
+/* DP PSFs of a query, Eq. (3) (Sec. 3.1), with the pupil sampling,
+ * trace, DP split, splat and normalisation of the hot path.
+ *   psf_out    device [P][2][ks][ks], f32 or f64 (query->out_dtype); side 0
+ *              = left, row i toward +y, column j toward +x, centred on the
+ *              field point.
+ *   stats_out  device [P][7] doubles (may be NULL): launched, vignetted,
+ *              transmitted, left-in-window, right-in-window,
+ *              missed-sub-pixel, outside-window energies (before
+ *              normalisation).
+ * Both buffers are overwritten. */
+int sdirt_trace_dp_psf(const sdirt_lens* lens, const sdirt_sensor* sensor,
+                       const sdirt_psf_query* query, void* psf_out,
+                       double* stats_out, void* stream);
+
+/* Number of parameters of the trace adjoint: 8 * n_surfaces + 1. */
+int sdirt_n_params(const sdirt_lens* lens);
+
+/* Adjoint of sdirt_trace_dp_psf (TENT splat, SIGMOID response, NORM_NONE,
+ * grid mode) under frozen framing: pupil samples, pupil, window centres and
+ * the set of surviving rays are those of the given parameters.
+ *   grad_psf        device [P][2][ks][ks] f32: dL/dPSF
+ *   grad_params_out device [8 S + 1] doubles, overwritten: per surface
+ *                   [c, t, conic, a4, a6, a8, a10, a12] (t of the last
+ *                   surface = sensor distance), then the response slope k.
+ * Each ray is re-traced forward in registers and swept in reverse; per-ray
+ * derivatives are reduced in the wave before global atomics. */
+int sdirt_trace_dp_psf_backward(const sdirt_lens* lens,
+                                const sdirt_sensor* sensor,
+                                const sdirt_psf_query* query,
+                                const float* grad_psf,
+                                double* grad_params_out, void* stream);
+
+/* ---- pixel-wise DP renderer (Sec. 3.2, Supplement S1.3) ---------------
+ * out[n, s*C + c, y, x] = sum_{i,j} K[n,y,x,c',s][i][j] *
+ *                         img[n, c, clamp(y+pad-i), clamp(x+pad-j)]
+ * pad = (ks-1)/2, s = 0 left / 1 right, c' = c (per-channel kernels) or 0
+ * (shared kernel).  Sources of K:
+ *   DENSE: psf device [N][H][W][Cp][2][ks][ks] (f32 or bf16);
+ *   BANK : psf device [F][D][L][2][ks][ks] f32 traced on radial fields
+ *          along +x; per pixel the nearest field radius and nearest
+ *          inverse depth of depth[n][y][x] are taken, channel c uses
+ *          wavelength slot lambda_of_channel[c]; pixels left of the centre
+ *          use the column-flipped kernel with sides swapped, pixels below
+ *          it the row-flipped kernel (an approximation off the x axis). */
+enum { SDIRT_SRC_DENSE = 0, SDIRT_SRC_BANK = 1 };
+
+typedef struct {
+    int N, C, H, W, ks;
+    int source;               /* SDIRT_SRC_*                               */
+    int psf_channels;         /* DENSE: Cp = 1 or C                        */
+    int psf_dtype;            /* DENSE: SDIRT_F32 or SDIRT_BF16; BANK: F32 */
+    int bank_fields, bank_depths, bank_lambdas;
+    const double* field_radii;   /* host [F], strictly increasing (mm)     */
+    const double* inv_depths;    /* host [D], strictly increasing (1/mm)   */
+    int lambda_of_channel[4];    /* BANK: slot per image channel           */
+    double pitch;                /* BANK: pixel pitch (mm)                 */
+} sdirt_render_desc;
+
+/* img device [N][C][H][W] f32; depth device [N][H][W] f32 (BANK only, may
+ * be NULL for DENSE); out device [N][2C][H][W] f32, overwritten. */
+int sdirt_render_dp(const sdirt_render_desc* desc, const float* img,
+                    const void* psf, const float* depth, float* out,
+                    void* stream);
+
+/* Adjoint with respect to the image: grad_img = R^T grad_out, clamped taps
+ * folding onto the border pixels.  grad_out device [N][2C][H][W] f32;
+ * grad_img device [N][C][H][W] f32, overwritten. */
+int sdirt_render_dp_backward(const sdirt_render_desc* desc, const void* psf,
+                             const float* depth, const float* grad_out,
+                             float* grad_img, void* stream);
+
+/* ---- misc ------------------------------------------------------------- */
+const char* sdirt_status_string(int status);
+int sdirt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDIRT_H */

@@ -143,3 +143,32 @@ def render_bank_adjoint(grad_out, bank, depth_maps, field_radii, inv_depths,
                         lam_of_c, pitch):
     K = dense_from_bank(bank, depth_maps, field_radii, inv_depths, lam_of_c, pitch)
     return render_dense_adjoint(grad_out, K)
+
+
+def render_bank_pixels(img, bank, depth_maps, field_radii, inv_depths, lam_of_c,
+                       pitch, pixels):
+    """The bank-source definition evaluated only at the listed output pixels
+    (n, y, x): returns [len(pixels), 2C]."""
+    img = np.asarray(img, dtype=np.float64)
+    bank = np.asarray(bank, dtype=np.float64)
+    N, C, H, W = img.shape
+    ks = bank.shape[-1]
+    pad = (ks - 1) // 2
+    out = np.zeros((len(pixels), 2 * C))
+    looked = {}
+    for k, (n, y, x) in enumerate(pixels):
+        if n not in looked:
+            looked[n] = bank_lookup(H, W, depth_maps[n], field_radii, inv_depths, pitch)
+        fi, di, mx, my = looked[n]
+        rows = np.clip(y + pad - np.arange(ks), 0, H - 1)
+        cols = np.clip(x + pad - np.arange(ks), 0, W - 1)
+        for c in range(C):
+            kern = bank[fi[y, x], di[y, x], lam_of_c[c]]
+            if mx[y, x]:
+                kern = kern[::-1, :, ::-1]
+            if my[y, x]:
+                kern = kern[:, ::-1, :]
+            patch = img[n, c][rows][:, cols]
+            for s in range(2):
+                out[k, s * C + c] = np.sum(kern[s] * patch)
+    return out

@@ -1,0 +1,116 @@
+// C ABI entry points (see include/sdirt.h).  Each validates and resolves
+// its arguments on the host, then enqueues the kernels on the caller's
+// stream without synchronising.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "../../include/sdirt.h"
+#include "host_optics.hpp"
+#include "pack.hpp"
+
+namespace sdirt {
+int trace_dp_psf_impl(const sdirt_lens*, const sdirt_sensor*, const sdirt_psf_query*,
+                      void*, double*, hipStream_t, int);
+int trace_rays_impl(const sdirt_lens*, double, int, int, const double*, const double*,
+                    double*, int*, hipStream_t);
+int trace_backward_impl(const sdirt_lens*, const sdirt_sensor*, const sdirt_psf_query*,
+                        const float*, double*, hipStream_t);
+int render_impl(const sdirt_render_desc*, const float*, const void*, const float*,
+                float*, hipStream_t);
+int render_backward_impl(const sdirt_render_desc*, const void*, const float*,
+                         const float*, float*, hipStream_t);
+}  // namespace sdirt
+
+using namespace sdirt;
+
+extern "C" {
+
+int sdirt_version(void) { return 1; }
+
+const char* sdirt_status_string(int status) {
+    switch (status) {
+        case SDIRT_OK: return "ok";
+        case SDIRT_EINVAL: return "invalid argument";
+        case SDIRT_EUNSUPPORTED: return "unsupported mode, dtype or size";
+        case SDIRT_ELAUNCH: return "HIP launch or runtime failure";
+        case SDIRT_ENODEVICE: return "no HIP device";
+        default: return "unknown status";
+    }
+}
+
+int sdirt_resolve_lens(const sdirt_lens* lens, sdirt_lens_info* out) {
+    if (!out) return SDIRT_EINVAL;
+    Resolved R;
+    const int rc = resolve_lens(lens, &R);
+    if (rc) return rc;
+    out->efl = R.efl;
+    out->bfd = R.bfd;
+    out->sensor_distance = R.sensor_distance;
+    out->stop_radius = R.stop_radius;
+    out->z_ep = R.z_ep_ref;
+    out->rho_ep = R.rho_ep_ref;
+    out->m_num = R.m_num;
+    out->sensor_z = R.sensor_z;
+    return SDIRT_OK;
+}
+
+int sdirt_pupil(const sdirt_lens* lens, double wavelength, double* z_ep, double* rho_ep) {
+    if (!z_ep || !rho_ep || !std::isfinite(wavelength) || !(wavelength > 0)) return SDIRT_EINVAL;
+    Resolved R;
+    const int rc = resolve_lens(lens, &R);
+    if (rc) return rc;
+    for (int m = 0; m <= R.S; ++m)
+        if (!(R.index(m, wavelength) > 0)) return SDIRT_EINVAL;
+    R.pupil(wavelength, z_ep, rho_ep);
+    return SDIRT_OK;
+}
+
+int sdirt_n_params(const sdirt_lens* lens) {
+    if (!lens || lens->n_surfaces < 1 || lens->n_surfaces > SDIRT_MAX_SURFACES) return SDIRT_EINVAL;
+    return 8 * lens->n_surfaces + 1;
+}
+
+int sdirt_trace_rays(const sdirt_lens* lens, double wavelength, int math, int n,
+                     const double* o, const double* d, double* hits_out,
+                     int* status_out, void* stream) {
+    return trace_rays_impl(lens, wavelength, math, n, o, d, hits_out, status_out,
+                           (hipStream_t)stream);
+}
+
+int sdirt_trace_dp_psf(const sdirt_lens* lens, const sdirt_sensor* sensor,
+                       const sdirt_psf_query* query, void* psf_out,
+                       double* stats_out, void* stream) {
+    return trace_dp_psf_impl(lens, sensor, query, psf_out, stats_out,
+                             (hipStream_t)stream, 0);
+}
+
+// Same as sdirt_trace_dp_psf with an explicit number of ray chunks per
+// point (workgroups per PSF point); used to sweep launch shapes.
+int sdirt_trace_dp_psf_chunks(const sdirt_lens* lens, const sdirt_sensor* sensor,
+                              const sdirt_psf_query* query, void* psf_out,
+                              double* stats_out, int chunks, void* stream) {
+    if (chunks < 1) return SDIRT_EINVAL;
+    return trace_dp_psf_impl(lens, sensor, query, psf_out, stats_out,
+                             (hipStream_t)stream, chunks);
+}
+
+int sdirt_trace_dp_psf_backward(const sdirt_lens* lens, const sdirt_sensor* sensor,
+                                const sdirt_psf_query* query, const float* grad_psf,
+                                double* grad_params_out, void* stream) {
+    return trace_backward_impl(lens, sensor, query, grad_psf, grad_params_out,
+                               (hipStream_t)stream);
+}
+
+int sdirt_render_dp(const sdirt_render_desc* desc, const float* img, const void* psf,
+                    const float* depth, float* out, void* stream) {
+    return render_impl(desc, img, psf, depth, out, (hipStream_t)stream);
+}
+
+int sdirt_render_dp_backward(const sdirt_render_desc* desc, const void* psf,
+                             const float* depth, const float* grad_out,
+                             float* grad_img, void* stream) {
+    return render_backward_impl(desc, psf, depth, grad_out, grad_img, (hipStream_t)stream);
+}
+
+}  // extern "C"

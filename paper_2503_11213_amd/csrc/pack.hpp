@@ -1,0 +1,47 @@
+// Packing of host-resolved lens / wavelength / query data into the kernel
+// argument structs, and query validation.
+#pragma once
+
+#include <cstring>
+#include <vector>
+
+#include "device_common.hpp"
+#include "host_optics.hpp"
+
+namespace sdirt {
+
+constexpr int kMaxF = SDIRT_MAX_FIELDS;
+constexpr int kMaxD = SDIRT_MAX_DEPTHS;
+
+struct PointArgs {
+    int P;
+    int F, D, L;                 // grid mode (points == nullptr)
+    double fields[kMaxF][2];
+    double depths[kMaxD];
+    const double* points;        // list mode: device [P][4]
+    double m_num, z_ep_ref;      // chief-ray magnification constants
+};
+
+struct SampleArgs {
+    int nx, ny;
+    uint32_t seed;
+    int jitter;
+    int chunks;
+    int rays_per_chunk;
+};
+
+struct SensorArgs {
+    int ks;
+    int dp_mode;
+    double ps;
+    double sig_k;
+    double ml_h, ml_f, ml_w, ml_r;   // mm
+};
+
+int pack_lens(const Resolved& R, LensArgs* out);
+int pack_lambdas(const Resolved& R, const double* lambdas, int L, LambdaArgs* out);
+int check_sensor(const sdirt_sensor* s, int ks, SensorArgs* out);
+int check_query(const sdirt_psf_query* q, const Resolved& R, PointArgs* pts,
+                SampleArgs* smp);
+
+}  // namespace sdirt

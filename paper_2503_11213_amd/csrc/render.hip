@@ -1,0 +1,361 @@
+// Pixel-wise DP rendering (Sec. 3.2, Supplement S1.3) for gfx950.
+//
+// out[n, s*C + c, y, x] = sum_{i,j} K[n,y,x,c',s][i][j]
+//                         * img[n, c, clamp(y+pad-i), clamp(x+pad-j)]
+//
+// A workgroup owns a TH x TW tile of output pixels and stages the clamped
+// (TH+ks-1) x (TW+ks-1) image halo of all C channels in LDS.  One wave
+// renders one pixel at a time: its 64 lanes stride over the ks*ks taps, so
+// every PSF row segment is read from HBM (dense source) or L2/MALL (bank
+// source) by contiguous lanes, each PSF value exactly once; the 2C partial
+// sums are reduced across the wave at the end.  The image adjoint mirrors
+// it: per tap the lanes scatter K * grad into the LDS halo with LDS atomics,
+// and the halo is folded back (clamped indices) with global atomics.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "../../include/sdirt.h"
+
+namespace sdirt {
+
+int launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
+
+constexpr int kRBlock = 256;
+constexpr int kWaves = kRBlock / 64;
+constexpr int kTH = 8, kTW = 8;
+
+struct RenderArgs {
+    int N, C, H, W, ks, pad;
+    int source, Cp, bf16;
+    int F, D, L;
+    long long t_r[SDIRT_MAX_BANK_F];   // squared-radius thresholds (half px)
+    float t_z[SDIRT_MAX_BANK_D];       // depth thresholds (rounded up)
+    int lam_of_c[4];
+    int tiles_x, tiles_y;
+    const float* img;
+    const void* psf;
+    const float* depth;
+    float* out;          // forward output
+    const float* gout;   // backward input
+    float* gimg;         // backward output
+};
+
+__device__ inline float wsum(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline float load_psf(const void* base, size_t idx, int bf16) {
+    if (bf16) {
+        const uint16_t u = reinterpret_cast<const uint16_t*>(base)[idx];
+        return __uint_as_float(((uint32_t)u) << 16);
+    }
+    return reinterpret_cast<const float*>(base)[idx];
+}
+
+// Kernel addressing of one output pixel: element offset of channel c / side
+// s, and the bank mirrors (side swap folded into the offsets).
+template <int NC>
+struct PixelKernel {
+    size_t base[NC][2];
+    int flip_x, flip_y;
+};
+
+template <int NC>
+__device__ inline void pixel_kernel(const RenderArgs& A, int n, int y, int x,
+                                    PixelKernel<NC>* pk) {
+    const int kk = A.ks * A.ks;
+    if (A.source == SDIRT_SRC_DENSE) {
+        const size_t pix = ((size_t)n * A.H + y) * A.W + x;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int cp = A.Cp == 1 ? 0 : c;
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                pk->base[c][s] = ((pix * A.Cp + cp) * 2 + s) * kk;
+        }
+        pk->flip_x = 0;
+        pk->flip_y = 0;
+    } else {
+        const long long X2 = 2LL * x - (A.W - 1);
+        const long long Y2 = 2LL * y - (A.H - 1);
+        const long long R2 = X2 * X2 + Y2 * Y2;
+        int fi = 0;
+        for (int k = 0; k < A.F - 1; ++k) fi += R2 > A.t_r[k];
+        const float z = A.depth[((size_t)n * A.H + y) * A.W + x];
+        int di = 0;
+        for (int k = 0; k < A.D - 1; ++k) di += z < A.t_z[k];
+        pk->flip_x = X2 < 0;
+        pk->flip_y = Y2 < 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const size_t e = ((size_t)fi * A.D + di) * A.L + A.lam_of_c[c];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int ss = pk->flip_x ? 1 - s : s;
+                pk->base[c][s] = (e * 2 + ss) * kk;
+            }
+        }
+    }
+}
+
+__device__ inline void stage_halo(const RenderArgs& A, int n, int y0, int x0,
+                                  float* halo, int hh, int hw) {
+    for (int c = 0; c < A.C; ++c) {
+        const float* im = A.img + ((size_t)n * A.C + c) * A.H * A.W;
+        for (int e = threadIdx.x; e < hh * hw; e += kRBlock) {
+            const int r = e / hw, q = e - r * hw;
+            const int yy = min(max(y0 - A.pad + r, 0), A.H - 1);
+            const int xx = min(max(x0 - A.pad + q, 0), A.W - 1);
+            halo[(c * hh + r) * hw + q] = im[(size_t)yy * A.W + xx];
+        }
+    }
+}
+
+template <int NC>
+__global__ __launch_bounds__(kRBlock) void render_fwd_kernel(const RenderArgs A) {
+    extern __shared__ float halo[];
+    const int ks = A.ks, kk = ks * ks;
+    const int hh = kTH + ks - 1, hw = kTW + ks - 1;
+    const int tile = blockIdx.x;
+    const int n = tile / (A.tiles_x * A.tiles_y);
+    const int rem = tile - n * A.tiles_x * A.tiles_y;
+    const int y0 = (rem / A.tiles_x) * kTH, x0 = (rem % A.tiles_x) * kTW;
+    stage_halo(A, n, y0, x0, halo, hh, hw);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int di = 64 / ks, dj = 64 % ks;
+    for (int p = wave; p < kTH * kTW; p += kWaves) {
+        const int y = y0 + p / kTW, x = x0 + p % kTW;
+        if (y >= A.H || x >= A.W) continue;
+        PixelKernel<NC> pk;
+        pixel_kernel<NC>(A, n, y, x, &pk);
+        float acc[2][NC];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[s][c] = 0.f;
+        const int ly = y - y0 + ks - 1, lx = x - x0 + ks - 1;
+        int i = lane / ks, j = lane % ks;
+        for (int t = lane; t < kk; t += 64) {
+            const int si = pk.flip_y ? ks - 1 - i : i;
+            const int sj = pk.flip_x ? ks - 1 - j : j;
+            const int st = si * ks + sj;
+            const int hoff = (ly - i) * hw + (lx - j);
+            if (A.Cp == 1 && A.source == SDIRT_SRC_DENSE) {
+                const float kl = load_psf(A.psf, pk.base[0][0] + st, A.bf16);
+                const float kr = load_psf(A.psf, pk.base[0][1] + st, A.bf16);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const float v = halo[c * hh * hw + hoff];
+                    acc[0][c] = fmaf(kl, v, acc[0][c]);
+                    acc[1][c] = fmaf(kr, v, acc[1][c]);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const float v = halo[c * hh * hw + hoff];
+                    const float kl = load_psf(A.psf, pk.base[c][0] + st, A.bf16);
+                    const float kr = load_psf(A.psf, pk.base[c][1] + st, A.bf16);
+                    acc[0][c] = fmaf(kl, v, acc[0][c]);
+                    acc[1][c] = fmaf(kr, v, acc[1][c]);
+                }
+            }
+            i += di;
+            j += dj;
+            if (j >= ks) { j -= ks; ++i; }
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const float v = wsum(acc[s][c]);
+                if (lane == 0)
+                    A.out[(((size_t)n * 2 * NC + s * NC + c) * A.H + y) * A.W + x] = v;
+            }
+    }
+}
+
+template <int NC>
+__global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A) {
+    extern __shared__ float halo[];
+    const int ks = A.ks, kk = ks * ks;
+    const int hh = kTH + ks - 1, hw = kTW + ks - 1;
+    const int tile = blockIdx.x;
+    const int n = tile / (A.tiles_x * A.tiles_y);
+    const int rem = tile - n * A.tiles_x * A.tiles_y;
+    const int y0 = (rem / A.tiles_x) * kTH, x0 = (rem % A.tiles_x) * kTW;
+    for (int e = threadIdx.x; e < NC * hh * hw; e += kRBlock) halo[e] = 0.f;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int di = 64 / ks, dj = 64 % ks;
+    for (int p = wave; p < kTH * kTW; p += kWaves) {
+        const int y = y0 + p / kTW, x = x0 + p % kTW;
+        if (y >= A.H || x >= A.W) continue;
+        PixelKernel<NC> pk;
+        pixel_kernel<NC>(A, n, y, x, &pk);
+        float g[2][NC];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                g[s][c] = A.gout[(((size_t)n * 2 * NC + s * NC + c) * A.H + y) * A.W + x];
+        const int ly = y - y0 + ks - 1, lx = x - x0 + ks - 1;
+        int i = lane / ks, j = lane % ks;
+        for (int t = lane; t < kk; t += 64) {
+            const int si = pk.flip_y ? ks - 1 - i : i;
+            const int sj = pk.flip_x ? ks - 1 - j : j;
+            const int st = si * ks + sj;
+            const int hoff = (ly - i) * hw + (lx - j);
+            if (A.Cp == 1 && A.source == SDIRT_SRC_DENSE) {
+                const float kl = load_psf(A.psf, pk.base[0][0] + st, A.bf16);
+                const float kr = load_psf(A.psf, pk.base[0][1] + st, A.bf16);
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    atomicAdd(&halo[c * hh * hw + hoff], kl * g[0][c] + kr * g[1][c]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const float kl = load_psf(A.psf, pk.base[c][0] + st, A.bf16);
+                    const float kr = load_psf(A.psf, pk.base[c][1] + st, A.bf16);
+                    atomicAdd(&halo[c * hh * hw + hoff], kl * g[0][c] + kr * g[1][c]);
+                }
+            }
+            i += di;
+            j += dj;
+            if (j >= ks) { j -= ks; ++i; }
+        }
+    }
+    __syncthreads();
+    for (int c = 0; c < NC; ++c) {
+        float* gi = A.gimg + ((size_t)n * NC + c) * A.H * A.W;
+        for (int e = threadIdx.x; e < hh * hw; e += kRBlock) {
+            const float v = halo[c * hh * hw + e];
+            if (v == 0.f) continue;
+            const int r = e / hw, q = e - r * hw;
+            const int yy = min(max(y0 - A.pad + r, 0), A.H - 1);
+            const int xx = min(max(x0 - A.pad + q, 0), A.W - 1);
+            atomicAdd(&gi[(size_t)yy * A.W + xx], v);
+        }
+    }
+}
+
+// ---- host ----------------------------------------------------------------
+
+static int pack_render(const sdirt_render_desc* d, RenderArgs* A) {
+    if (!d) return SDIRT_EINVAL;
+    std::memset(A, 0, sizeof(*A));
+    if (d->N < 1 || d->C < 1 || d->H < 1 || d->W < 1) return SDIRT_EINVAL;
+    if (d->C > 4) return SDIRT_EUNSUPPORTED;
+    if (d->ks < 1 || d->ks % 2 == 0) return SDIRT_EINVAL;
+    if (d->ks > SDIRT_MAX_KS) return SDIRT_EUNSUPPORTED;
+    if ((long long)d->H * d->W > (1LL << 30)) return SDIRT_EUNSUPPORTED;
+    A->N = d->N; A->C = d->C; A->H = d->H; A->W = d->W; A->ks = d->ks;
+    A->pad = (d->ks - 1) / 2;
+    A->source = d->source;
+    if (d->source == SDIRT_SRC_DENSE) {
+        if (d->psf_channels != 1 && d->psf_channels != d->C) return SDIRT_EINVAL;
+        A->Cp = d->psf_channels;
+        if (d->psf_dtype == SDIRT_BF16) A->bf16 = 1;
+        else if (d->psf_dtype != SDIRT_F32) return SDIRT_EUNSUPPORTED;
+    } else if (d->source == SDIRT_SRC_BANK) {
+        if (d->psf_dtype != SDIRT_F32) return SDIRT_EUNSUPPORTED;
+        A->Cp = d->C;
+        A->F = d->bank_fields; A->D = d->bank_depths; A->L = d->bank_lambdas;
+        if (A->F < 1 || A->D < 1 || A->L < 1) return SDIRT_EINVAL;
+        if (A->F > SDIRT_MAX_BANK_F || A->D > SDIRT_MAX_BANK_D) return SDIRT_EUNSUPPORTED;
+        if (!d->field_radii || !d->inv_depths) return SDIRT_EINVAL;
+        if (!std::isfinite(d->pitch) || !(d->pitch > 0)) return SDIRT_EINVAL;
+        for (int k = 0; k < A->F; ++k) {
+            if (!std::isfinite(d->field_radii[k])) return SDIRT_EINVAL;
+            if (k && !(d->field_radii[k] > d->field_radii[k - 1])) return SDIRT_EINVAL;
+        }
+        for (int k = 0; k < A->D; ++k) {
+            if (!std::isfinite(d->inv_depths[k]) || !(d->inv_depths[k] > 0)) return SDIRT_EINVAL;
+            if (k && !(d->inv_depths[k] > d->inv_depths[k - 1])) return SDIRT_EINVAL;
+        }
+        // nearest field radius: R2 (exact integer, half-pixel units) against
+        // floor((2 * midpoint / pitch)^2)
+        for (int k = 0; k + 1 < A->F; ++k) {
+            const double mid = 0.5 * (d->field_radii[k] + d->field_radii[k + 1]);
+            const double t = std::floor((2.0 * mid / d->pitch) * (2.0 * mid / d->pitch));
+            A->t_r[k] = t < 0 ? -1 : (long long)t;
+        }
+        // nearest inverse depth: depth < 1 / midpoint(1/d), threshold rounded
+        // up to float so the float comparison decides exactly as in float64
+        for (int k = 0; k + 1 < A->D; ++k) {
+            const double mid = 0.5 * (d->inv_depths[k] + d->inv_depths[k + 1]);
+            const double tz = 1.0 / mid;
+            float f = (float)tz;
+            if ((double)f < tz) f = std::nextafter(f, INFINITY);
+            A->t_z[k] = f;
+        }
+        for (int c = 0; c < d->C; ++c) {
+            if (d->lambda_of_channel[c] < 0 || d->lambda_of_channel[c] >= A->L) return SDIRT_EINVAL;
+            A->lam_of_c[c] = d->lambda_of_channel[c];
+        }
+    } else {
+        return SDIRT_EINVAL;
+    }
+    A->tiles_x = (d->W + kTW - 1) / kTW;
+    A->tiles_y = (d->H + kTH - 1) / kTH;
+    return SDIRT_OK;
+}
+
+template <int NC, bool BWD>
+static void launch_render(const RenderArgs& A, hipStream_t st) {
+    const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
+    const size_t shm = (size_t)NC * hh * hw * sizeof(float);
+    const dim3 grid((unsigned)((long long)A.N * A.tiles_x * A.tiles_y));
+    if (BWD) {
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bwd_kernel<NC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL(render_bwd_kernel<NC>, grid, dim3(kRBlock), shm, st, A);
+    } else {
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_fwd_kernel<NC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL(render_fwd_kernel<NC>, grid, dim3(kRBlock), shm, st, A);
+    }
+}
+
+template <bool BWD>
+static int dispatch_render(const RenderArgs& A, hipStream_t st) {
+    const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
+    if ((size_t)A.C * hh * hw * sizeof(float) > 160 * 1024) return SDIRT_EUNSUPPORTED;
+    switch (A.C) {
+        case 1: launch_render<1, BWD>(A, st); break;
+        case 2: launch_render<2, BWD>(A, st); break;
+        case 3: launch_render<3, BWD>(A, st); break;
+        default: launch_render<4, BWD>(A, st); break;
+    }
+    return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
+}
+
+int render_impl(const sdirt_render_desc* desc, const float* img, const void* psf,
+                const float* depth, float* out, hipStream_t stream) {
+    RenderArgs A;
+    int rc = pack_render(desc, &A);
+    if (rc) return rc;
+    if (!img || !psf || !out) return SDIRT_EINVAL;
+    if (A.source == SDIRT_SRC_BANK && !depth) return SDIRT_EINVAL;
+    A.img = img; A.psf = psf; A.depth = depth; A.out = out;
+    return dispatch_render<false>(A, stream);
+}
+
+int render_backward_impl(const sdirt_render_desc* desc, const void* psf,
+                         const float* depth, const float* gout, float* gimg,
+                         hipStream_t stream) {
+    RenderArgs A;
+    int rc = pack_render(desc, &A);
+    if (rc) return rc;
+    if (!gout || !psf || !gimg) return SDIRT_EINVAL;
+    if (A.source == SDIRT_SRC_BANK && !depth) return SDIRT_EINVAL;
+    A.psf = psf; A.depth = depth; A.gout = gout; A.gimg = gimg;
+    if ((rc = launch_fill_zero(gimg, (size_t)A.N * A.C * A.H * A.W * sizeof(float), stream)))
+        return rc;
+    return dispatch_render<true>(A, stream);
+}
+
+}  // namespace sdirt

@@ -1,0 +1,222 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Every function here fills the C structs of include/sdirt.h from plain
+Python descriptions (any object with the attribute names of the lens /
+sensor / query fields), allocates outputs as torch device tensors and calls
+the library on torch's current stream.  No step of the computation runs in
+Python or in torch.
+"""
+
+import ctypes as C
+
+import torch
+
+from . import _abi as abi
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _material(m):
+    kind, p0, p1 = m
+    return int(kind), float(p0), float(p1)
+
+
+def make_lens(lens):
+    """C struct for a lens description; returns (struct, keepalive)."""
+    S = len(lens.surfaces)
+    arr = (abi.Surface * S)()
+    for i, s in enumerate(lens.surfaces):
+        k, p0, p1 = _material(s.medium)
+        arr[i].kind = int(s.kind)
+        arr[i].material = k
+        arr[i].mat_p0 = p0
+        arr[i].mat_p1 = p1
+        arr[i].c = float(s.c)
+        arr[i].t = float(s.t)
+        arr[i].semi_diameter = float(s.semi_diameter)
+        arr[i].conic = float(getattr(s, "conic", 0.0))
+        for m, a in enumerate(getattr(s, "asph", (0.0,) * 5)):
+            arr[i].asph[m] = float(a)
+        arr[i].focal = float(getattr(s, "focal", 0.0))
+    L = abi.Lens()
+    L.n_surfaces = S
+    L.stop = int(lens.stop)
+    L.surfaces = C.cast(arr, C.POINTER(abi.Surface))
+    k, p0, p1 = _material(lens.object_medium)
+    L.object_material, L.object_p0, L.object_p1 = k, p0, p1
+    L.f_number = float(lens.f_number)
+    L.focus_depth = float(lens.focus_depth)
+    L.ref_wavelength = float(lens.ref_wavelength)
+    return L, arr
+
+
+def make_sensor(sensor):
+    s = abi.Sensor()
+    s.pitch = float(sensor.pitch)
+    s.dp_mode = int(sensor.dp_mode)
+    s.sigmoid_k = float(sensor.sigmoid_k)
+    s.ml_h, s.ml_f, s.ml_w, s.ml_r = (float(sensor.ml_h), float(sensor.ml_f),
+                                      float(sensor.ml_w), float(sensor.ml_r))
+    return s
+
+
+def _darr(vals):
+    vals = [float(v) for v in vals]
+    return (C.c_double * max(1, len(vals)))(*vals)
+
+
+def make_query(query, math=abi.F64, points=None):
+    """C struct for a PSF query; `points` (device float64 [P][4]) selects list
+    mode.  Returns (struct, keepalive)."""
+    q = abi.PsfQuery()
+    keep = []
+    flat = [v for f in query.fields for v in f]
+    fa, da, la = _darr(flat), _darr(query.depths), _darr(query.wavelengths)
+    keep += [fa, da, la]
+    q.n_fields = len(query.fields)
+    q.n_depths = len(query.depths)
+    q.n_wavelengths = len(query.wavelengths)
+    q.fields = C.cast(fa, C.POINTER(C.c_double))
+    q.depths = C.cast(da, C.POINTER(C.c_double))
+    q.wavelengths = C.cast(la, C.POINTER(C.c_double))
+    if points is not None:
+        q.n_points = int(points.shape[0])
+        q.points = points.data_ptr()
+        keep.append(points)
+    q.rays_x = int(query.rays_x)
+    q.rays_y = int(query.rays_y)
+    q.seed = int(query.seed) & 0xFFFFFFFF
+    q.jitter = 1 if query.jitter else 0
+    q.ks = int(query.ks)
+    q.splat = int(query.splat)
+    q.normalize = int(query.normalize)
+    q.out_dtype = abi.F64 if query.out_f64 else abi.F32
+    q.math = int(math)
+    return q, keep
+
+
+def resolve_lens(lens):
+    L, keep = make_lens(lens)
+    info = abi.LensInfo()
+    abi.check("sdirt_resolve_lens", abi.lib().sdirt_resolve_lens(C.byref(L), C.byref(info)))
+    return {n: getattr(info, n) for n, _ in abi.LensInfo._fields_}
+
+
+def pupil(lens, wavelength):
+    L, keep = make_lens(lens)
+    z, r = C.c_double(), C.c_double()
+    abi.check("sdirt_pupil", abi.lib().sdirt_pupil(C.byref(L), float(wavelength),
+                                                   C.byref(z), C.byref(r)))
+    return z.value, r.value
+
+
+def n_params(lens):
+    L, keep = make_lens(lens)
+    return abi.lib().sdirt_n_params(C.byref(L))
+
+
+def trace_rays(lens, wavelength, o, d, math=abi.F64):
+    """Per-surface hits [n][S+1][6] (float64) and status [n] (int32)."""
+    assert o.is_cuda and d.is_cuda and o.dtype == torch.float64 and d.dtype == torch.float64
+    o = o.contiguous()
+    d = d.contiguous()
+    n = o.shape[0]
+    L, keep = make_lens(lens)
+    S = len(lens.surfaces)
+    hits = torch.empty((n, S + 1, 6), dtype=torch.float64, device=o.device)
+    status = torch.empty((n,), dtype=torch.int32, device=o.device)
+    rc = abi.lib().sdirt_trace_rays(C.byref(L), float(wavelength), int(math), n,
+                                    _dptr(o), _dptr(d), _dptr(hits), _dptr(status),
+                                    _stream())
+    abi.check("sdirt_trace_rays", rc)
+    return hits, status
+
+
+def trace_dp_psf(lens, sensor, query, math=abi.F64, points=None, out=None,
+                 stats=True, chunks=None, device="cuda"):
+    """DP PSFs [P][2][ks][ks] and stats [P][7] on the device."""
+    L, keep = make_lens(lens)
+    s = make_sensor(sensor)
+    q, keep2 = make_query(query, math, points)
+    P = q.n_points if points is not None else q.n_fields * q.n_depths * q.n_wavelengths
+    dt = torch.float64 if query.out_f64 else torch.float32
+    if out is None:
+        out = torch.empty((P, 2, query.ks, query.ks), dtype=dt, device=device)
+    st = torch.empty((P, 7), dtype=torch.float64, device=out.device) if stats else None
+    if chunks is None:
+        rc = abi.lib().sdirt_trace_dp_psf(C.byref(L), C.byref(s), C.byref(q),
+                                          _dptr(out), _dptr(st), _stream())
+    else:
+        rc = abi.lib().sdirt_trace_dp_psf_chunks(C.byref(L), C.byref(s), C.byref(q),
+                                                 _dptr(out), _dptr(st), int(chunks),
+                                                 _stream())
+    abi.check("sdirt_trace_dp_psf", rc)
+    return out, st
+
+
+def trace_dp_psf_backward(lens, sensor, query, grad_psf, math=abi.F64):
+    """Gradient [8 S + 1] (float64) of <grad_psf, PSF> w.r.t. the lens
+    parameters and the response slope."""
+    L, keep = make_lens(lens)
+    s = make_sensor(sensor)
+    q, keep2 = make_query(query, math)
+    g = grad_psf.contiguous().float()
+    n = abi.lib().sdirt_n_params(C.byref(L))
+    out = torch.empty((n,), dtype=torch.float64, device=g.device)
+    rc = abi.lib().sdirt_trace_dp_psf_backward(C.byref(L), C.byref(s), C.byref(q),
+                                               _dptr(g), _dptr(out), _stream())
+    abi.check("sdirt_trace_dp_psf_backward", rc)
+    return out
+
+
+def make_render_desc(N, C_, H, W, ks, source=abi.SRC_DENSE, psf_channels=None,
+                     psf_dtype=abi.F32, field_radii=None, inv_depths=None,
+                     bank_lambdas=1, lambda_of_channel=None, pitch=0.0):
+    d = abi.RenderDesc()
+    d.N, d.C, d.H, d.W, d.ks = int(N), int(C_), int(H), int(W), int(ks)
+    d.source = int(source)
+    d.psf_channels = int(psf_channels if psf_channels is not None else C_)
+    d.psf_dtype = int(psf_dtype)
+    keep = []
+    if source == abi.SRC_BANK:
+        fr, iv = _darr(field_radii), _darr(inv_depths)
+        keep += [fr, iv]
+        d.bank_fields = len(field_radii)
+        d.bank_depths = len(inv_depths)
+        d.bank_lambdas = int(bank_lambdas)
+        d.field_radii = C.cast(fr, C.POINTER(C.c_double))
+        d.inv_depths = C.cast(iv, C.POINTER(C.c_double))
+        loc = lambda_of_channel if lambda_of_channel is not None else [0] * C_
+        for c in range(C_):
+            d.lambda_of_channel[c] = int(loc[c])
+        d.pitch = float(pitch)
+    return d, keep
+
+
+def render_dp(desc, img, psf, depth=None, out=None):
+    """out [N][2C][H][W] float32."""
+    assert img.is_cuda and img.dtype == torch.float32
+    if out is None:
+        out = torch.empty((desc.N, 2 * desc.C, desc.H, desc.W), dtype=torch.float32,
+                          device=img.device)
+    rc = abi.lib().sdirt_render_dp(C.byref(desc), _dptr(img.contiguous()),
+                                   _dptr(psf), _dptr(depth), _dptr(out), _stream())
+    abi.check("sdirt_render_dp", rc)
+    return out
+
+
+def render_dp_backward(desc, psf, grad_out, depth=None, grad_img=None):
+    if grad_img is None:
+        grad_img = torch.empty((desc.N, desc.C, desc.H, desc.W), dtype=torch.float32,
+                               device=grad_out.device)
+    rc = abi.lib().sdirt_render_dp_backward(C.byref(desc), _dptr(psf), _dptr(depth),
+                                            _dptr(grad_out.contiguous()),
+                                            _dptr(grad_img), _stream())
+    abi.check("sdirt_render_dp_backward", rc)
+    return grad_img

@@ -1,0 +1,115 @@
+"""GPU parity of the pixel-wise DP renderer and its image adjoint against the
+CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import scenes
+from oracle import render as R
+from oracle.mlp import to_bf16
+from paper_2503_11213_amd import sdirt, _abi as abi
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-4
+
+
+def _rel(g, r):
+    scale = max(np.abs(r).max(), 1e-30)
+    return np.max(np.abs(g - r) / np.maximum(np.abs(r), 1e-3 * scale))
+
+
+def _dense(N, C, H, W, ks, Cp, seed, bf16=False):
+    rng = np.random.default_rng(seed)
+    img = rng.uniform(0, 1, (N, C, H, W)).astype(np.float32)
+    K = rng.uniform(0, 1, (N, H, W, Cp, 2, ks, ks)).astype(np.float32)
+    if bf16:
+        K = to_bf16(K).astype(np.float32)
+    return img, K
+
+
+@pytest.mark.parametrize("shape", [(1, 3, 19, 37, 7, 3), (2, 3, 17, 9, 5, 1),
+                                   (1, 1, 8, 8, 1, 1), (1, 2, 23, 21, 9, 2),
+                                   (1, 3, 5, 4, 11, 3)])
+def test_dense_forward_and_adjoint(shape):
+    N, C, H, W, ks, Cp = shape
+    img, K = _dense(N, C, H, W, ks, Cp, 1)
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, psf_channels=Cp)
+    Kt = torch.from_numpy(K).cuda()
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), Kt)
+    ref = R.render_dense(img, K)
+    assert _rel(out.cpu().numpy(), ref) <= REL_TOL
+    g = np.random.default_rng(2).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, Kt, torch.from_numpy(g).cuda())
+    gref = R.render_dense_adjoint(g, K)
+    assert _rel(gi.cpu().numpy(), gref) <= REL_TOL
+
+
+def test_dense_bf16_kernels():
+    N, C, H, W, ks, Cp = 1, 3, 21, 26, 9, 3
+    img, K = _dense(N, C, H, W, ks, Cp, 3, bf16=True)
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, psf_channels=Cp, psf_dtype=abi.BF16)
+    Kb = torch.from_numpy(K).to(torch.bfloat16).cuda()
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), Kb)
+    ref = R.render_dense(img, K)
+    assert _rel(out.cpu().numpy(), ref) <= REL_TOL
+    g = np.random.default_rng(4).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, Kb, torch.from_numpy(g).cuda())
+    assert _rel(gi.cpu().numpy(), R.render_dense_adjoint(g, K)) <= REL_TOL
+
+
+def _bank_case(N, C, H, W, ks, F, D, L, ps, seed):
+    rng = np.random.default_rng(seed)
+    img = rng.uniform(0, 1, (N, C, H, W)).astype(np.float32)
+    bank = rng.uniform(0, 1, (F, D, L, 2, ks, ks)).astype(np.float32)
+    half_diag = np.hypot(W * ps / 2, H * ps / 2)
+    radii = np.linspace(0, half_diag, F)
+    depths = 1.0 / np.linspace(1 / 5000.0, 1 / 500.0, D)
+    dmap = np.stack([scenes.depth_voronoi(H, W, 500.0, 5000.0, seed=100 + n) for n in range(N)])
+    return img, bank, radii, 1.0 / depths, dmap
+
+
+def test_bank_forward_and_adjoint():
+    N, C, H, W, ks, F, D, L, ps = 2, 3, 33, 45, 7, 6, 5, 3, 0.01
+    img, bank, radii, iv, dmap = _bank_case(N, C, H, W, ks, F, D, L, ps, 5)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps)
+    bt, dt = torch.from_numpy(bank).cuda(), torch.from_numpy(dmap).cuda()
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), bt, depth=dt)
+    ref = R.render_bank(img, bank, dmap, radii, iv, loc, ps)
+    assert _rel(out.cpu().numpy(), ref) <= REL_TOL
+    g = np.random.default_rng(6).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, bt, torch.from_numpy(g).cuda(), depth=dt)
+    gref = R.render_bank_adjoint(g, bank, dmap, radii, iv, loc, ps)
+    assert _rel(gi.cpu().numpy(), gref) <= REL_TOL
+
+
+def test_bank_full_size_sampled_pixels():
+    # the benchmarked launch: one 1680 x 1120 RGB image, 32 x 16 x 3 bank, ks 63
+    N, C, H, W, ks, F, D, L, ps = 1, 3, 1120, 1680, 63, 32, 16, 3, 0.00536
+    rng = np.random.default_rng(7)
+    img = scenes.aif_blobs(H, W, C, n_blobs=300, seed=0)[None]
+    bank = rng.uniform(0, 1, (F, D, L, 2, ks, ks)).astype(np.float32)
+    radii = np.arange(F) * np.hypot(W * ps / 2, H * ps / 2) / (F - 1)
+    iv = np.linspace(1 / 5000.0, 1 / 500.0, D)
+    dmap = scenes.depth_voronoi(H, W, 500.0, 5000.0, seed=100)[None]
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps)
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), torch.from_numpy(bank).cuda(),
+                          depth=torch.from_numpy(dmap).cuda()).cpu().numpy()
+    pix = [(0, 0, 0), (0, H - 1, W - 1), (0, 0, W - 1), (0, 560, 840), (0, 559, 839),
+           (0, 17, 1201), (0, 1000, 3)] + [(0, int(rng.integers(H)), int(rng.integers(W)))
+                                          for _ in range(40)]
+    ref = R.render_bank_pixels(img, bank, dmap, radii, iv, loc, ps, pix)
+    got = np.stack([out[n, :, y, x] for (n, y, x) in pix])
+    assert np.max(np.abs(got - ref) / np.abs(ref)) <= REL_TOL
+    # constant image: every output pixel is its kernel's sum
+    one = np.ones((N, C, H, W), dtype=np.float32)
+    o1 = sdirt.render_dp(desc, torch.from_numpy(one).cuda(), torch.from_numpy(bank).cuda(),
+                         depth=torch.from_numpy(dmap).cuda()).cpu().numpy()
+    sums = bank.sum(axis=(-1, -2))          # [F, D, L, 2]
+    assert o1.min() >= sums.min() * (1 - 1e-5) and o1.max() <= sums.max() * (1 + 1e-5)

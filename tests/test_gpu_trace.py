@@ -1,0 +1,221 @@
+"""GPU parity of the ray tracer and the DP PSF estimator against the CPU
+oracle (float64), through the C ABI."""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import lenses, configs
+from workloads.lens import (Sensor, PsfQuery, DP_SIGMOID, DP_MICROLENS, SPLAT_BOX,
+                            SPLAT_TENT, NORM_SUM, NORM_MAX)
+from oracle import optics, psf as opsf, trace as otr
+from paper_2503_11213_amd import sdirt, _abi as abi
+
+pytestmark = pytest.mark.gpu
+
+L1_TOL = 1e-3          # energy L1 for identical seeded rays
+HIT_TOL = 1e-5         # relative, floor 1 mm
+
+
+def _rf50_f4():
+    L = lenses.rf50()
+    L.f_number = 4.0
+    L.focus_depth = 1000.0
+    return L
+
+
+def _energy_l1(g, r):
+    return np.abs(g - r).sum() / max(np.abs(r).sum(), 1e-300)
+
+
+def _rays(lens, query, points):
+    P = optics.Prepared(lens)
+    o, d, lam = [], [], []
+    for (f, dd, l) in points:
+        e, dirs = opsf.bundle(P, query, f, dd, l)
+        o.append(e); d.append(dirs); lam.append(query.wavelengths[l])
+    return P, o, d, lam
+
+
+@pytest.mark.parametrize("which", ["config1", "config2", "rf50_f4"])
+def test_trace_rays_hits_match_oracle(which):
+    if which == "config1":
+        lens, sensor, query = configs.config1()
+    elif which == "config2":
+        lens, sensor, query = configs.config2(rays=48)
+    else:
+        lens = _rf50_f4()
+        query = PsfQuery(fields=[(0, 0), (10.0, 6.0)], depths=[600.0, 4000.0],
+                         wavelengths=[0.55], rays_x=48, rays_y=48, ks=21)
+    pts = [(0, 0, 0), (len(query.fields) - 1, len(query.depths) - 1, len(query.wavelengths) - 1)]
+    P, os_, ds, lams = _rays(lens, query, pts)
+    for o, d, lam in zip(os_, ds, lams):
+        ref = otr.trace(P, lam, o, d, record=True)
+        hits, st = sdirt.trace_rays(lens, lam, torch.from_numpy(o).cuda(),
+                                    torch.from_numpy(d).cuda())
+        torch.cuda.synchronize()
+        hits, st = hits.cpu().numpy(), st.cpu().numpy()
+        assert np.array_equal(st, ref["status"])
+        ok = st == 0
+        assert ok.mean() > 0.5
+        h, r = hits[ok], ref["hits"][ok]
+        err = np.abs(h - r) / np.maximum(np.abs(r), 1.0)
+        assert err.max() <= HIT_TOL, err.max()
+
+
+def test_trace_rays_f32_mode_error_budget():
+    # the float32 trace is a fast mode; its error on the 12-surface lens is
+    # measured here (not the parity path)
+    lens, sensor, query = configs.config2(rays=48)
+    P, os_, ds, lams = _rays(lens, query, [(10, 5, 1)])
+    ref = otr.trace(P, lams[0], os_[0], ds[0], record=True)
+    hits, st = sdirt.trace_rays(lens, lams[0], torch.from_numpy(os_[0]).cuda(),
+                                torch.from_numpy(ds[0]).cuda(), math=abi.F32)
+    hits = hits.cpu().numpy()
+    ok = ref["status"] == 0
+    err = np.abs(hits[ok] - ref["hits"][ok]) / np.maximum(np.abs(ref["hits"][ok]), 1.0)
+    print("float32 trace max rel err", err.max())
+    assert err.max() < 2e-4
+
+
+def test_config1_psf_and_stats_match_oracle():
+    lens, sensor, query = configs.config1()
+    psf, st = sdirt.trace_dp_psf(lens, sensor, query)
+    torch.cuda.synchronize()
+    ref, rst = opsf.trace_dp_psf(lens, sensor, query)
+    g, gs = psf.cpu().numpy(), st.cpu().numpy()
+    assert psf.dtype == torch.float64
+    assert _energy_l1(g, ref) <= L1_TOL
+    assert np.array_equal(gs[:, :3], rst[:, :3])
+    assert np.allclose(gs[:, 3:], rst[:, 3:], rtol=1e-5, atol=1e-2)
+
+
+@pytest.mark.parametrize("mode", [DP_SIGMOID, DP_MICROLENS])
+@pytest.mark.parametrize("splat", [SPLAT_BOX, SPLAT_TENT])
+def test_modes_on_aspheric_lens_match_oracle(mode, splat):
+    lens = _rf50_f4()
+    sensor = Sensor(pitch=0.01, dp_mode=mode, sigmoid_k=20.0)
+    query = PsfQuery(fields=[(0.0, 0.0), (8.0, 3.0), (-12.0, -7.5)], depths=[550.0, 1000.0, 9000.0],
+                     wavelengths=[0.5, 0.62], rays_x=80, rays_y=72, seed=3, jitter=True,
+                     ks=45, splat=splat)
+    psf, st = sdirt.trace_dp_psf(lens, sensor, query)
+    torch.cuda.synchronize()
+    ref, rst = opsf.trace_dp_psf(lens, sensor, query)
+    g, gs = psf.cpu().numpy(), st.cpu().numpy()
+    for q in range(ref.shape[0]):
+        if ref[q].sum() > 0:
+            assert _energy_l1(g[q], ref[q]) <= L1_TOL, q
+    assert np.array_equal(gs[:, :3], rst[:, :3])
+    assert np.allclose(gs[:, 3:], rst[:, 3:], rtol=1e-5, atol=0.05)
+    assert np.allclose(gs[:, 0], gs[:, 1] + gs[:, 2])
+    assert np.allclose(gs[:, 2], gs[:, 3:].sum(axis=1), rtol=1e-6)
+
+
+def test_config2_grid_at_reduced_rays_matches_oracle():
+    lens, sensor, query = configs.config2(rays=40)
+    psf, st = sdirt.trace_dp_psf(lens, sensor, query)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    picks = [(int(rng.integers(32)), int(rng.integers(16)), int(rng.integers(3))) for _ in range(24)]
+    ref, rst = opsf.trace_dp_psf(lens, sensor, query, points=picks)
+    g, gs = psf.cpu().numpy(), st.cpu().numpy()
+    for (f, d, l) in picks:
+        q = opsf.point_index(f, d, l, 16, 3)
+        if ref[q].sum() > 0:
+            assert _energy_l1(g[q], ref[q]) <= L1_TOL, (f, d, l)
+        assert np.array_equal(gs[q, :3], rst[q, :3])
+
+
+def test_config2_full_size_sampled_points():
+    # the benchmarked launch: 1536 points x 512^2 rays, ks 63, float32 out
+    lens, sensor, query = configs.config2()
+    psf, st = sdirt.trace_dp_psf(lens, sensor, query)
+    torch.cuda.synchronize()
+    picks = [(0, 0, 1), (17, 9, 0), (31, 15, 2)]
+    ref, rst = opsf.trace_dp_psf(lens, sensor, query, points=picks)
+    g, gs = psf.cpu().numpy(), st.cpu().numpy()
+    for (f, d, l) in picks:
+        q = opsf.point_index(f, d, l, 16, 3)
+        assert _energy_l1(g[q], ref[q]) <= L1_TOL, (f, d, l)
+        assert np.array_equal(gs[q, :3], rst[q, :3])
+    # properties over every point: bookkeeping and launched rays
+    assert np.all(gs[:, 0] == 512 * 512)
+    assert np.allclose(gs[:, 0], gs[:, 1] + gs[:, 2])
+    assert np.allclose(gs[:, 2], gs[:, 3:].sum(axis=1), rtol=1e-5)
+    assert np.allclose(g.sum(axis=(2, 3))[:, 0], gs[:, 3], rtol=1e-4)
+
+
+@pytest.mark.parametrize("norm", [NORM_SUM, NORM_MAX])
+def test_normalisation_matches_oracle(norm):
+    lens, sensor, query = configs.config1()
+    query.normalize = norm
+    psf, _ = sdirt.trace_dp_psf(lens, sensor, query)
+    ref, _ = opsf.trace_dp_psf(lens, sensor, query)
+    g = psf.cpu().numpy()
+    for q in range(ref.shape[0]):
+        assert _energy_l1(g[q], ref[q]) <= L1_TOL
+
+
+def test_on_axis_mirror_symmetry_on_gpu():
+    lens = _rf50_f4()
+    for mode in (DP_MICROLENS, DP_SIGMOID):
+        sensor = Sensor(pitch=0.02, dp_mode=mode)
+        query = PsfQuery(fields=[(0.0, 0.0)], depths=[600.0, 2500.0], wavelengths=[0.55],
+                         rays_x=128, rays_y=128, jitter=False, ks=25)
+        psf, _ = sdirt.trace_dp_psf(lens, sensor, query)
+        g = psf.cpu().numpy()
+        for q in range(2):
+            if mode == DP_MICROLENS:
+                assert np.array_equal(g[q, 0], g[q, 1][:, ::-1])
+            else:
+                assert np.allclose(g[q, 0], g[q, 1][:, ::-1], rtol=1e-5, atol=1e-4)
+
+
+def test_edge_cases():
+    lens, sensor, query = configs.config1()
+    # one ray, ks 1
+    q = copy.deepcopy(query); q.rays_x = 1; q.rays_y = 1; q.ks = 1
+    psf, st = sdirt.trace_dp_psf(lens, sensor, q)
+    ref, rst = opsf.trace_dp_psf(lens, sensor, q)
+    assert np.allclose(psf.cpu().numpy(), ref, atol=1e-6)
+    assert np.array_equal(st.cpu().numpy()[:, :3], rst[:, :3])
+    # a field far outside the window: everything outside, zero PSF
+    q = copy.deepcopy(query); q.fields = [(0.0, 0.0)]
+    L = lenses.singlet(); L.focus_depth = 2000.0
+    psf, st = sdirt.trace_dp_psf(L, sensor, q)
+    ref, rst = opsf.trace_dp_psf(L, sensor, q)
+    assert np.allclose(st.cpu().numpy(), rst, rtol=1e-6, atol=1e-3)
+    # all rays vignetted: tiny clear aperture behind the stop
+    L = lenses.singlet(); L.surfaces[2].semi_diameter = 1e-4
+    psf, st = sdirt.trace_dp_psf(L, sensor, query)
+    s = st.cpu().numpy()
+    assert np.all(psf.cpu().numpy() == 0) and np.all(s[:, 1] == s[:, 0])
+    # ragged ray count not a multiple of the workgroup
+    q = copy.deepcopy(query); q.rays_x = 37; q.rays_y = 29
+    psf, st = sdirt.trace_dp_psf(lens, sensor, q)
+    ref, rst = opsf.trace_dp_psf(lens, sensor, q)
+    assert np.array_equal(st.cpu().numpy()[:, :3], rst[:, :3])
+    assert _energy_l1(psf.cpu().numpy(), ref) <= L1_TOL
+
+
+def test_list_mode_equals_grid_mode():
+    lens, sensor, query = configs.config2(rays=32)
+    psf, st = sdirt.trace_dp_psf(lens, sensor, query)
+    pts = []
+    for f, fld in enumerate(query.fields):
+        for d, dep in enumerate(query.depths):
+            for l in range(3):
+                pts.append([fld[0], fld[1], dep, l])
+    pts = torch.tensor(pts, dtype=torch.float64, device="cuda")
+    psf2, st2 = sdirt.trace_dp_psf(lens, sensor, query, points=pts)
+    assert torch.allclose(psf, psf2, rtol=1e-5, atol=1e-5)
+    assert torch.equal(st[:, :3], st2[:, :3])
+
+
+def test_chunking_does_not_change_result():
+    lens, sensor, query = configs.config2(rays=64)
+    a, sa = sdirt.trace_dp_psf(lens, sensor, query, chunks=1)
+    b, sb = sdirt.trace_dp_psf(lens, sensor, query, chunks=7)
+    assert torch.allclose(a, b, rtol=1e-5, atol=1e-4)
+    assert torch.equal(sa[:, :3], sb[:, :3])

@@ -10,7 +10,7 @@ CPU oracle and the HIP path consume these objects; neither is imported here.
 
 from .lens import (Surface, Lens, Sensor, PsfQuery, SPHERE, PLANE, STOP,
                    ASPHERE, IDEAL, air, abbe, cauchy)
-from . import lenses
+from . import lenses, scenes, configs
 
 __all__ = ["Surface", "Lens", "Sensor", "PsfQuery", "SPHERE", "PLANE", "STOP",
            "ASPHERE", "IDEAL", "air", "abbe", "cauchy", "lenses"]
