@@ -63,12 +63,12 @@ def cpu_baseline(lens, sensor, query, img, dmap, radii, iv, loc, ps, total_rs,
     import oracle.psf as opsf
     import oracle.render as orender
     n_surf = 12
-    picks = [(0, 0, 1), (15, 8, 0), (31, 15, 2)]
+    picks = [(f, (5 * f) % 16, f % 3) for f in range(0, 32, 3)]
     t0 = time.perf_counter()
     bank, _ = opsf.trace_dp_psf(lens, sensor, query, points=picks)
     t_trace = time.perf_counter() - t0
     sample_rays = len(picks) * query.n_rays
-    crop = 48
+    crop = 96
     ks = query.ks
     bank6 = bank.reshape(len(query.fields), len(query.depths), len(query.wavelengths), 2, ks, ks)
     y0, x0 = H // 2 - crop // 2, W // 2 - crop // 2

@@ -108,6 +108,89 @@ class FrozenEstimator:
                                           sensor, q.ks, q.splat)
         return out
 
+    def landing_sensitivity(self, p, h):
+        """Largest |dO/dtheta_p| over all rays (central differences of the
+        landing points, which are smooth in theta)."""
+        th0 = self.theta0
+        q = self.query
+        best = 0.0
+        for sgn_pair in [(h, -h)]:
+            outs = []
+            for dh in sgn_pair:
+                th = th0.copy(); th[p] += dh
+                prep, _ = with_theta(self.prep, self.sensor, th)
+                outs.append([tr.trace(prep, q.wavelengths[l], e, d)["O"]
+                             for (f, dd, l), (e, d) in zip(self.points, self.bundles)])
+            for a, b in zip(*outs):
+                best = max(best, float(np.max(np.abs(a - b))) / (2 * h))
+        return best
+
+    def fd_gradient_at(self, G, p, h):
+        """Central difference of <G, PSF(theta)> in parameter p with step h.
+        The tent splat is piecewise bilinear in the landing point, so the
+        step must move every landing point by much less than pitch / rays
+        for the difference to resolve the derivative rather than kinks."""
+        th0 = self.theta0
+        tp = th0.copy(); tp[p] += h
+        tm = th0.copy(); tm[p] -= h
+        return (np.sum(G * self.psfs(tp)) - np.sum(G * self.psfs(tm))) / (2 * h)
+
+    def ray_fd_gradient(self, G, p, h):
+        """<G, dPSF/dtheta_p> with the finite difference taken per ray: each
+        ray's landing point O and direction D are smooth in theta, so their
+        central differences converge as h^2; the tent and response
+        derivatives are then applied to them (the limit h -> 0 of the
+        PSF-level difference, without the pixel-centre kinks)."""
+        q = self.query
+        ps = self.sensor.pitch
+        k = self.sensor.sigmoid_k
+        pad = (q.ks - 1) // 2
+        th0 = self.theta0
+        slope = p == len(th0) - 1
+        total = 0.0
+        prep0, _ = with_theta(self.prep, self.sensor, th0)
+        for idx, ((f, d, l), (e, dirs)) in enumerate(zip(self.points, self.bundles)):
+            lam = q.wavelengths[l]
+            r0 = tr.trace(prep0, lam, e, dirs)
+            O, D = r0["O"], r0["D"]
+            if slope:
+                dO = np.zeros_like(O)
+                dD = np.zeros_like(D)
+            else:
+                tp = th0.copy(); tp[p] += h
+                tm = th0.copy(); tm[p] -= h
+                rp = tr.trace(with_theta(self.prep, self.sensor, tp)[0], lam, e, dirs)
+                rm = tr.trace(with_theta(self.prep, self.sensor, tm)[0], lam, e, dirs)
+                dO = (rp["O"] - rm["O"]) / (2 * h)
+                dD = (rp["D"] - rm["D"]) / (2 * h)
+            rr = np.sqrt(D[:, 0] ** 2 + D[:, 2] ** 2)
+            sx = D[:, 0] / rr
+            wl = 1.0 / (1.0 + np.exp(-k * sx))
+            sig1 = wl * (1.0 - wl)
+            dsx = (D[:, 2] ** 2 * dD[:, 0] - D[:, 0] * D[:, 2] * dD[:, 2]) / rr ** 3
+            dwl = sig1 * sx if slope else sig1 * k * dsx
+            w = (wl, 1.0 - wl)
+            dw = (dwl, -dwl)
+            hx, hy = q.fields[f]
+            u = (O[:, 0] - hx) / ps + pad
+            v = (O[:, 1] - hy) / ps + pad
+            du, dv = dO[:, 0] / ps, dO[:, 1] / ps
+            j0 = np.floor(u).astype(np.int64)
+            i0 = np.floor(v).astype(np.int64)
+            fx, fy = u - j0, v - i0
+            taps = [(0, 0, (1 - fy) * (1 - fx), -(1 - fy), -(1 - fx)),
+                    (0, 1, (1 - fy) * fx, (1 - fy), -fx),
+                    (1, 0, fy * (1 - fx), -fy, (1 - fx)),
+                    (1, 1, fy * fx, fy, fx)]
+            for (a, b, wt, wtu, wtv) in taps:
+                ii, jj = i0 + a, j0 + b
+                inw = (ii >= 0) & (ii < q.ks) & (jj >= 0) & (jj < q.ks)
+                for sd in range(2):
+                    g = np.zeros(len(u))
+                    g[inw] = G[idx, sd, ii[inw], jj[inw]]
+                    total += np.sum(g * (w[sd] * (wtu * du + wtv * dv) + dw[sd] * wt))
+        return total
+
     def fd_gradient(self, G, rel_step=1e-6, params=None, scale=None):
         """Central differences of <G, PSF(theta)> for each parameter."""
         th0 = self.theta0

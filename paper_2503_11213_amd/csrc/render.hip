@@ -36,6 +36,7 @@ struct RenderArgs {
     float t_z[SDIRT_MAX_BANK_D];       // depth thresholds (rounded up)
     int lam_of_c[4];
     int tiles_x, tiles_y;
+    int use_fast;        // bank source: register-blocked kernel when ks allows
     const float* img;
     const void* psf;
     const float* depth;
@@ -244,6 +245,244 @@ __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A)
     }
 }
 
+// ---- bank source, register-blocked path ----------------------------------
+//
+// Neighbouring pixels mostly share one bank entry, so the bank render is a
+// sum over entries of ordinary shift-invariant convolutions restricted to the
+// pixels that use them.  A thread owns a strip of 8 horizontally adjacent
+// output pixels, a wave an 8 x 64 block, a workgroup a 32 x 64 tile whose
+// clamped image halo (one channel at a time) sits in LDS.  The wave loops
+// over the distinct entries of its block (wave-uniform); for each it runs a
+// direct convolution with the entry's kernel read through the scalar cache
+// (wave-uniform addresses), a 70-wide register window of the halo row and
+// 16 accumulators, and keeps the result for the strip pixels that use the
+// entry.  The adjoint scatters each kernel row's 1-D correlation with the
+// strip's gradients into the LDS halo (one LDS atomic per halo column, not
+// per tap) and folds the halo back with clamped global atomics.
+constexpr int kFW = 64, kFH = 32, kStrip = 8;
+
+template <int KS>
+struct FastGeom {
+    static constexpr int HW = ((kFW + KS - 1 + 3) / 4) * 4 + 4;   // padded row
+    static constexpr int HH = kFH + KS - 1;
+    static constexpr int WIN = ((KS + kStrip - 1 + 3) / 4) * 4;   // window, float4s
+};
+
+__device__ inline int wave_min_int(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Bank key of pixel (y, x): ((fi * D + di) * 2 + flip_x) * 2 + flip_y.
+__device__ inline int bank_key(const RenderArgs& A, int n, int y, int x) {
+    const long long X2 = 2LL * x - (A.W - 1);
+    const long long Y2 = 2LL * y - (A.H - 1);
+    const long long R2 = X2 * X2 + Y2 * Y2;
+    int fi = 0;
+    for (int k = 0; k < A.F - 1; ++k) fi += R2 > A.t_r[k];
+    const float z = A.depth[((size_t)n * A.H + y) * A.W + x];
+    int di = 0;
+    for (int k = 0; k < A.D - 1; ++k) di += z < A.t_z[k];
+    return ((fi * A.D + di) * 2 + (X2 < 0 ? 1 : 0)) * 2 + (Y2 < 0 ? 1 : 0);
+}
+
+template <int KS>
+__device__ inline void stage_fast_halo(const RenderArgs& A, int n, int c, int y0, int x0,
+                                       float* halo) {
+    using G = FastGeom<KS>;
+    const int pad = (KS - 1) / 2;
+    const float* im = A.img + ((size_t)n * A.C + c) * A.H * A.W;
+    for (int e = threadIdx.x; e < G::HH * G::HW; e += kRBlock) {
+        const int r = e / G::HW, q = e - r * G::HW;
+        const int yy = min(max(y0 - pad + r, 0), A.H - 1);
+        const int xx = min(max(x0 - pad + q, 0), A.W - 1);
+        halo[e] = im[(size_t)yy * A.W + xx];
+    }
+}
+
+template <int KS, bool FX>
+__device__ inline void conv_strip(const float* __restrict__ kl, const float* __restrict__ kr,
+                                  bool fy, const float* halo, int ly, int hc,
+                                  float accL[kStrip], float accR[kStrip]) {
+    using G = FastGeom<KS>;
+#pragma unroll
+    for (int q = 0; q < kStrip; ++q) { accL[q] = 0.f; accR[q] = 0.f; }
+    for (int i = 0; i < KS; ++i) {
+        const int si = fy ? KS - 1 - i : i;
+        const float* rl = kl + si * KS;
+        const float* rr = kr + si * KS;
+        float win[G::WIN];
+        const float4* src = reinterpret_cast<const float4*>(halo + (ly - i) * G::HW + hc);
+#pragma unroll
+        for (int m = 0; m < G::WIN / 4; ++m) {
+            const float4 v = src[m];
+            win[4 * m] = v.x; win[4 * m + 1] = v.y; win[4 * m + 2] = v.z; win[4 * m + 3] = v.w;
+        }
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const int sj = FX ? KS - 1 - j : j;
+            const float a = rl[sj], b = rr[sj];
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q) {
+                accL[q] = fmaf(a, win[q - j + KS - 1], accL[q]);
+                accR[q] = fmaf(b, win[q - j + KS - 1], accR[q]);
+            }
+        }
+    }
+}
+
+template <int KS, bool FX>
+__device__ inline void conv_strip_bwd(const float* __restrict__ kl, const float* __restrict__ kr,
+                                      bool fy, float* hgrad, int ly, int hc,
+                                      const float gL[kStrip], const float gR[kStrip]) {
+    using G = FastGeom<KS>;
+    for (int i = 0; i < KS; ++i) {
+        const int si = fy ? KS - 1 - i : i;
+        const float* rl = kl + si * KS;
+        const float* rr = kr + si * KS;
+        float acc[KS + kStrip - 1];
+#pragma unroll
+        for (int m = 0; m < KS + kStrip - 1; ++m) acc[m] = 0.f;
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const int sj = FX ? KS - 1 - j : j;
+            const float a = rl[sj], b = rr[sj];
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q)
+                acc[q - j + KS - 1] = fmaf(a, gL[q], fmaf(b, gR[q], acc[q - j + KS - 1]));
+        }
+        float* dst = hgrad + (ly - i) * G::HW + hc;
+#pragma unroll
+        for (int m = 0; m < KS + kStrip - 1; ++m) atomicAdd(&dst[m], acc[m]);
+    }
+}
+
+template <int KS, bool BWD>
+__global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderArgs A) {
+    using G = FastGeom<KS>;
+    extern __shared__ float halo[];     // [HH][HW]
+    const int pad = (KS - 1) / 2;
+    const int kk = KS * KS;
+    const int tilesx = (A.W + kFW - 1) / kFW, tilesy = (A.H + kFH - 1) / kFH;
+    const int tile = blockIdx.x;
+    const int n = tile / (tilesx * tilesy);
+    const int rem = tile - n * tilesx * tilesy;
+    const int y0 = (rem / tilesx) * kFH, x0 = (rem % tilesx) * kFW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tr = wave * 8 + (lane >> 3);        // row within the tile
+    const int tc = lane & 7;                      // strip within the row
+    const int y = y0 + tr, xs = x0 + tc * kStrip;
+    const int ly = tr + KS - 1;                   // halo row of tap i = 0
+    const int hc = tc * kStrip;                   // halo column of the window start
+    int key[kStrip];
+#pragma unroll
+    for (int q = 0; q < kStrip; ++q)
+        key[q] = (y < A.H && xs + q < A.W) ? bank_key(A, n, y, xs + q) : 0x7fffffff;
+    for (int c = 0; c < A.C; ++c) {
+        const int lam = A.lam_of_c[c];
+        float gL[kStrip], gR[kStrip], resL[kStrip], resR[kStrip];
+        if (BWD) {
+            for (int e = threadIdx.x; e < G::HH * G::HW; e += kRBlock) halo[e] = 0.f;
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q) {
+                const bool ok = key[q] != 0x7fffffff;
+                const size_t o = ((size_t)n * 2 * A.C * A.H + y) * A.W + xs + q;
+                gL[q] = ok ? A.gout[o + (size_t)c * A.H * A.W] : 0.f;
+                gR[q] = ok ? A.gout[o + (size_t)(A.C + c) * A.H * A.W] : 0.f;
+            }
+        } else {
+            stage_fast_halo<KS>(A, n, c, y0, x0, halo);
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q) { resL[q] = 0.f; resR[q] = 0.f; }
+        }
+        __syncthreads();
+        unsigned done = 0;
+#pragma unroll
+        for (int q = 0; q < kStrip; ++q) if (key[q] == 0x7fffffff) done |= 1u << q;
+        while (true) {
+            int mine = 0x7fffffff;
+#pragma unroll
+            for (int q = kStrip - 1; q >= 0; --q) if (!(done & (1u << q))) mine = key[q];
+            const int k = __builtin_amdgcn_readfirstlane(wave_min_int(mine));
+            if (k == 0x7fffffff) break;
+            const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
+            const size_t base = ((size_t)fd * A.L + lam) * 2 * kk;
+            const float* bank = reinterpret_cast<const float*>(A.psf);
+            const float* kl = bank + base + (fxb ? kk : 0);
+            const float* kr = bank + base + (fxb ? 0 : kk);
+            if (BWD) {
+                float mL[kStrip], mR[kStrip];
+#pragma unroll
+                for (int q = 0; q < kStrip; ++q) {
+                    mL[q] = key[q] == k ? gL[q] : 0.f;
+                    mR[q] = key[q] == k ? gR[q] : 0.f;
+                }
+                if (fxb) conv_strip_bwd<KS, true>(kl, kr, fyb, halo, ly, hc, mL, mR);
+                else conv_strip_bwd<KS, false>(kl, kr, fyb, halo, ly, hc, mL, mR);
+            } else {
+                float aL[kStrip], aR[kStrip];
+                if (fxb) conv_strip<KS, true>(kl, kr, fyb, halo, ly, hc, aL, aR);
+                else conv_strip<KS, false>(kl, kr, fyb, halo, ly, hc, aL, aR);
+#pragma unroll
+                for (int q = 0; q < kStrip; ++q)
+                    if (key[q] == k) { resL[q] = aL[q]; resR[q] = aR[q]; }
+            }
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q) if (key[q] == k) done |= 1u << q;
+        }
+        if (BWD) {
+            __syncthreads();
+            float* gi = A.gimg + ((size_t)n * A.C + c) * A.H * A.W;
+            for (int e = threadIdx.x; e < G::HH * G::HW; e += kRBlock) {
+                const int r = e / G::HW, q = e - r * G::HW;
+                if (q >= kFW + KS - 1) continue;
+                const float v = halo[e];
+                if (v == 0.f) continue;
+                const int yy = min(max(y0 - pad + r, 0), A.H - 1);
+                const int xx = min(max(x0 - pad + q, 0), A.W - 1);
+                atomicAdd(&gi[(size_t)yy * A.W + xx], v);
+            }
+        } else if (y < A.H) {
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q) {
+                if (xs + q < A.W) {
+                    const size_t o = (((size_t)n * 2 * A.C + c) * A.H + y) * A.W + xs + q;
+                    A.out[o] = resL[q];
+                    A.out[o + (size_t)A.C * A.H * A.W] = resR[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int KS, bool BWD>
+static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
+    using G = FastGeom<KS>;
+    const size_t shm = (size_t)G::HH * G::HW * sizeof(float);
+    const int tilesx = (A.W + kFW - 1) / kFW, tilesy = (A.H + kFH - 1) / kFH;
+    const dim3 grid((unsigned)((long long)A.N * tilesx * tilesy));
+    auto k = render_bank_fast_kernel<KS, BWD>;
+    if (shm > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k, grid, dim3(kRBlock), shm, st, A);
+    return true;
+}
+
+template <bool BWD>
+static bool try_bank_fast(const RenderArgs& A, hipStream_t st) {
+    if (A.source != SDIRT_SRC_BANK) return false;
+    if ((long long)A.F * A.D * 4 >= 0x7fffffffLL) return false;
+    switch (A.ks) {
+        case 21: return launch_bank_fast<21, BWD>(A, st);
+        case 31: return launch_bank_fast<31, BWD>(A, st);
+        case 33: return launch_bank_fast<33, BWD>(A, st);
+        case 41: return launch_bank_fast<41, BWD>(A, st);
+        case 63: return launch_bank_fast<63, BWD>(A, st);
+        case 65: return launch_bank_fast<65, BWD>(A, st);
+        default: return false;
+    }
+}
+
 // ---- host ----------------------------------------------------------------
 
 static int pack_render(const sdirt_render_desc* d, RenderArgs* A) {
@@ -301,6 +540,7 @@ static int pack_render(const sdirt_render_desc* d, RenderArgs* A) {
     } else {
         return SDIRT_EINVAL;
     }
+    A->use_fast = 1;
     A->tiles_x = (d->W + kTW - 1) / kTW;
     A->tiles_y = (d->H + kTH - 1) / kTH;
     return SDIRT_OK;
@@ -322,6 +562,8 @@ static void launch_render(const RenderArgs& A, hipStream_t st) {
 
 template <bool BWD>
 static int dispatch_render(const RenderArgs& A, hipStream_t st) {
+    if (A.use_fast && try_bank_fast<BWD>(A, st))
+        return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
     const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
     if ((size_t)A.C * hh * hw * sizeof(float) > 160 * 1024) return SDIRT_EUNSUPPORTED;
     switch (A.C) {

@@ -1,0 +1,97 @@
+"""GPU adjoint of the trace + splat against float64 central finite
+differences of the oracle's estimator (frozen framing), through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import configs, lenses
+from workloads.lens import Sensor, PsfQuery, SPLAT_TENT, DP_SIGMOID
+from oracle import adjoint as A
+from paper_2503_11213_amd import sdirt
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-4
+
+
+def _check(lens, sensor, query, params, seed=11):
+    est = A.FrozenEstimator(lens, sensor, query)
+    G = np.random.default_rng(seed).normal(size=(query.n_points, 2, query.ks, query.ks)).astype(np.float32)
+    g_gpu = sdirt.trace_dp_psf_backward(lens, sensor, query, torch.from_numpy(G).cuda()).cpu().numpy()
+    G64 = G.astype(np.float64)
+    fd = {}
+    for p in params:
+        # per-ray central differences (smooth in theta): steps that move the
+        # landing points by about 1e-6 mm, and half of that as a check
+        sens = est.landing_sensitivity(p, 1e-7 * max(abs(est.theta0[p]), 1e-3))
+        h = 1e-6 / max(sens, 1e-12) if p != len(est.theta0) - 1 else 1.0
+        a = est.ray_fd_gradient(G64, p, h)
+        b = est.ray_fd_gradient(G64, p, h / 2)
+        fd[p] = (a, b)
+    scale = max(abs(v[1]) for v in fd.values())
+    for p, (a, b) in fd.items():
+        # the difference quotient itself is converged well below the bar
+        assert abs(a - b) <= 0.1 * REL * max(abs(b), 1e-3 * scale), (p, a, b)
+        assert abs(g_gpu[p] - b) <= REL * max(abs(b), 1e-3 * scale), (p, g_gpu[p], b)
+    # the PSF-level difference (kink-limited) agrees to its own resolution
+    for p in list(fd)[:3]:
+        sens = est.landing_sensitivity(p, 1e-7 * max(abs(est.theta0[p]), 1e-3))
+        h = 2e-9 / max(sens, 1e-12) if p != len(est.theta0) - 1 else 1e-6 * abs(est.theta0[p])
+        c = est.fd_gradient_at(G64, p, h)
+        assert abs(c - fd[p][1]) <= 1e-3 * max(abs(fd[p][1]), 1e-3 * scale), (p, c, fd[p][1])
+    return g_gpu
+
+
+def test_adjoint_spherical_lens_matches_fd():
+    lens = configs.config2_lens()
+    sensor = Sensor(pitch=0.00536, dp_mode=DP_SIGMOID, sigmoid_k=20.0)
+    query = PsfQuery(fields=[(0.0, 0.0), (3.0, 0.0)], depths=[700.0, 2000.0],
+                     wavelengths=[0.486, 0.656], rays_x=40, rays_y=40, seed=0,
+                     jitter=True, ks=41, splat=SPLAT_TENT)
+    S = len(lens.surfaces)
+    params = [0, 1, 8 * 3, 8 * 3 + 1, 8 * 6 + 1, 8 * 9, 8 * 11, 8 * 12, 8 * 12 + 1, 8 * S]
+    _check(lens, sensor, query, params)
+
+
+def test_adjoint_aspheric_lens_matches_fd():
+    lens = lenses.rf50()
+    lens.f_number = 4.0
+    lens.focus_depth = 1000.0
+    sensor = Sensor(pitch=0.01, dp_mode=DP_SIGMOID, sigmoid_k=15.0)
+    query = PsfQuery(fields=[(0.0, 0.0), (6.0, 2.0)], depths=[600.0, 3000.0],
+                     wavelengths=[0.55], rays_x=40, rays_y=40, seed=1, jitter=True,
+                     ks=31, splat=SPLAT_TENT)
+    # surfaces 9 and 10 (indices 8, 9) are even aspheres
+    params = [8 * 8 + k for k in range(8)] + [8 * 9 + k for k in (0, 1, 3, 4, 5)] + [8 * 5 + 1, 8 * 11 + 1, 96]
+    _check(lens, sensor, query, params)
+
+
+def test_adjoint_rejects_unsupported_modes():
+    lens, sensor, query = configs.config1()
+    G = torch.zeros((4, 2, 31, 31), device="cuda")
+    with pytest.raises(RuntimeError):
+        sdirt.trace_dp_psf_backward(lens, sensor, query, G)       # box splat
+
+
+def test_adjoint_config3_full_size_properties():
+    # the config-3 launch (8 x 8 x 3 points, 256^2 rays, ks 41): the slope
+    # gradient has a closed form in the traced PSFs' sensitivity, and the
+    # whole gradient is linear in the upstream gradient
+    lens, sensor, query = configs.config3()
+    rng = np.random.default_rng(5)
+    G1 = torch.from_numpy(rng.normal(size=(query.n_points, 2, 41, 41)).astype(np.float32)).cuda()
+    G2 = torch.from_numpy(rng.normal(size=(query.n_points, 2, 41, 41)).astype(np.float32)).cuda()
+    g1 = sdirt.trace_dp_psf_backward(lens, sensor, query, G1)
+    g2 = sdirt.trace_dp_psf_backward(lens, sensor, query, G2)
+    g12 = sdirt.trace_dp_psf_backward(lens, sensor, query, G1 + 2 * G2)
+    ref = g1 + 2 * g2
+    assert torch.allclose(g12, ref, rtol=1e-6, atol=1e-9 * ref.abs().max().item())
+    # slope: d<G, PSF>/dk by a forward difference of the traced PSFs
+    psf0, _ = sdirt.trace_dp_psf(lens, sensor, query)
+    import copy
+    s2 = copy.copy(sensor); s2.sigmoid_k = sensor.sigmoid_k * (1 + 1e-3)
+    psf1, _ = sdirt.trace_dp_psf(lens, s2, query)
+    s3 = copy.copy(sensor); s3.sigmoid_k = sensor.sigmoid_k * (1 - 1e-3)
+    psf2, _ = sdirt.trace_dp_psf(lens, s3, query)
+    fd = ((G1 * (psf1 - psf2)).sum() / (2e-3 * sensor.sigmoid_k)).item()
+    assert g1[-1].item() == pytest.approx(fd, rel=2e-3)

@@ -125,3 +125,19 @@ def test_fd_error_shrinks_quadratically_for_smooth_parameter():
     exact = est.fd_gradient(G, rel_step=1e-6, params=[p])[p]
     errs = [abs(est.fd_gradient(G, rel_step=r, params=[p])[p] - exact) for r in (4e-2, 2e-2)]
     assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.1)
+
+
+def test_per_ray_differences_equal_psf_level_difference():
+    # the per-ray form (smooth central differences of landing points plus
+    # the tent / response derivatives) is the kink-free limit of the
+    # PSF-level central difference
+    est, G = _setup()
+    for p in (8 * 2 + 0, 8 * 6 + 1, 8 * 8 + 3, len(est.theta0) - 1):
+        sens = est.landing_sensitivity(p, 1e-7 * max(abs(est.theta0[p]), 1e-3))
+        if p == len(est.theta0) - 1:
+            a = est.ray_fd_gradient(G, p, 1.0)
+            c = est.fd_gradient_at(G, p, 1e-6 * abs(est.theta0[p]))
+        else:
+            a = est.ray_fd_gradient(G, p, 1e-6 / sens)
+            c = est.fd_gradient_at(G, p, 2e-9 / sens)
+        assert c == pytest.approx(a, rel=1e-4)
