@@ -234,6 +234,63 @@ int sdirt_render_dp_backward(const sdirt_render_desc* desc, const void* psf,
                              const float* depth, const float* grad_out,
                              float* grad_img, void* stream);
 
+/* ---- PSF surrogate MLP (Sec. 3.2, Supplement S1.4) ---------------------
+ * Maps an image-plane point, inverse depth and wavelength to the jointly
+ * sum-normalised left/right PSF: Fourier encoding (sin / cos of
+ * 2^k pi v, k < n_freq, for the four inputs mapped to [-1, 1]), n_hidden
+ * ReLU layers of `width`, a linear layer to n_out = 2 ks ks logits and a
+ * softmax over all of them.  Training minimises the squared error of each
+ * output scaled by the largest value of its target PSF (max-normalised
+ * targets), averaged over the batch.
+ * Parameters: one float32 vector, per layer W [out][in] row-major then
+ * b [out], layers in order (sizes from sdirt_mlp_n_params).  Matrix
+ * products run in bf16 on the matrix cores with float32 accumulation.
+ * workspace: caller-owned device memory of sdirt_mlp_workspace_size(batch)
+ * bytes for batches of `batch` rows (a multiple of 64); it holds the bf16
+ * weights, activations and gradients of one batch. */
+typedef struct {
+    int n_hidden;            /* ReLU layers                                */
+    int width;               /* hidden width, multiple of 64               */
+    int n_out;               /* outputs, 2 * ks * ks                       */
+    int n_freq;              /* frequencies per input (features 8 n_freq)  */
+    double x_half, y_half;   /* h_x, h_y scale: image half-size (mm)       */
+    double iv_lo, iv_hi;     /* inverse-depth range (1/mm)                 */
+    double lam_lo, lam_hi;   /* wavelength range (um)                      */
+} sdirt_mlp_desc;
+
+int sdirt_mlp_n_params(const sdirt_mlp_desc* desc, long long* n_params);
+int sdirt_mlp_workspace_size(const sdirt_mlp_desc* desc, int batch, size_t* bytes);
+
+/* Inference of n_rows inputs x (device [n_rows][4]: h_x, h_y, 1/d, lambda)
+ * into out (device [n_rows][n_out], SDIRT_F32 or SDIRT_BF16), processed in
+ * chunks of ws_batch rows with a workspace sized for ws_batch. */
+int sdirt_mlp_forward(const sdirt_mlp_desc* desc, const float* params,
+                      long long n_rows, const float* x, void* out, int out_dtype,
+                      void* workspace, int ws_batch, void* stream);
+
+/* Loss and its gradient for one batch: grads_out device [n_params] f32,
+ * loss_out device [1] f32 (either may be NULL); target device
+ * [batch][n_out], each row a jointly sum-normalised PSF. */
+int sdirt_mlp_backward(const sdirt_mlp_desc* desc, const float* params, int batch,
+                       const float* x, const float* target, float* grads_out,
+                       float* loss_out, void* workspace, void* stream);
+
+/* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) of
+ * params with moments m, v (device [n_params] f32 each, updated). */
+int sdirt_mlp_adam(const sdirt_mlp_desc* desc, float* params, float* m, float* v,
+                   const float* grads, int step, float lr, void* stream);
+
+/* n_steps training steps on a device-resident dataset (x_all [n][4],
+ * t_all [n][n_out]): each step draws `batch` samples by a counter hash of
+ * (seed, step, row), runs forward, loss gradient and Adam with the learning
+ * rate lr_min + (lr0 - lr_min) (1 + cos(pi step / total_steps)) / 2.
+ * loss_trace device [n_steps] f32 or NULL receives each step's loss. */
+int sdirt_mlp_train(const sdirt_mlp_desc* desc, float* params, float* m, float* v,
+                    int step0, int n_steps, float lr0, float lr_min, int total_steps,
+                    int batch, long long n_samples, const float* x_all,
+                    const float* t_all, uint32_t seed, float* loss_trace,
+                    void* workspace, void* stream);
+
 /* ---- misc ------------------------------------------------------------- */
 const char* sdirt_status_string(int status);
 int sdirt_version(void);

@@ -73,8 +73,8 @@ class RenderDesc(C.Structure):
 
 
 class MlpDesc(C.Structure):
-    _fields_ = [("batch", C.c_int), ("hidden", C.c_int), ("n_hidden", C.c_int),
-                ("n_out", C.c_int), ("n_freq", C.c_int),
+    _fields_ = [("n_hidden", C.c_int), ("width", C.c_int), ("n_out", C.c_int),
+                ("n_freq", C.c_int),
                 ("x_half", C.c_double), ("y_half", C.c_double),
                 ("iv_lo", C.c_double), ("iv_hi", C.c_double),
                 ("lam_lo", C.c_double), ("lam_hi", C.c_double)]
@@ -105,6 +105,21 @@ SIGNATURES = {
     "sdirt_render_dp_backward": (C.c_int, [C.POINTER(RenderDesc), C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p]),
+    "sdirt_mlp_n_params": (C.c_int, [C.POINTER(MlpDesc), C.POINTER(C.c_longlong)]),
+    "sdirt_mlp_workspace_size": (C.c_int, [C.POINTER(MlpDesc), C.c_int,
+                                           C.POINTER(C.c_size_t)]),
+    "sdirt_mlp_forward": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_longlong,
+                                    C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                    C.c_int, C.c_void_p]),
+    "sdirt_mlp_backward": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_int,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
+    "sdirt_mlp_adam": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_int, C.c_float, C.c_void_p]),
+    "sdirt_mlp_train": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int, C.c_int, C.c_float, C.c_float, C.c_int,
+                                  C.c_int, C.c_longlong, C.c_void_p, C.c_void_p,
+                                  C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None

@@ -20,6 +20,16 @@ int render_impl(const sdirt_render_desc*, const float*, const void*, const float
                 float*, hipStream_t);
 int render_backward_impl(const sdirt_render_desc*, const void*, const float*,
                          const float*, float*, hipStream_t);
+int mlp_n_params(const sdirt_mlp_desc*, long long*);
+int mlp_workspace_size(const sdirt_mlp_desc*, int, size_t*);
+int mlp_forward(const sdirt_mlp_desc*, const float*, long long, const float*, void*, int,
+                void*, int, hipStream_t);
+int mlp_backward(const sdirt_mlp_desc*, const float*, int, const float*, const float*,
+                 float*, float*, void*, hipStream_t);
+int mlp_adam(const sdirt_mlp_desc*, float*, float*, float*, const float*, int, float,
+             hipStream_t);
+int mlp_train(const sdirt_mlp_desc*, float*, float*, float*, int, int, float, float, int, int,
+              long long, const float*, const float*, uint32_t, float*, void*, hipStream_t);
 }  // namespace sdirt
 
 using namespace sdirt;
@@ -111,6 +121,45 @@ int sdirt_render_dp_backward(const sdirt_render_desc* desc, const void* psf,
                              const float* depth, const float* grad_out,
                              float* grad_img, void* stream) {
     return render_backward_impl(desc, psf, depth, grad_out, grad_img, (hipStream_t)stream);
+}
+
+int sdirt_mlp_n_params(const sdirt_mlp_desc* desc, long long* n_params) {
+    if (!n_params) return SDIRT_EINVAL;
+    return mlp_n_params(desc, n_params);
+}
+
+int sdirt_mlp_workspace_size(const sdirt_mlp_desc* desc, int batch, size_t* bytes) {
+    if (!bytes) return SDIRT_EINVAL;
+    return mlp_workspace_size(desc, batch, bytes);
+}
+
+int sdirt_mlp_forward(const sdirt_mlp_desc* desc, const float* params, long long n_rows,
+                      const float* x, void* out, int out_dtype, void* workspace,
+                      int ws_batch, void* stream) {
+    return mlp_forward(desc, params, n_rows, x, out, out_dtype, workspace, ws_batch,
+                       (hipStream_t)stream);
+}
+
+int sdirt_mlp_backward(const sdirt_mlp_desc* desc, const float* params, int batch,
+                       const float* x, const float* target, float* grads_out,
+                       float* loss_out, void* workspace, void* stream) {
+    return mlp_backward(desc, params, batch, x, target, grads_out, loss_out, workspace,
+                        (hipStream_t)stream);
+}
+
+int sdirt_mlp_adam(const sdirt_mlp_desc* desc, float* params, float* m, float* v,
+                   const float* grads, int step, float lr, void* stream) {
+    return mlp_adam(desc, params, m, v, grads, step, lr, (hipStream_t)stream);
+}
+
+int sdirt_mlp_train(const sdirt_mlp_desc* desc, float* params, float* m, float* v,
+                    int step0, int n_steps, float lr0, float lr_min, int total_steps,
+                    int batch, long long n_samples, const float* x_all,
+                    const float* t_all, uint32_t seed, float* loss_trace,
+                    void* workspace, void* stream) {
+    return mlp_train(desc, params, m, v, step0, n_steps, lr0, lr_min, total_steps, batch,
+                     n_samples, x_all, t_all, seed, loss_trace, workspace,
+                     (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -358,7 +358,8 @@ __device__ inline void conv_strip_bwd(const float* __restrict__ kl, const float*
 }
 
 template <int KS, bool BWD>
-__global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderArgs A) {
+__global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderArgs A,
+                                                                 const float* __restrict__ bank) {
     using G = FastGeom<KS>;
     extern __shared__ float halo[];     // [HH][HW]
     const int pad = (KS - 1) / 2;
@@ -407,7 +408,6 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
             if (k == 0x7fffffff) break;
             const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
             const size_t base = ((size_t)fd * A.L + lam) * 2 * kk;
-            const float* bank = reinterpret_cast<const float*>(A.psf);
             const float* kl = bank + base + (fxb ? kk : 0);
             const float* kr = bank + base + (fxb ? 0 : kk);
             if (BWD) {
@@ -464,7 +464,7 @@ static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
     const dim3 grid((unsigned)((long long)A.N * tilesx * tilesy));
     auto k = render_bank_fast_kernel<KS, BWD>;
     if (shm > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k, grid, dim3(kRBlock), shm, st, A);
+    hipLaunchKernelGGL(k, grid, dim3(kRBlock), shm, st, A, reinterpret_cast<const float*>(A.psf));
     return true;
 }
 

@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             const double r3 = rr * rr * rr;
             // sensor plane: O = p + tau d, tau = -(z - t_S) / dz (ray holds O)
             const float* pl = path[S];
-            const double px0 = pl[0], py0 = pl[1], pz0 = pl[2];
+            const double pz0 = pl[2];
             const double pdx = pl[3], pdy = pl[4], pdz = pl[5];
             const double z1 = pz0 - A.lens.sensor_dist;
             const double tau = -z1 / pdz;

@@ -220,3 +220,67 @@ def render_dp_backward(desc, psf, grad_out, depth=None, grad_img=None):
                                             _dptr(grad_img), _stream())
     abi.check("sdirt_render_dp_backward", rc)
     return grad_img
+
+
+# ---- PSF surrogate MLP ------------------------------------------------------
+
+def make_mlp_desc(n_hidden=5, width=256, n_out=2 * 33 * 33, n_freq=8, x_half=1.0,
+                  y_half=1.0, iv_lo=0.0, iv_hi=1.0, lam_lo=0.4, lam_hi=0.7):
+    d = abi.MlpDesc()
+    d.n_hidden, d.width, d.n_out, d.n_freq = int(n_hidden), int(width), int(n_out), int(n_freq)
+    d.x_half, d.y_half = float(x_half), float(y_half)
+    d.iv_lo, d.iv_hi = float(iv_lo), float(iv_hi)
+    d.lam_lo, d.lam_hi = float(lam_lo), float(lam_hi)
+    return d
+
+
+def mlp_n_params(desc):
+    n = C.c_longlong()
+    abi.check("sdirt_mlp_n_params", abi.lib().sdirt_mlp_n_params(C.byref(desc), C.byref(n)))
+    return n.value
+
+
+def mlp_workspace(desc, batch, device="cuda"):
+    n = C.c_size_t()
+    abi.check("sdirt_mlp_workspace_size",
+              abi.lib().sdirt_mlp_workspace_size(C.byref(desc), int(batch), C.byref(n)))
+    return torch.empty((n.value,), dtype=torch.uint8, device=device)
+
+
+def mlp_forward(desc, params, x, workspace, ws_batch, out_dtype=abi.F32, out=None):
+    n = x.shape[0]
+    if out is None:
+        dt = torch.bfloat16 if out_dtype == abi.BF16 else torch.float32
+        out = torch.empty((n, desc.n_out), dtype=dt, device=x.device)
+    rc = abi.lib().sdirt_mlp_forward(C.byref(desc), _dptr(params), int(n), _dptr(x.contiguous()),
+                                     _dptr(out), int(out_dtype), _dptr(workspace),
+                                     int(ws_batch), _stream())
+    abi.check("sdirt_mlp_forward", rc)
+    return out
+
+
+def mlp_backward(desc, params, x, target, workspace):
+    grads = torch.empty_like(params)
+    loss = torch.empty((1,), dtype=torch.float32, device=params.device)
+    rc = abi.lib().sdirt_mlp_backward(C.byref(desc), _dptr(params), int(x.shape[0]),
+                                      _dptr(x.contiguous()), _dptr(target.contiguous()),
+                                      _dptr(grads), _dptr(loss), _dptr(workspace), _stream())
+    abi.check("sdirt_mlp_backward", rc)
+    return grads, loss
+
+
+def mlp_adam(desc, params, m, v, grads, step, lr):
+    rc = abi.lib().sdirt_mlp_adam(C.byref(desc), _dptr(params), _dptr(m), _dptr(v),
+                                  _dptr(grads), int(step), float(lr), _stream())
+    abi.check("sdirt_mlp_adam", rc)
+
+
+def mlp_train(desc, params, m, v, x_all, t_all, workspace, batch, step0, n_steps,
+              lr0=1e-3, lr_min=1e-5, total_steps=None, seed=1, loss_trace=None):
+    total = int(total_steps if total_steps is not None else step0 + n_steps)
+    rc = abi.lib().sdirt_mlp_train(C.byref(desc), _dptr(params), _dptr(m), _dptr(v),
+                                   int(step0), int(n_steps), float(lr0), float(lr_min), total,
+                                   int(batch), int(x_all.shape[0]), _dptr(x_all), _dptr(t_all),
+                                   int(seed) & 0xFFFFFFFF, _dptr(loss_trace),
+                                   _dptr(workspace), _stream())
+    abi.check("sdirt_mlp_train", rc)

@@ -1,0 +1,149 @@
+"""GPU parity of the bf16 matrix-core PSF surrogate (forward, loss gradient,
+Adam, training) against the CPU oracle's bf16 mirror, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import scenes
+from oracle import mlp as M
+from paper_2503_11213_amd import sdirt, _abi as abi
+
+pytestmark = pytest.mark.gpu
+
+NORM = dict(x_half=4.5024, y_half=3.0016, iv_lo=1 / 5000, iv_hi=1 / 500, lam_lo=0.486,
+            lam_hi=0.656)
+REL = 1e-2
+
+
+def _desc(n_out=2 * 33 * 33, width=256, n_hidden=5):
+    return sdirt.make_mlp_desc(n_hidden=n_hidden, width=width, n_out=n_out, n_freq=8, **NORM)
+
+
+def _params(widths, seed=0):
+    layers = scenes.mlp_init(widths, seed)
+    flat = np.concatenate([np.concatenate([W.ravel(), b]) for W, b in layers]).astype(np.float32)
+    return layers, flat
+
+
+def _inputs(B, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(-4.5, 4.5, B), rng.uniform(-3, 3, B),
+                     rng.uniform(1 / 5000, 1 / 500, B),
+                     rng.choice([0.486, 0.55, 0.656], B)], 1).astype(np.float32)
+
+
+def _targets(B, n, seed):
+    t = np.random.default_rng(seed).uniform(0, 1, (B, n)) ** 6
+    return (t / t.sum(axis=1, keepdims=True)).astype(np.float32)
+
+
+def _rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _oracle_params(layers):
+    return [(W.astype(np.float64), b.astype(np.float64)) for W, b in layers]
+
+
+def test_param_count():
+    assert sdirt.mlp_n_params(_desc()) == 839554
+
+
+@pytest.mark.parametrize("B,ws", [(128, 128), (200, 64)])
+def test_forward_matches_bf16_mirror(B, ws):
+    widths = [64, 256, 256, 256, 256, 256, 2178]
+    layers, flat = _params(widths, 0)
+    x = _inputs(B, 1)
+    d = _desc()
+    ws_t = sdirt.mlp_workspace(d, ws)
+    p = sdirt.mlp_forward(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(), ws_t, ws)
+    p = p.cpu().numpy()
+    ref, _ = M.forward(_oracle_params(layers), x.astype(np.float64), NORM, bf16=True)
+    assert np.allclose(p.sum(axis=1), 1.0, atol=1e-4)
+    assert _rel_l2(p, ref) <= REL
+    pb = sdirt.mlp_forward(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(), ws_t,
+                           ws, out_dtype=abi.BF16).float().cpu().numpy()
+    assert _rel_l2(pb, ref) <= REL
+
+
+def test_gradients_match_bf16_mirror():
+    widths = [64, 256, 256, 256, 256, 256, 2178]
+    layers, flat = _params(widths, 2)
+    B = 256
+    x = _inputs(B, 3)
+    t = _targets(B, 2178, 4)
+    d = _desc()
+    ws_t = sdirt.mlp_workspace(d, B)
+    g, loss = sdirt.mlp_backward(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(),
+                                 torch.from_numpy(t).cuda(), ws_t)
+    g = g.cpu().numpy()
+    P = _oracle_params(layers)
+    p, cache = M.forward(P, x.astype(np.float64), NORM, bf16=True)
+    ref = M.backward(P, p, cache, t.astype(np.float64), bf16=True)
+    assert loss.item() == pytest.approx(M.loss(p, t.astype(np.float64)), rel=1e-3)
+    off = 0
+    for (W, b), (gW, gb) in zip(layers, ref):
+        nW = W.size
+        assert _rel_l2(g[off:off + nW].reshape(W.shape), gW) <= REL
+        off += nW
+        assert _rel_l2(g[off:off + b.size], gb) <= REL
+        off += b.size
+    assert off == g.size
+
+
+def test_adam_matches_oracle():
+    widths = [64, 256, 256, 256, 256, 256, 2178]
+    layers, flat = _params(widths, 5)
+    d = _desc()
+    rng = np.random.default_rng(6)
+    pt = torch.from_numpy(flat).cuda()
+    m = torch.zeros_like(pt)
+    v = torch.zeros_like(pt)
+    P = _oracle_params(layers)
+    st = M.adam_init(P)
+    for step in range(1, 4):
+        g = rng.normal(size=flat.size).astype(np.float32) * 1e-2
+        sdirt.mlp_adam(d, pt, m, v, torch.from_numpy(g).cuda(), step, 1e-3)
+        grads, off = [], 0
+        for W, b in layers:
+            grads.append((g[off:off + W.size].reshape(W.shape).astype(np.float64),
+                          g[off + W.size:off + W.size + b.size].astype(np.float64)))
+            off += W.size + b.size
+        P = M.adam_step(P, grads, st, 1e-3)
+    ref = np.concatenate([np.concatenate([W.ravel(), b]) for W, b in P])
+    assert np.max(np.abs(pt.cpu().numpy() - ref)) <= 1e-6
+
+
+def test_training_reduces_loss():
+    # small dataset of smooth synthetic PSF-like targets; loss must drop
+    widths = [64, 256, 256, 256, 256, 256, 2 * 9 * 9]
+    d = _desc(n_out=2 * 9 * 9)
+    layers, flat = _params(widths, 7)
+    n = 4096
+    x = _inputs(n, 8)
+    yy, xx = np.meshgrid(np.arange(9) - 4, np.arange(9) - 4, indexing="ij")
+    sig = 0.8 + 2.0 * (x[:, 2] - NORM["iv_lo"]) / (NORM["iv_hi"] - NORM["iv_lo"])
+    cx = 1.5 * x[:, 0] / NORM["x_half"]
+    t = np.zeros((n, 2, 9, 9))
+    for s, sh in ((0, 1.0), (1, -1.0)):
+        t[:, s] = np.exp(-((xx[None] - cx[:, None, None] - sh) ** 2 + yy[None] ** 2) /
+                         (2 * sig[:, None, None] ** 2))
+    t = t.reshape(n, -1)
+    t = (t / t.sum(axis=1, keepdims=True)).astype(np.float32)
+    pt = torch.from_numpy(flat).cuda()
+    m, v = torch.zeros_like(pt), torch.zeros_like(pt)
+    B = 256
+    ws_t = sdirt.mlp_workspace(d, B)
+    xt, tt = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    trace = torch.zeros((600,), device="cuda")
+    sdirt.mlp_train(d, pt, m, v, xt, tt, ws_t, B, 0, 600, lr0=1e-3, lr_min=1e-4,
+                    total_steps=600, seed=3, loss_trace=trace)
+    tr = trace.cpu().numpy()
+    assert np.all(np.isfinite(tr))
+    assert tr[-50:].mean() < 0.2 * tr[:10].mean()
+
+
+def test_invalid_batch_is_rejected():
+    d = _desc()
+    with pytest.raises(RuntimeError):
+        sdirt.mlp_workspace(d, 100)

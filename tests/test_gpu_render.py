@@ -113,3 +113,23 @@ def test_bank_full_size_sampled_pixels():
                          depth=torch.from_numpy(dmap).cuda()).cpu().numpy()
     sums = bank.sum(axis=(-1, -2))          # [F, D, L, 2]
     assert o1.min() >= sums.min() * (1 - 1e-5) and o1.max() <= sums.max() * (1 + 1e-5)
+
+
+@pytest.mark.parametrize("ks", [21, 33])
+def test_bank_register_blocked_path(ks):
+    # window sizes with the register-blocked bank kernel; several 32 x 64
+    # tiles with ragged edges, both mirror flips, many entries per tile
+    N, C, H, W, F, D, L, ps = 2, 3, 45, 150, 6, 5, 3, 0.01
+    img, bank, radii, iv, dmap = _bank_case(N, C, H, W, ks, F, D, L, ps, 9)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps)
+    bt, dt = torch.from_numpy(bank).cuda(), torch.from_numpy(dmap).cuda()
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), bt, depth=dt)
+    ref = R.render_bank(img, bank, dmap, radii, iv, loc, ps)
+    assert _rel(out.cpu().numpy(), ref) <= REL_TOL
+    g = np.random.default_rng(10).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, bt, torch.from_numpy(g).cuda(), depth=dt)
+    gref = R.render_bank_adjoint(g, bank, dmap, radii, iv, loc, ps)
+    assert _rel(gi.cpu().numpy(), gref) <= REL_TOL
