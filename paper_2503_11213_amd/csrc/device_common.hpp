@@ -94,9 +94,37 @@ template <typename T> __device__ inline T tol_newton();
 template <> __device__ inline double tol_newton<double>() { return 1e-12; }
 template <> __device__ inline float tol_newton<float>() { return 2e-6f; }
 
+// Reciprocal, square root and reciprocal square root from the hardware
+// approximations refined by Newton steps (float64: two steps, relative error
+// a few ulp; no IEEE rounding or denormal handling is needed on this path).
+template <typename T> __device__ inline T rcp_t(T v);
+template <> __device__ inline double rcp_t<double>(double v) {
+    double r = __builtin_amdgcn_rcp(v);
+    double e = fma(-v, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-v, r, 1.0);
+    return fma(r, e, r);
+}
+template <> __device__ inline float rcp_t<float>(float v) { return 1.0f / v; }
+
 template <typename T> __device__ inline T rsqrt_t(T v);
-template <> __device__ inline double rsqrt_t<double>(double v) { return 1.0 / sqrt(v); }
+template <> __device__ inline double rsqrt_t<double>(double v) {
+    double y = __builtin_amdgcn_rsq(v);
+    double h = 0.5 * v;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
 template <> __device__ inline float rsqrt_t<float>(float v) { return 1.0f / sqrtf(v); }
+
+// sqrt of a non-negative argument (0 -> 0)
+template <typename T> __device__ inline T sqrt_t(T v);
+template <> __device__ inline double sqrt_t<double>(double v) {
+    if (!(v > 0.0)) return 0.0;
+    const double y = rsqrt_t<double>(v);
+    const double s = v * y;
+    return fma(0.5 * y, fma(-s, s, v), s);
+}
+template <> __device__ inline float sqrt_t<float>(float v) { return v > 0.f ? sqrtf(v) : 0.f; }
 
 // Even-asphere sag and its derivative in rho = r^2.
 template <typename T>
@@ -105,7 +133,7 @@ __device__ inline void asphere_sag(const double* co, T c, T rho, T* sag, T* dsag
     const T k = (T)co[0];
     const T arg = T(1) - (T(1) + k) * c * c * rho;
     *ok = arg >= T(0);
-    const T q = sqrt(arg >= T(0) ? arg : T(1));
+    const T q = sqrt_t<T>(arg >= T(0) ? arg : T(1));
     const T a4 = (T)co[1], a6 = (T)co[2], a8 = (T)co[3], a10 = (T)co[4], a12 = (T)co[5];
     *sag = c * rho / (T(1) + q) +
            rho * rho * (a4 + rho * (a6 + rho * (a8 + rho * (a10 + rho * a12))));
@@ -125,7 +153,7 @@ __device__ inline int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
         const int kind = L.kind[s];
         r.z -= (T)L.tprev[s];
         if (!(r.dz > T(0))) status = status ? status : kInvalid;
-        const T inv_dz = T(1) / r.dz;
+        const T inv_dz = rcp_t<T>(r.dz);
         const T tau = -r.z * inv_dz;
         r.x += tau * r.dx;
         r.y += tau * r.dy;
@@ -136,7 +164,7 @@ __device__ inline int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
             const T G = r.dz - c * (r.x * r.dx + r.y * r.dy);
             const T disc = G * G - c * F;
             if (disc < T(0)) status = status ? status : kMiss;
-            const T delta = F / (G + sqrt(disc > T(0) ? disc : T(0)));
+            const T delta = F * rcp_t<T>(G + sqrt_t<T>(disc));
             r.x += delta * r.dx;
             r.y += delta * r.dy;
             r.z = delta * r.dz;
@@ -147,7 +175,7 @@ __device__ inline int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
             const T G = r.dz - c * (r.x * r.dx + r.y * r.dy);
             const T a = c * (T(1) + k * r.dz * r.dz);
             const T disc = G * G - a * F;
-            T delta = disc >= T(0) ? F / (G + sqrt(disc)) : T(0);
+            T delta = disc >= T(0) ? F * rcp_t<T>(G + sqrt_t<T>(disc)) : T(0);
             bool conv = false, bad = false;
             for (int it = 0; it < 50 && !conv && !bad; ++it) {
                 const T xr = r.x + delta * r.dx;
@@ -158,7 +186,7 @@ __device__ inline int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
                 if (!ok) { bad = true; break; }
                 const T f = delta * r.dz - sag;
                 const T fp = r.dz - dsag * T(2) * (xr * r.dx + yr * r.dy);
-                const T step = f / fp;
+                const T step = f * rcp_t<T>(fp);
                 delta -= step;
                 conv = fabs(step) < tol_newton<T>() * (T(1) + fabs(delta));
             }
@@ -187,13 +215,14 @@ __device__ inline int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
             const T cosI = r.dx * nx + r.dy * ny + r.dz * nz;
             const T K = T(1) - m * m * (T(1) - cosI * cosI);
             if (K < T(0)) status = status ? status : kTir;
-            const T g = sqrt(K > T(0) ? K : T(0)) - m * cosI;
+            const T g = sqrt_t<T>(K) - m * cosI;
             r.dx = m * r.dx + g * nx;
             r.dy = m * r.dy + g * ny;
             r.dz = m * r.dz + g * nz;
         } else if (kind == SDIRT_IDEAL) {
-            const T tx = r.dx / r.dz - r.x * c;
-            const T ty = r.dy / r.dz - r.y * c;
+            const T idz = rcp_t<T>(r.dz);
+            const T tx = r.dx * idz - r.x * c;
+            const T ty = r.dy * idz - r.y * c;
             const T inv = rsqrt_t<T>(tx * tx + ty * ty + T(1));
             r.dx = tx * inv; r.dy = ty * inv; r.dz = inv;
         }
@@ -202,7 +231,7 @@ __device__ inline int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
     // to the sensor plane
     r.z -= (T)L.sensor_dist;
     if (!(r.dz > T(0))) status = status ? status : kInvalid;
-    const T tau = -r.z / r.dz;
+    const T tau = -r.z * rcp_t<T>(r.dz);
     r.x += tau * r.dx;
     r.y += tau * r.dy;
     r.z = T(0);

@@ -261,9 +261,15 @@ __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A)
 // per tap) and folds the halo back with clamped global atomics.
 constexpr int kFW = 64, kFH = 32, kStrip = 8;
 
-template <int KS>
+template <int KS, bool BWD = false>
 struct FastGeom {
-    static constexpr int HW = ((kFW + KS - 1 + 3) / 4) * 4 + 4;   // padded row
+    // Forward: rows padded to a multiple of 4 floats (+4) for float4 window
+    // reads.  Adjoint: an odd row stride (1 mod 32) so the 8 rows x 8 strips
+    // of a wave hit distinct LDS banks (at most 2 lanes per bank) in the
+    // scatter's atomic adds.
+    static constexpr int HWF = ((kFW + KS - 1 + 3) / 4) * 4 + 4;
+    static constexpr int HWB = ((kFW + KS - 1 + 30) / 32) * 32 + 1;
+    static constexpr int HW = BWD ? HWB : HWF;
     static constexpr int HH = kFH + KS - 1;
     static constexpr int WIN = ((KS + kStrip - 1 + 3) / 4) * 4;   // window, float4s
 };
@@ -335,7 +341,7 @@ template <int KS, bool FX>
 __device__ inline void conv_strip_bwd(const float* __restrict__ kl, const float* __restrict__ kr,
                                       bool fy, float* hgrad, int ly, int hc,
                                       const float gL[kStrip], const float gR[kStrip]) {
-    using G = FastGeom<KS>;
+    using G = FastGeom<KS, true>;
     for (int i = 0; i < KS; ++i) {
         const int si = fy ? KS - 1 - i : i;
         const float* rl = kl + si * KS;
@@ -360,7 +366,7 @@ __device__ inline void conv_strip_bwd(const float* __restrict__ kl, const float*
 template <int KS, bool BWD>
 __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderArgs A,
                                                                  const float* __restrict__ bank) {
-    using G = FastGeom<KS>;
+    using G = FastGeom<KS, BWD>;
     extern __shared__ float halo[];     // [HH][HW]
     const int pad = (KS - 1) / 2;
     const int kk = KS * KS;
@@ -456,13 +462,151 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
     }
 }
 
+// Bank-source image adjoint without LDS atomics.  Each wave owns 8 output
+// rows x 64 columns and a private LDS halo of (KS + 7) rows; for each kernel
+// row the lane computes the 1-D correlation of its strip's gradients with
+// the kernel row (KS + 7 partial column sums), the 8 strips of a row trade
+// those partial sums through lane shuffles so that every lane owns two
+// disjoint groups of 8 halo columns, and the owner adds them with a plain
+// read-modify-write.  The four private halos are summed and folded back
+// (clamped) with global atomics once per channel.
+constexpr int kBwdHW = 129;      // private halo row stride (1 mod 32: 2 lanes per bank)
+
+template <int KS>
+struct BwdGeom {
+    static constexpr int PR = KS + kStrip - 1;        // private halo rows
+    static constexpr int PW = PR * kBwdHW;            // floats per wave
+    static constexpr int NKX = (KS + kStrip - 1 + 7) / 8;
+};
+
+template <int KS, bool FX>
+__device__ inline void scatter_rows(const float* __restrict__ kl, const float* __restrict__ kr,
+                                    bool fy, float* priv, int r, int o, int lane,
+                                    const float gL[kStrip], const float gR[kStrip]) {
+    using G = BwdGeom<KS>;
+    const int base_lane = lane & ~7;
+    for (int i = 0; i < KS; ++i) {
+        const int si = fy ? KS - 1 - i : i;
+        const float* rl = kl + si * KS;
+        const float* rr = kr + si * KS;
+        float acc[8 * G::NKX];
+#pragma unroll
+        for (int m = 0; m < 8 * G::NKX; ++m) acc[m] = 0.f;
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const int sj = FX ? KS - 1 - j : j;
+            const float a = rl[sj], b = rr[sj];
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q)
+                acc[q - j + KS - 1] = fmaf(a, gL[q], fmaf(b, gR[q], acc[q - j + KS - 1]));
+        }
+        // column 8 * o_src + m of strip o_src belongs to group o_src + m / 8
+        float gA[8], gB[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) { gA[q] = 0.f; gB[q] = 0.f; }
+#pragma unroll
+        for (int kx = 0; kx < G::NKX; ++kx) {
+            const int src = base_lane | ((o - kx) & 7);
+            const bool lowgrp = o - kx >= 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float v = __shfl(acc[8 * kx + q], src, 64);
+                if (lowgrp) gA[q] += v; else gB[q] += v;
+            }
+        }
+        float* row = priv + (r + KS - 1 - i) * kBwdHW;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            row[8 * o + q] += gA[q];
+            row[64 + 8 * o + q] += gB[q];
+        }
+    }
+}
+
+template <int KS>
+__global__ __launch_bounds__(kRBlock) void render_bank_bwd_kernel(const RenderArgs A,
+                                                                const float* __restrict__ bank) {
+    using G = BwdGeom<KS>;
+    extern __shared__ float lds[];      // 4 private halos [PR][kBwdHW]
+    const int pad = (KS - 1) / 2;
+    const int kk = KS * KS;
+    const int tilesx = (A.W + kFW - 1) / kFW, tilesy = (A.H + kFH - 1) / kFH;
+    const int tile = blockIdx.x;
+    const int n = tile / (tilesx * tilesy);
+    const int rem = tile - n * tilesx * tilesy;
+    const int y0 = (rem / tilesx) * kFH, x0 = (rem % tilesx) * kFW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane >> 3, o = lane & 7;
+    const int y = y0 + wave * 8 + r, xs = x0 + o * kStrip;
+    float* priv = lds + wave * G::PW;
+    int key[kStrip];
+#pragma unroll
+    for (int q = 0; q < kStrip; ++q)
+        key[q] = (y < A.H && xs + q < A.W) ? bank_key(A, n, y, xs + q) : 0x7fffffff;
+    for (int c = 0; c < A.C; ++c) {
+        const int lam = A.lam_of_c[c];
+        for (int e = lane; e < G::PW; e += 64) priv[e] = 0.f;
+        float gL[kStrip], gR[kStrip];
+#pragma unroll
+        for (int q = 0; q < kStrip; ++q) {
+            const bool ok = key[q] != 0x7fffffff;
+            const size_t off = ((size_t)n * 2 * A.C * A.H + y) * A.W + xs + q;
+            gL[q] = ok ? A.gout[off + (size_t)c * A.H * A.W] : 0.f;
+            gR[q] = ok ? A.gout[off + (size_t)(A.C + c) * A.H * A.W] : 0.f;
+        }
+        unsigned done = 0;
+#pragma unroll
+        for (int q = 0; q < kStrip; ++q) if (key[q] == 0x7fffffff) done |= 1u << q;
+        while (true) {
+            int mine = 0x7fffffff;
+#pragma unroll
+            for (int q = kStrip - 1; q >= 0; --q) if (!(done & (1u << q))) mine = key[q];
+            const int k = __builtin_amdgcn_readfirstlane(wave_min_int(mine));
+            if (k == 0x7fffffff) break;
+            const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
+            const size_t base = ((size_t)fd * A.L + lam) * 2 * kk;
+            const float* kl = bank + base + (fxb ? kk : 0);
+            const float* kr = bank + base + (fxb ? 0 : kk);
+            float mL[kStrip], mR[kStrip];
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q) {
+                mL[q] = key[q] == k ? gL[q] : 0.f;
+                mR[q] = key[q] == k ? gR[q] : 0.f;
+            }
+            if (fxb) scatter_rows<KS, true>(kl, kr, fyb, priv, r, o, lane, mL, mR);
+            else scatter_rows<KS, false>(kl, kr, fyb, priv, r, o, lane, mL, mR);
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q) if (key[q] == k) done |= 1u << q;
+        }
+        __syncthreads();
+        // sum the four private halos (wave w covers tile-halo rows 8w .. 8w + PR)
+        float* gi = A.gimg + ((size_t)n * A.C + c) * A.H * A.W;
+        const int HH = kFH + KS - 1, HWc = kFW + KS - 1;
+        for (int e = threadIdx.x; e < HH * HWc; e += kRBlock) {
+            const int R = e / HWc, Cc = e - R * HWc;
+            float v = 0.f;
+#pragma unroll
+            for (int w = 0; w < kRBlock / 64; ++w) {
+                const int rr = R - 8 * w;
+                if (rr >= 0 && rr < G::PR) v += lds[w * G::PW + rr * kBwdHW + Cc];
+            }
+            if (v == 0.f) continue;
+            const int yy = min(max(y0 - pad + R, 0), A.H - 1);
+            const int xx = min(max(x0 - pad + Cc, 0), A.W - 1);
+            atomicAdd(&gi[(size_t)yy * A.W + xx], v);
+        }
+        __syncthreads();
+    }
+}
+
 template <int KS, bool BWD>
 static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
-    using G = FastGeom<KS>;
-    const size_t shm = (size_t)G::HH * G::HW * sizeof(float);
+    using G = FastGeom<KS, BWD>;
+    const size_t shm = BWD ? (size_t)(kRBlock / 64) * BwdGeom<KS>::PW * sizeof(float)
+                           : (size_t)G::HH * G::HW * sizeof(float);
     const int tilesx = (A.W + kFW - 1) / kFW, tilesy = (A.H + kFH - 1) / kFH;
     const dim3 grid((unsigned)((long long)A.N * tilesx * tilesy));
-    auto k = render_bank_fast_kernel<KS, BWD>;
+    auto k = BWD ? render_bank_bwd_kernel<KS> : render_bank_fast_kernel<KS, false>;
     if (shm > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(k, grid, dim3(kRBlock), shm, st, A, reinterpret_cast<const float*>(A.psf));
     return true;

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
         concentric(a, b, &u, &v);
         const double ex = rep * u, ey = rep * v;
         double ddx = ex - px, ddy = ey - py, ddz = zep - pz;
-        const double inv = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+        const double inv = rsqrt_t<double>(ddx * ddx + ddy * ddy + ddz * ddz);
         Ray<T> ray{(T)ex, (T)ey, (T)zep, (T)(ddx * inv), (T)(ddy * inv), (T)(ddz * inv)};
         const int st = trace_ray<T>(A.lens, mu, ray, NoRec());
         if (st != kAlive) { e_vig += 1.f; continue; }

@@ -93,3 +93,56 @@ def pixel_points(H, W, ps, depth_map, slot=0):
     hy = (yy - (H - 1) / 2.0) * ps
     return np.stack([hx.ravel(), hy.ravel(), np.asarray(depth_map, dtype=np.float64).ravel(),
                      np.full(H * W, float(slot))], axis=1)
+
+
+def config4_desc_kwargs():
+    """Normalisation ranges of the surrogate inputs for the 12-surface lens
+    workload: image half-size, 1/d in [0.2, 2] per metre, 486-656 nm."""
+    W, H, ps = 1680, 1120, 0.00536
+    return dict(x_half=W * ps / 2, y_half=H * ps / 2, iv_lo=0.2e-3, iv_hi=2.0e-3,
+                lam_lo=RGB_LAMBDAS[0], lam_hi=RGB_LAMBDAS[-1])
+
+
+def surrogate_points(n, seed):
+    """Random PSF points over the sensor and the depth range of the MLP
+    workload: returns list-mode points [n][4] (h_x, h_y, depth, slot) and
+    the matching MLP inputs [n][4] (h_x, h_y, 1/d, lambda)."""
+    k = config4_desc_kwargs()
+    rng = np.random.default_rng(seed)
+    hx = rng.uniform(-k["x_half"], k["x_half"], n)
+    hy = rng.uniform(-k["y_half"], k["y_half"], n)
+    iv = rng.uniform(k["iv_lo"], k["iv_hi"], n)
+    slot = rng.integers(0, len(RGB_LAMBDAS), n)
+    lam = np.asarray(RGB_LAMBDAS)[slot]
+    pts = np.stack([hx, hy, 1.0 / iv, slot.astype(np.float64)], 1)
+    x = np.stack([hx, hy, iv, lam], 1).astype(np.float32)
+    return pts, x
+
+
+def config4(rays=512):
+    """Lens, sensor and query template (ks 33, SUM-normalised) of the MLP
+    surrogate workload; points come from surrogate_points."""
+    lens = config2_lens()
+    W, H, ps = 1680, 1120, 0.00536
+    sensor = Sensor(pitch=ps, dp_mode=DP_SIGMOID, sigmoid_k=20.0, width_px=W, height_px=H)
+    from .lens import NORM_SUM
+    query = PsfQuery(fields=[(0.0, 0.0)], depths=[1000.0], wavelengths=list(RGB_LAMBDAS),
+                     rays_x=rays, rays_y=rays, seed=1, jitter=True, ks=33, splat=SPLAT_BOX,
+                     normalize=NORM_SUM, out_f64=False)
+    return lens, sensor, query
+
+
+def pixel_inputs(H, W, ps, depth_map, lambdas=RGB_LAMBDAS):
+    """MLP inputs for every pixel and channel of an image, row-major in
+    (y, x, channel) with channel c at wavelength lambdas[c]: [H*W*C][4]."""
+    yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    hx = ((xx - (W - 1) / 2.0) * ps).ravel()
+    hy = ((yy - (H - 1) / 2.0) * ps).ravel()
+    iv = 1.0 / np.asarray(depth_map, dtype=np.float64).ravel()
+    C = len(lambdas)
+    x = np.empty((H * W, C, 4), dtype=np.float32)
+    x[:, :, 0] = hx[:, None]
+    x[:, :, 1] = hy[:, None]
+    x[:, :, 2] = iv[:, None]
+    x[:, :, 3] = np.asarray(lambdas)[None, :]
+    return x.reshape(-1, 4)
