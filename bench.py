@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--pmc-target", action="store_true",
+                    help="for counter runs: a 1 GiB device copy (calibration), then one "
+                         "trace_dp_psf call of the step; prints nothing")
     return ap.parse_args()
 
 
@@ -63,12 +67,12 @@ def cpu_baseline(lens, sensor, query, img, dmap, radii, iv, loc, ps, total_rs,
     import oracle.psf as opsf
     import oracle.render as orender
     n_surf = 12
-    picks = [(f, (5 * f) % 16, f % 3) for f in range(0, 32, 3)]
+    picks = [(f, (5 * f + 3 * k) % 16, (f + k) % 3) for f in range(32) for k in range(2)]
     t0 = time.perf_counter()
     bank, _ = opsf.trace_dp_psf(lens, sensor, query, points=picks)
     t_trace = time.perf_counter() - t0
     sample_rays = len(picks) * query.n_rays
-    crop = 96
+    crop = 160
     ks = query.ks
     bank6 = bank.reshape(len(query.fields), len(query.depths), len(query.wavelengths), 2, ks, ks)
     y0, x0 = H // 2 - crop // 2, W // 2 - crop // 2
@@ -88,6 +92,107 @@ def cpu_baseline(lens, sensor, query, img, dmap, radii, iv, loc, ps, total_rs,
                        (len(picks), t_trace, crop, crop, t_render, est_step))}
 
 
+def extras(dev, stream):
+    """The other parts of the metric, each timed with HIP events on the
+    launch stream: trace adjoint (fwd+bwd vs fwd), dense render (HBM-bound),
+    MLP vs trace PSFs/s at ks 33, and the paper's own PSF-map workload."""
+    import numpy as np
+    import torch
+    from workloads import configs, scenes
+    from paper_2503_11213_amd import sdirt, _abi as abi
+    out = {}
+    # 1. adjoint of trace + splat, 8 x 8 x 3 points, 256^2 rays, ks 41, tent
+    lens, sensor, query = configs.config3()
+    psf, _ = sdirt.trace_dp_psf(lens, sensor, query, stats=False)
+    G = torch.randn_like(psf)
+    f = lambda: sdirt.trace_dp_psf(lens, sensor, query, out=psf, stats=False)
+    b = lambda: sdirt.trace_dp_psf_backward(lens, sensor, query, G)
+    f(); b()
+    tf, tb = timed(f, stream, 3), timed(b, stream, 3)
+    out["adjoint"] = {"workload": "12-surface lens, 192 PSFs x 256^2 rays, ks 41, tent splat",
+                      "fwd_ms": tf, "bwd_ms": tb, "fwd_plus_bwd_over_fwd": (tf + tb) / tf}
+    print("adjoint done", file=sys.stderr, flush=True)
+    # 2. dense render: 512 x 512 RGB, per-channel 41 x 41 kernels, float32
+    N, C, H, W, ks = 1, 3, 512, 512, 41
+    K = torch.rand((N, H, W, C, 2, ks, ks), device=dev)
+    img = torch.rand((N, C, H, W), device=dev)
+    gout = torch.randn((N, 2 * C, H, W), device=dev)
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks)
+    o = sdirt.render_dp(desc, img, K)
+    gi = sdirt.render_dp_backward(desc, K, gout)
+    tf = timed(lambda: sdirt.render_dp(desc, img, K, out=o), stream, 3)
+    tb = timed(lambda: sdirt.render_dp_backward(desc, K, gout, grad_img=gi), stream, 3)
+    nbytes = K.numel() * 4
+    out["render_dense"] = {"workload": "512x512 RGB, dense per-pixel per-channel 41x41 f32 map",
+                           "fwd_ms": tf, "bwd_ms": tb, "fwd_gbs": nbytes / tf / 1e6,
+                           "bwd_gbs": nbytes / tb / 1e6, "fwd_hbm_frac": nbytes / tf / 1e6 / PEAK_HBM_GBS,
+                           "fwd_plus_bwd_over_fwd": (tf + tb) / tf,
+                           "mpix_per_s": H * W / tf / 1e3}
+    del K, gout, gi, o
+    print("dense render done", file=sys.stderr, flush=True)
+    # 3. MLP inference vs tracing at ks 33 (12-surface lens, 512^2 rays)
+    lens, sensor, query = configs.config4()
+    pts, x = configs.surrogate_points(65536, seed=3)
+    pts_t = torch.from_numpy(pts).to(dev)
+    tq = torch.empty((65536, 2, 33, 33), device=dev)
+    tr = lambda: sdirt.trace_dp_psf(lens, sensor, query, points=pts_t, out=tq, stats=False)
+    tr()
+    t_trace = timed(tr, stream, 2)
+    desc = sdirt.make_mlp_desc(n_out=2 * 33 * 33, **configs.config4_desc_kwargs())
+    layers = scenes.mlp_init([64, 256, 256, 256, 256, 256, 2178], seed=0)
+    params = torch.from_numpy(np.concatenate([np.concatenate([Wt.ravel(), bt]) for Wt, bt in layers]).astype(np.float32)).to(dev)
+    nrow = 1 << 20
+    xb = torch.from_numpy(np.tile(x, (nrow // 65536, 1))).to(dev)
+    ob = torch.empty((nrow, 2178), dtype=torch.bfloat16, device=dev)
+    ws = sdirt.mlp_workspace(desc, 65536)
+    inf = lambda: sdirt.mlp_forward(desc, params, xb, ws, 65536, out_dtype=abi.BF16, out=ob)
+    inf()
+    t_mlp = timed(inf, stream, 2)
+    flop = nrow * 2.0 * (64 * 256 + 4 * 256 * 256 + 256 * 2178)
+    out["mlp_vs_trace"] = {"workload": "ks 33, 12-surface lens; trace 65536 PSFs x 512^2 rays; "
+                                       "MLP 2^20 PSFs, bf16 out",
+                           "trace_psfs_per_s": 65536 / (t_trace * 1e-3),
+                           "mlp_psfs_per_s": nrow / (t_mlp * 1e-3),
+                           "speedup": (nrow / t_mlp) / (65536 / t_trace),
+                           "mlp_tflops": flop / (t_mlp * 1e-3) / 1e12,
+                           "mlp_mfma_frac": flop / (t_mlp * 1e-3) / 2.5e15}
+    del xb, ob, ws, tq
+    print("mlp done", file=sys.stderr, flush=True)
+    # 4. the paper's PSF-map workload: RF50 at F/4, 512 x 768 pixels, one
+    #    microlens-model DP PSF per pixel (ks 21, 4096 rays)
+    lens, sensor, query, (H, W) = configs.paper_psf_map()
+    dmap = scenes.depth_uniform_inverse(H, W, 500.0, 20000.0, seed=100)
+    pts = torch.from_numpy(configs.pixel_points(H, W, sensor.pitch, dmap)).to(dev)
+    pm = torch.empty((H * W, 2, 21, 21), device=dev)
+    tr = lambda: sdirt.trace_dp_psf(lens, sensor, query, points=pts, out=pm, stats=False)
+    tr()
+    t_map = timed(tr, stream, 2)
+    img = torch.rand((1, 3, H, W), device=dev)
+    desc, keep = sdirt.make_render_desc(1, 3, H, W, 21, psf_channels=1)
+    ro = sdirt.render_dp(desc, img, pm)
+    t_r = timed(lambda: sdirt.render_dp(desc, img, pm, out=ro), stream, 3)
+    mdesc = sdirt.make_mlp_desc(n_out=2 * 21 * 21, x_half=18.0, y_half=12.0, iv_lo=1 / 20000.0,
+                                iv_hi=1 / 500.0, lam_lo=0.5, lam_hi=0.6)
+    layers = scenes.mlp_init([64, 256, 256, 256, 256, 256, 882], seed=0)
+    params = torch.from_numpy(np.concatenate([np.concatenate([Wt.ravel(), bt]) for Wt, bt in layers]).astype(np.float32)).to(dev)
+    xi = torch.from_numpy(np.stack([pts[:, 0].cpu().numpy(), pts[:, 1].cpu().numpy(),
+                                    1.0 / pts[:, 2].cpu().numpy(), np.full(H * W, 0.55)], 1).astype(np.float32)).to(dev)
+    ws = sdirt.mlp_workspace(mdesc, 65536)
+    mo = torch.empty((H * W, 882), dtype=torch.float32, device=dev)
+    inf = lambda: sdirt.mlp_forward(mdesc, params, xi, ws, 65536, out=mo)
+    inf()
+    t_inf = timed(inf, stream, 3)
+    out["paper_psf_map"] = {
+        "workload": "RF50 (Table S1) F/4, focus 1 m, 512x768 px over 24x36 mm, microlens DP "
+                    "model, ks 21, 4096 rays/PSF, 393216 PSFs, depth uniform in 1/d 0.5-20 m",
+        "trace_map_s": t_map * 1e-3, "paper_trace_map_s": 801.544,
+        "mlp_map_s": t_inf * 1e-3, "paper_mlp_map_s": 0.395,
+        "render_s": t_r * 1e-3, "paper_render_s": 0.2,
+        "paper_hardware": "i7-12700K + RTX 3090 (Sec. 5.1)"}
+    print("paper workload done", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -103,6 +208,12 @@ def main():
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
     lens, sensor, query = configs.config2()
+    if args.pmc_target:
+        src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)
+        torch.empty_like(src).copy_(src)
+        sdirt.trace_dp_psf(lens, sensor, query)
+        torch.cuda.synchronize()
+        return
     H, W, ps = sensor.height_px, sensor.width_px, sensor.pitch
     img_np = scenes.aif_blobs(H, W, 3, n_blobs=2000, seed=0)[None]
     dmap_np = scenes.depth_voronoi(H, W, 500.0, 5000.0, seed=100)[None]
@@ -189,6 +300,8 @@ def main():
                    "fwd_mpix_per_s": H * W / (ms_render * 1e-3) / 1e6,
                    "fwd_plus_bwd_over_fwd": (ms_render + ms_rbwd) / ms_render},
     }
+    if not args.no_extras:
+        line.update(extras(dev, stream))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(lens, sensor, query, img_np, dmap_np, radii,
                                             iv, loc, ps, rs, H, W)

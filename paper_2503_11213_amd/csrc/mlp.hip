@@ -72,21 +72,34 @@ __global__ __launch_bounds__(kGB) void gemm_nt_kernel(const GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int r16 = lane & 15, kg = (lane >> 4) * 8;
-    for (int k0 = 0; k0 < g.K; k0 += kBK) {
-        // stage A and B tiles: 128 rows x 64 bf16 = 8 x 16 B per row
+    // global -> register staging of one 128 x 64 tile of A and of B: each
+    // thread moves 4 x 16 B of each; the next tile's loads are in flight
+    // while the current tile feeds the matrix cores.
+    uint4 ra[4], rb[4];
+    auto load_tile = [&](int k0) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int e = tid + t * kGB;          // 0 .. 1023
+            const int e = tid + t * kGB;
             const int row = e >> 3, seg = (e & 7) * 8;
-            uint4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
+            ra[t] = uint4{0u, 0u, 0u, 0u};
+            rb[t] = uint4{0u, 0u, 0u, 0u};
             if (m0 + row < g.M)
-                va = *reinterpret_cast<const uint4*>(g.A + (size_t)(m0 + row) * g.lda + k0 + seg);
+                ra[t] = *reinterpret_cast<const uint4*>(g.A + (size_t)(m0 + row) * g.lda + k0 + seg);
             if (n0 + row < g.N)
-                vb = *reinterpret_cast<const uint4*>(g.B + (size_t)(n0 + row) * g.ldb + k0 + seg);
-            *reinterpret_cast<uint4*>(&sA[row * kLdsStride + seg]) = va;
-            *reinterpret_cast<uint4*>(&sB[row * kLdsStride + seg]) = vb;
+                rb[t] = *reinterpret_cast<const uint4*>(g.B + (size_t)(n0 + row) * g.ldb + k0 + seg);
+        }
+    };
+    load_tile(0);
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int e = tid + t * kGB;
+            const int row = e >> 3, seg = (e & 7) * 8;
+            *reinterpret_cast<uint4*>(&sA[row * kLdsStride + seg]) = ra[t];
+            *reinterpret_cast<uint4*>(&sB[row * kLdsStride + seg]) = rb[t];
         }
         __syncthreads();
+        if (k0 + kBK < g.K) load_tile(k0 + kBK);
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 32) {
             bf16x8 af[4], bfr[4];
@@ -423,7 +436,8 @@ static void cast_all(const MlpDims& m, const MlpWs& w, const float* params, hipS
 
 // forward of B rows whose inputs are x; logits left in w.logits
 static void forward_rows(const MlpDims& m, const sdirt_mlp_desc* d, const MlpWs& w,
-                         const float* params, int B, const float* x, hipStream_t st) {
+                         const float* params, int B, const float* x, hipStream_t st,
+                         bool keep_transposed) {
     EncArgs e;
     e.B = B; e.n_freq = m.n_freq; e.feat_pad = feat_pad(m);
     e.x_half = (float)d->x_half; e.y_half = (float)d->y_half;
@@ -440,7 +454,7 @@ static void forward_rows(const MlpDims& m, const sdirt_mlp_desc* d, const MlpWs&
         if (l < m.L - 1) {
             g.relu = 1;
             g.Cb = w.H[l + 1]; g.ldcb = m.width;
-            g.CbT = w.HT[l + 1]; g.ldcbt = B;
+            if (keep_transposed) { g.CbT = w.HT[l + 1]; g.ldcbt = B; }
         } else {
             g.Cf = w.logits; g.ldcf = m.n_out;
         }
@@ -536,7 +550,7 @@ int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, 
     const size_t esz = out_dtype == SDIRT_BF16 ? 2 : 4;
     for (long long r0 = 0; r0 < n_rows; r0 += ws_batch) {
         const int B = (int)std::min<long long>(ws_batch, n_rows - r0);
-        forward_rows(m, d, w, params, B, x + 4 * r0, st);
+        forward_rows(m, d, w, params, B, x + 4 * r0, st, false);
         SoftArgs s;
         std::memset(&s, 0, sizeof(s));
         s.B = B; s.n_out = m.n_out; s.n_out_pad = m.n_out_pad;
@@ -560,7 +574,7 @@ int mlp_backward(const sdirt_mlp_desc* d, const float* params, int batch, const 
     cast_all(m, w, params, st);
     if ((rc = launch_fill_zero(w.loss, 4, st))) return rc;
     zero_bias_grads(m, w, st);
-    forward_rows(m, d, w, params, batch, x, st);
+    forward_rows(m, d, w, params, batch, x, st, true);
     backward_rows(m, w, params, batch, target, st);
     if (grads_out)
         (void)hipMemcpyAsync(grads_out, w.grads, m.n_params() * 4, hipMemcpyDeviceToDevice, st);
@@ -610,7 +624,7 @@ int mlp_train(const sdirt_mlp_desc* d, float* params, float* m1, float* m2, int 
         cast_all(m, w, params, st);
         launch_fill_zero(w.loss, 4, st);
         zero_bias_grads(m, w, st);
-        forward_rows(m, d, w, params, batch, w.xb, st);
+        forward_rows(m, d, w, params, batch, w.xb, st, true);
         backward_rows(m, w, params, batch, w.target, st);
         adam_launch(m.n_params(), params, m1, m2, w.grads, step + 1, lr, st);
         if (loss_trace)

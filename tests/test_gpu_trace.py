@@ -219,3 +219,29 @@ def test_chunking_does_not_change_result():
     b, sb = sdirt.trace_dp_psf(lens, sensor, query, chunks=7)
     assert torch.allclose(a, b, rtol=1e-5, atol=1e-4)
     assert torch.equal(sa[:, :3], sb[:, :3])
+
+
+def test_paper_psf_map_sampled_pixels():
+    # the per-pixel map of the paper's workload (RF50 F/4, microlens DP
+    # model, ks 21, 4096 rays): list-mode points at sampled pixels against
+    # the oracle.  List point k draws the jitter stream of point index k, so
+    # the oracle evaluates point (k, 0, 0) of a grid whose fields all equal
+    # that pixel.
+    lens, sensor, query, (H, W) = configs.paper_psf_map()
+    from workloads import scenes
+    dmap = scenes.depth_uniform_inverse(H, W, 500.0, 20000.0, seed=100)
+    pts_all = configs.pixel_points(H, W, sensor.pitch, dmap)
+    rng = np.random.default_rng(4)
+    idx = [0, W - 1, (H // 2) * W + W // 2, H * W - 1] + [int(v) for v in rng.integers(0, H * W, 8)]
+    pts = torch.from_numpy(pts_all[idx]).cuda()
+    psf, st = sdirt.trace_dp_psf(lens, sensor, query, points=pts)
+    g, gs = psf.cpu().numpy(), st.cpu().numpy()
+    for k, i in enumerate(idx):
+        q = copy.deepcopy(query)
+        q.fields = [(pts_all[i, 0], pts_all[i, 1])] * (k + 1)
+        q.depths = [pts_all[i, 2]]
+        ref, rst = opsf.trace_dp_psf(lens, sensor, q, points=[(k, 0, 0)])
+        assert np.array_equal(gs[k, :3], rst[k, :3])
+        assert np.array_equal(g[k], np.round(g[k]))         # box + microlens: counts
+        if ref[k].sum() > 0:
+            assert _energy_l1(g[k], ref[k]) <= L1_TOL
