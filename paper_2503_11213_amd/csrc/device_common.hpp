@@ -128,7 +128,7 @@ template <> __device__ inline float sqrt_t<float>(float v) { return v > 0.f ? sq
 
 // Even-asphere sag and its derivative in rho = r^2.
 template <typename T>
-__device__ inline void asphere_sag(const double* co, T c, T rho, T* sag, T* dsag,
+__device__ __forceinline__ void asphere_sag(const double* co, T c, T rho, T* sag, T* dsag,
                                    bool* ok) {
     const T k = (T)co[0];
     const T arg = T(1) - (T(1) + k) * c * c * rho;
@@ -146,7 +146,7 @@ __device__ inline void asphere_sag(const double* co, T c, T rho, T* sag, T* dsag
 // the vertex-local state after the last surface.  `rec(s, r)` is called
 // after each surface (hit point + refracted direction).
 template <typename T, typename Rec>
-__device__ inline int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
+__device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
                                 Rec rec) {
     int status = kAlive;
     for (int s = 0; s < L.S; ++s) {

@@ -28,7 +28,7 @@ namespace sdirt {
 
 int launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
 
-constexpr int kBBlock = 256;
+constexpr int kBBlock = 64;        // one wave per workgroup
 constexpr int kPerSurf = 8;
 
 struct BwdArgs {
@@ -53,7 +53,7 @@ __device__ inline double wave_sum_d(double v) {
 
 // Adjoint of vector Snell refraction d' = mu d + g N, g = sqrt(K) - mu cosI,
 // K = 1 - mu^2 (1 - cosI^2), cosI = d . N.  Adds to db and nb.
-__device__ inline void refract_bwd(double mu, const double d[3], const double n[3],
+__device__ __forceinline__ void refract_bwd(double mu, const double d[3], const double n[3],
                                    const double ob[3], double db[3], double nb[3]) {
     const double cosI = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
     const double K = 1.0 - mu * mu * (1.0 - cosI * cosI);
@@ -79,7 +79,7 @@ struct SagD {
     double sag_c, sag_k, s1_c, s1_k;
 };
 
-__device__ inline SagD sag_derivs(const double* co, double c, double rho) {
+__device__ __forceinline__ SagD sag_derivs(const double* co, double c, double rho) {
     const double k = co[0];
     const double a4 = co[1], a6 = co[2], a8 = co[3], a10 = co[4], a12 = co[5];
     const double al = (1.0 + k) * c * c;
@@ -104,7 +104,7 @@ __device__ inline SagD sag_derivs(const double* co, double c, double rho) {
 // refracted direction).  Writes the adjoint of `in` to `ib` and the
 // parameter adjoints [c, t_{s-1}, k, a4..a12] to pg (t_{s-1} at index 1 is
 // the thickness of the previous surface).
-__device__ inline void surface_bwd(const LensArgs& L, int s, double mu, const St& in,
+__device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu, const St& in,
                                    const St& ob, St& ib, double pg[kPerSurf]) {
     for (int k = 0; k < kPerSurf; ++k) pg[k] = 0.0;
     const int kind = L.kind[s];
@@ -117,7 +117,7 @@ __device__ inline void surface_bwd(const LensArgs& L, int s, double mu, const St
     const double x1 = in.x + tau * dx, y1 = in.y + tau * dy;
     double D = 0.0, F = 0.0, G = 0.0, den = 1.0, sq = 0.0;
     double xh = x1, yh = y1, zh = 0.0;
-    const double* co = kind == SDIRT_ASPHERE ? L.asph[L.aslot[s]] : nullptr;
+    const double* co = L.asph[L.aslot[s] > 0 ? L.aslot[s] : 0];   // read only for ASPHERE
     if (kind == SDIRT_SPHERE) {
         F = c * (x1 * x1 + y1 * y1);
         G = dz - c * (x1 * dx + y1 * dy);
@@ -265,32 +265,42 @@ __device__ inline void surface_bwd(const LensArgs& L, int s, double mu, const St
     pg[1] += -z1b;
 }
 
-template <int MAXS>
-struct Path {
-    float v[MAXS + 1][6];
-};
-
+// The state entering every surface, kept in LDS as float32 (structure of
+// arrays: entry (s, k) of lane l at [(6 s + k) * 64 + l], conflict-free).
 struct PathRec {
-    float (*v)[6];
+    float* v;
+    int lane;
     __device__ void operator()(int s, const Ray<double>& r) const {
-        float* o = v[s + 1];
-        o[0] = (float)r.x; o[1] = (float)r.y; o[2] = (float)r.z;
-        o[3] = (float)r.dx; o[4] = (float)r.dy; o[5] = (float)r.dz;
+        float* o = v + 6 * (s + 1) * 64 + lane;
+        o[0] = (float)r.x; o[64] = (float)r.y; o[128] = (float)r.z;
+        o[192] = (float)r.dx; o[256] = (float)r.dy; o[320] = (float)r.dz;
     }
 };
 
+__device__ inline void path_put(float* v, int s, int lane, const Ray<double>& r) {
+    PathRec{v, lane}(s - 1, r);
+}
+
+__device__ inline St path_get(const float* v, int s, int lane) {
+    const float* o = v + 6 * s * 64 + lane;
+    return St{o[0], o[64], o[128], o[192], o[256], o[320]};
+}
+
 __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
     __shared__ double gsh[kPerSurf * kMaxS + 1];
+    extern __shared__ float path[];     // [(S + 1) * 6][64]
     const int S = A.lens.S;
     const int np = kPerSurf * S + 1;
     const int tid = threadIdx.x, lane = tid & 63;
     for (int i = tid; i < np; i += kBBlock) gsh[i] = 0.0;
     const int ks = A.sen.ks, kk = ks * ks, pad = (ks - 1) / 2;
-    const int q = blockIdx.x / A.smp.chunks;
-    const int chunk = blockIdx.x - q * A.smp.chunks;
-    const int l = q % A.pts.L;
-    const int dix = (q / A.pts.L) % A.pts.D;
-    const int f = q / (A.pts.L * A.pts.D);
+    // wave-uniform indices, kept in scalar registers so that the kernel
+    // arguments are read with scalar loads (no private copy of them)
+    const int q = __builtin_amdgcn_readfirstlane(blockIdx.x / A.smp.chunks);
+    const int chunk = __builtin_amdgcn_readfirstlane(blockIdx.x - q * A.smp.chunks);
+    const int l = __builtin_amdgcn_readfirstlane(q % A.pts.L);
+    const int dix = __builtin_amdgcn_readfirstlane((q / A.pts.L) % A.pts.D);
+    const int f = __builtin_amdgcn_readfirstlane(q / (A.pts.L * A.pts.D));
     const double hx = A.pts.fields[f][0], hy = A.pts.fields[f][1];
     const double depth = A.pts.depths[dix];
     const double m = A.pts.m_num / (A.pts.z_ep_ref + depth);
@@ -307,7 +317,6 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
     const int r1 = min(r0 + A.smp.rays_per_chunk, n_rays);
     double g_slope = 0.0;
     __syncthreads();
-    float path[kMaxS + 1][6];
     for (int base = r0; base < r1; base += kBBlock) {
         const int r = base + tid;
         bool live = r < r1;
@@ -327,9 +336,8 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             const double ddx = ex - px, ddy = ey - py, ddz = zep - pz;
             const double inv = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
             ray = Ray<double>{ex, ey, zep, ddx * inv, ddy * inv, ddz * inv};
-            path[0][0] = (float)ray.x; path[0][1] = (float)ray.y; path[0][2] = (float)ray.z;
-            path[0][3] = (float)ray.dx; path[0][4] = (float)ray.dy; path[0][5] = (float)ray.dz;
-            const int st = trace_ray<double>(A.lens, mu, ray, PathRec{path});
+            path_put(path, 0, lane, ray);
+            const int st = trace_ray<double>(A.lens, mu, ray, PathRec{path, lane});
             live = st == kAlive;
         }
         // ---- splat adjoint: dL/dO, dL/dD, dL/dk -----------------------
@@ -364,9 +372,9 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             const double sxb = glr * sig1 * ksig;
             const double r3 = rr * rr * rr;
             // sensor plane: O = p + tau d, tau = -(z - t_S) / dz (ray holds O)
-            const float* pl = path[S];
-            const double pz0 = pl[2];
-            const double pdx = pl[3], pdy = pl[4], pdz = pl[5];
+            const St pl = path_get(path, S, lane);
+            const double pz0 = pl.z;
+            const double pdx = pl.dx, pdy = pl.dy, pdz = pl.dz;
             const double z1 = pz0 - A.lens.sensor_dist;
             const double tau = -z1 / pdz;
             const double Oxb = gu * inv_ps, Oyb = gv * inv_ps;
@@ -389,8 +397,7 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             double pg[kPerSurf];
             St ib{0, 0, 0, 0, 0, 0};
             if (live) {
-                const float* pi = path[s];
-                const St in{pi[0], pi[1], pi[2], pi[3], pi[4], pi[5]};
+                const St in = path_get(path, s, lane);
                 surface_bwd(A.lens, s, mu[s], in, ob, ib, pg);
                 ob = ib;
             } else {
@@ -444,11 +451,12 @@ int trace_backward_impl(const sdirt_lens* lens, const sdirt_sensor* sensor,
     const int n_rays = A.smp.nx * A.smp.ny;
     const int np = kPerSurf * R.S + 1;
     if ((rc = launch_fill_zero(grad_out, (size_t)np * sizeof(double), stream))) return rc;
-    int chunks = std::max(1, std::min((4096 + P - 1) / P, n_rays / (kBBlock * 4)));
+    int chunks = std::max(1, std::min((16384 + P - 1) / P, n_rays / (kBBlock * 4)));
     A.smp.chunks = chunks;
     A.smp.rays_per_chunk = (n_rays + chunks - 1) / chunks;
+    const size_t shm = (size_t)(R.S + 1) * 6 * kBBlock * sizeof(float);
     hipLaunchKernelGGL(trace_bwd_kernel, dim3((unsigned)((long long)chunks * P)),
-                       dim3(kBBlock), 0, stream, A);
+                       dim3(kBBlock), shm, stream, A);
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
 }
 
