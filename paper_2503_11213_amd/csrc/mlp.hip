@@ -537,6 +537,19 @@ int mlp_workspace_size(const sdirt_mlp_desc* d, int batch, size_t* out) {
     return SDIRT_OK;
 }
 
+struct FusedArgs {
+    long long n_rows;
+    int n_hidden, n_out, n_freq, feat_pad;
+    float x_half, y_half, iv_lo, iv_hi, lam_lo, lam_hi;
+    const float* x;
+    const float* params;
+    long long b_off[17];
+    const bf16_t* W[17];
+    void* out;
+    int out_bf16;
+};
+int launch_mlp_fused(const FusedArgs& A, hipStream_t st);
+
 int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, const float* x,
                 void* out, int out_dtype, void* workspace, int ws_batch, hipStream_t st) {
     MlpDims m;
@@ -547,6 +560,21 @@ int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, 
     if (out_dtype != SDIRT_F32 && out_dtype != SDIRT_BF16) return SDIRT_EUNSUPPORTED;
     const MlpWs w = carve(m, ws_batch, (char*)workspace);
     cast_all(m, w, params, st);
+    if (m.width == 256) {
+        // fused kernel: every layer and the softmax in one pass over the rows
+        FusedArgs f;
+        std::memset(&f, 0, sizeof(f));
+        f.n_rows = n_rows;
+        f.n_hidden = m.n_hidden; f.n_out = m.n_out; f.n_freq = m.n_freq;
+        f.feat_pad = feat_pad(m);
+        f.x_half = (float)d->x_half; f.y_half = (float)d->y_half;
+        f.iv_lo = (float)d->iv_lo; f.iv_hi = (float)d->iv_hi;
+        f.lam_lo = (float)d->lam_lo; f.lam_hi = (float)d->lam_hi;
+        f.x = x; f.params = params;
+        for (int l = 0; l < m.L; ++l) { f.b_off[l] = (long long)m.b_off(l); f.W[l] = w.W[l]; }
+        f.out = out; f.out_bf16 = out_dtype == SDIRT_BF16;
+        return launch_mlp_fused(f, st);
+    }
     const size_t esz = out_dtype == SDIRT_BF16 ? 2 : 4;
     for (long long r0 = 0; r0 < n_rows; r0 += ws_batch) {
         const int B = (int)std::min<long long>(ws_batch, n_rows - r0);

@@ -73,6 +73,16 @@ int check_sensor(const sdirt_sensor* s, int ks, SensorArgs* A) {
     return SDIRT_OK;
 }
 
+void div_magic_for(uint32_t d, uint64_t* magic, uint32_t* shift) {
+    // q = (n * m) >> (32 + l) with l = ceil(log2 d), m = ceil(2^(32+l) / d):
+    // the error n (m - 2^(32+l)/d) / 2^(32+l) < n / 2^32 < 1/d for n < 2^32,
+    // so q = floor(n / d); n < 2^30 and m < 2^33 keep n m below 2^63.
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    *magic = ((1ull << (32 + l)) + d - 1) / d;
+    *shift = 32 + l;
+}
+
 int check_query(const sdirt_psf_query* q, const Resolved& R, PointArgs* P,
                 SampleArgs* S) {
     if (!q) return SDIRT_EINVAL;
@@ -118,6 +128,7 @@ int check_query(const sdirt_psf_query* q, const Resolved& R, PointArgs* P,
     std::memset(S, 0, sizeof(*S));
     S->nx = q->rays_x;
     S->ny = q->rays_y;
+    div_magic_for((uint32_t)q->rays_x, &S->div_magic, &S->div_shift);
     S->seed = q->seed;
     S->jitter = q->jitter ? 1 : 0;
     return SDIRT_OK;

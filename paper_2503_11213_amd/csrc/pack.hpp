@@ -28,7 +28,12 @@ struct SampleArgs {
     int jitter;
     int chunks;
     int rays_per_chunk;
+    uint64_t div_magic;              // r / nx == (r * div_magic) >> div_shift
+    uint32_t div_shift;
 };
+
+// Multiplier and shift for exact unsigned division by d of every n < 2^30.
+void div_magic_for(uint32_t d, uint64_t* magic, uint32_t* shift);
 
 struct SensorArgs {
     int ks;

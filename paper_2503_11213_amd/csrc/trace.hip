@@ -79,28 +79,29 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
     const double ps = A.sen.ps, inv_ps = 1.0 / ps;
     const int nx = A.smp.nx;
     const int n_rays = nx * A.smp.ny;
+    const double two_nx = 2.0 / nx, two_ny = 2.0 / A.smp.ny;
     const int r0 = chunk * A.smp.rays_per_chunk;
     const int r1 = min(r0 + A.smp.rays_per_chunk, n_rays);
     float e_vig = 0.f, e_tr = 0.f, e_l = 0.f, e_r = 0.f, e_miss = 0.f, e_out = 0.f;
     __syncthreads();
 
     for (int r = r0 + tid; r < r1 && slot_ok; r += kBlock) {
-        const int ci = r % nx;
-        const int cj = r / nx;
+        const int cj = (int)(((uint64_t)(uint32_t)r * A.smp.div_magic) >> A.smp.div_shift);
+        const int ci = r - cj * nx;
         double x1 = 0.5, x2 = 0.5;
         if (A.smp.jitter) {
             x1 = jitter01(key, (uint32_t)r, 0u);
             x2 = jitter01(key, (uint32_t)r, 1u);
         }
-        const double a = -1.0 + 2.0 * (ci + x1) / nx;
-        const double b = -1.0 + 2.0 * (cj + x2) / A.smp.ny;
+        const double a = -1.0 + (ci + x1) * two_nx;
+        const double b = -1.0 + (cj + x2) * two_ny;
         double u, v;
         concentric(a, b, &u, &v);
         const double ex = rep * u, ey = rep * v;
         double ddx = ex - px, ddy = ey - py, ddz = zep - pz;
         const double inv = rsqrt_t<double>(ddx * ddx + ddy * ddy + ddz * ddz);
         Ray<T> ray{(T)ex, (T)ey, (T)zep, (T)(ddx * inv), (T)(ddy * inv), (T)(ddz * inv)};
-        const int st = trace_ray<T>(A.lens, mu, ray, NoRec());
+        const int st = trace_ray<T, NoRec, false>(A.lens, mu, ray, NoRec());
         if (st != kAlive) { e_vig += 1.f; continue; }
         e_tr += 1.f;
         const double wu = ((double)ray.x - hx) * inv_ps + pad;
@@ -110,8 +111,8 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
         const int ib = (int)floor(wv + 0.5);
         if (DP == SDIRT_DP_SIGMOID) {
             const float dxf = (float)ray.dx, dzf = (float)ray.dz;
-            const float sx = dxf / sqrtf(dxf * dxf + dzf * dzf);
-            wl = 1.0f / (1.0f + expf(-(float)A.sen.sig_k * sx));
+            const float sx = dxf * rsqrtf(dxf * dxf + dzf * dzf);
+            wl = 1.0f / (1.0f + __expf(-(float)A.sen.sig_k * sx));
             wr = 1.0f - wl;
         } else {
             const double xk = (double)ray.x, yk = (double)ray.y;

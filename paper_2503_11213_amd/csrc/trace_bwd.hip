@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             const double inv = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
             ray = Ray<double>{ex, ey, zep, ddx * inv, ddy * inv, ddz * inv};
             path_put(path, 0, lane, ray);
-            const int st = trace_ray<double>(A.lens, mu, ray, PathRec{path, lane});
+            const int st = trace_ray<double, PathRec, false>(A.lens, mu, ray, PathRec{path, lane});
             live = st == kAlive;
         }
         // ---- splat adjoint: dL/dO, dL/dD, dL/dk -----------------------
