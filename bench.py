@@ -190,6 +190,19 @@ def extras(dev, stream):
         "render_s": t_r * 1e-3, "paper_render_s": 0.2,
         "paper_hardware": "i7-12700K + RTX 3090 (Sec. 5.1)"}
     print("paper workload done", file=sys.stderr, flush=True)
+    # 5. smartphone-like 16-surface aspheric lens: 64 x 32 x 3 PSFs, 1024^2
+    #    rays each, ks 65 (trace only; its render batch is ~10 PFLOP)
+    lens, sensor, query = configs.config5()
+    b5 = torch.empty((query.n_points, 2, 65, 65), device=dev)
+    tr = lambda: sdirt.trace_dp_psf(lens, sensor, query, out=b5, stats=False)
+    tr()
+    t5 = timed(tr, stream, 2)
+    n_surf = sum(1 for s_ in lens.surfaces if s_.kind != 2)
+    out["phone_lens_trace"] = {
+        "workload": "16-surface aspheric lens (EFL 4.3 mm, f/1.8), 6144 PSFs x 1024^2 rays, ks 65",
+        "ms": t5, "psfs_per_s": query.n_points / (t5 * 1e-3),
+        "rays_surfaces_per_s": query.n_points * query.n_rays * n_surf / (t5 * 1e-3)}
+    print("phone lens done", file=sys.stderr, flush=True)
     return out
 
 

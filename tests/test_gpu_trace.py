@@ -245,3 +245,20 @@ def test_paper_psf_map_sampled_pixels():
         assert np.array_equal(g[k], np.round(g[k]))         # box + microlens: counts
         if ref[k].sum() > 0:
             assert _energy_l1(g[k], ref[k]) <= L1_TOL
+
+
+def test_config5_phone_lens_sampled_points():
+    # 16 refracting surfaces with six even aspheres, 1 um pixels, ks 65:
+    # the full 64 x 32 x 3 grid at reduced rays, sampled points vs the oracle
+    lens, sensor, query = configs.config5(rays=48)
+    psf, st = sdirt.trace_dp_psf(lens, sensor, query)
+    torch.cuda.synchronize()
+    picks = [(0, 0, 1), (20, 16, 0), (40, 31, 2), (63, 5, 1), (63, 31, 0)]
+    ref, rst = opsf.trace_dp_psf(lens, sensor, query, points=picks)
+    g, gs = psf.cpu().numpy(), st.cpu().numpy()
+    for (f, d, l) in picks:
+        q = opsf.point_index(f, d, l, 32, 3)
+        assert np.array_equal(gs[q, :3], rst[q, :3]), (f, d, l)
+        if ref[q].sum() > 0:
+            assert _energy_l1(g[q], ref[q]) <= L1_TOL, (f, d, l)
+    assert np.allclose(gs[:, 0], gs[:, 1] + gs[:, 2])

@@ -123,3 +123,21 @@ def test_f_number_resizes_stop():
     z, r = P.pupil(L.ref_wavelength)
     assert P.efl / (2 * r) == pytest.approx(4.0, rel=1e-13)
     assert 2 * P.stop_radius == pytest.approx(7.52, abs=0.01)
+
+
+def test_phone_lens_focal_length_and_surfaces():
+    from workloads.lens import ASPHERE, STOP
+    L = lenses.phone_lens_16(0)
+    assert optics.efl(L, 0.55) == pytest.approx(4.3, rel=1e-12)
+    assert sum(1 for s in L.surfaces if s.kind != STOP) == 16
+    assert sum(1 for s in L.surfaces if s.kind == ASPHERE) == 6
+    P = optics.Prepared(L)
+    z, r = P.pupil(0.55)
+    assert P.efl / (2 * r) == pytest.approx(1.8, rel=1e-12)
+    # asphere terms stay small against the base sag (Newton starts close)
+    for s in L.surfaces:
+        if s.kind == ASPHERE:
+            rho = s.semi_diameter ** 2
+            extra = sum(a * rho ** (m + 2) for m, a in enumerate(s.asph))
+            base = s.c * rho / (1 + np.sqrt(1 - s.c * s.c * rho))
+            assert abs(extra) <= 0.5 * abs(base) + 2e-3

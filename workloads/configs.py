@@ -146,3 +146,22 @@ def pixel_inputs(H, W, ps, depth_map, lambdas=RGB_LAMBDAS):
     x[:, :, 2] = iv[:, None]
     x[:, :, 3] = np.asarray(lambdas)[None, :]
     return x.reshape(-1, 4)
+
+
+def config5(rays=1024):
+    """Smartphone-like 16-surface aspheric lens (EFL 4.3 mm, f/1.8); sensor
+    4032 x 3024 at 1.0 um; 64 radial fields to the half-diagonal x 32 depths
+    uniform in 1/d over 0.1-5 m (focus at the 1/d midpoint) x 3 wavelengths;
+    ks 65, box splat, sigmoid response."""
+    from . import lenses as _l
+    lens = _l.phone_lens_16(0)
+    lens.focus_depth = 2.0 / (1.0 / 100.0 + 1.0 / 5000.0)
+    lens.ref_wavelength = 0.55
+    W, H, ps = 4032, 3024, 0.001
+    sensor = Sensor(pitch=ps, dp_mode=DP_SIGMOID, sigmoid_k=20.0, width_px=W, height_px=H)
+    half_diag = float(np.hypot(W * ps / 2, H * ps / 2))
+    fields = [(k * half_diag / 63.0, 0.0) for k in range(64)]
+    query = PsfQuery(fields=fields, depths=inverse_uniform_depths(100.0, 5000.0, 32),
+                     wavelengths=list(RGB_LAMBDAS), rays_x=rays, rays_y=rays, seed=0,
+                     jitter=True, ks=65, splat=SPLAT_BOX, out_f64=False)
+    return lens, sensor, query

@@ -159,3 +159,62 @@ def double_gauss_12(seed=0):
                          b0 * rng.uniform(0.99, 1.01))
         out.append(Surface(kind=kind, c=c, t=t, semi_diameter=sd, medium=med))
     return Lens(surfaces=out, stop=6, f_number=2.0, name="dgauss12 seed=%d" % seed)
+
+
+# Paraxial focal length of the unscaled 16-surface design below is
+# 51.99701660498591 mm at 0.55 um (asphere terms do not change it); the
+# literal scale brings it to 4.3 mm.  A non-GPU test checks the result.
+PHONE16_SCALE = 4.3 / 51.99701660498591
+
+
+def phone_lens_16(seed=0, aperture_scale=1.3):
+    """Seeded smartphone-like lens: 8 elements, 16 refracting surfaces, even
+    aspheres up to r^10, EFL 4.3 mm, f/1.8.
+
+    Recipe: the six elements of Table S1 (cemented surface 4 split by a
+    0.05 mm air gap; the a12 terms of surfaces 9 and 10 dropped), followed by
+    two weak plastic menisci (Cauchy 1.4905/0.0047 and 1.5700/0.0100) whose
+    four surfaces carry seeded a4..a10 (|a4| <= 3e-7, |a6| <= 1e-9,
+    |a8| <= 5e-12, |a10| <= 2e-14 in the unscaled millimetre units: at most
+    ~12 um of sag at 12 mm); clear semi-diameters enlarged by
+    `aperture_scale` (capped at 0.9 |R|) to pass the wider sensor diagonal;
+    then every length scaled by PHONE16_SCALE.  The stop is resized to f/1.8
+    and the sensor focused by the consumer.
+    """
+    import copy
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i, s in enumerate(rf50().surfaces):
+        s = copy.deepcopy(s)
+        if s.kind == ASPHERE:
+            s.asph = tuple(s.asph[:4]) + (0.0,)
+        if i == 3:
+            gap = copy.deepcopy(s)
+            gap.medium = air()
+            gap.t = 0.05
+            rows.append(gap)
+        rows.append(s)
+    rows[-1].t = 2.0
+
+    def asph():
+        return (rng.uniform(-3e-7, 3e-7), rng.uniform(-1e-9, 1e-9),
+                rng.uniform(-5e-12, 5e-12), rng.uniform(-2e-14, 2e-14), 0.0)
+
+    rows.append(Surface(kind=ASPHERE, c=-1 / 40.0, t=1.0, semi_diameter=13.5,
+                        medium=cauchy(1.4905, 0.0047), asph=asph()))
+    rows.append(Surface(kind=ASPHERE, c=-1 / 45.0, t=1.0, semi_diameter=14.0, asph=asph()))
+    rows.append(Surface(kind=ASPHERE, c=1 / 100.0, t=1.0, semi_diameter=14.5,
+                        medium=cauchy(1.5700, 0.0100), asph=asph()))
+    rows.append(Surface(kind=ASPHERE, c=1 / 90.0, t=10.0, semi_diameter=14.5, asph=asph()))
+    k = PHONE16_SCALE
+    out = []
+    for s in rows:
+        sd = s.semi_diameter
+        if s.kind != STOP:
+            sd = aperture_scale * sd
+            if s.c != 0:
+                sd = min(sd, 0.9 / abs(s.c))
+        out.append(Surface(kind=s.kind, c=s.c / k, t=s.t * k, semi_diameter=sd * k,
+                           medium=s.medium, conic=s.conic,
+                           asph=tuple(a / k ** (2 * m + 3) for m, a in enumerate(s.asph))))
+    return Lens(surfaces=out, stop=6, f_number=1.8, name="phone16 seed=%d" % seed)
