@@ -21,17 +21,21 @@ enum RayStatus : int { kAlive = 0, kMiss = 1, kClip = 2, kTir = 3,
                        kNewton = 4, kInvalid = 5 };
 
 // Prescription as kernel arguments: read with scalar loads in the hot loop.
+// code[s] = kind | (asphere slot << 8) (slot -1 when not an asphere); a
+// 32-bit word so that it is fetched by a scalar load.
 struct LensArgs {
     int S;
     int stop;
-    int8_t kind[kMaxS];
-    int8_t aslot[kMaxS];        // asphere slot or -1
+    int code[kMaxS];
     double c[kMaxS];            // curvature; 1/f for IDEAL
     double tprev[kMaxS];        // distance from the previous vertex (0 for s=0)
     double semi2[kMaxS];        // squared clear semi-diameter
     double asph[kMaxAsph][6];   // conic, a4, a6, a8, a10, a12
     double sensor_dist;         // last vertex -> sensor plane
 };
+
+__device__ __host__ inline int kind_of(const LensArgs& L, int s) { return L.code[s] & 0xff; }
+__device__ __host__ inline int aslot_of(const LensArgs& L, int s) { return L.code[s] >> 8; }
 
 // Per-wavelength data: index ratios and entrance pupil.
 struct LambdaArgs {
@@ -62,27 +66,50 @@ __device__ inline double jitter01(uint32_t key, uint32_t ray, uint32_t dim) {
     return (double)(h >> 8) * (1.0 / 16777216.0);
 }
 
-// Shirley-Chiu concentric map of [-1,1]^2 onto the unit disk, in a form
-// that commutes exactly with a -> -a and b -> -b.  float32 trigonometry on
-// |phi| <= pi/4.
+// Reciprocal from the hardware approximation (v_rcp_f64, ~5e-8 relative)
+// refined by one Newton step (~2e-15).
+__device__ inline double rcp_d(double v) {
+    const double r = __builtin_amdgcn_rcp(v);
+    return fma(r, fma(-v, r, 1.0), r);
+}
+
+// sin and cos for |x| <= pi/4 from their Taylor series through x^15 and
+// x^16 (truncation below 1e-16 on that interval), in float64.  sin is odd
+// and cos even bit for bit.
+__device__ inline void sincos_quarter(double x, double* s, double* c) {
+    const double x2 = x * x;
+    double p = -1.0 / 1307674368000.0;           // -1/15!
+    p = fma(p, x2, 1.0 / 6227020800.0);          //  1/13!
+    p = fma(p, x2, -1.0 / 39916800.0);           // -1/11!
+    p = fma(p, x2, 1.0 / 362880.0);              //  1/9!
+    p = fma(p, x2, -1.0 / 5040.0);               // -1/7!
+    p = fma(p, x2, 1.0 / 120.0);                 //  1/5!
+    p = fma(p, x2, -1.0 / 6.0);                  // -1/3!
+    *s = fma(x * x2, p, x);
+    double q = 1.0 / 20922789888000.0;           //  1/16!
+    q = fma(q, x2, -1.0 / 87178291200.0);        // -1/14!
+    q = fma(q, x2, 1.0 / 479001600.0);           //  1/12!
+    q = fma(q, x2, -1.0 / 3628800.0);            // -1/10!
+    q = fma(q, x2, 1.0 / 40320.0);               //  1/8!
+    q = fma(q, x2, -1.0 / 720.0);                // -1/6!
+    q = fma(q, x2, 1.0 / 24.0);                  //  1/4!
+    q = fma(q, x2, -0.5);                        // -1/2!
+    *c = fma(x2, q, 1.0);
+}
+
+// Shirley-Chiu concentric map of [-1,1]^2 onto the unit disk in float64,
+// in a form that commutes exactly with a -> -a and b -> -b:
+//   |a| > |b|: phi = (pi/4) b/a, (u, v) = (a cos phi, a sin phi)
+//   else:      phi = (pi/4) a/b, (u, v) = (b sin phi, b cos phi)
 __device__ inline void concentric(double a, double b, double* u, double* v) {
-    const float af = (float)a, bf = (float)b;
-    if (fabsf(af) > fabsf(bf)) {
-        const float phi = 0.785398163397448309616f * (bf / af);
-        float s, c;
-        sincosf(phi, &s, &c);
-        *u = (double)(af * c);
-        *v = (double)(af * s);
-    } else if (bf != 0.0f) {
-        const float phi = 0.785398163397448309616f * (af / bf);
-        float s, c;
-        sincosf(phi, &s, &c);
-        *u = (double)(bf * s);
-        *v = (double)(bf * c);
-    } else {
-        *u = 0.0;
-        *v = 0.0;
-    }
+    const bool wide = fabs(a) > fabs(b);
+    const double num = wide ? b : a, den = wide ? a : b;
+    const double phi = den != 0.0 ? 0.78539816339744830962 * (num * rcp_d(den)) : 0.0;
+    double sn, cs;
+    sincos_quarter(phi, &sn, &cs);
+    const double p = den * cs, o = den * sn;
+    *u = wide ? p : o;
+    *v = wide ? o : p;
 }
 
 template <typename T>
@@ -94,34 +121,49 @@ template <typename T> __device__ inline T tol_newton();
 template <> __device__ inline double tol_newton<double>() { return 1e-12; }
 template <> __device__ inline float tol_newton<float>() { return 2e-6f; }
 
-// Reciprocal, square root and reciprocal square root from the hardware
-// approximations refined by one Newton step.  On gfx950 v_rcp_f64 and
-// v_rsq_f64 are accurate to ~5e-8 relative; one step brings them to
-// ~4e-15 (measured over 1e6 arguments in [1e-3, 1e3]), far below what the
-// trace needs; no IEEE rounding or denormal handling is needed on this path.
+// Reciprocal, square root and reciprocal square root.  float64: the hardware
+// approximations (v_rcp_f64, v_rsq_f64: ~5e-8 relative on gfx950) refined
+// by one Newton step to ~4e-15 (measured over 1e6 arguments in [1e-3, 1e3]),
+// far below what the trace needs; no IEEE rounding or denormal handling is
+// needed on this path.  float32: the hardware instructions (1 ulp).
 template <typename T> __device__ inline T rcp_t(T v);
-template <> __device__ inline double rcp_t<double>(double v) {
-    const double r = __builtin_amdgcn_rcp(v);
-    return fma(r, fma(-v, r, 1.0), r);
-}
-template <> __device__ inline float rcp_t<float>(float v) { return 1.0f / v; }
+template <> __device__ inline double rcp_t<double>(double v) { return rcp_d(v); }
+template <> __device__ inline float rcp_t<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 
 template <typename T> __device__ inline T rsqrt_t(T v);
 template <> __device__ inline double rsqrt_t<double>(double v) {
     const double y = __builtin_amdgcn_rsq(v);
     return y * fma(-0.5 * v * y, y, 1.5);
 }
-template <> __device__ inline float rsqrt_t<float>(float v) { return 1.0f / sqrtf(v); }
+template <> __device__ inline float rsqrt_t<float>(float v) { return __builtin_amdgcn_rsqf(v); }
 
-// sqrt of a non-negative argument (0 -> 0)
+// sqrt of a non-negative argument (0 for v <= 0): s = v y with the raw
+// y ~ 1/sqrt(v), corrected once by s + (y/2)(v - s^2); relative error
+// 1.5 e^2 for a raw error e.
 template <typename T> __device__ inline T sqrt_t(T v);
 template <> __device__ inline double sqrt_t<double>(double v) {
     if (!(v > 0.0)) return 0.0;
-    const double y = rsqrt_t<double>(v);
+    const double y = __builtin_amdgcn_rsq(v);
     const double s = v * y;
     return fma(0.5 * y, fma(-s, s, v), s);
 }
-template <> __device__ inline float sqrt_t<float>(float v) { return v > 0.f ? sqrtf(v) : 0.f; }
+template <> __device__ inline float sqrt_t<float>(float v) {
+    return v > 0.f ? __builtin_amdgcn_sqrtf(v) : 0.f;
+}
+
+// sqrt where a negative argument marks a ray that the caller already counts
+// as lost: the argument is clamped instead of selected on, and the result
+// for such a ray is finite and unused.
+template <typename T> __device__ inline T sqrt_live(T v);
+template <> __device__ inline double sqrt_live<double>(double v) {
+    v = fmax(v, 1e-300);
+    const double y = __builtin_amdgcn_rsq(v);
+    const double s = v * y;
+    return fma(0.5 * y, fma(-s, s, v), s);
+}
+template <> __device__ inline float sqrt_live<float>(float v) {
+    return __builtin_amdgcn_sqrtf(fmaxf(v, 1e-30f));
+}
 
 // Even-asphere sag and its derivative in rho = r^2.
 template <typename T>
@@ -130,18 +172,37 @@ __device__ __forceinline__ void asphere_sag(const double* co, T c, T rho, T* sag
     const T k = (T)co[0];
     const T arg = T(1) - (T(1) + k) * c * c * rho;
     *ok = arg >= T(0);
-    const T q = sqrt_t<T>(arg >= T(0) ? arg : T(1));
+    const T q = sqrt_live<T>(arg);
     const T a4 = (T)co[1], a6 = (T)co[2], a8 = (T)co[3], a10 = (T)co[4], a12 = (T)co[5];
-    *sag = c * rho / (T(1) + q) +
+    *sag = c * rho * rcp_t<T>(T(1) + q) +
            rho * rho * (a4 + rho * (a6 + rho * (a8 + rho * (a10 + rho * a12))));
-    *dsag = c / (T(2) * q) +
+    *dsag = T(0.5) * c * rcp_t<T>(q) +
             rho * (T(2) * a4 + rho * (T(3) * a6 + rho * (T(4) * a8 +
                    rho * (T(5) * a10 + rho * T(6) * a12))));
+}
+
+// Vector Snell refraction at the unit normal n (pointing along +z) with
+// index ratio m = n_before / n_after.  Returns K = cos^2 of the refracted
+// angle; K < 0 is total internal reflection, which the caller records.
+template <typename T>
+__device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m) {
+    const T cosI = r.dx * nx + r.dy * ny + r.dz * nz;
+    const T K = T(1) - m * m * (T(1) - cosI * cosI);
+    const T g = sqrt_live<T>(K) - m * cosI;
+    r.dx = m * r.dx + g * nx;
+    r.dy = m * r.dy + g * ny;
+    r.dz = m * r.dz + g * nz;
+    return K;
 }
 
 // Sequential trace of one ray through surfaces [0, S): on return r holds
 // the vertex-local state after the last surface.  `rec(s, r)` is called
 // after each surface (hit point + refracted direction).
+// Spheres are intersected straight from the current point (the quadratic
+// c |p + t d|^2 - 2 (p_z + t d_z) = 0 in the root form F / (G + sqrt(G^2 - cF)),
+// whose discriminant does not depend on where along the ray p sits);
+// aspheres, planes, the stop and ideal lenses first move the ray to the
+// vertex plane.
 // EXACT: report the first failure's code (ray-level debugging); otherwise
 // only whether the ray survived (kAlive or kMiss), which keeps the
 // bookkeeping in scalar lane masks.
@@ -156,81 +217,82 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         else alive = alive && !(cond);                           \
     } while (0)
     for (int s = 0; s < L.S; ++s) {
-        const int kind = L.kind[s];
+        const int code = L.code[s];
+        const int kind = code & 0xff;
+        const T c = (T)L.c[s];
+        const T semi2 = (T)L.semi2[s];
         r.z -= (T)L.tprev[s];
         SDIRT_FAIL(!(r.dz > T(0)), kInvalid);
-        const T inv_dz = rcp_t<T>(r.dz);
-        const T tau = -r.z * inv_dz;
-        r.x += tau * r.dx;
-        r.y += tau * r.dy;
-        r.z = T(0);
-        const T c = (T)L.c[s];
         if (kind == SDIRT_SPHERE) {
-            const T F = c * (r.x * r.x + r.y * r.y);
-            const T G = r.dz - c * (r.x * r.dx + r.y * r.dy);
+            const T F = c * (r.x * r.x + r.y * r.y + r.z * r.z) - T(2) * r.z;
+            const T G = r.dz - c * (r.x * r.dx + r.y * r.dy + r.z * r.dz);
             const T disc = G * G - c * F;
             SDIRT_FAIL(disc < T(0), kMiss);
-            const T delta = F * rcp_t<T>(G + sqrt_t<T>(disc));
-            r.x += delta * r.dx;
-            r.y += delta * r.dy;
-            r.z = delta * r.dz;
-        } else if (kind == SDIRT_ASPHERE) {
-            const double* co = L.asph[L.aslot[s]];
-            const T k = (T)co[0];
-            const T F = c * (r.x * r.x + r.y * r.y);
-            const T G = r.dz - c * (r.x * r.dx + r.y * r.dy);
-            const T a = c * (T(1) + k * r.dz * r.dz);
-            const T disc = G * G - a * F;
-            T delta = disc >= T(0) ? F * rcp_t<T>(G + sqrt_t<T>(disc)) : T(0);
-            bool conv = false, bad = false;
-            for (int it = 0; it < 50 && !conv && !bad; ++it) {
-                const T xr = r.x + delta * r.dx;
-                const T yr = r.y + delta * r.dy;
-                T sag, dsag;
-                bool ok;
-                asphere_sag(co, c, xr * xr + yr * yr, &sag, &dsag, &ok);
-                if (!ok) { bad = true; break; }
-                const T f = delta * r.dz - sag;
-                const T fp = r.dz - dsag * T(2) * (xr * r.dx + yr * r.dy);
-                const T step = f * rcp_t<T>(fp);
-                delta -= step;
-                conv = fabs(step) < tol_newton<T>() * (T(1) + fabs(delta));
-            }
-            SDIRT_FAIL(!conv || bad, kNewton);
-            r.x += delta * r.dx;
-            r.y += delta * r.dy;
-            r.z = delta * r.dz;
-        }
-        const T r2 = r.x * r.x + r.y * r.y;
-        SDIRT_FAIL(r2 > (T)L.semi2[s], kClip);
-        if (kind == SDIRT_SPHERE || kind == SDIRT_ASPHERE || kind == SDIRT_PLANE) {
-            T nx, ny, nz;
-            if (kind == SDIRT_SPHERE) {
-                nx = -c * r.x; ny = -c * r.y; nz = T(1) - c * r.z;
-            } else if (kind == SDIRT_ASPHERE) {
-                T sag, dsag;
-                bool ok;
-                asphere_sag(L.asph[L.aslot[s]], c, r2, &sag, &dsag, &ok);
-                nx = T(-2) * r.x * dsag; ny = T(-2) * r.y * dsag; nz = T(1);
-                const T inv = rsqrt_t<T>(nx * nx + ny * ny + T(1));
-                nx *= inv; ny *= inv; nz = inv;
-            } else {
-                nx = T(0); ny = T(0); nz = T(1);
-            }
-            const T m = (T)mu[s];
-            const T cosI = r.dx * nx + r.dy * ny + r.dz * nz;
-            const T K = T(1) - m * m * (T(1) - cosI * cosI);
+            const T t = F * rcp_t<T>(G + sqrt_live<T>(disc));
+            r.x += t * r.dx;
+            r.y += t * r.dy;
+            r.z += t * r.dz;
+            SDIRT_FAIL(r.x * r.x + r.y * r.y > semi2, kClip);
+            const T K = refract<T>(r, -c * r.x, -c * r.y, T(1) - c * r.z, (T)mu[s]);
             SDIRT_FAIL(K < T(0), kTir);
-            const T g = sqrt_t<T>(K) - m * cosI;
-            r.dx = m * r.dx + g * nx;
-            r.dy = m * r.dy + g * ny;
-            r.dz = m * r.dz + g * nz;
-        } else if (kind == SDIRT_IDEAL) {
-            const T idz = rcp_t<T>(r.dz);
-            const T tx = r.dx * idz - r.x * c;
-            const T ty = r.dy * idz - r.y * c;
-            const T inv = rsqrt_t<T>(tx * tx + ty * ty + T(1));
-            r.dx = tx * inv; r.dy = ty * inv; r.dz = inv;
+        } else {
+            const T tau = -r.z * rcp_t<T>(r.dz);
+            r.x += tau * r.dx;
+            r.y += tau * r.dy;
+            r.z = T(0);
+            if (kind == SDIRT_ASPHERE) {
+                const double* co = L.asph[code >> 8];
+                const T k = (T)co[0];
+                const T F = c * (r.x * r.x + r.y * r.y);
+                const T G = r.dz - c * (r.x * r.dx + r.y * r.dy);
+                const T a = c * (T(1) + k * r.dz * r.dz);
+                const T disc = G * G - a * F;
+                T delta = disc >= T(0) ? F * rcp_t<T>(G + sqrt_t<T>(disc)) : T(0);
+                bool conv = false, bad = false;
+                for (int it = 0; it < 50 && !conv && !bad; ++it) {
+                    const T xr = r.x + delta * r.dx;
+                    const T yr = r.y + delta * r.dy;
+                    T sag, dsag;
+                    bool ok;
+                    asphere_sag(co, c, xr * xr + yr * yr, &sag, &dsag, &ok);
+                    if (!ok) { bad = true; break; }
+                    const T f = delta * r.dz - sag;
+                    const T fp = r.dz - dsag * T(2) * (xr * r.dx + yr * r.dy);
+                    const T step = f * rcp_t<T>(fp);
+                    delta -= step;
+                    conv = fabs(step) < tol_newton<T>() * (T(1) + fabs(delta));
+                }
+                SDIRT_FAIL(!conv || bad, kNewton);
+                r.x += delta * r.dx;
+                r.y += delta * r.dy;
+                r.z = delta * r.dz;
+                const T r2 = r.x * r.x + r.y * r.y;
+                SDIRT_FAIL(r2 > semi2, kClip);
+                T sag, dsag;
+                bool ok;
+                asphere_sag(co, c, r2, &sag, &dsag, &ok);
+                T nx = T(-2) * r.x * dsag, ny = T(-2) * r.y * dsag;
+                const T inv = rsqrt_t<T>(nx * nx + ny * ny + T(1));
+                const T K = refract<T>(r, nx * inv, ny * inv, inv, (T)mu[s]);
+                SDIRT_FAIL(K < T(0), kTir);
+            } else {
+                SDIRT_FAIL(r.x * r.x + r.y * r.y > semi2, kClip);
+                if (kind == SDIRT_PLANE) {
+                    // normal (0, 0, 1): the refracted dz is sqrt(K)
+                    const T m = (T)mu[s];
+                    const T K = T(1) - m * m * (T(1) - r.dz * r.dz);
+                    SDIRT_FAIL(K < T(0), kTir);
+                    r.dx *= m;
+                    r.dy *= m;
+                    r.dz = sqrt_live<T>(K);
+                } else if (kind == SDIRT_IDEAL) {
+                    const T idz = rcp_t<T>(r.dz);
+                    const T tx = r.dx * idz - r.x * c;
+                    const T ty = r.dy * idz - r.y * c;
+                    const T inv = rsqrt_t<T>(tx * tx + ty * ty + T(1));
+                    r.dx = tx * inv; r.dy = ty * inv; r.dz = inv;
+                }
+            }
         }
         rec(s, r);
     }

@@ -11,18 +11,18 @@ int pack_lens(const Resolved& R, LensArgs* A) {
     A->stop = R.stop;
     int nas = 0;
     for (int s = 0; s < R.S; ++s) {
-        A->kind[s] = (int8_t)R.kind[s];
-        A->aslot[s] = -1;
+        int slot = -1;
         A->c[s] = R.kind[s] == SDIRT_IDEAL ? 1.0 / R.focal[s] : R.c[s];
         A->tprev[s] = s == 0 ? 0.0 : R.t[s - 1];
         A->semi2[s] = R.semi[s] * R.semi[s];
         if (R.kind[s] == SDIRT_ASPHERE) {
             if (nas >= kMaxAsph) return SDIRT_EUNSUPPORTED;
-            A->aslot[s] = (int8_t)nas;
+            slot = nas;
             A->asph[nas][0] = R.conic[s];
             for (int m = 0; m < 5; ++m) A->asph[nas][m + 1] = R.asph[5 * s + m];
             ++nas;
         }
+        A->code[s] = (R.kind[s] & 0xff) | (int)((unsigned)slot << 8);
     }
     A->sensor_dist = R.sensor_distance;
     return SDIRT_OK;

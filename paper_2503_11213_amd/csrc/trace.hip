@@ -111,14 +111,14 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
         const int ib = (int)floor(wv + 0.5);
         if (DP == SDIRT_DP_SIGMOID) {
             const float dxf = (float)ray.dx, dzf = (float)ray.dz;
-            const float sx = dxf * rsqrtf(dxf * dxf + dzf * dzf);
-            wl = 1.0f / (1.0f + __expf(-(float)A.sen.sig_k * sx));
+            const float sx = dxf * __builtin_amdgcn_rsqf(dxf * dxf + dzf * dzf);
+            wl = __builtin_amdgcn_rcpf(1.0f + __expf(-(float)A.sen.sig_k * sx));
             wr = 1.0f - wl;
         } else {
             const double xk = (double)ray.x, yk = (double)ray.y;
             const double xc = hx + (jb - pad) * ps;
             const double yc = hy + (ib - pad) * ps;
-            const double tn = (double)ray.dx / (double)ray.dz;
+            const double tn = (double)ray.dx * rcp_d((double)ray.dz);
             const double h = A.sen.ml_h, f = A.sen.ml_f, w = A.sen.ml_w, rr = A.sen.ml_r;
             const bool inside = (xk - xc) * (xk - xc) + (yk - yc) * (yk - yc) <= rr * rr;
             double xL, xM, xR;

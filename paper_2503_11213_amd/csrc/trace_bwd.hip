@@ -107,7 +107,7 @@ __device__ __forceinline__ SagD sag_derivs(const double* co, double c, double rh
 __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu, const St& in,
                                    const St& ob, St& ib, double pg[kPerSurf]) {
     for (int k = 0; k < kPerSurf; ++k) pg[k] = 0.0;
-    const int kind = L.kind[s];
+    const int kind = kind_of(L, s);
     const double c = L.c[s];
     const double tprev = L.tprev[s];
     // ---- forward recompute -------------------------------------------
@@ -117,7 +117,8 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
     const double x1 = in.x + tau * dx, y1 = in.y + tau * dy;
     double D = 0.0, F = 0.0, G = 0.0, den = 1.0, sq = 0.0;
     double xh = x1, yh = y1, zh = 0.0;
-    const double* co = L.asph[L.aslot[s] > 0 ? L.aslot[s] : 0];   // read only for ASPHERE
+    const int slot = aslot_of(L, s);
+    const double* co = L.asph[slot > 0 ? slot : 0];   // read only for ASPHERE
     if (kind == SDIRT_SPHERE) {
         F = c * (x1 * x1 + y1 * y1);
         G = dz - c * (x1 * dx + y1 * dy);
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             } else {
                 for (int k = 0; k < kPerSurf; ++k) pg[k] = 0.0;
             }
-            const int kind = A.lens.kind[s];
+            const int kind = kind_of(A.lens, s);
             // c (sphere/asphere), t_{s-1} (s > 0), conic and a's (asphere)
             if (kind == SDIRT_SPHERE || kind == SDIRT_ASPHERE) {
                 const double v = wave_sum_d(pg[0]);
