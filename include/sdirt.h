@@ -239,15 +239,21 @@ int sdirt_render_dp_backward(const sdirt_render_desc* desc, const void* psf,
  * sum-normalised left/right PSF: Fourier encoding (sin / cos of
  * 2^k pi v, k < n_freq, for the four inputs mapped to [-1, 1]), n_hidden
  * ReLU layers of `width`, a linear layer to n_out = 2 ks ks logits and a
- * softmax over all of them.  Training minimises the squared error of each
- * output scaled by the largest value of its target PSF (max-normalised
- * targets), averaged over the batch.
+ * softmax over all of them.  Training minimises, averaged over the batch,
+ * either (loss = SDIRT_LOSS_L2MAX) the L2 loss of Eq. (5) with each
+ * sample's squared error scaled by the largest value of its target PSF
+ * (max-normalised targets), or (SDIRT_LOSS_KL) the Kullback-Leibler
+ * divergence sum_i t_i log(t_i / p_i) of the prediction from the target
+ * distribution, whose logit gradient (p - t) does not vanish where the
+ * network predicts no energy.
  * Parameters: one float32 vector, per layer W [out][in] row-major then
  * b [out], layers in order (sizes from sdirt_mlp_n_params).  Matrix
  * products run in bf16 on the matrix cores with float32 accumulation.
  * workspace: caller-owned device memory of sdirt_mlp_workspace_size(batch)
  * bytes for batches of `batch` rows (a multiple of 64); it holds the bf16
  * weights, activations and gradients of one batch. */
+enum { SDIRT_LOSS_L2MAX = 0, SDIRT_LOSS_KL = 1 };
+
 typedef struct {
     int n_hidden;            /* ReLU layers                                */
     int width;               /* hidden width, multiple of 64               */
@@ -256,6 +262,7 @@ typedef struct {
     double x_half, y_half;   /* h_x, h_y scale: image half-size (mm)       */
     double iv_lo, iv_hi;     /* inverse-depth range (1/mm)                 */
     double lam_lo, lam_hi;   /* wavelength range (um)                      */
+    int loss;                /* SDIRT_LOSS_L2MAX or SDIRT_LOSS_KL          */
 } sdirt_mlp_desc;
 
 int sdirt_mlp_n_params(const sdirt_mlp_desc* desc, long long* n_params);

@@ -16,7 +16,11 @@ normalised by a joint softmax.  Readings:
   * the softmax output is already sum-normalised; the max normalisation of
     the targets enters as the per-sample scale of the squared error:
         loss = mean_b sum_i ((p_bi - t_bi) / max_j t_bj)^2,
-    with t the jointly sum-normalised traced PSF;
+    with t the jointly sum-normalised traced PSF ("l2max");
+  * alternative training loss (not the paper's): the Kullback-Leibler
+    divergence of p from t,  loss = mean_b sum_i t_bi log(t_bi / p_bi)
+    (0 log 0 = 0), whose logit gradient (p sum(t) - t) / B does not vanish
+    on outputs the network predicts as empty ("kl");
   * optimiser Adam(beta1 0.9, beta2 0.999, eps 1e-8).
 bf16 mirror: weights and every GEMM operand are rounded to bfloat16
 (round-to-nearest-even, through float32) where the device kernels round
@@ -82,18 +86,24 @@ def forward(params, x, norm, bf16=False):
     return softmax(h), cache
 
 
-def loss(p, t):
+def loss(p, t, kind="l2max"):
+    if kind == "kl":
+        tl = np.where(t > 0.0, t * np.log(np.where(t > 0.0, t, 1.0)), 0.0)
+        return float(np.mean(np.sum(tl - t * np.log(p), axis=1)))
     m = t.max(axis=1, keepdims=True)
     return float(np.mean(np.sum(((p - t) / m) ** 2, axis=1)))
 
 
-def backward(params, p, cache, t, bf16=False):
-    """Gradients [(dW, db)] of loss(p, t) through softmax and the layers."""
+def backward(params, p, cache, t, bf16=False, kind="l2max"):
+    """Gradients [(dW, db)] of loss(p, t, kind) through softmax and the layers."""
     rnd = to_bf16 if bf16 else (lambda a: a)
     B = p.shape[0]
-    m = t.max(axis=1, keepdims=True)
-    gp = 2.0 * (p - t) / (m * m) / B
-    dz = p * (gp - np.sum(p * gp, axis=1, keepdims=True))
+    if kind == "kl":
+        dz = (p * t.sum(axis=1, keepdims=True) - t) / B
+    else:
+        m = t.max(axis=1, keepdims=True)
+        gp = 2.0 * (p - t) / (m * m) / B
+        dz = p * (gp - np.sum(p * gp, axis=1, keepdims=True))
     grads = [None] * len(params)
     for li in range(len(params) - 1, -1, -1):
         W, _ = params[li]

@@ -18,6 +18,7 @@ SPLAT_BOX, SPLAT_TENT = 0, 1
 NORM_NONE, NORM_SUM, NORM_MAX = 0, 1, 2
 F32, F64, BF16 = 0, 1, 2
 SRC_DENSE, SRC_BANK = 0, 1
+LOSS_L2MAX, LOSS_KL = 0, 1
 MAX_SURFACES = 24
 
 
@@ -77,7 +78,7 @@ class MlpDesc(C.Structure):
                 ("n_freq", C.c_int),
                 ("x_half", C.c_double), ("y_half", C.c_double),
                 ("iv_lo", C.c_double), ("iv_hi", C.c_double),
-                ("lam_lo", C.c_double), ("lam_hi", C.c_double)]
+                ("lam_lo", C.c_double), ("lam_hi", C.c_double), ("loss", C.c_int)]
 
 
 # exported symbol -> (restype, argtypes)

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kGB) void gemm_nt_kernel(const GemmArgs g) {
 // ---- network pieces -------------------------------------------------------
 
 struct MlpDims {
-    int n_hidden, width, n_out, n_freq, n_feat, n_out_pad;
+    int n_hidden, width, n_out, n_freq, n_feat, n_out_pad, loss;
     int L;                              // number of linear layers
     int in_of(int l) const { return l == 0 ? n_feat : width; }
     int out_of(int l) const { return l == L - 1 ? n_out : width; }
@@ -173,6 +173,8 @@ static int dims_of(const sdirt_mlp_desc* d, MlpDims* m) {
         return SDIRT_EINVAL;
     if (!(d->x_half > 0) || !(d->y_half > 0) || !(d->iv_hi > d->iv_lo) || !(d->lam_hi > d->lam_lo))
         return SDIRT_EINVAL;
+    if (d->loss != SDIRT_LOSS_L2MAX && d->loss != SDIRT_LOSS_KL) return SDIRT_EINVAL;
+    m->loss = d->loss;
     m->n_hidden = d->n_hidden;
     m->width = d->width;
     m->n_out = d->n_out;
@@ -298,6 +300,7 @@ __global__ void encode_kernel(const EncArgs a) {
 struct SoftArgs {
     int B, n_out, n_out_pad;
     float inv_batch;
+    int kl;                  // Kullback-Leibler loss instead of max-scaled L2
     const float* logits;
     const float* target;     // null: inference
     void* out;               // inference output [B][n_out] (f32 or bf16) or null
@@ -342,6 +345,31 @@ __global__ __launch_bounds__(256) void softmax_loss_kernel(const SoftArgs a) {
         return;
     }
     const float* t = a.target + (size_t)b * a.n_out;
+    if (a.kl) {
+        // KL(t || p) = sum_i t_i (log t_i - log p_i); d/dz_i = p_i sum(t) - t_i
+        const float lse = mx + __logf(sum);
+        float lsum = 0.f, ts = 0.f;
+        for (int i = threadIdx.x; i < a.n_out; i += blockDim.x) {
+            const float ti = t[i];
+            ts += ti;
+            if (ti > 0.f) lsum += ti * (__logf(ti) - (z[i] - lse));
+        }
+        lsum = block_reduce(lsum, red, false);
+        ts = block_reduce(ts, red, false);
+        if (threadIdx.x == 0) atomicAdd(a.loss, lsum * a.inv_batch);
+        for (int i = threadIdx.x; i < a.n_out_pad; i += blockDim.x) {
+            float g = 0.f;
+            if (i < a.n_out) {
+                const float p = __expf(z[i] - mx) * inv;
+                g = (p * ts - t[i]) * a.inv_batch;
+                a.dz[(size_t)b * a.n_out + i] = g;
+            }
+            const bf16_t gb = f2bf(g);
+            a.dzb[(size_t)b * a.n_out_pad + i] = gb;
+            a.dzT[(size_t)i * a.B + b] = gb;
+        }
+        return;
+    }
     float tm = 0.f;
     for (int i = threadIdx.x; i < a.n_out; i += blockDim.x) tm = fmaxf(tm, t[i]);
     tm = block_reduce(tm, red, true);
@@ -468,6 +496,7 @@ static void backward_rows(const MlpDims& m, const MlpWs& w, const float* params,
     SoftArgs s;
     std::memset(&s, 0, sizeof(s));
     s.B = B; s.n_out = m.n_out; s.n_out_pad = m.n_out_pad; s.inv_batch = 1.f / B;
+    s.kl = m.loss == SDIRT_LOSS_KL;
     s.logits = w.logits; s.target = target; s.dz = w.dz; s.dzb = w.dzb; s.dzT = w.dzT;
     s.loss = w.loss;
     hipLaunchKernelGGL(softmax_loss_kernel, dim3(B), dim3(256), 0, st, s);

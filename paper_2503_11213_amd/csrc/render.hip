@@ -8,9 +8,8 @@
 // renders one pixel at a time: its 64 lanes stride over the ks*ks taps, so
 // every PSF row segment is read from HBM (dense source) or L2/MALL (bank
 // source) by contiguous lanes, each PSF value exactly once; the 2C partial
-// sums are reduced across the wave at the end.  The image adjoint mirrors
-// it: per tap the lanes scatter K * grad into the LDS halo with LDS atomics,
-// and the halo is folded back (clamped indices) with global atomics.
+// sums are reduced across the wave at the end.  The image adjoint gathers
+// per halo position instead (see render_bwd_kernel).
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
@@ -50,34 +49,41 @@ __device__ inline float wsum(float v) {
     return v;
 }
 
-__device__ inline float load_psf(const void* base, size_t idx, int bf16) {
-    if (bf16) {
-        const uint16_t u = reinterpret_cast<const uint16_t*>(base)[idx];
-        return __uint_as_float(((uint32_t)u) << 16);
-    }
-    return reinterpret_cast<const float*>(base)[idx];
+// Generic-path variants: dense kernels shared by all channels (Cp = 1),
+// dense per-channel kernels, traced bank (nearest entry, mirrored).
+enum RenderMode { kModeShared = 0, kModeDense = 1, kModeBank = 2 };
+
+template <bool BF16> struct PsfT { typedef float type; };
+template <> struct PsfT<true> { typedef uint16_t type; };
+
+template <bool BF16>
+__device__ inline float psf_at(const typename PsfT<BF16>::type* p, int idx) {
+    if constexpr (BF16) return __uint_as_float(((uint32_t)p[idx]) << 16);
+    else return p[idx];
 }
 
-// Kernel addressing of one output pixel: element offset of channel c / side
-// s, and the bank mirrors (side swap folded into the offsets).
-template <int NC>
+// Kernels of one output pixel: a pointer per channel c and side s (wave
+// uniform), and the bank mirrors (the side swap folded into the pointers).
+template <int NC, bool BF16>
 struct PixelKernel {
-    size_t base[NC][2];
+    const typename PsfT<BF16>::type* ptr[NC][2];
     int flip_x, flip_y;
 };
 
-template <int NC>
+template <int NC, int MODE, bool BF16>
 __device__ inline void pixel_kernel(const RenderArgs& A, int n, int y, int x,
-                                    PixelKernel<NC>* pk) {
+                                    PixelKernel<NC, BF16>* pk) {
+    typedef typename PsfT<BF16>::type T;
+    const T* psf = reinterpret_cast<const T*>(A.psf);
     const int kk = A.ks * A.ks;
-    if (A.source == SDIRT_SRC_DENSE) {
+    if (MODE != kModeBank) {
         const size_t pix = ((size_t)n * A.H + y) * A.W + x;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const int cp = A.Cp == 1 ? 0 : c;
+            const int cp = MODE == kModeShared ? 0 : c;
 #pragma unroll
             for (int s = 0; s < 2; ++s)
-                pk->base[c][s] = ((pix * A.Cp + cp) * 2 + s) * kk;
+                pk->ptr[c][s] = psf + ((pix * A.Cp + cp) * 2 + s) * kk;
         }
         pk->flip_x = 0;
         pk->flip_y = 0;
@@ -98,7 +104,7 @@ __device__ inline void pixel_kernel(const RenderArgs& A, int n, int y, int x,
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int ss = pk->flip_x ? 1 - s : s;
-                pk->base[c][s] = (e * 2 + ss) * kk;
+                pk->ptr[c][s] = psf + (e * 2 + ss) * kk;
             }
         }
     }
@@ -117,7 +123,7 @@ __device__ inline void stage_halo(const RenderArgs& A, int n, int y0, int x0,
     }
 }
 
-template <int NC>
+template <int NC, int MODE, bool BF16>
 __global__ __launch_bounds__(kRBlock) void render_fwd_kernel(const RenderArgs A) {
     extern __shared__ float halo[];
     const int ks = A.ks, kk = ks * ks;
@@ -133,8 +139,8 @@ __global__ __launch_bounds__(kRBlock) void render_fwd_kernel(const RenderArgs A)
     for (int p = wave; p < kTH * kTW; p += kWaves) {
         const int y = y0 + p / kTW, x = x0 + p % kTW;
         if (y >= A.H || x >= A.W) continue;
-        PixelKernel<NC> pk;
-        pixel_kernel<NC>(A, n, y, x, &pk);
+        PixelKernel<NC, BF16> pk;
+        pixel_kernel<NC, MODE, BF16>(A, n, y, x, &pk);
         float acc[2][NC];
 #pragma unroll
         for (int s = 0; s < 2; ++s)
@@ -142,14 +148,15 @@ __global__ __launch_bounds__(kRBlock) void render_fwd_kernel(const RenderArgs A)
             for (int c = 0; c < NC; ++c) acc[s][c] = 0.f;
         const int ly = y - y0 + ks - 1, lx = x - x0 + ks - 1;
         int i = lane / ks, j = lane % ks;
+#pragma unroll 4
         for (int t = lane; t < kk; t += 64) {
-            const int si = pk.flip_y ? ks - 1 - i : i;
-            const int sj = pk.flip_x ? ks - 1 - j : j;
+            const int si = (MODE == kModeBank && pk.flip_y) ? ks - 1 - i : i;
+            const int sj = (MODE == kModeBank && pk.flip_x) ? ks - 1 - j : j;
             const int st = si * ks + sj;
             const int hoff = (ly - i) * hw + (lx - j);
-            if (A.Cp == 1 && A.source == SDIRT_SRC_DENSE) {
-                const float kl = load_psf(A.psf, pk.base[0][0] + st, A.bf16);
-                const float kr = load_psf(A.psf, pk.base[0][1] + st, A.bf16);
+            if (MODE == kModeShared) {
+                const float kl = psf_at<BF16>(pk.ptr[0][0], st);
+                const float kr = psf_at<BF16>(pk.ptr[0][1], st);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const float v = halo[c * hh * hw + hoff];
@@ -157,13 +164,17 @@ __global__ __launch_bounds__(kRBlock) void render_fwd_kernel(const RenderArgs A)
                     acc[1][c] = fmaf(kr, v, acc[1][c]);
                 }
             } else {
+                float kl[NC], kr[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    kl[c] = psf_at<BF16>(pk.ptr[c][0], st);
+                    kr[c] = psf_at<BF16>(pk.ptr[c][1], st);
+                }
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const float v = halo[c * hh * hw + hoff];
-                    const float kl = load_psf(A.psf, pk.base[c][0] + st, A.bf16);
-                    const float kr = load_psf(A.psf, pk.base[c][1] + st, A.bf16);
-                    acc[0][c] = fmaf(kl, v, acc[0][c]);
-                    acc[1][c] = fmaf(kr, v, acc[1][c]);
+                    acc[0][c] = fmaf(kl[c], v, acc[0][c]);
+                    acc[1][c] = fmaf(kr[c], v, acc[1][c]);
                 }
             }
             i += di;
@@ -181,66 +192,86 @@ __global__ __launch_bounds__(kRBlock) void render_fwd_kernel(const RenderArgs A)
     }
 }
 
-template <int NC>
+// Image adjoint as a gather: a thread owns halo positions of the tile (the
+// clamped image pixels its 8 x 8 output pixels read) and, looping over those
+// output pixels, accumulates K[tap] * grad for the one tap of each pixel that
+// lands on its position.  Every kernel value is read once, by contiguous
+// lanes along kernel rows, with no LDS traffic and no LDS atomics; the
+// accumulated halo is folded onto the clamped image pixels with global
+// atomics (neighbouring tiles overlap there).
+constexpr int kGPer = 10;  // halo positions per thread per pass
+
+template <int NC, int MODE, bool BF16>
 __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A) {
-    extern __shared__ float halo[];
-    const int ks = A.ks, kk = ks * ks;
-    const int hh = kTH + ks - 1, hw = kTW + ks - 1;
+    const int ks = A.ks;
+    const int hh = kTH + ks - 1, hw = kTW + ks - 1, nh = hh * hw;
     const int tile = blockIdx.x;
     const int n = tile / (A.tiles_x * A.tiles_y);
     const int rem = tile - n * A.tiles_x * A.tiles_y;
     const int y0 = (rem / A.tiles_x) * kTH, x0 = (rem % A.tiles_x) * kTW;
-    for (int e = threadIdx.x; e < NC * hh * hw; e += kRBlock) halo[e] = 0.f;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int di = 64 / ks, dj = 64 % ks;
-    for (int p = wave; p < kTH * kTW; p += kWaves) {
-        const int y = y0 + p / kTW, x = x0 + p % kTW;
-        if (y >= A.H || x >= A.W) continue;
-        PixelKernel<NC> pk;
-        pixel_kernel<NC>(A, n, y, x, &pk);
-        float g[2][NC];
+    const int tid = threadIdx.x;
+    for (int base = 0; base < nh; base += kRBlock * kGPer) {
+        int rr[kGPer], qq[kGPer];
+        float acc[kGPer][NC];
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < kGPer; ++k) {
+            const int e = base + k * kRBlock + tid;
+            rr[k] = e < nh ? e / hw : -(1 << 20);    // out of range: no tap matches
+            qq[k] = e < nh ? e - rr[k] * hw : 0;
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
-                g[s][c] = A.gout[(((size_t)n * 2 * NC + s * NC + c) * A.H + y) * A.W + x];
-        const int ly = y - y0 + ks - 1, lx = x - x0 + ks - 1;
-        int i = lane / ks, j = lane % ks;
-        for (int t = lane; t < kk; t += 64) {
-            const int si = pk.flip_y ? ks - 1 - i : i;
-            const int sj = pk.flip_x ? ks - 1 - j : j;
-            const int st = si * ks + sj;
-            const int hoff = (ly - i) * hw + (lx - j);
-            if (A.Cp == 1 && A.source == SDIRT_SRC_DENSE) {
-                const float kl = load_psf(A.psf, pk.base[0][0] + st, A.bf16);
-                const float kr = load_psf(A.psf, pk.base[0][1] + st, A.bf16);
+            for (int c = 0; c < NC; ++c) acc[k][c] = 0.f;
+        }
+        for (int p = 0; p < kTH * kTW; ++p) {
+            const int y = y0 + p / kTW, x = x0 + p % kTW;
+            if (y >= A.H || x >= A.W) continue;
+            PixelKernel<NC, BF16> pk;
+            pixel_kernel<NC, MODE, BF16>(A, n, y, x, &pk);
+            float g[2][NC];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
-                    atomicAdd(&halo[c * hh * hw + hoff], kl * g[0][c] + kr * g[1][c]);
-            } else {
+                    g[s][c] = A.gout[(((size_t)n * 2 * NC + s * NC + c) * A.H + y) * A.W + x];
+            const int ly = y - y0 + ks - 1, lx = x - x0 + ks - 1;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const float kl = load_psf(A.psf, pk.base[c][0] + st, A.bf16);
-                    const float kr = load_psf(A.psf, pk.base[c][1] + st, A.bf16);
-                    atomicAdd(&halo[c * hh * hw + hoff], kl * g[0][c] + kr * g[1][c]);
+            for (int k = 0; k < kGPer; ++k) {
+                // positions outside this pixel's taps load tap 0 and add
+                // nothing: the loads stay unconditional so that all of them
+                // are in flight together
+                const int i = ly - rr[k], j = lx - qq[k];
+                const bool hit = (unsigned)i < (unsigned)ks && (unsigned)j < (unsigned)ks;
+                const int si = (MODE == kModeBank && pk.flip_y) ? ks - 1 - i : i;
+                const int sj = (MODE == kModeBank && pk.flip_x) ? ks - 1 - j : j;
+                const int st = hit ? si * ks + sj : 0;
+                if (MODE == kModeShared) {
+                    float kl = psf_at<BF16>(pk.ptr[0][0], st);
+                    float kr = psf_at<BF16>(pk.ptr[0][1], st);
+                    kl = hit ? kl : 0.f;
+                    kr = hit ? kr : 0.f;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        acc[k][c] = fmaf(kl, g[0][c], fmaf(kr, g[1][c], acc[k][c]));
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        float kl = psf_at<BF16>(pk.ptr[c][0], st);
+                        float kr = psf_at<BF16>(pk.ptr[c][1], st);
+                        kl = hit ? kl : 0.f;
+                        kr = hit ? kr : 0.f;
+                        acc[k][c] = fmaf(kl, g[0][c], fmaf(kr, g[1][c], acc[k][c]));
+                    }
                 }
             }
-            i += di;
-            j += dj;
-            if (j >= ks) { j -= ks; ++i; }
         }
-    }
-    __syncthreads();
-    for (int c = 0; c < NC; ++c) {
-        float* gi = A.gimg + ((size_t)n * NC + c) * A.H * A.W;
-        for (int e = threadIdx.x; e < hh * hw; e += kRBlock) {
-            const float v = halo[c * hh * hw + e];
-            if (v == 0.f) continue;
-            const int r = e / hw, q = e - r * hw;
-            const int yy = min(max(y0 - A.pad + r, 0), A.H - 1);
-            const int xx = min(max(x0 - A.pad + q, 0), A.W - 1);
-            atomicAdd(&gi[(size_t)yy * A.W + xx], v);
+#pragma unroll
+        for (int k = 0; k < kGPer; ++k) {
+            if (rr[k] < 0) continue;
+            const int yy = min(max(y0 - A.pad + rr[k], 0), A.H - 1);
+            const int xx = min(max(x0 - A.pad + qq[k], 0), A.W - 1);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (acc[k][c] != 0.f)
+                    atomicAdd(&A.gimg[(((size_t)n * NC + c) * A.H + yy) * A.W + xx], acc[k][c]);
         }
     }
 }
@@ -690,17 +721,30 @@ static int pack_render(const sdirt_render_desc* d, RenderArgs* A) {
     return SDIRT_OK;
 }
 
-template <int NC, bool BWD>
-static void launch_render(const RenderArgs& A, hipStream_t st) {
+template <int NC, bool BWD, int MODE, bool BF16>
+static void launch_render3(const RenderArgs& A, hipStream_t st) {
     const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
     const size_t shm = (size_t)NC * hh * hw * sizeof(float);
     const dim3 grid((unsigned)((long long)A.N * A.tiles_x * A.tiles_y));
     if (BWD) {
-        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bwd_kernel<NC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL(render_bwd_kernel<NC>, grid, dim3(kRBlock), shm, st, A);
+        hipLaunchKernelGGL((render_bwd_kernel<NC, MODE, BF16>), grid, dim3(kRBlock), 0, st, A);
     } else {
-        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_fwd_kernel<NC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL(render_fwd_kernel<NC>, grid, dim3(kRBlock), shm, st, A);
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_fwd_kernel<NC, MODE, BF16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL((render_fwd_kernel<NC, MODE, BF16>), grid, dim3(kRBlock), shm, st, A);
+    }
+}
+
+template <int NC, bool BWD>
+static void launch_render(const RenderArgs& A, hipStream_t st) {
+    if (A.source == SDIRT_SRC_BANK) {
+        if (A.bf16) launch_render3<NC, BWD, kModeBank, true>(A, st);
+        else launch_render3<NC, BWD, kModeBank, false>(A, st);
+    } else if (A.Cp == 1) {
+        if (A.bf16) launch_render3<NC, BWD, kModeShared, true>(A, st);
+        else launch_render3<NC, BWD, kModeShared, false>(A, st);
+    } else {
+        if (A.bf16) launch_render3<NC, BWD, kModeDense, true>(A, st);
+        else launch_render3<NC, BWD, kModeDense, false>(A, st);
     }
 }
 
@@ -709,7 +753,7 @@ static int dispatch_render(const RenderArgs& A, hipStream_t st) {
     if (A.use_fast && try_bank_fast<BWD>(A, st))
         return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
     const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
-    if ((size_t)A.C * hh * hw * sizeof(float) > 160 * 1024) return SDIRT_EUNSUPPORTED;
+    if (!BWD && (size_t)A.C * hh * hw * sizeof(float) > 160 * 1024) return SDIRT_EUNSUPPORTED;
     switch (A.C) {
         case 1: launch_render<1, BWD>(A, st); break;
         case 2: launch_render<2, BWD>(A, st); break;

@@ -225,8 +225,10 @@ def render_dp_backward(desc, psf, grad_out, depth=None, grad_img=None):
 # ---- PSF surrogate MLP ------------------------------------------------------
 
 def make_mlp_desc(n_hidden=5, width=256, n_out=2 * 33 * 33, n_freq=8, x_half=1.0,
-                  y_half=1.0, iv_lo=0.0, iv_hi=1.0, lam_lo=0.4, lam_hi=0.7):
+                  y_half=1.0, iv_lo=0.0, iv_hi=1.0, lam_lo=0.4, lam_hi=0.7,
+                  loss=abi.LOSS_L2MAX):
     d = abi.MlpDesc()
+    d.loss = int(loss)
     d.n_hidden, d.width, d.n_out, d.n_freq = int(n_hidden), int(width), int(n_out), int(n_freq)
     d.x_half, d.y_half = float(x_half), float(y_half)
     d.iv_lo, d.iv_hi = float(iv_lo), float(iv_hi)

@@ -125,3 +125,19 @@ def test_invalid_render_descs_are_rejected():
 
 def test_n_params():
     assert sdirt.n_params(configs.config2_lens()) == 8 * 13 + 1
+
+
+def test_mlp_desc_validation():
+    lib = abi.lib()
+    n = C.c_longlong()
+    d = sdirt.make_mlp_desc(n_hidden=5, width=256, n_out=2178, n_freq=8, x_half=4.5,
+                            y_half=3.0, iv_lo=2e-4, iv_hi=2e-3, lam_lo=0.486, lam_hi=0.656)
+    assert lib.sdirt_mlp_n_params(C.byref(d), C.byref(n)) == abi.OK
+    assert n.value == 839554
+    d.loss = abi.LOSS_KL
+    assert lib.sdirt_mlp_n_params(C.byref(d), C.byref(n)) == abi.OK
+    d.loss = 7
+    assert lib.sdirt_mlp_n_params(C.byref(d), C.byref(n)) == abi.EINVAL
+    d.loss = abi.LOSS_L2MAX
+    d.width = 100
+    assert lib.sdirt_mlp_n_params(C.byref(d), C.byref(n)) == abi.EINVAL

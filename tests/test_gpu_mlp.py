@@ -15,8 +15,9 @@ NORM = dict(x_half=4.5024, y_half=3.0016, iv_lo=1 / 5000, iv_hi=1 / 500, lam_lo=
 REL = 1e-2
 
 
-def _desc(n_out=2 * 33 * 33, width=256, n_hidden=5):
-    return sdirt.make_mlp_desc(n_hidden=n_hidden, width=width, n_out=n_out, n_freq=8, **NORM)
+def _desc(n_out=2 * 33 * 33, width=256, n_hidden=5, loss=abi.LOSS_L2MAX):
+    return sdirt.make_mlp_desc(n_hidden=n_hidden, width=width, n_out=n_out, n_freq=8, loss=loss,
+                               **NORM)
 
 
 def _params(widths, seed=0):
@@ -66,21 +67,24 @@ def test_forward_matches_bf16_mirror(B, ws):
     assert _rel_l2(pb, ref) <= REL
 
 
-def test_gradients_match_bf16_mirror():
+@pytest.mark.parametrize("loss", ["l2max", "kl"])
+def test_gradients_match_bf16_mirror(loss):
     widths = [64, 256, 256, 256, 256, 256, 2178]
     layers, flat = _params(widths, 2)
     B = 256
     x = _inputs(B, 3)
     t = _targets(B, 2178, 4)
-    d = _desc()
+    t[:, :100] = 0.0
+    t /= t.sum(axis=1, keepdims=True)
+    d = _desc(loss=abi.LOSS_KL if loss == "kl" else abi.LOSS_L2MAX)
     ws_t = sdirt.mlp_workspace(d, B)
-    g, loss = sdirt.mlp_backward(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(),
+    g, lval = sdirt.mlp_backward(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(),
                                  torch.from_numpy(t).cuda(), ws_t)
     g = g.cpu().numpy()
     P = _oracle_params(layers)
     p, cache = M.forward(P, x.astype(np.float64), NORM, bf16=True)
-    ref = M.backward(P, p, cache, t.astype(np.float64), bf16=True)
-    assert loss.item() == pytest.approx(M.loss(p, t.astype(np.float64)), rel=1e-3)
+    ref = M.backward(P, p, cache, t.astype(np.float64), bf16=True, kind=loss)
+    assert lval.item() == pytest.approx(M.loss(p, t.astype(np.float64), kind=loss), rel=1e-3)
     off = 0
     for (W, b), (gW, gb) in zip(layers, ref):
         nW = W.size

@@ -133,3 +133,44 @@ def test_bank_register_blocked_path(ks):
     gi = sdirt.render_dp_backward(desc, bt, torch.from_numpy(g).cuda(), depth=dt)
     gref = R.render_bank_adjoint(g, bank, dmap, radii, iv, loc, ps)
     assert _rel(gi.cpu().numpy(), gref) <= REL_TOL
+
+
+@pytest.mark.parametrize("Cp", [3, 1])
+def test_dense_adjoint_several_halo_passes(Cp):
+    # ks 41: the 48 x 48 halo of an 8 x 8 tile takes two passes of the gather
+    N, C, H, W, ks = 1, 3, 13, 21, 41
+    img, K = _dense(N, C, H, W, ks, Cp, 7)
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, psf_channels=Cp)
+    Kt = torch.from_numpy(K).cuda()
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), Kt)
+    assert _rel(out.cpu().numpy(), R.render_dense(img, K)) <= REL_TOL
+    g = np.random.default_rng(8).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, Kt, torch.from_numpy(g).cuda())
+    assert _rel(gi.cpu().numpy(), R.render_dense_adjoint(g, K)) <= REL_TOL
+
+
+def test_dense_full_size_sampled_pixels():
+    # the benchmarked dense launch: 512 x 512 RGB, per-channel 41 x 41 kernels;
+    # each sampled output (forward) or input pixel (adjoint) depends only on a
+    # (2 pad + 1)^2 neighbourhood, so the oracle runs on that crop (anchored at
+    # the image border for border pixels, where clamping folds taps)
+    N, C, H, W, ks, Cp = 1, 3, 512, 512, 41, 3
+    pad = ks // 2
+    rng = np.random.default_rng(21)
+    img = rng.random((N, C, H, W), dtype=np.float32)
+    K = rng.random((N, H, W, Cp, 2, ks, ks), dtype=np.float32)
+    g = rng.normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, psf_channels=Cp)
+    Kt = torch.from_numpy(K).cuda()
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), Kt).cpu().numpy()
+    gi = sdirt.render_dp_backward(desc, Kt, torch.from_numpy(g).cuda()).cpu().numpy()
+    del Kt
+    picks = [(0, 0), (511, 511), (0, 300), (255, 256), (100, 7), (400, 480), (37, 211)]
+    for (y, x) in picks:
+        ya = min(max(y - 2 * pad, 0), H - 4 * pad - 1)
+        xa = min(max(x - 2 * pad, 0), W - 4 * pad - 1)
+        sl = (slice(ya, ya + 4 * pad + 1), slice(xa, xa + 4 * pad + 1))
+        ref = R.render_dense(img[:, :, sl[0], sl[1]], K[:, sl[0], sl[1]])
+        gref = R.render_dense_adjoint(g[:, :, sl[0], sl[1]], K[:, sl[0], sl[1]])
+        assert _rel(out[:, :, y, x], ref[:, :, y - ya, x - xa]) <= REL_TOL, (y, x)
+        assert _rel(gi[:, :, y, x], gref[:, :, y - ya, x - xa]) <= REL_TOL, (y, x)

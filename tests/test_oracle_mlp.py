@@ -110,3 +110,30 @@ def test_bf16_rounding_matches_torch():
     ours = mlp.to_bf16(x)
     ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(ours, ref)
+
+
+def test_kl_loss_and_gradient_match_torch_library():
+    # pinned to torch's own KL divergence and soft-target cross entropy
+    widths = [64, 16, 16, 16, 16, 16, 50]
+    params = _params(widths, 11)
+    x = _inputs(6, 12)
+    t = _targets(6, 50, 13)
+    t[0, :7] = 0.0                      # empty outputs (0 log 0 = 0)
+    t /= t.sum(axis=1, keepdims=True)
+    p, cache = mlp.forward(params, x, NORM)
+    grads = mlp.backward(params, p, cache, t, kind="kl")
+    h = torch.from_numpy(mlp.encode(x, NORM))
+    tw = [(torch.tensor(W, requires_grad=True), torch.tensor(b, requires_grad=True)) for W, b in params]
+    for li, (W, b) in enumerate(tw):
+        h = torch.nn.functional.linear(h, W, b)
+        if li < len(tw) - 1:
+            h = torch.relu(h)
+    tt = torch.from_numpy(t)
+    kl = torch.nn.functional.kl_div(torch.log_softmax(h, dim=1), tt, reduction="batchmean")
+    assert mlp.loss(p, t, kind="kl") == pytest.approx(kl.item(), rel=1e-12)
+    # the cross entropy differs from the KL divergence by the target entropy only
+    ce = torch.nn.functional.cross_entropy(h, tt)
+    ce.backward()
+    for (gW, gb), (W, b) in zip(grads, tw):
+        assert np.allclose(gW, W.grad.numpy(), rtol=1e-10, atol=1e-15)
+        assert np.allclose(gb, b.grad.numpy(), rtol=1e-10, atol=1e-15)
