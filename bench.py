@@ -33,6 +33,25 @@ PEAK_HBM_GBS = 8000.0
 # pupil sampling, sensor transfer, DP split and binning.
 FLOP_SPHERE, FLOP_STOP, FLOP_RAY = 56, 10, 60
 
+# HBM bytes of one trace launch, from two rocprofv3 --pmc runs of
+# `bench.py --pmc-target` (FETCH_SIZE, then WRITE_SIZE), each scaled by what
+# the counter reads on a 1 GiB device copy in the same run.  The figure holds
+# for the kernel sources with this digest only; otherwise traffic is null.
+TRACE_SOURCES = ("paper_2503_11213_amd/csrc/device_common.hpp",
+                 "paper_2503_11213_amd/csrc/trace.hip",
+                 "paper_2503_11213_amd/csrc/pack.hpp")
+TRACE_TRAFFIC = {"sources_sha256": "4ad23acf14c46834b534f2fd6cfb0cf69fec78d2e8c23ad54ad232b65c642073",
+                 "bytes": 65710894}
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -191,7 +210,9 @@ def extras(dev, stream):
         "paper_hardware": "i7-12700K + RTX 3090 (Sec. 5.1)"}
     print("paper workload done", file=sys.stderr, flush=True)
     # 5. smartphone-like 16-surface aspheric lens: 64 x 32 x 3 PSFs, 1024^2
-    #    rays each, ks 65 (trace only; its render batch is ~10 PFLOP)
+    #    rays each, ks 65; then its render batch: 16 RGB 4032 x 3024 images
+    #    (one AiF image, four depth maps, each used four times) from that
+    #    bank, forward plus image adjoint
     lens, sensor, query = configs.config5()
     b5 = torch.empty((query.n_points, 2, 65, 65), device=dev)
     tr = lambda: sdirt.trace_dp_psf(lens, sensor, query, out=b5, stats=False)
@@ -202,6 +223,34 @@ def extras(dev, stream):
         "workload": "16-surface aspheric lens (EFL 4.3 mm, f/1.8), 6144 PSFs x 1024^2 rays, ks 65",
         "ms": t5, "psfs_per_s": query.n_points / (t5 * 1e-3),
         "rays_surfaces_per_s": query.n_points * query.n_rays * n_surf / (t5 * 1e-3)}
+    H5, W5, N5 = sensor.height_px, sensor.width_px, 16
+    img1 = torch.from_numpy(scenes.aif_blobs(H5, W5, 3, n_blobs=2000, seed=0)).to(dev)
+    imgs = img1.unsqueeze(0).expand(N5, -1, -1, -1).contiguous()
+    del img1
+    dms = [torch.from_numpy(scenes.depth_voronoi(H5, W5, 100.0, 5000.0, seed=200 + k)).to(dev)
+           for k in range(4)]
+    dmap5 = torch.stack([dms[k % 4] for k in range(N5)])
+    del dms
+    desc5, keep5 = sdirt.make_render_desc(N5, 3, H5, W5, query.ks, source=abi.SRC_BANK,
+                                          field_radii=[f[0] for f in query.fields],
+                                          inv_depths=[1.0 / d for d in query.depths],
+                                          bank_lambdas=3, lambda_of_channel=list(configs.LAMBDA_OF_RGB),
+                                          pitch=sensor.pitch)
+    o5 = torch.empty((N5, 6, H5, W5), device=dev)
+    g5 = torch.randn((N5, 6, H5, W5), device=dev)
+    gi5 = torch.empty_like(imgs)
+    rf = lambda: sdirt.render_dp(desc5, imgs, b5, depth=dmap5, out=o5)
+    rb = lambda: sdirt.render_dp_backward(desc5, b5, g5, depth=dmap5, grad_img=gi5)
+    rf()
+    rb()
+    tf, tb = timed(rf, stream, 2), timed(rb, stream, 2)
+    npx = N5 * H5 * W5
+    out["phone_lens_render"] = {
+        "workload": "16 x 4032x3024 RGB from the 6144-PSF bank (ks 65), forward + image adjoint",
+        "fwd_ms": tf, "bwd_ms": tb, "fwd_mpix_per_s": npx / (tf * 1e-3) / 1e6,
+        "fwd_tflops": npx * 4.0 * 3 * query.ks ** 2 / (tf * 1e-3) / 1e12,
+        "fwd_plus_bwd_over_fwd": (tf + tb) / tf}
+    del imgs, dmap5, o5, g5, gi5, b5
     print("phone lens done", file=sys.stderr, flush=True)
     return out
 
@@ -303,7 +352,8 @@ def main():
         "roofline": {"kernel": "trace_splat_kernel<double, box, sigmoid, float>",
                      "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": None,
+                     "traffic": (TRACE_TRAFFIC["bytes"]
+                                 if TRACE_TRAFFIC["sources_sha256"] == sources_digest() else None),
                      "flop_per_launch": flop},
         "trace": {"ms": ms_trace, "rays_surfaces_per_s": rs / (ms_trace * 1e-3),
                   "psfs_per_s": P / (ms_trace * 1e-3),
