@@ -276,33 +276,34 @@ __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A)
     }
 }
 
-// ---- bank source, register-blocked path ----------------------------------
+// ---- bank source, register-blocked paths ---------------------------------
 //
 // Neighbouring pixels mostly share one bank entry, so the bank render is a
 // sum over entries of ordinary shift-invariant convolutions restricted to the
-// pixels that use them.  A thread owns a strip of 8 horizontally adjacent
-// output pixels, a wave an 8 x 64 block, a workgroup a 32 x 64 tile whose
-// clamped image halo (one channel at a time) sits in LDS.  The wave loops
-// over the distinct entries of its block (wave-uniform); for each it runs a
-// direct convolution with the entry's kernel read through the scalar cache
-// (wave-uniform addresses), a 70-wide register window of the halo row and
-// 16 accumulators, and keeps the result for the strip pixels that use the
-// entry.  The adjoint scatters each kernel row's 1-D correlation with the
-// strip's gradients into the LDS halo (one LDS atomic per halo column, not
-// per tap) and folds the halo back with clamped global atomics.
-constexpr int kFW = 64, kFH = 32, kStrip = 8;
+// pixels that use them.  The unit of work is a strip of 8 horizontally
+// adjacent output pixels and one entry: a lane runs the direct convolution
+// of its strip with the entry's kernel (read through the scalar cache, so the
+// entry must be wave-uniform), a 72-wide register window of the image halo
+// row and 16 accumulators.
+//
+// Forward: a workgroup owns a 64 x 64 pixel tile (512 strips) and first lists
+// its (strip, entry, pixel mask) items grouped by entry, in chunks of at most
+// 64 items of one entry; its four waves then take the chunks in turn, with
+// the clamped image halo of one channel at a time in LDS.  Grouping by entry
+// over the whole tile keeps lanes busy where a wave-sized pixel block would
+// straddle several entries.
+constexpr int kStrip = 8;
+constexpr int kGT = 64;                         // grouped forward: tile side
+constexpr int kGStrips = kGT * kGT / kStrip;    // 512 strips per tile
+constexpr int kGMaxItems = 2048;                // item list capacity per batch
+constexpr int kGMaxChunks = 256;                // chunk table capacity per batch
 
-template <int KS, bool BWD = false>
-struct FastGeom {
-    // Forward: rows padded to a multiple of 4 floats (+4) for float4 window
-    // reads.  Adjoint: an odd row stride (1 mod 32) so the 8 rows x 8 strips
-    // of a wave hit distinct LDS banks (at most 2 lanes per bank) in the
-    // scatter's atomic adds.
-    static constexpr int HWF = ((kFW + KS - 1 + 3) / 4) * 4 + 4;
-    static constexpr int HWB = ((kFW + KS - 1 + 30) / 32) * 32 + 1;
-    static constexpr int HW = BWD ? HWB : HWF;
-    static constexpr int HH = kFH + KS - 1;
-    static constexpr int WIN = ((KS + kStrip - 1 + 3) / 4) * 4;   // window, float4s
+template <int KS>
+struct GroupGeom {
+    // rows padded to a multiple of 4 floats (+4) for float4 window reads
+    static constexpr int HW = ((kGT + KS - 1 + 3) / 4) * 4 + 4;
+    static constexpr int HH = kGT + KS - 1;
+    static constexpr int WIN = ((KS + kStrip - 1 + 3) / 4) * 4;   // window, floats
 };
 
 __device__ inline int wave_min_int(int v) {
@@ -323,35 +324,21 @@ __device__ inline int bank_key(const RenderArgs& A, int n, int y, int x) {
     return ((fi * A.D + di) * 2 + (X2 < 0 ? 1 : 0)) * 2 + (Y2 < 0 ? 1 : 0);
 }
 
-template <int KS>
-__device__ inline void stage_fast_halo(const RenderArgs& A, int n, int c, int y0, int x0,
-                                       float* halo) {
-    using G = FastGeom<KS>;
-    const int pad = (KS - 1) / 2;
-    const float* im = A.img + ((size_t)n * A.C + c) * A.H * A.W;
-    for (int e = threadIdx.x; e < G::HH * G::HW; e += kRBlock) {
-        const int r = e / G::HW, q = e - r * G::HW;
-        const int yy = min(max(y0 - pad + r, 0), A.H - 1);
-        const int xx = min(max(x0 - pad + q, 0), A.W - 1);
-        halo[e] = im[(size_t)yy * A.W + xx];
-    }
-}
-
 template <int KS, bool FX>
 __device__ inline void conv_strip(const float* __restrict__ kl, const float* __restrict__ kr,
-                                  bool fy, const float* halo, int ly, int hc,
+                                  bool fy, const float* halo, int hw, int ly, int hc,
                                   float accL[kStrip], float accR[kStrip]) {
-    using G = FastGeom<KS>;
+    constexpr int WIN = GroupGeom<KS>::WIN;
 #pragma unroll
     for (int q = 0; q < kStrip; ++q) { accL[q] = 0.f; accR[q] = 0.f; }
     for (int i = 0; i < KS; ++i) {
         const int si = fy ? KS - 1 - i : i;
         const float* rl = kl + si * KS;
         const float* rr = kr + si * KS;
-        float win[G::WIN];
-        const float4* src = reinterpret_cast<const float4*>(halo + (ly - i) * G::HW + hc);
+        float win[WIN];
+        const float4* src = reinterpret_cast<const float4*>(halo + (ly - i) * hw + hc);
 #pragma unroll
-        for (int m = 0; m < G::WIN / 4; ++m) {
+        for (int m = 0; m < WIN / 4; ++m) {
             const float4 v = src[m];
             win[4 * m] = v.x; win[4 * m + 1] = v.y; win[4 * m + 2] = v.z; win[4 * m + 3] = v.w;
         }
@@ -368,161 +355,162 @@ __device__ inline void conv_strip(const float* __restrict__ kl, const float* __r
     }
 }
 
-template <int KS, bool FX>
-__device__ inline void conv_strip_bwd(const float* __restrict__ kl, const float* __restrict__ kr,
-                                      bool fy, float* hgrad, int ly, int hc,
-                                      const float gL[kStrip], const float gR[kStrip]) {
-    using G = FastGeom<KS, true>;
-    for (int i = 0; i < KS; ++i) {
-        const int si = fy ? KS - 1 - i : i;
-        const float* rl = kl + si * KS;
-        const float* rr = kr + si * KS;
-        float acc[KS + kStrip - 1];
-#pragma unroll
-        for (int m = 0; m < KS + kStrip - 1; ++m) acc[m] = 0.f;
-#pragma unroll
-        for (int j = 0; j < KS; ++j) {
-            const int sj = FX ? KS - 1 - j : j;
-            const float a = rl[sj], b = rr[sj];
-#pragma unroll
-            for (int q = 0; q < kStrip; ++q)
-                acc[q - j + KS - 1] = fmaf(a, gL[q], fmaf(b, gR[q], acc[q - j + KS - 1]));
-        }
-        float* dst = hgrad + (ly - i) * G::HW + hc;
-#pragma unroll
-        for (int m = 0; m < KS + kStrip - 1; ++m) atomicAdd(&dst[m], acc[m]);
-    }
-}
-
-template <int KS, bool BWD>
+template <int KS>
 __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderArgs A,
                                                                  const float* __restrict__ bank) {
-    using G = FastGeom<KS, BWD>;
-    extern __shared__ float halo[];     // [HH][HW]
+    using G = GroupGeom<KS>;
+    extern __shared__ __align__(16) float halo[];        // [HH][HW], float4 reads
+    __shared__ int items[kGMaxItems];                    // strip | mask << 9
+    __shared__ int chunk_key[kGMaxChunks], chunk_pos[kGMaxChunks];
+    __shared__ int red[kRBlock / 64];
+    __shared__ int n_items, n_chunks;
     const int pad = (KS - 1) / 2;
     const int kk = KS * KS;
-    const int tilesx = (A.W + kFW - 1) / kFW, tilesy = (A.H + kFH - 1) / kFH;
+    const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
     const int tile = blockIdx.x;
     const int n = tile / (tilesx * tilesy);
     const int rem = tile - n * tilesx * tilesy;
-    const int y0 = (rem / tilesx) * kFH, x0 = (rem % tilesx) * kFW;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tr = wave * 8 + (lane >> 3);        // row within the tile
-    const int tc = lane & 7;                      // strip within the row
-    const int y = y0 + tr, xs = x0 + tc * kStrip;
-    const int ly = tr + KS - 1;                   // halo row of tap i = 0
-    const int hc = tc * kStrip;                   // halo column of the window start
-    int key[kStrip];
+    const int y0 = (rem / tilesx) * kGT, x0 = (rem % tilesx) * kGT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // keys of the two strips this thread lists (strip sid: row sid / 8, column block sid % 8)
+    int key[2][kStrip];
 #pragma unroll
-    for (int q = 0; q < kStrip; ++q)
-        key[q] = (y < A.H && xs + q < A.W) ? bank_key(A, n, y, xs + q) : 0x7fffffff;
-    for (int c = 0; c < A.C; ++c) {
-        const int lam = A.lam_of_c[c];
-        float gL[kStrip], gR[kStrip], resL[kStrip], resR[kStrip];
-        if (BWD) {
-            for (int e = threadIdx.x; e < G::HH * G::HW; e += kRBlock) halo[e] = 0.f;
+    for (int h = 0; h < 2; ++h) {
+        const int sid = tid + h * kRBlock;
+        const int y = y0 + (sid >> 3), xs = x0 + (sid & 7) * kStrip;
 #pragma unroll
-            for (int q = 0; q < kStrip; ++q) {
-                const bool ok = key[q] != 0x7fffffff;
-                const size_t o = ((size_t)n * 2 * A.C * A.H + y) * A.W + xs + q;
-                gL[q] = ok ? A.gout[o + (size_t)c * A.H * A.W] : 0.f;
-                gR[q] = ok ? A.gout[o + (size_t)(A.C + c) * A.H * A.W] : 0.f;
-            }
-        } else {
-            stage_fast_halo<KS>(A, n, c, y0, x0, halo);
+        for (int q = 0; q < kStrip; ++q)
+            key[h][q] = (y < A.H && xs + q < A.W) ? bank_key(A, n, y, xs + q) : 0x7fffffff;
+    }
+    unsigned done = 0;                                   // bit 8 h + q: pixel listed
 #pragma unroll
-            for (int q = 0; q < kStrip; ++q) { resL[q] = 0.f; resR[q] = 0.f; }
-        }
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < kStrip; ++q)
+            if (key[h][q] == 0x7fffffff) done |= 1u << (8 * h + q);
+    bool more = true;
+    while (more) {
+        // ---- list a batch of entries, grouped, in chunks of <= 64 items
+        if (tid == 0) { n_items = 0; n_chunks = 0; }
         __syncthreads();
-        unsigned done = 0;
-#pragma unroll
-        for (int q = 0; q < kStrip; ++q) if (key[q] == 0x7fffffff) done |= 1u << q;
         while (true) {
             int mine = 0x7fffffff;
 #pragma unroll
-            for (int q = kStrip - 1; q >= 0; --q) if (!(done & (1u << q))) mine = key[q];
-            const int k = __builtin_amdgcn_readfirstlane(wave_min_int(mine));
-            if (k == 0x7fffffff) break;
-            const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
-            const size_t base = ((size_t)fd * A.L + lam) * 2 * kk;
-            const float* kl = bank + base + (fxb ? kk : 0);
-            const float* kr = bank + base + (fxb ? 0 : kk);
-            if (BWD) {
-                float mL[kStrip], mR[kStrip];
-#pragma unroll
-                for (int q = 0; q < kStrip; ++q) {
-                    mL[q] = key[q] == k ? gL[q] : 0.f;
-                    mR[q] = key[q] == k ? gR[q] : 0.f;
-                }
-                if (fxb) conv_strip_bwd<KS, true>(kl, kr, fyb, halo, ly, hc, mL, mR);
-                else conv_strip_bwd<KS, false>(kl, kr, fyb, halo, ly, hc, mL, mR);
-            } else {
-                float aL[kStrip], aR[kStrip];
-                if (fxb) conv_strip<KS, true>(kl, kr, fyb, halo, ly, hc, aL, aR);
-                else conv_strip<KS, false>(kl, kr, fyb, halo, ly, hc, aL, aR);
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int q = 0; q < kStrip; ++q)
-                    if (key[q] == k) { resL[q] = aL[q]; resR[q] = aR[q]; }
-            }
-#pragma unroll
-            for (int q = 0; q < kStrip; ++q) if (key[q] == k) done |= 1u << q;
-        }
-        if (BWD) {
+                    if (!(done & (1u << (8 * h + q)))) mine = min(mine, key[h][q]);
+            const int wm = wave_min_int(mine);
+            if (lane == 0) red[wave] = wm;
             __syncthreads();
-            float* gi = A.gimg + ((size_t)n * A.C + c) * A.H * A.W;
-            for (int e = threadIdx.x; e < G::HH * G::HW; e += kRBlock) {
-                const int r = e / G::HW, q = e - r * G::HW;
-                if (q >= kFW + KS - 1) continue;
-                const float v = halo[e];
-                if (v == 0.f) continue;
-                const int yy = min(max(y0 - pad + r, 0), A.H - 1);
-                const int xx = min(max(x0 - pad + q, 0), A.W - 1);
-                atomicAdd(&gi[(size_t)yy * A.W + xx], v);
-            }
-        } else if (y < A.H) {
+            int k = red[0];
 #pragma unroll
-            for (int q = 0; q < kStrip; ++q) {
-                if (xs + q < A.W) {
-                    const size_t o = (((size_t)n * 2 * A.C + c) * A.H + y) * A.W + xs + q;
-                    A.out[o] = resL[q];
-                    A.out[o + (size_t)A.C * A.H * A.W] = resR[q];
+            for (int w = 1; w < kRBlock / 64; ++w) k = min(k, red[w]);
+            const int start = n_items;
+            // capacity: a batch ends before an entry that might not fit
+            const bool fits = start + kGStrips <= kGMaxItems &&
+                              n_chunks + kGStrips / 64 <= kGMaxChunks;
+            __syncthreads();
+            if (k == 0x7fffffff) { more = false; break; }
+            if (!fits) break;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                unsigned m = 0;
+#pragma unroll
+                for (int q = 0; q < kStrip; ++q)
+                    if (key[h][q] == k) m |= 1u << q;
+                if (m) {
+                    const int pos = atomicAdd(&n_items, 1);
+                    items[pos] = (tid + h * kRBlock) | (int)(m << 9);
+                    done |= m << (8 * h);
                 }
             }
+            __syncthreads();
+            if (tid == 0) {
+                for (int s0 = start; s0 < n_items; s0 += 64) {
+                    chunk_key[n_chunks] = k;
+                    chunk_pos[n_chunks] = s0 | (min(64, n_items - s0) << 16);
+                    ++n_chunks;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        const int T = n_chunks;
+        // ---- render the batch, one channel at a time
+        for (int c = 0; c < A.C; ++c) {
+            const int lam = A.lam_of_c[c];
+            const float* im = A.img + ((size_t)n * A.C + c) * A.H * A.W;
+            for (int e = tid; e < G::HH * G::HW; e += kRBlock) {
+                const int r = e / G::HW, q = e - r * G::HW;
+                const int yy = min(max(y0 - pad + r, 0), A.H - 1);
+                const int xx = min(max(x0 - pad + q, 0), A.W - 1);
+                halo[e] = im[(size_t)yy * A.W + xx];
+            }
+            __syncthreads();
+            for (int ch = wave; ch < T; ch += kRBlock / 64) {
+                const int k = __builtin_amdgcn_readfirstlane(chunk_key[ch]);
+                const int cp = __builtin_amdgcn_readfirstlane(chunk_pos[ch]);
+                const int cnt = cp >> 16, s0 = cp & 0xffff;
+                const int it = items[s0 + min(lane, cnt - 1)];
+                const int sid = it & 511;
+                const unsigned msk = lane < cnt ? (unsigned)it >> 9 : 0u;
+                const int tr = sid >> 3, tc = sid & 7;
+                const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
+                const size_t base = ((size_t)fd * A.L + lam) * 2 * kk;
+                const float* kl = bank + base + (fxb ? kk : 0);
+                const float* kr = bank + base + (fxb ? 0 : kk);
+                float aL[kStrip], aR[kStrip];
+                if (fxb) conv_strip<KS, true>(kl, kr, fyb, halo, G::HW, tr + KS - 1, tc * kStrip, aL, aR);
+                else conv_strip<KS, false>(kl, kr, fyb, halo, G::HW, tr + KS - 1, tc * kStrip, aL, aR);
+                const int y = y0 + tr, xs = x0 + tc * kStrip;
+                const size_t o = (((size_t)n * 2 * A.C + c) * A.H + y) * A.W + xs;
+#pragma unroll
+                for (int q = 0; q < kStrip; ++q) {
+                    if (msk & (1u << q)) {
+                        A.out[o + q] = aL[q];
+                        A.out[o + q + (size_t)A.C * A.H * A.W] = aR[q];
+                    }
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
-// Bank-source image adjoint without LDS atomics.  Each wave owns 8 output
-// rows x 64 columns and a private LDS halo of (KS + 7) rows; for each kernel
-// row the lane computes the 1-D correlation of its strip's gradients with
-// the kernel row (KS + 7 partial column sums), the 8 strips of a row trade
-// those partial sums through lane shuffles so that every lane owns two
-// disjoint groups of 8 halo columns, and the owner adds them with a plain
-// read-modify-write.  The four private halos are summed and folded back
-// (clamped) with global atomics once per channel.
-constexpr int kBwdHW = 129;      // private halo row stride (1 mod 32: 2 lanes per bank)
-
+// Bank-source image adjoint.  A one-wave workgroup owns a 32 x 32 pixel band
+// (128 strips) and a private LDS copy of the band's image-halo gradient
+// (under 40 KB for ks <= 65, so four such waves share a compute unit).  It
+// takes the band's entries one at a time (wave-uniform), lists the strips
+// that use the entry and processes them in chunks of 64 lanes: per kernel
+// row a lane forms the 1-D correlation of its strip's masked gradients with
+// the row (KS + 7 partial column sums) and adds them into the halo with
+// plain float4 read-modify-writes (one wave, distinct strips per chunk: no
+// two lanes touch one address in an instruction, and the kernel rows run in
+// program order).  The halo is folded onto the clamped image pixels with
+// global atomics once per channel.
+constexpr int kBR = 32, kBW = 32;                     // band rows, columns
+constexpr int kBS = kBW / kStrip;                     // strips per band row
+static_assert(kBR * kBS == 128, "two strips per lane");
 template <int KS>
-struct BwdGeom {
-    static constexpr int PR = KS + kStrip - 1;        // private halo rows
-    static constexpr int PW = PR * kBwdHW;            // floats per wave
-    static constexpr int NKX = (KS + kStrip - 1 + 7) / 8;
+struct BandGeom {
+    static constexpr int ACC = ((KS + kStrip - 1 + 3) / 4) * 4;   // partial sums, float4s
+    static constexpr int HH = kBR + KS - 1;
+    static constexpr int HWc = kBW - kStrip + ACC;                // columns touched
+    static constexpr int HW = HWc + 4;                            // row stride (16-byte rows)
 };
 
 template <int KS, bool FX>
-__device__ inline void scatter_rows(const float* __restrict__ kl, const float* __restrict__ kr,
-                                    bool fy, float* priv, int r, int o, int lane,
-                                    const float gL[kStrip], const float gR[kStrip]) {
-    using G = BwdGeom<KS>;
-    const int base_lane = lane & ~7;
+__device__ inline void scatter_strip(const float* __restrict__ kl, const float* __restrict__ kr,
+                                     bool fy, float* hgrad, int ly, int hc,
+                                     const float gL[kStrip], const float gR[kStrip]) {
+    using G = BandGeom<KS>;
     for (int i = 0; i < KS; ++i) {
         const int si = fy ? KS - 1 - i : i;
         const float* rl = kl + si * KS;
         const float* rr = kr + si * KS;
-        float acc[8 * G::NKX];
+        float acc[G::ACC];
 #pragma unroll
-        for (int m = 0; m < 8 * G::NKX; ++m) acc[m] = 0.f;
+        for (int m = 0; m < G::ACC; ++m) acc[m] = 0.f;
 #pragma unroll
         for (int j = 0; j < KS; ++j) {
             const int sj = FX ? KS - 1 - j : j;
@@ -531,97 +519,122 @@ __device__ inline void scatter_rows(const float* __restrict__ kl, const float* _
             for (int q = 0; q < kStrip; ++q)
                 acc[q - j + KS - 1] = fmaf(a, gL[q], fmaf(b, gR[q], acc[q - j + KS - 1]));
         }
-        // column 8 * o_src + m of strip o_src belongs to group o_src + m / 8
-        float gA[8], gB[8];
+        // Lanes of one band row overlap: float4 m of a strip is float4 m - 2
+        // of the next strip to the right.  LDS accesses of a wave execute in
+        // program order, so the read of float4 m + 2 is issued only after the
+        // write of float4 m (compiler barriers), and a kernel row's writes
+        // all precede the next row's reads.
+        float4* dst = reinterpret_cast<float4*>(hgrad + (ly - i) * G::HW + hc);
+        float4 cur = dst[0];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) { gA[q] = 0.f; gB[q] = 0.f; }
-#pragma unroll
-        for (int kx = 0; kx < G::NKX; ++kx) {
-            const int src = base_lane | ((o - kx) & 7);
-            const bool lowgrp = o - kx >= 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const float v = __shfl(acc[8 * kx + q], src, 64);
-                if (lowgrp) gA[q] += v; else gB[q] += v;
-            }
-        }
-        float* row = priv + (r + KS - 1 - i) * kBwdHW;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            row[8 * o + q] += gA[q];
-            row[64 + 8 * o + q] += gB[q];
+        for (int m = 0; m < G::ACC / 4; ++m) {
+            const float4 nxt = m + 1 < G::ACC / 4 ? dst[m + 1] : cur;
+            asm volatile("" ::: "memory");
+            cur.x += acc[4 * m]; cur.y += acc[4 * m + 1];
+            cur.z += acc[4 * m + 2]; cur.w += acc[4 * m + 3];
+            dst[m] = cur;
+            asm volatile("" ::: "memory");
+            cur = nxt;
         }
     }
 }
 
 template <int KS>
-__global__ __launch_bounds__(kRBlock) void render_bank_bwd_kernel(const RenderArgs A,
-                                                                const float* __restrict__ bank) {
-    using G = BwdGeom<KS>;
-    extern __shared__ float lds[];      // 4 private halos [PR][kBwdHW]
+__global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
+                                                           const float* __restrict__ bank) {
+    using G = BandGeom<KS>;
+    extern __shared__ __align__(16) float hgrad[];       // [HH][HW]
+    __shared__ int items[2 * 64];
     const int pad = (KS - 1) / 2;
     const int kk = KS * KS;
-    const int tilesx = (A.W + kFW - 1) / kFW, tilesy = (A.H + kFH - 1) / kFH;
-    const int tile = blockIdx.x;
-    const int n = tile / (tilesx * tilesy);
-    const int rem = tile - n * tilesx * tilesy;
-    const int y0 = (rem / tilesx) * kFH, x0 = (rem % tilesx) * kFW;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r = lane >> 3, o = lane & 7;
-    const int y = y0 + wave * 8 + r, xs = x0 + o * kStrip;
-    float* priv = lds + wave * G::PW;
-    int key[kStrip];
+    const int bandsx = (A.W + kBW - 1) / kBW, bandsy = (A.H + kBR - 1) / kBR;
+    const int band = blockIdx.x;
+    const int n = band / (bandsx * bandsy);
+    const int rem = band - n * bandsx * bandsy;
+    const int y0 = (rem / bandsx) * kBR, x0 = (rem % bandsx) * kBW;
+    const int lane = threadIdx.x;
+    int key[2][kStrip];
 #pragma unroll
-    for (int q = 0; q < kStrip; ++q)
-        key[q] = (y < A.H && xs + q < A.W) ? bank_key(A, n, y, xs + q) : 0x7fffffff;
+    for (int h = 0; h < 2; ++h) {
+        const int sid = lane + 64 * h;
+        const int y = y0 + sid / kBS, xs = x0 + (sid % kBS) * kStrip;
+#pragma unroll
+        for (int q = 0; q < kStrip; ++q)
+            key[h][q] = (y < A.H && xs + q < A.W) ? bank_key(A, n, y, xs + q) : 0x7fffffff;
+    }
+    for (int e = lane; e < G::HH * G::HW; e += 64) hgrad[e] = 0.f;
     for (int c = 0; c < A.C; ++c) {
         const int lam = A.lam_of_c[c];
-        for (int e = lane; e < G::PW; e += 64) priv[e] = 0.f;
-        float gL[kStrip], gR[kStrip];
-#pragma unroll
-        for (int q = 0; q < kStrip; ++q) {
-            const bool ok = key[q] != 0x7fffffff;
-            const size_t off = ((size_t)n * 2 * A.C * A.H + y) * A.W + xs + q;
-            gL[q] = ok ? A.gout[off + (size_t)c * A.H * A.W] : 0.f;
-            gR[q] = ok ? A.gout[off + (size_t)(A.C + c) * A.H * A.W] : 0.f;
-        }
         unsigned done = 0;
 #pragma unroll
-        for (int q = 0; q < kStrip; ++q) if (key[q] == 0x7fffffff) done |= 1u << q;
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < kStrip; ++q)
+                if (key[h][q] == 0x7fffffff) done |= 1u << (8 * h + q);
         while (true) {
             int mine = 0x7fffffff;
 #pragma unroll
-            for (int q = kStrip - 1; q >= 0; --q) if (!(done & (1u << q))) mine = key[q];
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < kStrip; ++q)
+                    if (!(done & (1u << (8 * h + q)))) mine = min(mine, key[h][q]);
             const int k = __builtin_amdgcn_readfirstlane(wave_min_int(mine));
             if (k == 0x7fffffff) break;
+            // list the band's strips that use entry k (at most 128)
+            int cnt = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                unsigned m = 0;
+#pragma unroll
+                for (int q = 0; q < kStrip; ++q)
+                    if (key[h][q] == k) m |= 1u << q;
+                const unsigned long long bal = __ballot(m != 0);
+                const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+                if (m) {
+                    items[cnt + pre] = (lane + 64 * h) | (int)(m << 9);
+                    done |= m << (8 * h);
+                }
+                cnt += __popcll(bal);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
             const size_t base = ((size_t)fd * A.L + lam) * 2 * kk;
             const float* kl = bank + base + (fxb ? kk : 0);
             const float* kr = bank + base + (fxb ? 0 : kk);
-            float mL[kStrip], mR[kStrip];
+            for (int s0 = 0; s0 < cnt; s0 += 64) {
+                const int it = items[s0 + min(lane, cnt - s0 - 1)];
+                const int sid = it & 127;
+                const unsigned msk = lane < cnt - s0 ? (unsigned)it >> 9 : 0u;
+                const int tr = sid / kBS, tc = sid % kBS;
+                const int y = y0 + tr, xs = x0 + tc * kStrip;
+                float gL[kStrip], gR[kStrip];
+                const size_t orow = (((size_t)n * 2 * A.C + c) * A.H + min(y, A.H - 1)) * A.W;
 #pragma unroll
-            for (int q = 0; q < kStrip; ++q) {
-                mL[q] = key[q] == k ? gL[q] : 0.f;
-                mR[q] = key[q] == k ? gR[q] : 0.f;
+                for (int q = 0; q < kStrip; ++q) {
+                    const bool on = msk & (1u << q);
+                    const size_t o = orow + min(xs + q, A.W - 1);     // in bounds even if off
+                    gL[q] = on ? A.gout[o] : 0.f;
+                    gR[q] = on ? A.gout[o + (size_t)A.C * A.H * A.W] : 0.f;
+                }
+                // lanes past the chunk's end hold a copy of its last strip:
+                // they must not take part in the read-modify-writes
+                if (lane < cnt - s0) {
+                    if (fxb) scatter_strip<KS, true>(kl, kr, fyb, hgrad, tr + KS - 1, tc * kStrip, gL, gR);
+                    else scatter_strip<KS, false>(kl, kr, fyb, hgrad, tr + KS - 1, tc * kStrip, gL, gR);
+                }
             }
-            if (fxb) scatter_rows<KS, true>(kl, kr, fyb, priv, r, o, lane, mL, mR);
-            else scatter_rows<KS, false>(kl, kr, fyb, priv, r, o, lane, mL, mR);
-#pragma unroll
-            for (int q = 0; q < kStrip; ++q) if (key[q] == k) done |= 1u << q;
+            __builtin_amdgcn_wave_barrier();
         }
+        // fold the band's halo gradient of channel c (clamped) and clear it
         __syncthreads();
-        // sum the four private halos (wave w covers tile-halo rows 8w .. 8w + PR)
         float* gi = A.gimg + ((size_t)n * A.C + c) * A.H * A.W;
-        const int HH = kFH + KS - 1, HWc = kFW + KS - 1;
-        for (int e = threadIdx.x; e < HH * HWc; e += kRBlock) {
-            const int R = e / HWc, Cc = e - R * HWc;
-            float v = 0.f;
-#pragma unroll
-            for (int w = 0; w < kRBlock / 64; ++w) {
-                const int rr = R - 8 * w;
-                if (rr >= 0 && rr < G::PR) v += lds[w * G::PW + rr * kBwdHW + Cc];
-            }
+        for (int e = lane; e < G::HH * G::HW; e += 64) {
+            const int R = e / G::HW, Cc = e - R * G::HW;
+            const float v = hgrad[e];
             if (v == 0.f) continue;
+            hgrad[e] = 0.f;
+            if (Cc >= kBW + KS - 1) continue;
             const int yy = min(max(y0 - pad + R, 0), A.H - 1);
             const int xx = min(max(x0 - pad + Cc, 0), A.W - 1);
             atomicAdd(&gi[(size_t)yy * A.W + xx], v);
@@ -632,14 +645,22 @@ __global__ __launch_bounds__(kRBlock) void render_bank_bwd_kernel(const RenderAr
 
 template <int KS, bool BWD>
 static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
-    using G = FastGeom<KS, BWD>;
-    const size_t shm = BWD ? (size_t)(kRBlock / 64) * BwdGeom<KS>::PW * sizeof(float)
-                           : (size_t)G::HH * G::HW * sizeof(float);
-    const int tilesx = (A.W + kFW - 1) / kFW, tilesy = (A.H + kFH - 1) / kFH;
-    const dim3 grid((unsigned)((long long)A.N * tilesx * tilesy));
-    auto k = BWD ? render_bank_bwd_kernel<KS> : render_bank_fast_kernel<KS, false>;
-    if (shm > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k, grid, dim3(kRBlock), shm, st, A, reinterpret_cast<const float*>(A.psf));
+    if (BWD) {
+        const size_t shm = (size_t)BandGeom<KS>::HH * BandGeom<KS>::HW * sizeof(float);
+        const int bandsx = (A.W + kBW - 1) / kBW, bandsy = (A.H + kBR - 1) / kBR;
+        const dim3 grid((unsigned)((long long)A.N * bandsx * bandsy));
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_bwd_kernel<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL(render_bank_bwd_kernel<KS>, grid, dim3(64), shm, st, A,
+                           reinterpret_cast<const float*>(A.psf));
+    } else {
+        using G = GroupGeom<KS>;
+        const size_t shm = (size_t)G::HH * G::HW * sizeof(float);
+        const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
+        const dim3 grid((unsigned)((long long)A.N * tilesx * tilesy));
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL(render_bank_fast_kernel<KS>, grid, dim3(kRBlock), shm, st, A,
+                           reinterpret_cast<const float*>(A.psf));
+    }
     return true;
 }
 

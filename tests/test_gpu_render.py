@@ -117,8 +117,9 @@ def test_bank_full_size_sampled_pixels():
 
 @pytest.mark.parametrize("ks", [21, 33])
 def test_bank_register_blocked_path(ks):
-    # window sizes with the register-blocked bank kernel; several 32 x 64
-    # tiles with ragged edges, both mirror flips, many entries per tile
+    # window sizes with the register-blocked bank kernels; several 64 x 64
+    # (forward) and 32 x 64 (adjoint) tiles with ragged edges, both mirror
+    # flips, many entries per tile
     N, C, H, W, F, D, L, ps = 2, 3, 45, 150, 6, 5, 3, 0.01
     img, bank, radii, iv, dmap = _bank_case(N, C, H, W, ks, F, D, L, ps, 9)
     loc = [2, 1, 0]
@@ -130,6 +131,30 @@ def test_bank_register_blocked_path(ks):
     ref = R.render_bank(img, bank, dmap, radii, iv, loc, ps)
     assert _rel(out.cpu().numpy(), ref) <= REL_TOL
     g = np.random.default_rng(10).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, bt, torch.from_numpy(g).cuda(), depth=dt)
+    gref = R.render_bank_adjoint(g, bank, dmap, radii, iv, loc, ps)
+    assert _rel(gi.cpu().numpy(), gref) <= REL_TOL
+
+
+def test_bank_entry_per_pixel_noise():
+    # white-noise depth: up to 8 entries per 8-pixel strip, so a 64 x 64 tile
+    # lists more (strip, entry) items than one batch holds and the forward
+    # kernel renders it in several batches
+    N, C, H, W, ks, F, D, L, ps = 1, 3, 130, 200, 21, 9, 24, 3, 0.01
+    rng = np.random.default_rng(31)
+    img = rng.uniform(0, 1, (N, C, H, W)).astype(np.float32)
+    bank = rng.uniform(0, 1, (F, D, L, 2, ks, ks)).astype(np.float32)
+    radii = np.linspace(0, np.hypot(W * ps / 2, H * ps / 2), F)
+    iv = np.linspace(1 / 5000.0, 1 / 500.0, D)
+    dmap = (1.0 / rng.uniform(1 / 5000.0, 1 / 500.0, (N, H, W))).astype(np.float32)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps)
+    bt, dt = torch.from_numpy(bank).cuda(), torch.from_numpy(dmap).cuda()
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), bt, depth=dt)
+    assert _rel(out.cpu().numpy(), R.render_bank(img, bank, dmap, radii, iv, loc, ps)) <= REL_TOL
+    g = rng.normal(size=(N, 2 * C, H, W)).astype(np.float32)
     gi = sdirt.render_dp_backward(desc, bt, torch.from_numpy(g).cuda(), depth=dt)
     gref = R.render_bank_adjoint(g, bank, dmap, radii, iv, loc, ps)
     assert _rel(gi.cpu().numpy(), gref) <= REL_TOL
