@@ -28,6 +28,7 @@ struct LensArgs {
     int stop;
     int code[kMaxS];
     double c[kMaxS];            // curvature; 1/f for IDEAL
+    double inv_c[kMaxS];        // 1/c for spheres with |c| >= 1e-6 per mm, else 0
     double tprev[kMaxS];        // distance from the previous vertex (0 for s=0)
     double semi2[kMaxS];        // squared clear semi-diameter
     double asph[kMaxAsph][6];   // conic, a4, a6, a8, a10, a12
@@ -151,6 +152,15 @@ template <> __device__ inline float sqrt_t<float>(float v) {
     return v > 0.f ? __builtin_amdgcn_sqrtf(v) : 0.f;
 }
 
+// Raw hardware approximations (~5e-8 relative in float64), for quantities
+// whose error only slows an iteration down (Newton derivatives).
+template <typename T> __device__ inline T rcp_raw(T v);
+template <> __device__ inline double rcp_raw<double>(double v) { return __builtin_amdgcn_rcp(v); }
+template <> __device__ inline float rcp_raw<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <typename T> __device__ inline T rsq_raw(T v);
+template <> __device__ inline double rsq_raw<double>(double v) { return __builtin_amdgcn_rsq(v); }
+template <> __device__ inline float rsq_raw<float>(float v) { return __builtin_amdgcn_rsqf(v); }
+
 // sqrt where a negative argument marks a ray that the caller already counts
 // as lost: the argument is clamped instead of selected on, and the result
 // for such a ray is finite and unused.
@@ -165,20 +175,33 @@ template <> __device__ inline float sqrt_live<float>(float v) {
     return __builtin_amdgcn_sqrtf(fmaxf(v, 1e-30f));
 }
 
-// Even-asphere sag and its derivative in rho = r^2.
+// Even-asphere surface constants, read once per surface.
 template <typename T>
-__device__ __forceinline__ void asphere_sag(const double* co, T c, T rho, T* sag, T* dsag,
-                                   bool* ok) {
-    const T k = (T)co[0];
-    const T arg = T(1) - (T(1) + k) * c * c * rho;
+struct Asph {
+    T c, kc2, a4, a6, a8, a10, a12;
+    __device__ Asph(const double* co, T cc)
+        : c(cc), kc2((T(1) + (T)co[0]) * cc * cc), a4((T)co[1]), a6((T)co[2]), a8((T)co[3]),
+          a10((T)co[4]), a12((T)co[5]) {}
+};
+
+// Even-asphere sag and its derivative in rho = r^2; *ok is false where the
+// conic root is imaginary.  EXACT_D: derivative from the refined 1/sqrt;
+// otherwise from the raw hardware value (for Newton steps, whose
+// convergence a 5e-8 relative error in the slope does not spoil).
+template <typename T, bool EXACT_D>
+__device__ __forceinline__ void asphere_sag(const Asph<T>& S, T rho, T* sag, T* dsag, bool* ok) {
+    const T arg = T(1) - S.kc2 * rho;
     *ok = arg >= T(0);
-    const T q = sqrt_live<T>(arg);
-    const T a4 = (T)co[1], a6 = (T)co[2], a8 = (T)co[3], a10 = (T)co[4], a12 = (T)co[5];
-    *sag = c * rho * rcp_t<T>(T(1) + q) +
-           rho * rho * (a4 + rho * (a6 + rho * (a8 + rho * (a10 + rho * a12))));
-    *dsag = T(0.5) * c * rcp_t<T>(q) +
-            rho * (T(2) * a4 + rho * (T(3) * a6 + rho * (T(4) * a8 +
-                   rho * (T(5) * a10 + rho * T(6) * a12))));
+    const T a = fmax(arg, T(1e-30));
+    const T y = rsq_raw<T>(a);
+    const T s0 = a * y;
+    const T q = fma(T(0.5) * y, fma(-s0, s0, a), s0);                 // sqrt(a)
+    const T iq = EXACT_D ? y * fma(T(-0.5) * a * y, y, T(1.5)) : y;   // 1 / sqrt(a)
+    *sag = S.c * rho * rcp_t<T>(T(1) + q) +
+           rho * rho * (S.a4 + rho * (S.a6 + rho * (S.a8 + rho * (S.a10 + rho * S.a12))));
+    *dsag = T(0.5) * S.c * iq +
+            rho * (T(2) * S.a4 + rho * (T(3) * S.a6 + rho * (T(4) * S.a8 +
+                   rho * (T(5) * S.a10 + rho * T(6) * S.a12))));
 }
 
 // Vector Snell refraction at the unit normal n (pointing along +z) with
@@ -198,15 +221,19 @@ __device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m) {
 // Sequential trace of one ray through surfaces [0, S): on return r holds
 // the vertex-local state after the last surface.  `rec(s, r)` is called
 // after each surface (hit point + refracted direction).
-// Spheres are intersected straight from the current point (the quadratic
-// c |p + t d|^2 - 2 (p_z + t d_z) = 0 in the root form F / (G + sqrt(G^2 - cF)),
-// whose discriminant does not depend on where along the ray p sits);
+// Spheres are intersected straight from the current point: the root of the
+// quadratic c t^2 - 2 G t + F = 0 (c |p + t d|^2 - 2 (p_z + t d_z) = 0), whose
+// discriminant does not depend on where along the ray p sits, in float64 as
+// (G - sqrt(G^2 - cF)) / c with 1/c from the host (absolute error about
+// eps G / |c|, below 1e-10 mm for |c| >= 1e-6 per mm), else and in float32 as
+// F / (G + sqrt(G^2 - cF));
 // aspheres, planes, the stop and ideal lenses first move the ray to the
 // vertex plane.
 // EXACT: report the first failure's code (ray-level debugging); otherwise
 // only whether the ray survived (kAlive or kMiss), which keeps the
-// bookkeeping in scalar lane masks.
-template <typename T, typename Rec, bool EXACT = true>
+// bookkeeping in scalar lane masks.  ASPH = false compiles the even-asphere
+// path out (for prescriptions without aspheres: fewer registers).
+template <typename T, typename Rec, bool EXACT = true, bool ASPH = true>
 __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
                                 Rec rec) {
     int status = kAlive;
@@ -228,7 +255,12 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
             const T G = r.dz - c * (r.x * r.dx + r.y * r.dy + r.z * r.dz);
             const T disc = G * G - c * F;
             SDIRT_FAIL(disc < T(0), kMiss);
-            const T t = F * rcp_t<T>(G + sqrt_live<T>(disc));
+            T t;
+            // (integer test of the bits: a scalar branch, no vector compare)
+            if (sizeof(T) == sizeof(double) && __double_as_longlong(L.inv_c[s]) != 0)
+                t = (G - sqrt_live<T>(disc)) * (T)L.inv_c[s];
+            else
+                t = F * rcp_t<T>(G + sqrt_live<T>(disc));
             r.x += t * r.dx;
             r.y += t * r.dy;
             r.z += t * r.dz;
@@ -240,27 +272,37 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
             r.x += tau * r.dx;
             r.y += tau * r.dy;
             r.z = T(0);
-            if (kind == SDIRT_ASPHERE) {
+            if (ASPH && kind == SDIRT_ASPHERE) {
                 const double* co = L.asph[code >> 8];
+                const Asph<T> S(co, c);
                 const T k = (T)co[0];
                 const T F = c * (r.x * r.x + r.y * r.y);
                 const T G = r.dz - c * (r.x * r.dx + r.y * r.dy);
                 const T a = c * (T(1) + k * r.dz * r.dz);
                 const T disc = G * G - a * F;
                 T delta = disc >= T(0) ? F * rcp_t<T>(G + sqrt_t<T>(disc)) : T(0);
+                // Converged when the step is below the tolerance, or (float64)
+                // below 1e-7 mm while shrinking more than 1000-fold on the
+                // previous one: Newton is then in its quadratic regime and the
+                // next step would be under r^2 |step| < 1e-13 mm (r the ratio),
+                // so that step is skipped.
                 bool conv = false, bad = false;
+                T prev = T(1e30);
                 for (int it = 0; it < 50 && !conv && !bad; ++it) {
                     const T xr = r.x + delta * r.dx;
                     const T yr = r.y + delta * r.dy;
                     T sag, dsag;
                     bool ok;
-                    asphere_sag(co, c, xr * xr + yr * yr, &sag, &dsag, &ok);
+                    asphere_sag<T, false>(S, xr * xr + yr * yr, &sag, &dsag, &ok);
                     if (!ok) { bad = true; break; }
                     const T f = delta * r.dz - sag;
                     const T fp = r.dz - dsag * T(2) * (xr * r.dx + yr * r.dy);
-                    const T step = f * rcp_t<T>(fp);
+                    const T step = f * rcp_raw<T>(fp);
                     delta -= step;
-                    conv = fabs(step) < tol_newton<T>() * (T(1) + fabs(delta));
+                    const T as = fabs(step), sc = T(1) + fabs(delta);
+                    conv = as < tol_newton<T>() * sc ||
+                           (sizeof(T) == sizeof(double) && as < T(1e-7) * sc && as < T(1e-3) * prev);
+                    prev = as;
                 }
                 SDIRT_FAIL(!conv || bad, kNewton);
                 r.x += delta * r.dx;
@@ -270,7 +312,7 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
                 SDIRT_FAIL(r2 > semi2, kClip);
                 T sag, dsag;
                 bool ok;
-                asphere_sag(co, c, r2, &sag, &dsag, &ok);
+                asphere_sag<T, true>(S, r2, &sag, &dsag, &ok);
                 T nx = T(-2) * r.x * dsag, ny = T(-2) * r.y * dsag;
                 const T inv = rsqrt_t<T>(nx * nx + ny * ny + T(1));
                 const T K = refract<T>(r, nx * inv, ny * inv, inv, (T)mu[s]);

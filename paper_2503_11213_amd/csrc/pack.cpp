@@ -13,6 +13,7 @@ int pack_lens(const Resolved& R, LensArgs* A) {
     for (int s = 0; s < R.S; ++s) {
         int slot = -1;
         A->c[s] = R.kind[s] == SDIRT_IDEAL ? 1.0 / R.focal[s] : R.c[s];
+        A->inv_c[s] = (R.kind[s] == SDIRT_SPHERE && std::fabs(R.c[s]) >= 1e-6) ? 1.0 / R.c[s] : 0.0;
         A->tprev[s] = s == 0 ? 0.0 : R.t[s - 1];
         A->semi2[s] = R.semi[s] * R.semi[s];
         if (R.kind[s] == SDIRT_ASPHERE) {

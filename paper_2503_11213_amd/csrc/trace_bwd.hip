@@ -133,11 +133,12 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
         const double a = c * (1.0 + kk * dz * dz);
         const double disc = GG * GG - a * FF;
         D = disc >= 0.0 ? FF / (GG + sqrt(disc)) : 0.0;
+        const Asph<double> SA(co, c);
         for (int it = 0; it < 50; ++it) {
             const double xr = x1 + D * dx, yr = y1 + D * dy;
             double sag, dsag;
             bool ok;
-            asphere_sag<double>(co, c, xr * xr + yr * yr, &sag, &dsag, &ok);
+            asphere_sag<double, true>(SA, xr * xr + yr * yr, &sag, &dsag, &ok);
             if (!ok) break;
             const double f = D * dz - sag;
             const double fp = dz - dsag * 2.0 * (xr * dx + yr * dy);
