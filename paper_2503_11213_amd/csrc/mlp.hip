@@ -191,6 +191,7 @@ static int feat_pad(const MlpDims& m) { return ((m.n_feat + kBK - 1) / kBK) * kB
 struct MlpWs {
     bf16_t* W[17];   // [out][in_pad]
     bf16_t* WT[17];  // [in][out_pad]
+    bf16_t* WF[17];  // fragment-major copy for the fused inference kernels
     bf16_t* H[17];   // H[0] features [B][feat_pad]; H[l] [B][width]
     bf16_t* HT[17];  // transposed [width or feat_pad][B]
     float* logits;   // [B][n_out]
@@ -220,6 +221,7 @@ static MlpWs carve(const MlpDims& m, int B, char* base) {
         const int out_pad = l == m.L - 1 ? m.n_out_pad : m.width;
         w.W[l] = (bf16_t*)take((size_t)out * in_pad * 2);
         w.WT[l] = (bf16_t*)take((size_t)in_pad * out_pad * 2);
+        w.WF[l] = (bf16_t*)take((size_t)((out + 63) / 64) * 64 * in_pad * 2);
     }
     w.H[0] = (bf16_t*)take((size_t)B * fp * 2);
     w.HT[0] = (bf16_t*)take((size_t)fp * B * 2);
@@ -254,6 +256,26 @@ __global__ void cast_weights_kernel(const float* W, int out, int in, int in_pad,
         const bf16_t b = f2bf(v);
         if (o < out) Wb[(size_t)o * in_pad + i] = b;
         WTb[(size_t)i * out_pad + o] = b;
+    }
+}
+
+// float32 master parameters -> bf16 in matrix-core fragment order for the
+// fused inference kernels: WF[((nb * KS + ks) * 64 + lane) * 8 + e] holds
+// W[16 nb + lane % 16][32 ks + 8 (lane / 16) + e] (KS = in_pad / 32), zero
+// past `out` (rows padded to a multiple of 64) and past `in`, so that one
+// B fragment of v_mfma_f32_16x16x32_bf16 is 1 KB of contiguous memory.
+__global__ void frag_weights_kernel(const float* W, int out, int in, int in_pad, int out_pad64,
+                                    bf16_t* WF) {
+    const size_t n = (size_t)out_pad64 * in_pad;
+    const int KS = in_pad / 32;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int el = (int)(e & 7);
+        const int ln = (int)((e >> 3) & 63);
+        const size_t blk = e >> 9;                      // nb * KS + ks
+        const int ks = (int)(blk % KS), nb = (int)(blk / KS);
+        const int o = 16 * nb + (ln & 15), i = 32 * ks + 8 * (ln >> 4) + el;
+        WF[e] = f2bf((o < out && i < in) ? W[(size_t)o * in + i] : 0.f);
     }
 }
 
@@ -462,6 +484,19 @@ static void cast_all(const MlpDims& m, const MlpWs& w, const float* params, hipS
     }
 }
 
+static void frag_all(const MlpDims& m, const MlpWs& w, const float* params, hipStream_t st) {
+    const int fp = feat_pad(m);
+    for (int l = 0; l < m.L; ++l) {
+        const int in = m.in_of(l), out = m.out_of(l);
+        const int in_pad = l == 0 ? fp : m.width;
+        const int out_pad64 = (out + 63) / 64 * 64;
+        const size_t n = (size_t)out_pad64 * in_pad;
+        const int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);
+        hipLaunchKernelGGL(frag_weights_kernel, dim3(blocks), dim3(256), 0, st,
+                           params + m.w_off(l), out, in, in_pad, out_pad64, w.WF[l]);
+    }
+}
+
 // forward of B rows whose inputs are x; logits left in w.logits
 static void forward_rows(const MlpDims& m, const sdirt_mlp_desc* d, const MlpWs& w,
                          const float* params, int B, const float* x, hipStream_t st,
@@ -577,7 +612,7 @@ struct FusedArgs {
     void* out;
     int out_bf16;
 };
-int launch_mlp_fused(const FusedArgs& A, hipStream_t st);
+int launch_mlp_fused(const FusedArgs& A, bf16_t* hbuf, long long chunk, hipStream_t st);
 
 int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, const float* x,
                 void* out, int out_dtype, void* workspace, int ws_batch, hipStream_t st) {
@@ -588,8 +623,8 @@ int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, 
     if (ws_batch < 64 || ws_batch % 64) return SDIRT_EINVAL;
     if (out_dtype != SDIRT_F32 && out_dtype != SDIRT_BF16) return SDIRT_EUNSUPPORTED;
     const MlpWs w = carve(m, ws_batch, (char*)workspace);
-    cast_all(m, w, params, st);
     if (m.width == 256) {
+        frag_all(m, w, params, st);
         // fused kernel: every layer and the softmax in one pass over the rows
         FusedArgs f;
         std::memset(&f, 0, sizeof(f));
@@ -600,10 +635,11 @@ int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, 
         f.iv_lo = (float)d->iv_lo; f.iv_hi = (float)d->iv_hi;
         f.lam_lo = (float)d->lam_lo; f.lam_hi = (float)d->lam_hi;
         f.x = x; f.params = params;
-        for (int l = 0; l < m.L; ++l) { f.b_off[l] = (long long)m.b_off(l); f.W[l] = w.W[l]; }
+        for (int l = 0; l < m.L; ++l) { f.b_off[l] = (long long)m.b_off(l); f.W[l] = w.WF[l]; }
         f.out = out; f.out_bf16 = out_dtype == SDIRT_BF16;
-        return launch_mlp_fused(f, st);
+        return launch_mlp_fused(f, w.H[m.n_hidden], ws_batch, st);
     }
+    cast_all(m, w, params, st);
     const size_t esz = out_dtype == SDIRT_BF16 ? 2 : 4;
     for (long long r0 = 0; r0 < n_rows; r0 += ws_batch) {
         const int B = (int)std::min<long long>(ws_batch, n_rows - r0);

@@ -1,22 +1,25 @@
-// Fused inference of the PSF surrogate MLP (Sec. 3.2, Supplement S1.4):
-// Fourier encoding, every hidden layer and the softmax output layer in one
-// kernel, so activations never leave LDS and logits never leave registers.
+// Inference of the PSF surrogate MLP (Sec. 3.2, Supplement S1.4) in two
+// kernels per chunk of rows, with every matrix product on
+// v_mfma_f32_16x16x32_bf16 (float32 accumulation).
 //
-// A workgroup of four waves owns 64 rows.  Hidden layers: the bf16
-// activations [64][256] live in LDS (double buffer); wave w computes output
-// columns [64 w, 64 w + 64) with v_mfma_f32_16x16x32_bf16, its weight
-// fragments read straight from L2 (the whole bf16 network is 1.8 MB) one
-// k-step ahead of use.  Output layer (2 ks^2 columns, tiles of 64): pass 1
-// computes each tile's logits and keeps a running (max, sum of exp) per row
-// and lane; the lanes of a row and then the four waves merge them; pass 2
-// recomputes the tiles and writes softmax probabilities (bf16 or float32).
-// The recomputation doubles the output layer's matrix work but removes the
-// float32 logit round trip through HBM.
+// Trunk: a workgroup of four waves owns 64 rows; the Fourier encoding and
+// every hidden layer run with the bf16 activations [64][256] in LDS (double
+// buffer), wave w computing output columns [64 w, 64 w + 64); the last
+// activations go to a chunk buffer in HBM (512 B per row).
+// Head: the softmax output layer (2 ks^2 columns, tiles of 64) of 64 rows,
+// two workgroups per compute unit.  Pass 1 computes each tile's logits and
+// keeps a running (max, sum of 2^z) per row and lane; the lanes of a row and
+// then the four waves merge them; pass 2 recomputes the tiles and writes
+// 2^(z - max - log2 sum) (bf16 or float32).  Recomputing doubles the output
+// layer's matrix work but keeps the float32 logits out of HBM.
+// Weights are read in matrix-core fragment order (one 1 KB contiguous piece
+// per B fragment), two k-steps ahead of use.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "../../include/sdirt.h"
 
@@ -43,75 +46,95 @@ struct FusedArgs {
     int out_bf16;
 };
 
+// float -> bf16, round to nearest even (v_cvt_pk_bf16_f32)
 __device__ inline bf16_t f2bf_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (bf16_t)(u >> 16);
+    const __bf16 h = (__bf16)f;
+    return __builtin_bit_cast(bf16_t, h);
 }
 
 __device__ inline bf16x8_t load_b8(const bf16_t* p) {
     return *reinterpret_cast<const bf16x8_t*>(p);
 }
 
-__device__ inline void merge_ms(float& m, float& s, float m2, float s2) {
-    const float mn = fmaxf(m, m2);
-    s = (m == -INFINITY ? 0.f : s * __expf(m - mn)) + (m2 == -INFINITY ? 0.f : s2 * __expf(m2 - mn));
-    m = mn;
+// Weights arrive in matrix-core fragment order (see frag_weights_kernel):
+// the B fragment of column block nb (16 outputs) and k-step ks of a layer
+// with KS k-steps is the 1 KB at WF + (nb * KS + ks) * 512 elements, lane l
+// reading its 16 bytes at offset 8 l.  One load instruction of a wave then
+// covers 8 contiguous cache lines instead of 64 scattered ones.
+__device__ inline bf16x8_t load_frag(const bf16_t* WF, int KS, int nb, int ks, int lane) {
+    return load_b8(WF + ((size_t)(nb * KS + ks) * 64 + lane) * 8);
 }
 
-// acc[i][j] = H[rows 16 i ..][0..K) x W[cols 16 j ..][0..K)^T for this wave's
-// column block; B fragments prefetched one k-step ahead.
-__device__ inline void layer_mma(const bf16_t* H, const bf16_t* W, int ldw, int K, int col0,
-                                 int n_valid, floatx4_t acc[4][4]) {
+// acc[i][j] = H[rows 16 i ..][0..K) x W[cols col0 + 16 j ..][0..K)^T, K = 32 KS,
+// with B fragments two k-steps ahead in static even/odd buffers and the
+// first products starting from zero.
+__device__ inline void frag_mma(const bf16_t* H, const bf16_t* WF, int KS, int col0,
+                                floatx4_t acc[4][4]) {
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, kg = (lane >> 4) * 8;
+    const int nb0 = col0 / 16;
+    const bf16_t* hp[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    bf16x8_t b[4], bn[4];
+    for (int i = 0; i < 4; ++i) hp[i] = H + (16 * i + r16) * kFStride + kg;
+    bf16x8_t be[4], bo[4], a[4];
     const bf16x8_t zero = {};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int n = col0 + 16 * j + r16;
-        b[j] = n < n_valid ? load_b8(W + (size_t)n * ldw + kg) : zero;
+        be[j] = load_frag(WF, KS, nb0 + j, 0, lane);
+        bo[j] = KS > 1 ? load_frag(WF, KS, nb0 + j, 1, lane) : zero;
     }
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        if (k0 + 32 < K) {
+#pragma unroll 1
+    for (int ks = 0; ks < KS; ks += 2) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int n = col0 + 16 * j + r16;
-                bn[j] = n < n_valid ? load_b8(W + (size_t)n * ldw + k0 + 32 + kg) : zero;
-            }
+        for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8_t*>(hp[i] + 32 * ks);
+        if (ks == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        a[i], be[j], floatx4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], be[j], acc[i][j], 0, 0, 0);
         }
-        bf16x8_t a[4];
+        if (ks + 2 < KS) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            a[i] = *reinterpret_cast<const bf16x8_t*>(H + (16 * i + r16) * kFStride + k0 + kg);
+            for (int j = 0; j < 4; ++j) be[j] = load_frag(WF, KS, nb0 + j, ks + 2, lane);
+        }
+        if (ks + 1 < KS) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8_t*>(hp[i] + 32 * ks + 32);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        if (k0 + 32 < K) {
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = bn[j];
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bo[j], acc[i][j], 0, 0, 0);
+            if (ks + 3 < KS) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bo[j] = load_frag(WF, KS, nb0 + j, ks + 3, lane);
+            }
         }
     }
 }
 
-__global__ __launch_bounds__(kFThreads) void mlp_fused_fwd_kernel(const FusedArgs A) {
+// Trunk: encoding and hidden layers of 64 rows of the chunk [r_begin, r_end);
+// the last hidden activations go to hout ([rows of the chunk][256] bf16).
+__global__ __launch_bounds__(kFThreads, 2) void mlp_trunk_kernel(const FusedArgs A, long long r_begin,
+                                                            long long r_end, bf16_t* hout) {
     __shared__ bf16_t H[2][kFRows * kFStride];
-    __shared__ float stat_m[4][kFRows], stat_s[4][kFRows];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g4 = (lane >> 4) * 4;
-    const long long row0 = (long long)blockIdx.x * kFRows;
+    const long long row0 = r_begin + (long long)blockIdx.x * kFRows;
     // ---- encoding: 64 rows x feat_pad features, 4 threads per row ----------
     {
         const int row = tid >> 2, part = tid & 3;     // input `part` of the row
         const long long gr = row0 + row;
         float v = 0.f;
-        if (gr < A.n_rows) {
+        if (gr < r_end) {
             const float xv = A.x[gr * 4 + part];
             if (part == 0) v = xv / A.x_half;
             else if (part == 1) v = xv / A.y_half;
@@ -136,7 +159,7 @@ __global__ __launch_bounds__(kFThreads) void mlp_fused_fwd_kernel(const FusedArg
     for (int l = 0; l < A.n_hidden; ++l) {
         const int K = l == 0 ? A.feat_pad : kFWidth;
         const int col0 = wave * 64;
-        layer_mma(H[cur], A.W[l], K, K, col0, kFWidth, acc);
+        frag_mma(H[cur], A.W[l], K / 32, col0, acc);
         const float* bias = A.params + A.b_off[l];
         bf16_t* Ho = H[1 - cur];
 #pragma unroll
@@ -152,32 +175,70 @@ __global__ __launch_bounds__(kFThreads) void mlp_fused_fwd_kernel(const FusedArg
         __syncthreads();
         cur = 1 - cur;
     }
+    // ---- last hidden activations to the chunk buffer (16-byte pieces) ------
+    for (int e = tid; e < kFRows * (kFWidth / 8); e += kFThreads) {
+        const int row = e / (kFWidth / 8), c8 = e % (kFWidth / 8);
+        if (row0 + row < r_end)
+            *reinterpret_cast<bf16x8_t*>(hout + (size_t)(row0 - r_begin + row) * kFWidth + 8 * c8) =
+                *reinterpret_cast<const bf16x8_t*>(H[cur] + row * kFStride + 8 * c8);
+    }
+}
+
+// Head: the softmax output layer of 64 rows of the chunk, from the trunk's
+// activations.  Two passes over the output tiles (the logits are recomputed
+// rather than stored); two workgroups share a compute unit.
+template <bool BF16>
+__global__ __launch_bounds__(kFThreads, 2) void mlp_head_kernel(const FusedArgs A, long long r_begin,
+                                                              long long r_end, const bf16_t* hin) {
+    __shared__ bf16_t Hs[kFRows * kFStride];
+    __shared__ float stat_m[4][kFRows], stat_s[4][kFRows];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g4 = (lane >> 4) * 4;
+    const long long row0 = r_begin + (long long)blockIdx.x * kFRows;
+    for (int e = tid; e < kFRows * (kFWidth / 8); e += kFThreads) {
+        const int row = e / (kFWidth / 8), c8 = e % (kFWidth / 8);
+        const bf16x8_t zero = {};
+        *reinterpret_cast<bf16x8_t*>(Hs + row * kFStride + 8 * c8) =
+            row0 + row < r_end
+                ? *reinterpret_cast<const bf16x8_t*>(hin + (size_t)(row0 - r_begin + row) * kFWidth + 8 * c8)
+                : zero;
+    }
+    __syncthreads();
+    floatx4_t acc[4][4];
     // ---- output layer: pass 1, running max / sum per row ---------------------
+    // Logits are carried in base 2 (z log2 e) so that every exponential is
+    // one v_exp_f32; -1e30 stands for "no column yet" (finite, so no
+    // special cases: its exponentials vanish).
+    constexpr float kL2E = 1.4426950408889634f;
+    constexpr float kNone = -1e30f;
     const int Lo = A.n_hidden;
     const bf16_t* Wo = A.W[Lo];
     const float* bo = A.params + A.b_off[Lo];
     const int ntile = (A.n_out + 63) / 64;
     float m[16], s[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) { m[k] = -INFINITY; s[k] = 0.f; }
+    for (int k = 0; k < 16; ++k) { m[k] = kNone; s[k] = 0.f; }
     for (int t = wave; t < ntile; t += 4) {
-        layer_mma(H[cur], Wo, kFWidth, kFWidth, 64 * t, A.n_out, acc);
+        frag_mma(Hs, Wo, kFWidth / 32, 64 * t, acc);
+        float bl[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = 64 * t + 16 * j + r16;
+            bl[j] = n < A.n_out ? bo[n] * kL2E : kNone;
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                float tm = -INFINITY;
+                const int k = 4 * i + r;
                 float z[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int n = 64 * t + 16 * j + r16;
-                    z[j] = n < A.n_out ? acc[i][j][r] + bo[n] : -INFINITY;
-                    tm = fmaxf(tm, z[j]);
-                }
-                float ts = 0.f;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) ts += z[j] == -INFINITY ? 0.f : __expf(z[j] - tm);
-                merge_ms(m[4 * i + r], s[4 * i + r], tm, ts);
+                for (int j = 0; j < 4; ++j) z[j] = fmaf(acc[i][j][r], kL2E, bl[j]);
+                const float mn = fmaxf(fmaxf(m[k], fmaxf(z[0], z[1])), fmaxf(z[2], z[3]));
+                // rescale the sum only when some lane of the wave raised its max
+                if (__ballot(mn > m[k])) s[k] *= __builtin_amdgcn_exp2f(m[k] - mn);
+                s[k] += (__builtin_amdgcn_exp2f(z[0] - mn) + __builtin_amdgcn_exp2f(z[1] - mn)) + (__builtin_amdgcn_exp2f(z[2] - mn) + __builtin_amdgcn_exp2f(z[3] - mn));
+                m[k] = mn;
             }
     }
     // merge over the 16 lanes holding the same rows, then over the 4 waves
@@ -187,7 +248,9 @@ __global__ __launch_bounds__(kFThreads) void mlp_fused_fwd_kernel(const FusedArg
         for (int o = 1; o < 16; o <<= 1) {
             const float m2 = __shfl_xor(m[k], o, 64);
             const float s2 = __shfl_xor(s[k], o, 64);
-            merge_ms(m[k], s[k], m2, s2);
+            const float mn = fmaxf(m[k], m2);
+            s[k] = s[k] * __builtin_amdgcn_exp2f(m[k] - mn) + s2 * __builtin_amdgcn_exp2f(m2 - mn);
+            m[k] = mn;
         }
     }
     if (r16 == 0) {
@@ -200,44 +263,65 @@ __global__ __launch_bounds__(kFThreads) void mlp_fused_fwd_kernel(const FusedArg
             }
     }
     __syncthreads();
-    float inv_s[16];
+    // per row: M + log2(S), so that p = 2^(z - M - log2 S)
+    float mls[16];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * i + g4 + r;
             float mm = stat_m[0][row], ss = stat_s[0][row];
-            for (int w = 1; w < 4; ++w) merge_ms(mm, ss, stat_m[w][row], stat_s[w][row]);
-            m[4 * i + r] = mm;
-            inv_s[4 * i + r] = ss > 0.f ? 1.f / ss : 0.f;
+            for (int w = 1; w < 4; ++w) {
+                const float m2 = stat_m[w][row], s2 = stat_s[w][row];
+                const float mn = fmaxf(mm, m2);
+                ss = ss * __builtin_amdgcn_exp2f(mm - mn) + s2 * __builtin_amdgcn_exp2f(m2 - mn);
+                mm = mn;
+            }
+            mls[4 * i + r] = ss > 0.f ? mm + __builtin_amdgcn_logf(ss) : 1e30f;
         }
     // ---- pass 2: recompute and write probabilities ---------------------------
+    typedef typename std::conditional<BF16, __bf16, float>::type OutT;
+    OutT* outp = reinterpret_cast<OutT*>(A.out);
     for (int t = wave; t < ntile; t += 4) {
-        layer_mma(H[cur], Wo, kFWidth, kFWidth, 64 * t, A.n_out, acc);
+        frag_mma(Hs, Wo, kFWidth / 32, 64 * t, acc);
+        float bl[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = 64 * t + 16 * j + r16;
-            if (n >= A.n_out) continue;
-            const float bn = bo[n];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const long long gr = row0 + 16 * i + g4 + r;
-                    if (gr >= A.n_rows) continue;
-                    const float p = __expf(acc[i][j][r] + bn - m[4 * i + r]) * inv_s[4 * i + r];
-                    if (A.out_bf16) reinterpret_cast<bf16_t*>(A.out)[gr * A.n_out + n] = f2bf_rne(p);
-                    else reinterpret_cast<float*>(A.out)[gr * A.n_out + n] = p;
-                }
+            bl[j] = n < A.n_out ? bo[n] * kL2E : 0.f;
         }
+        const bool full = 64 * t + 64 <= A.n_out;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long gr = row0 + 16 * i + g4 + r;
+                if (gr >= r_end) continue;
+                OutT* rowp = outp + gr * A.n_out + 64 * t + r16;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float p = __builtin_amdgcn_exp2f(fmaf(acc[i][j][r], kL2E, bl[j]) - mls[4 * i + r]);
+                    if (full || 64 * t + 16 * j + r16 < A.n_out) rowp[16 * j] = (OutT)p;
+                }
+            }
     }
 }
 
-int launch_mlp_fused(const FusedArgs& A, hipStream_t st) {
+int launch_mlp_fused(const FusedArgs& A, bf16_t* hbuf, long long chunk, hipStream_t st) {
     if (A.n_rows <= 0) return SDIRT_OK;
-    const long long blocks = (A.n_rows + kFRows - 1) / kFRows;
-    if (blocks > 0x7fffffffLL) return SDIRT_EUNSUPPORTED;
-    hipLaunchKernelGGL(mlp_fused_fwd_kernel, dim3((unsigned)blocks), dim3(kFThreads), 0, st, A);
+    if (chunk < kFRows) return SDIRT_EINVAL;
+    for (long long r0 = 0; r0 < A.n_rows; r0 += chunk) {
+        const long long r1 = std::min(A.n_rows, r0 + chunk);
+        const long long blocks = (r1 - r0 + kFRows - 1) / kFRows;
+        if (blocks > 0x7fffffffLL) return SDIRT_EUNSUPPORTED;
+        hipLaunchKernelGGL(mlp_trunk_kernel, dim3((unsigned)blocks), dim3(kFThreads), 0, st, A, r0, r1, hbuf);
+        if (A.out_bf16)
+            hipLaunchKernelGGL(mlp_head_kernel<true>, dim3((unsigned)blocks), dim3(kFThreads), 0, st, A, r0, r1,
+                               (const bf16_t*)hbuf);
+        else
+            hipLaunchKernelGGL(mlp_head_kernel<false>, dim3((unsigned)blocks), dim3(kFThreads), 0, st, A, r0, r1,
+                               (const bf16_t*)hbuf);
+    }
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
 }
 

@@ -151,3 +151,20 @@ def test_invalid_batch_is_rejected():
     d = _desc()
     with pytest.raises(RuntimeError):
         sdirt.mlp_workspace(d, 100)
+
+
+@pytest.mark.parametrize("n_out", [99, 64, 130])
+def test_fused_forward_output_widths(n_out):
+    # odd widths take the 2-byte bf16 store path; 64 is one exact tile; 130
+    # leaves a 2-column tail tile
+    widths = [64, 256, 256, 256, 256, 256, n_out]
+    layers, flat = _params(widths, 12)
+    x = _inputs(70, 13)
+    d = _desc(n_out=n_out)
+    ws_t = sdirt.mlp_workspace(d, 64)
+    ref, _ = M.forward(_oracle_params(layers), x.astype(np.float64), NORM, bf16=True)
+    for dt in (abi.F32, abi.BF16):
+        p = sdirt.mlp_forward(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(), ws_t,
+                              64, out_dtype=dt).float().cpu().numpy()
+        assert _rel_l2(p, ref) <= REL
+        assert np.allclose(p.sum(axis=1), 1.0, atol=2e-2 if dt == abi.BF16 else 1e-4)
