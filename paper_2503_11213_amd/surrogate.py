@@ -7,9 +7,12 @@ tracer stays the judge of the network's error.
 
     python -m paper_2503_11213_amd.surrogate [--samples N] [--steps S]
 
-traces the training set, trains, measures the held-out energy L1 against
-high-ray traces, times MLP inference against tracing at the same window
-size, renders one image through the MLP PSF map and prints one JSON line.
+traces the training set, trains (Kullback-Leibler loss by default; the
+paper's L2 loss with --loss l2max), measures the held-out energy L1 against
+high-ray traces (8192^2 rays: their own noise is ~0.1 %), the error of
+plain tracing at several ray counts against the same judge, the paper's
+per-element L1 / L2 figures, times MLP inference against tracing at the
+same window size and prints one JSON line.
 """
 
 import argparse
@@ -52,12 +55,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--judge-rays", type=int, default=2048)
-    ap.add_argument("--render", action="store_true")
+    ap.add_argument("--judge-rays", type=int, default=8192)
+    ap.add_argument("--loss", choices=["kl", "l2max"], default="kl")
     args = ap.parse_args()
     dev = torch.device("cuda", 0)
     lens, sensor, query = configs.config4()
     desc = sdirt.make_mlp_desc(n_hidden=5, width=256, n_out=2 * query.ks ** 2, n_freq=8,
+                               loss=abi.LOSS_KL if args.loss == "kl" else abi.LOSS_L2MAX,
                                **configs.config4_desc_kwargs())
     rec = {}
     # training set
@@ -94,20 +98,30 @@ def main():
                     "ms_per_step": t_train * 1e3 / args.steps,
                     "loss_first": float(trace[:10].mean()), "loss_last": float(trace[-100:].mean())}
     del targets
+    torch.cuda.empty_cache()
     # held-out error, judged by the tracer at more rays
     hpts, hx = configs.surrogate_points(args.heldout, seed=2)
     hpts_t = torch.from_numpy(hpts).to(dev)
-    judge = trace_points(lens, sensor, query, hpts_t, rays=args.judge_rays)
-    same = trace_points(lens, sensor, query, hpts_t)
+    judge = trace_points(lens, sensor, query, hpts_t, rays=args.judge_rays, chunk=4096)
     hx_t = torch.from_numpy(hx).to(dev)
     ws_inf = sdirt.mlp_workspace(desc, 4096)
     pred = sdirt.mlp_forward(desc, params, hx_t, ws_inf, 4096)
     e_mlp = energy_l1(pred, judge)
-    e_trace = energy_l1(same, judge)
+    kk2 = pred.shape[1]
     rec["heldout"] = {"points": args.heldout, "judge_rays": args.judge_rays ** 2,
                       "mlp_energy_l1_mean": float(e_mlp.mean()),
                       "mlp_energy_l1_median": float(e_mlp.median()),
-                      "trace512_energy_l1_mean": float(e_trace.mean())}
+                      # the paper's Table S3 figures: mean |p - t| and (p - t)^2 per element
+                      "mlp_l1_per_element": float((pred.float() - judge).abs().mean()),
+                      "mlp_l2_per_element": float(((pred.float() - judge) ** 2).mean()),
+                      "outputs_per_psf": kk2}
+    # plain tracing: error against the same judge and speed, per ray count
+    rec["trace_error"] = {}
+    for rays in (128, 256, 512, 1024, 2048):
+        same = trace_points(lens, sensor, query, hpts_t, rays=rays)
+        rec["trace_error"][str(rays)] = float(energy_l1(same, judge).mean())
+    print("held-out energy L1: mlp %.4f; trace %s" % (rec["heldout"]["mlp_energy_l1_mean"],
+                                                   rec["trace_error"]), flush=True)
     # throughput at ks 33: MLP inference vs tracing (512^2 rays)
     nb = 1 << 20
     xb = x_t[:nb] if x_t.shape[0] >= nb else x_t.repeat((nb + x_t.shape[0] - 1) // x_t.shape[0], 1)[:nb]
@@ -120,9 +134,33 @@ def main():
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
     flop = nb * 2.0 * sum(a * b for a, b in [(64, 256)] + [(256, 256)] * 4 + [(256, desc.n_out)])
-    rec["throughput"] = {"mlp_psfs_per_s": nb / t_inf, "mlp_tflops": flop / t_inf / 1e12,
-                         "trace_psfs_per_s": rec["dataset"]["trace_psfs_per_s"],
-                         "speedup": (nb / t_inf) / rec["dataset"]["trace_psfs_per_s"]}
+    mlp_rate = nb / t_inf
+    del out, xb, ws_big
+    # tracing speed per ray count (65536 PSFs each)
+    tpts = torch.from_numpy(configs.surrogate_points(65536, seed=5)[0]).to(dev)
+    trace_rate = {}
+    for rays in rec["trace_error"]:
+        trace_points(lens, sensor, query, tpts[:4096], rays=int(rays))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        trace_points(lens, sensor, query, tpts, rays=int(rays))
+        torch.cuda.synchronize()
+        trace_rate[rays] = 65536 / (time.perf_counter() - t0)
+    e_m = rec["heldout"]["mlp_energy_l1_mean"]
+
+    def rays_for(err):
+        ok = [int(r) for r, e in rec["trace_error"].items() if e <= err]
+        return str(min(ok)) if ok else None
+
+    r_same, r_2pc = rays_for(e_m), rays_for(0.02)
+    rec["throughput"] = {
+        "mlp_psfs_per_s": mlp_rate, "mlp_tflops": flop / t_inf / 1e12,
+        "trace_psfs_per_s": trace_rate,
+        "speedup_vs_trace_512": mlp_rate / trace_rate["512"],
+        "trace_rays_at_mlp_error": r_same,
+        "speedup_at_mlp_error": mlp_rate / trace_rate[r_same] if r_same else None,
+        "trace_rays_at_2pc": r_2pc,
+        "mlp_rate_over_trace_rate_at_2pc": mlp_rate / trace_rate[r_2pc] if r_2pc else None}
     print(json.dumps(rec), flush=True)
 
 
