@@ -40,8 +40,8 @@ FLOP_SPHERE, FLOP_STOP, FLOP_RAY = 56, 10, 60
 TRACE_SOURCES = ("paper_2503_11213_amd/csrc/device_common.hpp",
                  "paper_2503_11213_amd/csrc/trace.hip",
                  "paper_2503_11213_amd/csrc/pack.hpp")
-TRACE_TRAFFIC = {"sources_sha256": "4ad23acf14c46834b534f2fd6cfb0cf69fec78d2e8c23ad54ad232b65c642073",
-                 "bytes": 65710894}
+TRACE_TRAFFIC = {"sources_sha256": "5ac3ad86da82e0f5103ba5fa158f498bd77d7be28426d4c460a42ce357fcb0da",
+                 "bytes": 65721132}
 
 
 def sources_digest():
