@@ -175,7 +175,35 @@ def extras(dev, stream):
                            "speedup": (nrow / t_mlp) / (65536 / t_trace),
                            "mlp_tflops": flop / (t_mlp * 1e-3) / 1e12,
                            "mlp_mfma_frac": flop / (t_mlp * 1e-3) / 2.5e15}
-    del xb, ob, ws, tq
+    del xb, ob, tq
+    # 3b. the surrogate workload end to end: per-pixel MLP PSFs (bf16, one per
+    #     pixel and wavelength) for a batch of 8 images of 1680 x 1120 RGB,
+    #     each image's dense map then rendered (24.6 GB per image)
+    H4, W4, ps4 = 1120, 1680, 0.00536
+    img4 = torch.from_numpy(scenes.aif_blobs(H4, W4, 3, n_blobs=2000, seed=0)[None]).to(dev)
+    dmaps4 = [scenes.depth_voronoi(H4, W4, 500.0, 5000.0, seed=100 + k) for k in range(8)]
+    kmap = torch.empty((H4 * W4 * 3, 2178), dtype=torch.bfloat16, device=dev)
+    o4 = torch.empty((1, 6, H4, W4), device=dev)
+    desc4, keep4 = sdirt.make_render_desc(1, 3, H4, W4, 33, psf_channels=3, psf_dtype=abi.BF16)
+    lam_rgb = [configs.RGB_LAMBDAS[i] for i in configs.LAMBDA_OF_RGB]    # image channel -> wavelength
+    xin = [torch.from_numpy(configs.pixel_inputs(H4, W4, ps4, dm, lambdas=lam_rgb)).to(dev)
+           for dm in dmaps4]
+
+    def pipeline():
+        for k in range(8):
+            sdirt.mlp_forward(desc, params, xin[k], ws, 65536, out_dtype=abi.BF16, out=kmap)
+            sdirt.render_dp(desc4, img4, kmap, out=o4)
+
+    pipeline()
+    t_pipe = timed(pipeline, stream, 1)
+    t_r4 = timed(lambda: sdirt.render_dp(desc4, img4, kmap, out=o4), stream, 2)
+    out["mlp_render_batch"] = {
+        "workload": "8 x 1680x1120 RGB: per-pixel per-wavelength MLP PSFs (2x33x33, bf16) "
+                    "rendered from the dense map, image by image",
+        "ms": t_pipe, "mpix_per_s": 8 * H4 * W4 / (t_pipe * 1e-3) / 1e6,
+        "render_ms_per_image": t_r4,
+        "render_gbs": kmap.numel() * 2 / (t_r4 * 1e-3) / 1e9}
+    del kmap, xin, ws
     print("mlp done", file=sys.stderr, flush=True)
     # 4. the paper's PSF-map workload: RF50 at F/4, 512 x 768 pixels, one
     #    microlens-model DP PSF per pixel (ks 21, 4096 rays)

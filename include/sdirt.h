@@ -240,7 +240,7 @@ int sdirt_render_dp_backward(const sdirt_render_desc* desc, const void* psf,
  * 2^k pi v, k < n_freq, for the four inputs mapped to [-1, 1]), n_hidden
  * ReLU layers of `width`, a linear layer to n_out = 2 ks ks logits and a
  * softmax over all of them.  Training minimises, averaged over the batch,
- * either (loss = SDIRT_LOSS_L2MAX) the L2 loss of Eq. (5) with each
+ * either (loss = SDIRT_LOSS_L2MAX) the L2 loss of Eq. (4) with each
  * sample's squared error scaled by the largest value of its target PSF
  * (max-normalised targets), or (SDIRT_LOSS_KL) the Kullback-Leibler
  * divergence sum_i t_i log(t_i / p_i) of the prediction from the target
