@@ -35,7 +35,7 @@ struct RenderArgs {
     float t_z[SDIRT_MAX_BANK_D];       // depth thresholds (rounded up)
     int lam_of_c[4];
     int tiles_x, tiles_y;
-    int use_fast;        // bank source: register-blocked kernel when ks allows
+    int use_fast;        // bank source: grouped kernels when ks allows
     const float* img;
     const void* psf;
     const float* depth;
@@ -276,34 +276,54 @@ __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A)
     }
 }
 
-// ---- bank source, register-blocked paths ---------------------------------
+// ---- bank source, grouped paths ------------------------------------------
 //
 // Neighbouring pixels mostly share one bank entry, so the bank render is a
 // sum over entries of ordinary shift-invariant convolutions restricted to the
 // pixels that use them.  The unit of work is a strip of 8 horizontally
-// adjacent output pixels and one entry: a lane runs the direct convolution
-// of its strip with the entry's kernel (read through the scalar cache, so the
-// entry must be wave-uniform), a 72-wide register window of the image halo
-// row and 16 accumulators.
+// adjacent output pixels and one entry.
 //
 // Forward: a workgroup owns a 64 x 64 pixel tile (512 strips) and first lists
 // its (strip, entry, pixel mask) items grouped by entry, in chunks of at most
 // 64 items of one entry; its four waves then take the chunks in turn, with
 // the clamped image halo of one channel at a time in LDS.  Grouping by entry
-// over the whole tile keeps lanes busy where a wave-sized pixel block would
-// straddle several entries.
+// over the whole tile keeps the matrix-core columns busy where a fixed pixel
+// block would straddle several entries.
+//
+// A chunk runs on the fp32 matrix cores.  For kernel row i the 8 outputs of a
+// strip on both sides are the product of a 16 x P Toeplitz matrix made from
+// the row (output (side, q) against window column p holds tap q - p + KS - 1,
+// zero outside the kernel) with the strip's P-wide image window, so 16 strips
+// of one entry are the 16 columns of a chain of v_mfma_f32_16x16x4_f32.  MFMA
+// step t of lane group g = lane / 16 covers window column p = TPG g + t: a
+// lane reads TPG consecutive window floats (8-byte LDS reads) and TPG
+// consecutive taps.  Each wave stages the entry's kernel row pair in its own
+// LDS row buffer between zero margins (mirrored when the entry is flipped in
+// x), one row ahead of its use, so out-of-kernel taps read zeros.
 constexpr int kStrip = 8;
 constexpr int kGT = 64;                         // grouped forward: tile side
 constexpr int kGStrips = kGT * kGT / kStrip;    // 512 strips per tile
-constexpr int kGMaxItems = 2048;                // item list capacity per batch
-constexpr int kGMaxChunks = 256;                // chunk table capacity per batch
+constexpr int kGMaxItems = 1024;                // item list capacity per batch
+constexpr int kGMaxChunks = 64;                 // chunk table capacity per batch
+
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 template <int KS>
 struct GroupGeom {
-    // rows padded to a multiple of 4 floats (+4) for float4 window reads
+    // rows padded to a multiple of 4 floats (+4) for vector window reads
     static constexpr int HW = ((kGT + KS - 1 + 3) / 4) * 4 + 4;
     static constexpr int HH = kGT + KS - 1;
-    static constexpr int WIN = ((KS + kStrip - 1 + 3) / 4) * 4;   // window, floats
+};
+
+template <int KS>
+struct MfmaGeom {
+    static constexpr int TPG = 2 * ((KS + kStrip - 1 + 7) / 8);   // MFMA steps per kernel row
+    static constexpr int P = 4 * TPG;                              // window columns covered
+    static constexpr int PADL = P - KS;                            // zero margin before the taps
+    static constexpr int ROW = ((P + kStrip - 1 + 3) / 4) * 4;     // staged row length
+    static constexpr int NST = (2 * KS + 63) / 64;                 // staged taps per lane
+    static_assert(P >= KS + kStrip - 1, "window covers every tap of 8 outputs");
+    static_assert(kGT - kStrip + P <= GroupGeom<KS>::HW, "window inside the halo row");
 };
 
 __device__ inline int wave_min_int(int v) {
@@ -324,46 +344,98 @@ __device__ inline int bank_key(const RenderArgs& A, int n, int y, int x) {
     return ((fi * A.D + di) * 2 + (X2 < 0 ? 1 : 0)) * 2 + (Y2 < 0 ? 1 : 0);
 }
 
-template <int KS, bool FX>
-__device__ inline void conv_strip(const float* __restrict__ kl, const float* __restrict__ kr,
-                                  bool fy, const float* halo, int hw, int ly, int hc,
-                                  float accL[kStrip], float accR[kStrip]) {
-    constexpr int WIN = GroupGeom<KS>::WIN;
+// One lane's share of staging a kernel row pair: taps lane + 64 k of the
+// concatenated [left row, right row], mirrored in x when fx.
+template <int KS>
+struct RowStager {
+    int src[MfmaGeom<KS>::NST], dst[MfmaGeom<KS>::NST];
+    float v[MfmaGeom<KS>::NST];
+    __device__ void init(int lane, bool fx) {
 #pragma unroll
-    for (int q = 0; q < kStrip; ++q) { accL[q] = 0.f; accR[q] = 0.f; }
-    for (int i = 0; i < KS; ++i) {
-        const int si = fy ? KS - 1 - i : i;
-        const float* rl = kl + si * KS;
-        const float* rr = kr + si * KS;
-        float win[WIN];
-        const float4* src = reinterpret_cast<const float4*>(halo + (ly - i) * hw + hc);
-#pragma unroll
-        for (int m = 0; m < WIN / 4; ++m) {
-            const float4 v = src[m];
-            win[4 * m] = v.x; win[4 * m + 1] = v.y; win[4 * m + 2] = v.z; win[4 * m + 3] = v.w;
-        }
-#pragma unroll
-        for (int j = 0; j < KS; ++j) {
-            const int sj = FX ? KS - 1 - j : j;
-            const float a = rl[sj], b = rr[sj];
-#pragma unroll
-            for (int q = 0; q < kStrip; ++q) {
-                accL[q] = fmaf(a, win[q - j + KS - 1], accL[q]);
-                accR[q] = fmaf(b, win[q - j + KS - 1], accR[q]);
-            }
+        for (int k = 0; k < MfmaGeom<KS>::NST; ++k) {
+            const int e = min(lane + 64 * k, 2 * KS - 1);
+            const int side = e >= KS, c = e - side * KS;
+            // relative to the left row; the right kernel is the other half of
+            // the entry, after it (or before it, when mirrored)
+            src[k] = (side ? (fx ? -KS * KS : KS * KS) : 0) + (fx ? KS - 1 - c : c);
+            dst[k] = side * MfmaGeom<KS>::ROW + MfmaGeom<KS>::PADL + c;
         }
     }
+    __device__ void load(const float* __restrict__ kl, int row_ofs) {
+#pragma unroll
+        for (int k = 0; k < MfmaGeom<KS>::NST; ++k) v[k] = kl[row_ofs + src[k]];
+    }
+    __device__ void store(float* buf) const {
+#pragma unroll
+        for (int k = 0; k < MfmaGeom<KS>::NST; ++k) buf[dst[k]] = v[k];
+    }
+};
+
+// Rows of one chunk: NG groups of 16 strips, two accumulator chains each.
+template <int KS, int NG>
+__device__ inline void bank_mfma_rows(const float* __restrict__ kl, int rstep, bool fx, bool fy,
+                                      const float* halo, float* arow, int lane,
+                                      const int (&bofs)[4], floatx4_t (&out)[4]) {
+    using M = MfmaGeom<KS>;
+    using G = GroupGeom<KS>;
+    const int m = lane & 15, g = lane >> 4;
+    // A read index of step t = 0 (taps then run backwards with t)
+    const int aofs = (m >> 3) * M::ROW + M::PADL + (m & 7) + KS - 1 - M::TPG * g;
+    RowStager<KS> sg;
+    sg.init(lane, fx);
+    sg.load(kl, (fy ? KS - 1 : 0) * KS);
+    sg.store(arow);
+    floatx4_t acc[2][4];
+#pragma unroll
+    for (int u = 0; u < NG; ++u) {
+        acc[0][u] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        acc[1][u] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    int row_ofs = (fy ? KS - 1 : 0) * KS;
+    for (int i = 0; i < KS; ++i) {
+        const bool more = i + 1 < KS;
+        row_ofs += rstep;
+        if (more) sg.load(kl, row_ofs);
+        __builtin_amdgcn_sched_barrier(0);      // next row's taps in flight during this row
+        const float* ar = arow + (i & 1) * 2 * M::ROW + aofs;
+        float a[M::TPG];
+#pragma unroll
+        for (int t = 0; t < M::TPG; ++t) a[t] = ar[-t];
+        float b[NG][M::TPG];
+#pragma unroll
+        for (int u = 0; u < NG; ++u) {
+            const float2* src = reinterpret_cast<const float2*>(halo + bofs[u] - i * G::HW);
+#pragma unroll
+            for (int t = 0; t < M::TPG / 2; ++t) {
+                const float2 w = src[t];
+                b[u][2 * t] = w.x;
+                b[u][2 * t + 1] = w.y;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < M::TPG; ++t)
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+                acc[t & 1][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[u][t], acc[t & 1][u], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        // the other buffer was last read in row i - 1
+        if (more) sg.store(arow + ((i + 1) & 1) * 2 * M::ROW);
+    }
+#pragma unroll
+    for (int u = 0; u < NG; ++u) out[u] = acc[0][u] + acc[1][u];
 }
 
 template <int KS>
 __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderArgs A,
                                                                  const float* __restrict__ bank) {
     using G = GroupGeom<KS>;
-    extern __shared__ __align__(16) float halo[];        // [HH][HW], float4 reads
+    using M = MfmaGeom<KS>;
+    extern __shared__ __align__(16) float halo[];        // [HH][HW]
     __shared__ int items[kGMaxItems];                    // strip | mask << 9
     __shared__ int chunk_key[kGMaxChunks], chunk_pos[kGMaxChunks];
     __shared__ int red[kRBlock / 64];
     __shared__ int n_items, n_chunks;
+    __shared__ __align__(16) float arows[kRBlock / 64][4 * M::ROW];   // per wave: 2 buffers x 2 sides
     const int pad = (KS - 1) / 2;
     const int kk = KS * KS;
     const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
@@ -372,6 +444,8 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
     const int rem = tile - n * tilesx * tilesy;
     const int y0 = (rem / tilesx) * kGT, x0 = (rem % tilesx) * kGT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float* arow = arows[wave];
+    for (int e = lane; e < 4 * M::ROW; e += 64) arow[e] = 0.f;   // margins stay zero
     // keys of the two strips this thread lists (strip sid: row sid / 8, column block sid % 8)
     int key[2][kStrip];
 #pragma unroll
@@ -451,25 +525,39 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
                 const int k = __builtin_amdgcn_readfirstlane(chunk_key[ch]);
                 const int cp = __builtin_amdgcn_readfirstlane(chunk_pos[ch]);
                 const int cnt = cp >> 16, s0 = cp & 0xffff;
-                const int it = items[s0 + min(lane, cnt - 1)];
-                const int sid = it & 511;
-                const unsigned msk = lane < cnt ? (unsigned)it >> 9 : 0u;
-                const int tr = sid >> 3, tc = sid & 7;
                 const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
-                const size_t base = ((size_t)fd * A.L + lam) * 2 * kk;
-                const float* kl = bank + base + (fxb ? kk : 0);
-                const float* kr = bank + base + (fxb ? 0 : kk);
-                float aL[kStrip], aR[kStrip];
-                if (fxb) conv_strip<KS, true>(kl, kr, fyb, halo, G::HW, tr + KS - 1, tc * kStrip, aL, aR);
-                else conv_strip<KS, false>(kl, kr, fyb, halo, G::HW, tr + KS - 1, tc * kStrip, aL, aR);
-                const int y = y0 + tr, xs = x0 + tc * kStrip;
-                const size_t o = (((size_t)n * 2 * A.C + c) * A.H + y) * A.W + xs;
+                // left output side reads the stored right kernel when mirrored
+                const float* kl = bank + ((size_t)fd * A.L + lam) * 2 * kk + (fxb ? kk : 0);
+                int its[4], bofs[4];
 #pragma unroll
-                for (int q = 0; q < kStrip; ++q) {
-                    if (msk & (1u << q)) {
-                        A.out[o + q] = aL[q];
-                        A.out[o + q + (size_t)A.C * A.H * A.W] = aR[q];
-                    }
+                for (int u = 0; u < 4; ++u) {
+                    its[u] = items[s0 + min(16 * u + (lane & 15), cnt - 1)];
+                    const int sid = its[u] & 511;
+                    bofs[u] = ((sid >> 3) + KS - 1) * G::HW + (sid & 7) * kStrip + M::TPG * (lane >> 4);
+                }
+                const int ng = (cnt + 15) >> 4;
+                const int rstep = fyb ? -KS : KS;
+                floatx4_t acc[4];
+                switch (ng) {
+                    case 1: bank_mfma_rows<KS, 1>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
+                    case 2: bank_mfma_rows<KS, 2>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
+                    case 3: bank_mfma_rows<KS, 3>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
+                    default: bank_mfma_rows<KS, 4>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
+                }
+                // lane holds outputs q = 4 (g & 1) + r of side g >> 1 of its strip
+                const int g = lane >> 4;
+                const size_t side_ofs = (g >> 1) ? (size_t)A.C * A.H * A.W : 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (u >= ng) break;
+                    const bool valid = 16 * u + (lane & 15) < cnt;
+                    const unsigned msk = valid ? (unsigned)its[u] >> 9 : 0u;
+                    const int sid = its[u] & 511;
+                    const int y = y0 + (sid >> 3), xs = x0 + (sid & 7) * kStrip + 4 * (g & 1);
+                    const size_t o = (((size_t)n * 2 * A.C + c) * A.H + y) * A.W + xs + side_ofs;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (msk & (1u << (4 * (g & 1) + r))) A.out[o + r] = acc[u][r];
                 }
             }
             __syncthreads();

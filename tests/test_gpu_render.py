@@ -115,10 +115,10 @@ def test_bank_full_size_sampled_pixels():
     assert o1.min() >= sums.min() * (1 - 1e-5) and o1.max() <= sums.max() * (1 + 1e-5)
 
 
-@pytest.mark.parametrize("ks", [21, 33])
-def test_bank_register_blocked_path(ks):
-    # window sizes with the register-blocked bank kernels; several 64 x 64
-    # (forward) and 32 x 64 (adjoint) tiles with ragged edges, both mirror
+@pytest.mark.parametrize("ks", [21, 31, 33, 41, 63, 65])
+def test_bank_grouped_path(ks):
+    # every window size of the grouped bank kernels; several 64 x 64
+    # (forward) and 32 x 32 (adjoint) tiles with ragged edges, both mirror
     # flips, many entries per tile
     N, C, H, W, F, D, L, ps = 2, 3, 45, 150, 6, 5, 3, 0.01
     img, bank, radii, iv, dmap = _bank_case(N, C, H, W, ks, F, D, L, ps, 9)
