@@ -321,7 +321,6 @@ struct MfmaGeom {
     static constexpr int P = 4 * TPG;                              // window columns covered
     static constexpr int PADL = P - KS;                            // zero margin before the taps
     static constexpr int ROW = ((P + kStrip - 1 + 3) / 4) * 4;     // staged row length
-    static constexpr int NST = (2 * KS + 63) / 64;                 // staged taps per lane
     static_assert(P >= KS + kStrip - 1, "window covers every tap of 8 outputs");
     static_assert(kGT - kStrip + P <= GroupGeom<KS>::HW, "window inside the halo row");
 };
@@ -344,30 +343,32 @@ __device__ inline int bank_key(const RenderArgs& A, int n, int y, int x) {
     return ((fi * A.D + di) * 2 + (X2 < 0 ? 1 : 0)) * 2 + (Y2 < 0 ? 1 : 0);
 }
 
-// One lane's share of staging a kernel row pair: taps lane + 64 k of the
-// concatenated [left row, right row], mirrored in x when fx.
-template <int KS>
+// One lane's share of staging a kernel row pair into a row buffer of ROW
+// floats per side (taps from PADL on): taps lane + 64 k of the concatenated
+// [left row, right row], mirrored in x when fx.
+template <int KS, int ROW, int PADL>
 struct RowStager {
-    int src[MfmaGeom<KS>::NST], dst[MfmaGeom<KS>::NST];
-    float v[MfmaGeom<KS>::NST];
+    static constexpr int NST = (2 * KS + 63) / 64;
+    int src[NST], dst[NST];
+    float v[NST];
     __device__ void init(int lane, bool fx) {
 #pragma unroll
-        for (int k = 0; k < MfmaGeom<KS>::NST; ++k) {
+        for (int k = 0; k < NST; ++k) {
             const int e = min(lane + 64 * k, 2 * KS - 1);
             const int side = e >= KS, c = e - side * KS;
             // relative to the left row; the right kernel is the other half of
             // the entry, after it (or before it, when mirrored)
             src[k] = (side ? (fx ? -KS * KS : KS * KS) : 0) + (fx ? KS - 1 - c : c);
-            dst[k] = side * MfmaGeom<KS>::ROW + MfmaGeom<KS>::PADL + c;
+            dst[k] = side * ROW + PADL + c;
         }
     }
     __device__ void load(const float* __restrict__ kl, int row_ofs) {
 #pragma unroll
-        for (int k = 0; k < MfmaGeom<KS>::NST; ++k) v[k] = kl[row_ofs + src[k]];
+        for (int k = 0; k < NST; ++k) v[k] = kl[row_ofs + src[k]];
     }
     __device__ void store(float* buf) const {
 #pragma unroll
-        for (int k = 0; k < MfmaGeom<KS>::NST; ++k) buf[dst[k]] = v[k];
+        for (int k = 0; k < NST; ++k) buf[dst[k]] = v[k];
     }
 };
 
@@ -381,7 +382,7 @@ __device__ inline void bank_mfma_rows(const float* __restrict__ kl, int rstep, b
     const int m = lane & 15, g = lane >> 4;
     // A read index of step t = 0 (taps then run backwards with t)
     const int aofs = (m >> 3) * M::ROW + M::PADL + (m & 7) + KS - 1 - M::TPG * g;
-    RowStager<KS> sg;
+    RowStager<KS, M::ROW, M::PADL> sg;
     sg.init(lane, fx);
     sg.load(kl, (fy ? KS - 1 : 0) * KS);
     sg.store(arow);
@@ -565,64 +566,136 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
     }
 }
 
-// Bank-source image adjoint.  A one-wave workgroup owns a 32 x 32 pixel band
-// (128 strips) and a private LDS copy of the band's image-halo gradient
-// (under 40 KB for ks <= 65, so four such waves share a compute unit).  It
-// takes the band's entries one at a time (wave-uniform), lists the strips
-// that use the entry and processes them in chunks of 64 lanes: per kernel
-// row a lane forms the 1-D correlation of its strip's masked gradients with
-// the row (KS + 7 partial column sums) and adds them into the halo with
-// plain float4 read-modify-writes (one wave, distinct strips per chunk: no
-// two lanes touch one address in an instruction, and the kernel rows run in
-// program order).  The halo is folded onto the clamped image pixels with
-// global atomics once per channel.
+// Bank-source image adjoint on the matrix cores.  A one-wave workgroup owns
+// a 32 x 32 pixel band (4 strip columns of 32 rows) and a private LDS copy of
+// the band's image-halo gradient (under 40 KB for ks <= 65, so four such
+// waves share a compute unit).  It takes the band's entries one at a time and,
+// per entry, one strip column at a time: the column's strips of the entry
+// (at most 32, all in distinct rows) form one or two groups of 16.  For
+// kernel row i a group's halo contribution is the transposed Toeplitz matrix
+// of the row pair (window column p against output (side, q)) times the
+// 16 x 16 matrix of the strips' masked output gradients, in blocks of 16
+// window columns (four k-steps of v_mfma_f32_16x16x4_f32 over (side, q)).
+// Lane l then holds the block's columns 4 (l / 16) .. + 3 for strip l % 16
+// and adds them into the halo with one float4 read-modify-write.  The
+// strips of a column lie in distinct rows, so one kernel row's
+// read-modify-writes never touch one address twice and go out together,
+// interleaved with the next row's products; successive rows and columns are
+// ordered by program order (LDS operations of one wave execute in order).
+// The halo is folded onto the clamped image pixels with global atomics once
+// per channel.
 constexpr int kBR = 32, kBW = 32;                     // band rows, columns
 constexpr int kBS = kBW / kStrip;                     // strips per band row
 static_assert(kBR * kBS == 128, "two strips per lane");
+
 template <int KS>
 struct BandGeom {
-    static constexpr int ACC = ((KS + kStrip - 1 + 3) / 4) * 4;   // partial sums, float4s
+    static constexpr int NB = (KS + kStrip - 1 + 15) / 16;         // 16-column blocks of the window
+    static constexpr int WP = ((KS + kStrip - 1 + 3) / 4) * 4;     // window columns written
     static constexpr int HH = kBR + KS - 1;
-    static constexpr int HWc = kBW - kStrip + ACC;                // columns touched
-    static constexpr int HW = HWc + 4;                            // row stride (16-byte rows)
+    static constexpr int HW = kBW - kStrip + WP;                   // row stride (16-byte rows)
+    static constexpr int PADL = 16 * NB - KS;                      // staged row: zero margin
+    static constexpr int ROW = ((16 * NB + kStrip - 1 + 3) / 4) * 4;
+    static_assert(HW % 4 == 0, "float4 rows");
 };
 
-template <int KS, bool FX>
-__device__ inline void scatter_strip(const float* __restrict__ kl, const float* __restrict__ kr,
-                                     bool fy, float* hgrad, int ly, int hc,
-                                     const float gL[kStrip], const float gR[kStrip]) {
+// Kernel rows of one strip column: NG groups of 16 strips.  gb: the lane's B
+// operands (output gradients of (side, q) for the four k-steps), hofs: the
+// lane's halo offset at i = 0, act: the lane holds a strip.  Lanes with
+// nothing to add at a block (no strip, or window columns past the last tap)
+// direct that block's read-modify-write to a private float4 past the halo,
+// so every read-modify-write runs on all lanes.
+template <int KS, int NG>
+__device__ inline void band_mfma_column(const float* __restrict__ kl, int rstep, bool fx, bool fy,
+                                        float* hgrad, float* arow, int lane,
+                                        const float (&gb)[2][4], const int (&hofs)[2],
+                                        const bool (&act)[2]) {
     using G = BandGeom<KS>;
-    for (int i = 0; i < KS; ++i) {
-        const int si = fy ? KS - 1 - i : i;
-        const float* rl = kl + si * KS;
-        const float* rr = kr + si * KS;
-        float acc[G::ACC];
+    const int prow = lane & 15, g = lane >> 4;
+    // A operand of block b, k-step k: tap q + KS - 1 - p of side k >> 1,
+    // q = 4 (k & 1) + g, p = 16 b + prow
+    const int aofs = G::PADL + g + KS - 1 - prow;
+    int taddr[NG][G::NB], tstep[NG][G::NB];
 #pragma unroll
-        for (int m = 0; m < G::ACC; ++m) acc[m] = 0.f;
+    for (int u = 0; u < NG; ++u)
 #pragma unroll
-        for (int j = 0; j < KS; ++j) {
-            const int sj = FX ? KS - 1 - j : j;
-            const float a = rl[sj], b = rr[sj];
-#pragma unroll
-            for (int q = 0; q < kStrip; ++q)
-                acc[q - j + KS - 1] = fmaf(a, gL[q], fmaf(b, gR[q], acc[q - j + KS - 1]));
+        for (int b = 0; b < G::NB; ++b) {
+            const bool ok = act[u] && 16 * b + 4 * g < G::WP;
+            taddr[u][b] = ok ? hofs[u] + 16 * b : G::HH * G::HW + 4 * lane;
+            tstep[u][b] = ok ? G::HW : 0;
         }
-        // Lanes of one band row overlap: float4 m of a strip is float4 m - 2
-        // of the next strip to the right.  LDS accesses of a wave execute in
-        // program order, so the read of float4 m + 2 is issued only after the
-        // write of float4 m (compiler barriers), and a kernel row's writes
-        // all precede the next row's reads.
-        float4* dst = reinterpret_cast<float4*>(hgrad + (ly - i) * G::HW + hc);
-        float4 cur = dst[0];
+    RowStager<KS, G::ROW, G::PADL> sg;
+    sg.init(lane, fx);
+    int row_ofs = (fy ? KS - 1 : 0) * KS;
+    sg.load(kl, row_ofs);
+    sg.store(arow);
+    row_ofs += rstep;
+    sg.load(kl, row_ofs);
+    sg.store(arow + 2 * G::ROW);
+    float a[G::NB][4];
 #pragma unroll
-        for (int m = 0; m < G::ACC / 4; ++m) {
-            const float4 nxt = m + 1 < G::ACC / 4 ? dst[m + 1] : cur;
-            asm volatile("" ::: "memory");
-            cur.x += acc[4 * m]; cur.y += acc[4 * m + 1];
-            cur.z += acc[4 * m + 2]; cur.w += acc[4 * m + 3];
-            dst[m] = cur;
-            asm volatile("" ::: "memory");
-            cur = nxt;
+    for (int b = 0; b < G::NB; ++b)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[b][k] = arow[(k >> 1) * G::ROW + aofs + 4 * (k & 1) - 16 * b];
+    floatx4_t dprev[NG][G::NB];
+    for (int i = 0; i <= KS; ++i) {
+        const bool prev = i > 0, cur_row = i < KS;
+        if (i + 2 < KS) {
+            row_ofs += rstep;
+            sg.load(kl, row_ofs);                       // row i + 2 in flight
+        }
+        // previous row's halo targets, read ahead of this row's products
+        float4 cur[NG][G::NB];
+        if (prev) {
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+#pragma unroll
+                for (int b = 0; b < G::NB; ++b)
+                    cur[u][b] = *reinterpret_cast<const float4*>(hgrad + taddr[u][b]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        floatx4_t d[NG][G::NB];
+        if (cur_row) {
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+#pragma unroll
+                for (int b = 0; b < G::NB; ++b)
+                    d[u][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b][0], gb[u][0],
+                                                                   floatx4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+            for (int k = 1; k < 4; ++k)
+#pragma unroll
+                for (int u = 0; u < NG; ++u)
+#pragma unroll
+                    for (int b = 0; b < G::NB; ++b)
+                        d[u][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b][k], gb[u][k], d[u][b], 0, 0, 0);
+        }
+        if (prev) {
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+#pragma unroll
+                for (int b = 0; b < G::NB; ++b) {
+                    float4 v = cur[u][b];
+                    v.x += dprev[u][b][0]; v.y += dprev[u][b][1];
+                    v.z += dprev[u][b][2]; v.w += dprev[u][b][3];
+                    *reinterpret_cast<float4*>(hgrad + taddr[u][b]) = v;
+                    taddr[u][b] -= tstep[u][b];
+                }
+        }
+        if (i + 1 < KS) {
+            const float* ar = arow + ((i + 1) & 1) * 2 * G::ROW + aofs;
+#pragma unroll
+            for (int b = 0; b < G::NB; ++b)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) a[b][k] = ar[(k >> 1) * G::ROW + 4 * (k & 1) - 16 * b];
+        }
+        // row i's buffer was read one row ago
+        if (i + 2 < KS) sg.store(arow + (i & 1) * 2 * G::ROW);
+        if (cur_row) {
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+#pragma unroll
+                for (int b = 0; b < G::NB; ++b) dprev[u][b] = d[u][b];
         }
     }
 }
@@ -631,8 +704,9 @@ template <int KS>
 __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
                                                            const float* __restrict__ bank) {
     using G = BandGeom<KS>;
-    extern __shared__ __align__(16) float hgrad[];       // [HH][HW]
-    __shared__ int items[2 * 64];
+    extern __shared__ __align__(16) float hgrad[];       // [HH][HW], then 64 private float4s
+    __shared__ int items[kBS * kBR];                     // per strip column: strip | mask << 9
+    __shared__ __align__(16) float arow[4 * G::ROW];     // 2 buffers x 2 sides
     const int pad = (KS - 1) / 2;
     const int kk = KS * KS;
     const int bandsx = (A.W + kBW - 1) / kBW, bandsy = (A.H + kBR - 1) / kBR;
@@ -641,6 +715,7 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
     const int rem = band - n * bandsx * bandsy;
     const int y0 = (rem / bandsx) * kBR, x0 = (rem % bandsx) * kBW;
     const int lane = threadIdx.x;
+    // strip lane + 64 h: row (lane + 64 h) / 4, column lane % 4
     int key[2][kStrip];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -651,6 +726,9 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
             key[h][q] = (y < A.H && xs + q < A.W) ? bank_key(A, n, y, xs + q) : 0x7fffffff;
     }
     for (int e = lane; e < G::HH * G::HW; e += 64) hgrad[e] = 0.f;
+    for (int e = lane; e < 4 * G::ROW; e += 64) arow[e] = 0.f;   // margins stay zero
+    const unsigned long long colmask = 0x1111111111111111ull << (lane & 3);
+    const size_t plane = (size_t)A.C * A.H * A.W;
     for (int c = 0; c < A.C; ++c) {
         const int lam = A.lam_of_c[c];
         unsigned done = 0;
@@ -668,49 +746,55 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
                     if (!(done & (1u << (8 * h + q)))) mine = min(mine, key[h][q]);
             const int k = __builtin_amdgcn_readfirstlane(wave_min_int(mine));
             if (k == 0x7fffffff) break;
-            // list the band's strips that use entry k (at most 128)
-            int cnt = 0;
+            // list the entry's strips per column (at most 32 each)
+            int ccount = 0;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 unsigned m = 0;
 #pragma unroll
                 for (int q = 0; q < kStrip; ++q)
                     if (key[h][q] == k) m |= 1u << q;
-                const unsigned long long bal = __ballot(m != 0);
+                const unsigned long long bal = __ballot(m != 0) & colmask;
                 const int pre = __popcll(bal & ((1ull << lane) - 1ull));
                 if (m) {
-                    items[cnt + pre] = (lane + 64 * h) | (int)(m << 9);
+                    items[(lane & 3) * kBR + ccount + pre] = (lane + 64 * h) | (int)(m << 9);
                     done |= m << (8 * h);
                 }
-                cnt += __popcll(bal);
+                ccount += __popcll(bal);
             }
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
-            const size_t base = ((size_t)fd * A.L + lam) * 2 * kk;
-            const float* kl = bank + base + (fxb ? kk : 0);
-            const float* kr = bank + base + (fxb ? 0 : kk);
-            for (int s0 = 0; s0 < cnt; s0 += 64) {
-                const int it = items[s0 + min(lane, cnt - s0 - 1)];
-                const int sid = it & 127;
-                const unsigned msk = lane < cnt - s0 ? (unsigned)it >> 9 : 0u;
-                const int tr = sid / kBS, tc = sid % kBS;
-                const int y = y0 + tr, xs = x0 + tc * kStrip;
-                float gL[kStrip], gR[kStrip];
-                const size_t orow = (((size_t)n * 2 * A.C + c) * A.H + min(y, A.H - 1)) * A.W;
+            const float* kl = bank + ((size_t)fd * A.L + lam) * 2 * kk + (fxb ? kk : 0);
+            const int rstep = fyb ? -KS : KS;
+            const int g = lane >> 4;
+            for (int col = 0; col < kBS; ++col) {
+                const int cnt = __builtin_amdgcn_readlane(ccount, col);
+                if (cnt == 0) continue;
+                float gb[2][4];
+                int hofs[2];
+                bool act[2];
 #pragma unroll
-                for (int q = 0; q < kStrip; ++q) {
-                    const bool on = msk & (1u << q);
-                    const size_t o = orow + min(xs + q, A.W - 1);     // in bounds even if off
-                    gL[q] = on ? A.gout[o] : 0.f;
-                    gR[q] = on ? A.gout[o + (size_t)A.C * A.H * A.W] : 0.f;
+                for (int u = 0; u < 2; ++u) {
+                    const int j = 16 * u + (lane & 15);
+                    act[u] = j < cnt;
+                    const int it = items[col * kBR + min(j, cnt - 1)];
+                    const int sid = it & 127;
+                    const unsigned msk = act[u] ? (unsigned)it >> 9 : 0u;
+                    const int tr = sid / kBS, tc = sid % kBS;
+                    hofs[u] = (tr + KS - 1) * G::HW + tc * kStrip + 4 * g;
+                    const int y = min(y0 + tr, A.H - 1);
+                    const size_t orow = (((size_t)n * 2 * A.C + c) * A.H + y) * A.W;
+#pragma unroll
+                    for (int kq = 0; kq < 4; ++kq) {
+                        const int q = 4 * (kq & 1) + g;
+                        const size_t o = orow + min(x0 + tc * kStrip + q, A.W - 1) + (kq >> 1) * plane;
+                        const float v = A.gout[o];                   // in bounds even if masked
+                        gb[u][kq] = (msk >> q) & 1u ? v : 0.f;
+                    }
                 }
-                // lanes past the chunk's end hold a copy of its last strip:
-                // they must not take part in the read-modify-writes
-                if (lane < cnt - s0) {
-                    if (fxb) scatter_strip<KS, true>(kl, kr, fyb, hgrad, tr + KS - 1, tc * kStrip, gL, gR);
-                    else scatter_strip<KS, false>(kl, kr, fyb, hgrad, tr + KS - 1, tc * kStrip, gL, gR);
-                }
+                if (cnt > 16) band_mfma_column<KS, 2>(kl, rstep, fxb, fyb, hgrad, arow, lane, gb, hofs, act);
+                else band_mfma_column<KS, 1>(kl, rstep, fxb, fyb, hgrad, arow, lane, gb, hofs, act);
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -734,7 +818,7 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
 template <int KS, bool BWD>
 static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
     if (BWD) {
-        const size_t shm = (size_t)BandGeom<KS>::HH * BandGeom<KS>::HW * sizeof(float);
+        const size_t shm = ((size_t)BandGeom<KS>::HH * BandGeom<KS>::HW + 4 * 64) * sizeof(float);
         const int bandsx = (A.W + kBW - 1) / kBW, bandsy = (A.H + kBR - 1) / kBR;
         const dim3 grid((unsigned)((long long)A.N * bandsx * bandsy));
         if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_bwd_kernel<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
