@@ -283,12 +283,14 @@ __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A)
 // pixels that use them.  The unit of work is a strip of 8 horizontally
 // adjacent output pixels and one entry.
 //
-// Forward: a workgroup owns a 64 x 64 pixel tile (512 strips) and first lists
-// its (strip, entry, pixel mask) items grouped by entry, in chunks of at most
-// 64 items of one entry; its four waves then take the chunks in turn, with
-// the clamped image halo of one channel at a time in LDS.  Grouping by entry
-// over the whole tile keeps the matrix-core columns busy where a fixed pixel
-// block would straddle several entries.
+// Forward: a workgroup owns one channel of a 64 x 64 pixel tile (512 strips)
+// and first lists its (strip, entry, pixel mask) items grouped by entry, in
+// chunks of at most 64 items of one entry; its four waves then take the
+// chunks in turn, with the clamped image halo in LDS.  Grouping by entry over
+// the whole tile keeps the matrix-core columns busy where a fixed pixel block
+// would straddle several entries.  Channels are separate workgroups (the
+// slowest grid index), which evens out the work per workgroup and keeps one
+// wavelength's bank entries in the caches at a time.
 //
 // A chunk runs on the fp32 matrix cores.  For kernel row i the 8 outputs of a
 // strip on both sides are the product of a 16 x P Toeplitz matrix made from
@@ -440,7 +442,9 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
     const int pad = (KS - 1) / 2;
     const int kk = KS * KS;
     const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
-    const int tile = blockIdx.x;
+    const int nt = A.N * tilesx * tilesy;
+    const int c = blockIdx.x / nt;                       // channel slowest: one wavelength's entries at a time
+    const int tile = blockIdx.x - c * nt;
     const int n = tile / (tilesx * tilesy);
     const int rem = tile - n * tilesx * tilesy;
     const int y0 = (rem / tilesx) * kGT, x0 = (rem % tilesx) * kGT;
@@ -511,8 +515,8 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
             __syncthreads();
         }
         const int T = n_chunks;
-        // ---- render the batch, one channel at a time
-        for (int c = 0; c < A.C; ++c) {
+        // ---- render the batch
+        {
             const int lam = A.lam_of_c[c];
             const float* im = A.img + ((size_t)n * A.C + c) * A.H * A.W;
             for (int e = tid; e < G::HH * G::HW; e += kRBlock) {
@@ -582,8 +586,8 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
 // read-modify-writes never touch one address twice and go out together,
 // interleaved with the next row's products; successive rows and columns are
 // ordered by program order (LDS operations of one wave execute in order).
-// The halo is folded onto the clamped image pixels with global atomics once
-// per channel.
+// A workgroup handles one channel of its band and finally folds the halo
+// onto the clamped image pixels with global atomics.
 constexpr int kBR = 32, kBW = 32;                     // band rows, columns
 constexpr int kBS = kBW / kStrip;                     // strips per band row
 static_assert(kBR * kBS == 128, "two strips per lane");
@@ -593,18 +597,24 @@ struct BandGeom {
     static constexpr int NB = (KS + kStrip - 1 + 15) / 16;         // 16-column blocks of the window
     static constexpr int WP = ((KS + kStrip - 1 + 3) / 4) * 4;     // window columns written
     static constexpr int HH = kBR + KS - 1;
-    static constexpr int HW = kBW - kStrip + WP;                   // row stride (16-byte rows)
+    // written columns, then one float4 column of lane-private slots; an odd
+    // number of float4s per row puts 16 consecutive rows in distinct banks
+    static constexpr int HW0 = kBW - kStrip + WP + 4;
+    static constexpr int HW = (HW0 / 4) % 2 ? HW0 : HW0 + 4;
+    static constexpr int SLOT = HW - 4;                            // private slot column
     static constexpr int PADL = 16 * NB - KS;                      // staged row: zero margin
     static constexpr int ROW = ((16 * NB + kStrip - 1 + 3) / 4) * 4;
     static_assert(HW % 4 == 0, "float4 rows");
+    static_assert(SLOT >= kBW + KS - 1, "private slots lie outside the folded halo");
 };
 
 // Kernel rows of one strip column: NG groups of 16 strips.  gb: the lane's B
 // operands (output gradients of (side, q) for the four k-steps), hofs: the
 // lane's halo offset at i = 0, act: the lane holds a strip.  Lanes with
 // nothing to add at a block (no strip, or window columns past the last tap)
-// direct that block's read-modify-write to a private float4 past the halo,
-// so every read-modify-write runs on all lanes.
+// direct that block's read-modify-write to a private float4 in the halo's
+// last column, which is never folded, so every read-modify-write runs on all
+// lanes.
 template <int KS, int NG>
 __device__ inline void band_mfma_column(const float* __restrict__ kl, int rstep, bool fx, bool fy,
                                         float* hgrad, float* arow, int lane,
@@ -621,7 +631,7 @@ __device__ inline void band_mfma_column(const float* __restrict__ kl, int rstep,
 #pragma unroll
         for (int b = 0; b < G::NB; ++b) {
             const bool ok = act[u] && 16 * b + 4 * g < G::WP;
-            taddr[u][b] = ok ? hofs[u] + 16 * b : G::HH * G::HW + 4 * lane;
+            taddr[u][b] = ok ? hofs[u] + 16 * b : (lane % G::HH) * G::HW + G::SLOT;
             tstep[u][b] = ok ? G::HW : 0;
         }
     RowStager<KS, G::ROW, G::PADL> sg;
@@ -704,13 +714,15 @@ template <int KS>
 __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
                                                            const float* __restrict__ bank) {
     using G = BandGeom<KS>;
-    extern __shared__ __align__(16) float hgrad[];       // [HH][HW], then 64 private float4s
+    extern __shared__ __align__(16) float hgrad[];       // [HH][HW]
     __shared__ int items[kBS * kBR];                     // per strip column: strip | mask << 9
     __shared__ __align__(16) float arow[4 * G::ROW];     // 2 buffers x 2 sides
     const int pad = (KS - 1) / 2;
     const int kk = KS * KS;
     const int bandsx = (A.W + kBW - 1) / kBW, bandsy = (A.H + kBR - 1) / kBR;
-    const int band = blockIdx.x;
+    const int nb = A.N * bandsx * bandsy;
+    const int c = blockIdx.x / nb;                       // channel slowest: one wavelength's entries at a time
+    const int band = blockIdx.x - c * nb;
     const int n = band / (bandsx * bandsy);
     const int rem = band - n * bandsx * bandsy;
     const int y0 = (rem / bandsx) * kBR, x0 = (rem % bandsx) * kBW;
@@ -729,7 +741,7 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
     for (int e = lane; e < 4 * G::ROW; e += 64) arow[e] = 0.f;   // margins stay zero
     const unsigned long long colmask = 0x1111111111111111ull << (lane & 3);
     const size_t plane = (size_t)A.C * A.H * A.W;
-    for (int c = 0; c < A.C; ++c) {
+    {
         const int lam = A.lam_of_c[c];
         unsigned done = 0;
 #pragma unroll
@@ -798,29 +810,26 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
             }
             __builtin_amdgcn_wave_barrier();
         }
-        // fold the band's halo gradient of channel c (clamped) and clear it
+        // fold the band's halo gradient (clamped)
         __syncthreads();
         float* gi = A.gimg + ((size_t)n * A.C + c) * A.H * A.W;
         for (int e = lane; e < G::HH * G::HW; e += 64) {
             const int R = e / G::HW, Cc = e - R * G::HW;
             const float v = hgrad[e];
-            if (v == 0.f) continue;
-            hgrad[e] = 0.f;
-            if (Cc >= kBW + KS - 1) continue;
+            if (v == 0.f || Cc >= kBW + KS - 1) continue;
             const int yy = min(max(y0 - pad + R, 0), A.H - 1);
             const int xx = min(max(x0 - pad + Cc, 0), A.W - 1);
             atomicAdd(&gi[(size_t)yy * A.W + xx], v);
         }
-        __syncthreads();
     }
 }
 
 template <int KS, bool BWD>
 static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
     if (BWD) {
-        const size_t shm = ((size_t)BandGeom<KS>::HH * BandGeom<KS>::HW + 4 * 64) * sizeof(float);
+        const size_t shm = (size_t)BandGeom<KS>::HH * BandGeom<KS>::HW * sizeof(float);
         const int bandsx = (A.W + kBW - 1) / kBW, bandsy = (A.H + kBR - 1) / kBR;
-        const dim3 grid((unsigned)((long long)A.N * bandsx * bandsy));
+        const dim3 grid((unsigned)((long long)A.C * A.N * bandsx * bandsy));
         if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_bwd_kernel<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         hipLaunchKernelGGL(render_bank_bwd_kernel<KS>, grid, dim3(64), shm, st, A,
                            reinterpret_cast<const float*>(A.psf));
@@ -828,7 +837,7 @@ static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
         using G = GroupGeom<KS>;
         const size_t shm = (size_t)G::HH * G::HW * sizeof(float);
         const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
-        const dim3 grid((unsigned)((long long)A.N * tilesx * tilesy));
+        const dim3 grid((unsigned)((long long)A.C * A.N * tilesx * tilesy));
         if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         hipLaunchKernelGGL(render_bank_fast_kernel<KS>, grid, dim3(kRBlock), shm, st, A,
                            reinterpret_cast<const float*>(A.psf));
