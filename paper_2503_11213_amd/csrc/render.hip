@@ -573,19 +573,20 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
 // Bank-source image adjoint on the matrix cores.  A one-wave workgroup owns
 // a 32 x 32 pixel band (4 strip columns of 32 rows) and a private LDS copy of
 // the band's image-halo gradient (under 40 KB for ks <= 65, so four such
-// waves share a compute unit).  It takes the band's entries one at a time and,
-// per entry, one strip column at a time: the column's strips of the entry
-// (at most 32, all in distinct rows) form one or two groups of 16.  For
+// waves share a compute unit).  It takes the band's entries one at a time;
+// per strip column, an entry's strips (at most 32, all in distinct rows) form
+// one or two groups of 16, and up to four groups run together.  For
 // kernel row i a group's halo contribution is the transposed Toeplitz matrix
 // of the row pair (window column p against output (side, q)) times the
 // 16 x 16 matrix of the strips' masked output gradients, in blocks of 16
 // window columns (four k-steps of v_mfma_f32_16x16x4_f32 over (side, q)).
 // Lane l then holds the block's columns 4 (l / 16) .. + 3 for strip l % 16
 // and adds them into the halo with one float4 read-modify-write.  The
-// strips of a column lie in distinct rows, so one kernel row's
-// read-modify-writes never touch one address twice and go out together,
-// interleaved with the next row's products; successive rows and columns are
-// ordered by program order (LDS operations of one wave execute in order).
+// strips of a group lie in distinct rows, so a group's read-modify-writes of
+// one kernel row never touch one address twice and go out together,
+// interleaved with the group's products of the next row; successive groups
+// and rows are ordered by program order (LDS operations of one wave execute
+// in order).
 // A workgroup handles one channel of its band and finally folds the halo
 // onto the clamped image pixels with global atomics.
 constexpr int kBR = 32, kBW = 32;                     // band rows, columns
@@ -608,18 +609,22 @@ struct BandGeom {
     static_assert(SLOT >= kBW + KS - 1, "private slots lie outside the folded halo");
 };
 
-// Kernel rows of one strip column: NG groups of 16 strips.  gb: the lane's B
-// operands (output gradients of (side, q) for the four k-steps), hofs: the
-// lane's halo offset at i = 0, act: the lane holds a strip.  Lanes with
-// nothing to add at a block (no strip, or window columns past the last tap)
-// direct that block's read-modify-write to a private float4 in the halo's
-// last column, which is never folded, so every read-modify-write runs on all
-// lanes.
+// All kernel rows of one pass: NG groups of 16 strips of one entry (each
+// group from a single strip column).  gb: the lane's B operands (output
+// gradients of (side, q) for the four k-steps), hofs: the lane's halo offset
+// at i = 0, act: the lane holds a strip.  Lanes with nothing to add at a
+// block (no strip, or window columns past the last tap) direct that block's
+// read-modify-write to a private float4 in the halo's last column, which is
+// never folded, so every read-modify-write runs on all lanes.  Row i's
+// products are added in during row i + 1, group by group: a group's reads,
+// its products of the next row (covering the read latency), then its sums.
+// Groups of different columns may overlap, so each group's writes precede
+// the next group's reads.
 template <int KS, int NG>
-__device__ inline void band_mfma_column(const float* __restrict__ kl, int rstep, bool fx, bool fy,
-                                        float* hgrad, float* arow, int lane,
-                                        const float (&gb)[2][4], const int (&hofs)[2],
-                                        const bool (&act)[2]) {
+__device__ inline void band_mfma_pass(const float* __restrict__ kl, int rstep, bool fx, bool fy,
+                                      float* hgrad, float* arow, int lane,
+                                      const float (&gb)[4][4], const int (&hofs)[4],
+                                      const bool (&act)[4]) {
     using G = BandGeom<KS>;
     const int prow = lane & 15, g = lane >> 4;
     // A operand of block b, k-step k: tap q + KS - 1 - p of side k >> 1,
@@ -654,43 +659,36 @@ __device__ inline void band_mfma_column(const float* __restrict__ kl, int rstep,
             row_ofs += rstep;
             sg.load(kl, row_ofs);                       // row i + 2 in flight
         }
-        // previous row's halo targets, read ahead of this row's products
-        float4 cur[NG][G::NB];
-        if (prev) {
+        floatx4_t d[NG][G::NB];
 #pragma unroll
-            for (int u = 0; u < NG; ++u)
+        for (int u = 0; u < NG; ++u) {
+            float4 cur[G::NB];
+            if (prev) {
 #pragma unroll
                 for (int b = 0; b < G::NB; ++b)
-                    cur[u][b] = *reinterpret_cast<const float4*>(hgrad + taddr[u][b]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        floatx4_t d[NG][G::NB];
-        if (cur_row) {
-#pragma unroll
-            for (int u = 0; u < NG; ++u)
+                    cur[b] = *reinterpret_cast<const float4*>(hgrad + taddr[u][b]);
+            }
+            if (cur_row) {
 #pragma unroll
                 for (int b = 0; b < G::NB; ++b)
                     d[u][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b][0], gb[u][0],
                                                                    floatx4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
 #pragma unroll
-            for (int k = 1; k < 4; ++k)
-#pragma unroll
-                for (int u = 0; u < NG; ++u)
+                for (int k = 1; k < 4; ++k)
 #pragma unroll
                     for (int b = 0; b < G::NB; ++b)
                         d[u][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b][k], gb[u][k], d[u][b], 0, 0, 0);
-        }
-        if (prev) {
-#pragma unroll
-            for (int u = 0; u < NG; ++u)
+            }
+            if (prev) {
 #pragma unroll
                 for (int b = 0; b < G::NB; ++b) {
-                    float4 v = cur[u][b];
+                    float4 v = cur[b];
                     v.x += dprev[u][b][0]; v.y += dprev[u][b][1];
                     v.z += dprev[u][b][2]; v.w += dprev[u][b][3];
                     *reinterpret_cast<float4*>(hgrad + taddr[u][b]) = v;
                     taddr[u][b] -= tstep[u][b];
                 }
+            }
         }
         if (i + 1 < KS) {
             const float* ar = arow + ((i + 1) & 1) * 2 * G::ROW + aofs;
@@ -707,6 +705,18 @@ __device__ inline void band_mfma_column(const float* __restrict__ kl, int rstep,
 #pragma unroll
                 for (int b = 0; b < G::NB; ++b) dprev[u][b] = d[u][b];
         }
+    }
+}
+
+// Group j of an entry's strips in a band: groups of 16 taken column by
+// column (nc: strips per column).
+__device__ inline void band_group(int j, const int (&nc)[kBS], int& col, int& s0, int& cnt) {
+    col = -1; s0 = 0; cnt = 0;
+#pragma unroll
+    for (int c = 0; c < kBS; ++c) {
+        const int gc = (nc[c] + 15) >> 4;
+        if (col < 0 && j < gc) { col = c; s0 = 16 * j; cnt = min(16, nc[c] - s0); }
+        if (col < 0) j -= gc;
     }
 }
 
@@ -780,17 +790,24 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
             const float* kl = bank + ((size_t)fd * A.L + lam) * 2 * kk + (fxb ? kk : 0);
             const int rstep = fyb ? -KS : KS;
             const int g = lane >> 4;
-            for (int col = 0; col < kBS; ++col) {
-                const int cnt = __builtin_amdgcn_readlane(ccount, col);
-                if (cnt == 0) continue;
-                float gb[2][4];
-                int hofs[2];
-                bool act[2];
+            int nc[kBS], ngt = 0;
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int j = 16 * u + (lane & 15);
-                    act[u] = j < cnt;
-                    const int it = items[col * kBR + min(j, cnt - 1)];
+            for (int col = 0; col < kBS; ++col) {
+                nc[col] = __builtin_amdgcn_readlane(ccount, col);
+                ngt += (nc[col] + 15) >> 4;
+            }
+            // passes of up to four groups share the staged kernel rows
+            for (int p0 = 0; p0 < ngt; p0 += 4) {
+                const int np = min(4, ngt - p0);
+                float gb[4][4];
+                int hofs[4];
+                bool act[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    int col, s0, cnt;
+                    band_group(min(p0 + u, ngt - 1), nc, col, s0, cnt);
+                    act[u] = u < np && (lane & 15) < cnt;
+                    const int it = items[col * kBR + s0 + min(lane & 15, cnt - 1)];
                     const int sid = it & 127;
                     const unsigned msk = act[u] ? (unsigned)it >> 9 : 0u;
                     const int tr = sid / kBS, tc = sid % kBS;
@@ -805,8 +822,12 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
                         gb[u][kq] = (msk >> q) & 1u ? v : 0.f;
                     }
                 }
-                if (cnt > 16) band_mfma_column<KS, 2>(kl, rstep, fxb, fyb, hgrad, arow, lane, gb, hofs, act);
-                else band_mfma_column<KS, 1>(kl, rstep, fxb, fyb, hgrad, arow, lane, gb, hofs, act);
+                switch (np) {
+                    case 1: band_mfma_pass<KS, 1>(kl, rstep, fxb, fyb, hgrad, arow, lane, gb, hofs, act); break;
+                    case 2: band_mfma_pass<KS, 2>(kl, rstep, fxb, fyb, hgrad, arow, lane, gb, hofs, act); break;
+                    case 3: band_mfma_pass<KS, 3>(kl, rstep, fxb, fyb, hgrad, arow, lane, gb, hofs, act); break;
+                    default: band_mfma_pass<KS, 4>(kl, rstep, fxb, fyb, hgrad, arow, lane, gb, hofs, act); break;
+                }
             }
             __builtin_amdgcn_wave_barrier();
         }
