@@ -21,8 +21,9 @@ enum RayStatus : int { kAlive = 0, kMiss = 1, kClip = 2, kTir = 3,
                        kNewton = 4, kInvalid = 5 };
 
 // Prescription as kernel arguments: read with scalar loads in the hot loop.
-// code[s] = kind | (asphere slot << 8) (slot -1 when not an asphere); a
-// 32-bit word so that it is fetched by a scalar load.
+// code[s] = kind | 0x80 if inv_c[s] holds 1/c | (asphere slot << 8) (slot -1
+// when not an asphere); a 32-bit word so that it is fetched by a scalar load
+// and tested with scalar instructions.
 struct LensArgs {
     int S;
     int stop;
@@ -35,7 +36,7 @@ struct LensArgs {
     double sensor_dist;         // last vertex -> sensor plane
 };
 
-__device__ __host__ inline int kind_of(const LensArgs& L, int s) { return L.code[s] & 0xff; }
+__device__ __host__ inline int kind_of(const LensArgs& L, int s) { return L.code[s] & 0x7f; }
 __device__ __host__ inline int aslot_of(const LensArgs& L, int s) { return L.code[s] >> 8; }
 
 // Per-wavelength data: index ratios and entrance pupil.
@@ -245,7 +246,7 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
     } while (0)
     for (int s = 0; s < L.S; ++s) {
         const int code = L.code[s];
-        const int kind = code & 0xff;
+        const int kind = code & 0x7f;
         const T c = (T)L.c[s];
         const T semi2 = (T)L.semi2[s];
         r.z -= (T)L.tprev[s];
@@ -255,18 +256,28 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
             const T G = r.dz - c * (r.x * r.dx + r.y * r.dy + r.z * r.dz);
             const T disc = G * G - c * F;
             SDIRT_FAIL(disc < T(0), kMiss);
+            // sqrt(disc) is also the cosine of the incidence angle at the
+            // hit: with n = (-c x, -c y, 1 - c z) there, d.n = G - c t
+            const T cosI = sqrt_live<T>(disc);
             T t;
-            // (integer test of the bits: a scalar branch, no vector compare)
-            if (sizeof(T) == sizeof(double) && __double_as_longlong(L.inv_c[s]) != 0)
-                t = (G - sqrt_live<T>(disc)) * (T)L.inv_c[s];
+            if (sizeof(T) == sizeof(double) && (code & 0x80))
+                t = (G - cosI) * (T)L.inv_c[s];
             else
-                t = F * rcp_t<T>(G + sqrt_live<T>(disc));
+                t = F * rcp_t<T>(G + cosI);
             r.x += t * r.dx;
             r.y += t * r.dy;
             r.z += t * r.dz;
             SDIRT_FAIL(r.x * r.x + r.y * r.y > semi2, kClip);
-            const T K = refract<T>(r, -c * r.x, -c * r.y, T(1) - c * r.z, (T)mu[s]);
+            // vector Snell with cos^2 I = disc: K = 1 - m^2 (1 - disc)
+            const T m = (T)mu[s];
+            const T m2 = m * m;
+            const T K = fma(m2, disc, T(1) - m2);
             SDIRT_FAIL(K < T(0), kTir);
+            const T g = sqrt_live<T>(K) - m * cosI;
+            const T gc = g * c;
+            r.dx = fma(-gc, r.x, m * r.dx);
+            r.dy = fma(-gc, r.y, m * r.dy);
+            r.dz = fma(g, fma(-c, r.z, T(1)), m * r.dz);
         } else {
             const T tau = -r.z * rcp_t<T>(r.dz);
             r.x += tau * r.dx;

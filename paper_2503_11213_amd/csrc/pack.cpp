@@ -23,7 +23,8 @@ int pack_lens(const Resolved& R, LensArgs* A) {
             for (int m = 0; m < 5; ++m) A->asph[nas][m + 1] = R.asph[5 * s + m];
             ++nas;
         }
-        A->code[s] = (R.kind[s] & 0xff) | (int)((unsigned)slot << 8);
+        A->code[s] = (R.kind[s] & 0x7f) | (A->inv_c[s] != 0.0 ? 0x80 : 0) |
+                     (int)((unsigned)slot << 8);
     }
     A->sensor_dist = R.sensor_distance;
     return SDIRT_OK;
