@@ -377,7 +377,7 @@ def main():
                                "1680x1120 RGB image from the PSF bank",
                    "psfs": P, "rays_per_psf": query.n_rays, "surfaces": n_surf,
                    "ks": query.ks, "image": [H, W, 3]},
-        "roofline": {"kernel": "trace_splat_kernel<double, box, sigmoid, float, no asphere path>",
+        "roofline": {"kernel": "trace_splat_kernel<double, box, sigmoid, float, spheres and flats>",
                      "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": (TRACE_TRAFFIC["bytes"]

@@ -232,9 +232,12 @@ __device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m) {
 // vertex plane.
 // EXACT: report the first failure's code (ray-level debugging); otherwise
 // only whether the ray survived (kAlive or kMiss), which keeps the
-// bookkeeping in scalar lane masks.  ASPH = false compiles the even-asphere
-// path out (for prescriptions without aspheres: fewer registers).
-template <typename T, typename Rec, bool EXACT = true, bool ASPH = true>
+// bookkeeping in scalar lane masks.  GENERAL = false is for prescriptions of
+// spheres, planes and stops only: a flat surface is a sphere of curvature 0
+// (the quadratic's root is then the plane transfer) and a stop has index
+// ratio 1 (the refraction then leaves the direction unchanged), so every
+// surface takes the sphere path, without per-surface branches.
+template <typename T, typename Rec, bool EXACT = true, bool GENERAL = true>
 __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
                                 Rec rec) {
     int status = kAlive;
@@ -251,7 +254,7 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         const T semi2 = (T)L.semi2[s];
         r.z -= (T)L.tprev[s];
         SDIRT_FAIL(!(r.dz > T(0)), kInvalid);
-        if (kind == SDIRT_SPHERE) {
+        if (!GENERAL || kind == SDIRT_SPHERE) {
             const T F = c * (r.x * r.x + r.y * r.y + r.z * r.z) - T(2) * r.z;
             const T G = r.dz - c * (r.x * r.dx + r.y * r.dy + r.z * r.dz);
             const T disc = G * G - c * F;
@@ -283,7 +286,7 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
             r.x += tau * r.dx;
             r.y += tau * r.dy;
             r.z = T(0);
-            if (ASPH && kind == SDIRT_ASPHERE) {
+            if (kind == SDIRT_ASPHERE) {
                 const double* co = L.asph[code >> 8];
                 const Asph<T> S(co, c);
                 const T k = (T)co[0];

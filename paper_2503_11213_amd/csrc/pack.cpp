@@ -41,8 +41,9 @@ int pack_lambdas(const Resolved& R, const double* lambdas, int L, LambdaArgs* A)
         A->lambda[l] = lam;
         for (int m = 0; m <= R.S; ++m)
             if (!(R.index(m, lam) > 0)) return SDIRT_EINVAL;
+        // the stop is an aperture only: no refraction there
         for (int s = 0; s < R.S; ++s)
-            A->mu[l][s] = R.index(s, lam) / R.index(s + 1, lam);
+            A->mu[l][s] = R.kind[s] == SDIRT_STOP ? 1.0 : R.index(s, lam) / R.index(s + 1, lam);
         R.pupil(lam, &A->z_ep[l], &A->rho_ep[l]);
         if (!std::isfinite(A->z_ep[l]) || !std::isfinite(A->rho_ep[l]))
             return SDIRT_EINVAL;

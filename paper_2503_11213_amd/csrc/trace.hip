@@ -54,7 +54,7 @@ __device__ inline void point_of(const PointArgs& P, int q, double* hx, double* h
     }
 }
 
-template <typename T, int SPLAT, int DP, typename OutT, bool ASPH>
+template <typename T, int SPLAT, int DP, typename OutT, bool GENERAL>
 __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) {
     extern __shared__ float tile[];          // [2][ks][ks]
     __shared__ float red[kBlock / 64][8];
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
         double ddx = ex - px, ddy = ey - py, ddz = zep - pz;
         const double inv = rsqrt_t<double>(ddx * ddx + ddy * ddy + ddz * ddz);
         Ray<T> ray{(T)ex, (T)ey, (T)zep, (T)(ddx * inv), (T)(ddy * inv), (T)(ddz * inv)};
-        const int st = trace_ray<T, NoRec, false, ASPH>(A.lens, mu, ray, NoRec());
+        const int st = trace_ray<T, NoRec, false, GENERAL>(A.lens, mu, ray, NoRec());
         if (st != kAlive) { e_vig += 1.f; continue; }
         e_tr += 1.f;
         const double wu = ((double)ray.x - hx) * inv_ps + pad;
@@ -270,8 +270,8 @@ int launch_fill_zero(void* p, size_t bytes, hipStream_t stream) {
 }
 
 template <typename T, int SPLAT, int DP, typename OutT>
-static void launch_splat(const SplatArgs& A, dim3 grid, size_t shm, hipStream_t st, bool asph) {
-    auto k = asph ? trace_splat_kernel<T, SPLAT, DP, OutT, true>
+static void launch_splat(const SplatArgs& A, dim3 grid, size_t shm, hipStream_t st, bool general) {
+    auto k = general ? trace_splat_kernel<T, SPLAT, DP, OutT, true>
                   : trace_splat_kernel<T, SPLAT, DP, OutT, false>;
     if (shm > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(k, grid, dim3(kBlock), shm, st, A);
@@ -280,12 +280,14 @@ static void launch_splat(const SplatArgs& A, dim3 grid, size_t shm, hipStream_t 
 template <typename T, typename OutT>
 static void dispatch_splat(const SplatArgs& A, dim3 grid, size_t shm, hipStream_t st) {
     const int sp = A.splat, dp = A.sen.dp_mode;
-    bool asph = false;
-    for (int s = 0; s < A.lens.S; ++s) asph = asph || kind_of(A.lens, s) == SDIRT_ASPHERE;
-    if (sp == SDIRT_SPLAT_BOX && dp == SDIRT_DP_SIGMOID) launch_splat<T, SDIRT_SPLAT_BOX, SDIRT_DP_SIGMOID, OutT>(A, grid, shm, st, asph);
-    else if (sp == SDIRT_SPLAT_BOX) launch_splat<T, SDIRT_SPLAT_BOX, SDIRT_DP_MICROLENS, OutT>(A, grid, shm, st, asph);
-    else if (dp == SDIRT_DP_SIGMOID) launch_splat<T, SDIRT_SPLAT_TENT, SDIRT_DP_SIGMOID, OutT>(A, grid, shm, st, asph);
-    else launch_splat<T, SDIRT_SPLAT_TENT, SDIRT_DP_MICROLENS, OutT>(A, grid, shm, st, asph);
+    // spheres, planes and stops only: the branch-free surface loop
+    bool general = false;
+    for (int s = 0; s < A.lens.S; ++s)
+        general = general || kind_of(A.lens, s) == SDIRT_ASPHERE || kind_of(A.lens, s) == SDIRT_IDEAL;
+    if (sp == SDIRT_SPLAT_BOX && dp == SDIRT_DP_SIGMOID) launch_splat<T, SDIRT_SPLAT_BOX, SDIRT_DP_SIGMOID, OutT>(A, grid, shm, st, general);
+    else if (sp == SDIRT_SPLAT_BOX) launch_splat<T, SDIRT_SPLAT_BOX, SDIRT_DP_MICROLENS, OutT>(A, grid, shm, st, general);
+    else if (dp == SDIRT_DP_SIGMOID) launch_splat<T, SDIRT_SPLAT_TENT, SDIRT_DP_SIGMOID, OutT>(A, grid, shm, st, general);
+    else launch_splat<T, SDIRT_SPLAT_TENT, SDIRT_DP_MICROLENS, OutT>(A, grid, shm, st, general);
 }
 
 // Chunks per point so that the grid holds enough workgroups to fill the

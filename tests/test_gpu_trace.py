@@ -7,8 +7,9 @@ import pytest
 import torch
 
 from workloads import lenses, configs
-from workloads.lens import (Sensor, PsfQuery, DP_SIGMOID, DP_MICROLENS, SPLAT_BOX,
-                            SPLAT_TENT, NORM_SUM, NORM_MAX)
+from workloads.lens import (Sensor, PsfQuery, Surface, Lens, SPHERE, PLANE, STOP, cauchy,
+                            DP_SIGMOID, DP_MICROLENS, SPLAT_BOX, SPLAT_TENT, NORM_SUM,
+                            NORM_MAX)
 from oracle import optics, psf as opsf, trace as otr
 from paper_2503_11213_amd import sdirt, _abi as abi
 
@@ -197,6 +198,37 @@ def test_edge_cases():
     ref, rst = opsf.trace_dp_psf(lens, sensor, q)
     assert np.array_equal(st.cpu().numpy()[:, :3], rst[:, :3])
     assert _energy_l1(psf.cpu().numpy(), ref) <= L1_TOL
+
+
+@pytest.mark.parametrize("which", ["plano_convex", "plate"])
+def test_flat_surfaces_on_the_spheres_and_flats_path(which):
+    # prescriptions of spheres, planes and stops take the branch-free surface
+    # loop, where a refracting plane is a sphere of curvature 0 and the stop
+    # an index ratio of 1
+    if which == "plate":
+        # no power: the blur is the stop's shadow, so coarse pixels
+        lens, pitch = lenses.plate(), 0.3
+        fields = [(0.0, 0.0), (2.0, 1.4)]
+    else:
+        pitch = 0.006
+        lens = Lens(surfaces=[
+            Surface(kind=STOP, c=0.0, t=1.0, semi_diameter=8.0),
+            Surface(kind=SPHERE, c=1.0 / 31.0, t=4.0, semi_diameter=12.0,
+                    medium=cauchy(1.62, 0.012)),
+            Surface(kind=PLANE, c=0.0, t=48.0, semi_diameter=12.0)],
+            stop=0, f_number=2.8, focus_depth=1500.0)
+        fields = [(0.0, 0.0), (1.2, -0.7), (-2.5, 1.5)]
+    sensor = Sensor(pitch=pitch, dp_mode=DP_SIGMOID, sigmoid_k=15.0)
+    query = PsfQuery(fields=fields, depths=[800.0, 3000.0], wavelengths=[0.48, 0.63],
+                     rays_x=96, rays_y=80, seed=5, jitter=True, ks=41)
+    psf, st = sdirt.trace_dp_psf(lens, sensor, query)
+    ref, rst = opsf.trace_dp_psf(lens, sensor, query)
+    g, gs = psf.cpu().numpy(), st.cpu().numpy()
+    for q in range(ref.shape[0]):
+        if ref[q].sum() > 0:
+            assert _energy_l1(g[q], ref[q]) <= L1_TOL, q
+    assert np.array_equal(gs[:, :3], rst[:, :3])
+    assert np.allclose(gs[:, 3:], rst[:, 3:], rtol=1e-5, atol=0.05)
 
 
 def test_list_mode_equals_grid_mode():
