@@ -236,7 +236,8 @@ __device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m) {
 // spheres, planes and stops only: a flat surface is a sphere of curvature 0
 // (the quadratic's root is then the plane transfer) and a stop has index
 // ratio 1 (the refraction then leaves the direction unchanged), so every
-// surface takes the sphere path, without per-surface branches.
+// surface but the aperture stop takes the sphere path, without per-surface
+// branches; the aperture stop is a plane transfer and a clip.
 template <typename T, typename Rec, bool EXACT = true, bool GENERAL = true>
 __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
                                 Rec rec) {
@@ -247,40 +248,71 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         if (EXACT) { if ((cond) && status == kAlive) status = (code); } \
         else alive = alive && !(cond);                           \
     } while (0)
-    for (int s = 0; s < L.S; ++s) {
+    // sphere, or a flat surface as a sphere of curvature 0
+    auto sphere = [&](const int s, const int code, const T c, const T semi2)
+                      __attribute__((always_inline)) {
+        const T F = c * (r.x * r.x + r.y * r.y + r.z * r.z) - T(2) * r.z;
+        const T G = r.dz - c * (r.x * r.dx + r.y * r.dy + r.z * r.dz);
+        const T disc = G * G - c * F;
+        SDIRT_FAIL(disc < T(0), kMiss);
+        // sqrt(disc) is also the cosine of the incidence angle at the
+        // hit: with n = (-c x, -c y, 1 - c z) there, d.n = G - c t
+        const T cosI = sqrt_live<T>(disc);
+        T t;
+        if (sizeof(T) == sizeof(double) && (code & 0x80))
+            t = (G - cosI) * (T)L.inv_c[s];
+        else
+            t = F * rcp_t<T>(G + cosI);
+        r.x += t * r.dx;
+        r.y += t * r.dy;
+        r.z += t * r.dz;
+        SDIRT_FAIL(r.x * r.x + r.y * r.y > semi2, kClip);
+        // vector Snell with cos^2 I = disc: K = 1 - m^2 (1 - disc)
+        const T m = (T)mu[s];
+        const T m2 = m * m;
+        const T K = fma(m2, disc, T(1) - m2);
+        SDIRT_FAIL(K < T(0), kTir);
+        const T g = sqrt_live<T>(K) - m * cosI;
+        const T gc = g * c;
+        r.dx = fma(-gc, r.x, m * r.dx);
+        r.dy = fma(-gc, r.y, m * r.dy);
+        r.dz = fma(g, fma(-c, r.z, T(1)), m * r.dz);
+    };
+    int s0 = 0;
+    if (!GENERAL) {
+        // spheres and flats only: every surface but the aperture stop takes
+        // the sphere path (no per-surface branches); the stop, a plane of
+        // index ratio 1, is a transfer and a clip
+        auto surf = [&](const int s) __attribute__((always_inline)) {
+            r.z -= (T)L.tprev[s];
+            SDIRT_FAIL(!(r.dz > T(0)), kInvalid);
+            sphere(s, L.code[s], (T)L.c[s], (T)L.semi2[s]);
+            rec(s, r);
+        };
+        const int stop = L.stop;
+        for (; s0 < stop; ++s0) surf(s0);
+        if (s0 < L.S && (L.code[s0] & 0x7f) == SDIRT_STOP) {
+            r.z -= (T)L.tprev[s0];
+            SDIRT_FAIL(!(r.dz > T(0)), kInvalid);
+            const T tau = -r.z * rcp_t<T>(r.dz);
+            r.x += tau * r.dx;
+            r.y += tau * r.dy;
+            r.z = T(0);
+            SDIRT_FAIL(r.x * r.x + r.y * r.y > (T)L.semi2[s0], kClip);
+            rec(s0, r);
+            ++s0;
+        }
+        for (; s0 < L.S; ++s0) surf(s0);
+    }
+    for (int s = s0; GENERAL && s < L.S; ++s) {
         const int code = L.code[s];
         const int kind = code & 0x7f;
         const T c = (T)L.c[s];
         const T semi2 = (T)L.semi2[s];
         r.z -= (T)L.tprev[s];
         SDIRT_FAIL(!(r.dz > T(0)), kInvalid);
-        if (!GENERAL || kind == SDIRT_SPHERE) {
-            const T F = c * (r.x * r.x + r.y * r.y + r.z * r.z) - T(2) * r.z;
-            const T G = r.dz - c * (r.x * r.dx + r.y * r.dy + r.z * r.dz);
-            const T disc = G * G - c * F;
-            SDIRT_FAIL(disc < T(0), kMiss);
-            // sqrt(disc) is also the cosine of the incidence angle at the
-            // hit: with n = (-c x, -c y, 1 - c z) there, d.n = G - c t
-            const T cosI = sqrt_live<T>(disc);
-            T t;
-            if (sizeof(T) == sizeof(double) && (code & 0x80))
-                t = (G - cosI) * (T)L.inv_c[s];
-            else
-                t = F * rcp_t<T>(G + cosI);
-            r.x += t * r.dx;
-            r.y += t * r.dy;
-            r.z += t * r.dz;
-            SDIRT_FAIL(r.x * r.x + r.y * r.y > semi2, kClip);
-            // vector Snell with cos^2 I = disc: K = 1 - m^2 (1 - disc)
-            const T m = (T)mu[s];
-            const T m2 = m * m;
-            const T K = fma(m2, disc, T(1) - m2);
-            SDIRT_FAIL(K < T(0), kTir);
-            const T g = sqrt_live<T>(K) - m * cosI;
-            const T gc = g * c;
-            r.dx = fma(-gc, r.x, m * r.dx);
-            r.dy = fma(-gc, r.y, m * r.dy);
-            r.dz = fma(g, fma(-c, r.z, T(1)), m * r.dz);
+        if (kind == SDIRT_SPHERE) {
+            sphere(s, code, c, semi2);
         } else {
             const T tau = -r.z * rcp_t<T>(r.dz);
             r.x += tau * r.dx;
