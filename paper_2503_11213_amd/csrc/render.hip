@@ -285,8 +285,9 @@ __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A)
 //
 // Forward: a workgroup owns one channel of a 64 x 64 pixel tile (512 strips)
 // and first lists its (strip, entry, pixel mask) items grouped by entry, in
-// chunks of at most 64 items of one entry; its four waves then take the
-// chunks in turn, with the clamped image halo in LDS.  Grouping by entry over
+// chunks of at most 64 items of one entry; its four waves then take chunks
+// as they free up (whole chunks first), with the clamped image halo in LDS.
+// Grouping by entry over
 // the whole tile keeps the matrix-core columns busy where a fixed pixel block
 // would straddle several entries.  Channels are separate workgroups (the
 // slowest grid index), which evens out the work per workgroup and keeps one
@@ -437,7 +438,7 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
     __shared__ int items[kGMaxItems];                    // strip | mask << 9
     __shared__ int chunk_key[kGMaxChunks], chunk_pos[kGMaxChunks];
     __shared__ int red[kRBlock / 64];
-    __shared__ int n_items, n_chunks;
+    __shared__ int n_items, n_full, n_part, next_chunk;
     __shared__ __align__(16) float arows[kRBlock / 64][4 * M::ROW];   // per wave: 2 buffers x 2 sides
     const int pad = (KS - 1) / 2;
     const int kk = KS * KS;
@@ -470,7 +471,7 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
     bool more = true;
     while (more) {
         // ---- list a batch of entries, grouped, in chunks of <= 64 items
-        if (tid == 0) { n_items = 0; n_chunks = 0; }
+        if (tid == 0) { n_items = 0; n_full = 0; n_part = 0; }
         __syncthreads();
         while (true) {
             int mine = 0x7fffffff;
@@ -488,7 +489,7 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
             const int start = n_items;
             // capacity: a batch ends before an entry that might not fit
             const bool fits = start + kGStrips <= kGMaxItems &&
-                              n_chunks + kGStrips / 64 <= kGMaxChunks;
+                              n_full + n_part + kGStrips / 64 <= kGMaxChunks;
             __syncthreads();
             if (k == 0x7fffffff) { more = false; break; }
             if (!fits) break;
@@ -506,15 +507,19 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
             }
             __syncthreads();
             if (tid == 0) {
+                // full chunks from the front of the table, partial ones from
+                // the back: the waves take the full ones first
                 for (int s0 = start; s0 < n_items; s0 += 64) {
-                    chunk_key[n_chunks] = k;
-                    chunk_pos[n_chunks] = s0 | (min(64, n_items - s0) << 16);
-                    ++n_chunks;
+                    const int cnt = min(64, n_items - s0);
+                    const int slot = cnt == 64 ? n_full++ : kGMaxChunks - 1 - n_part++;
+                    chunk_key[slot] = k;
+                    chunk_pos[slot] = s0 | (cnt << 16);
                 }
+                next_chunk = 0;
             }
             __syncthreads();
         }
-        const int T = n_chunks;
+        const int T = n_full + n_part, nf = n_full;
         // ---- render the batch
         {
             const int lam = A.lam_of_c[c];
@@ -526,7 +531,13 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
                 halo[e] = im[(size_t)yy * A.W + xx];
             }
             __syncthreads();
-            for (int ch = wave; ch < T; ch += kRBlock / 64) {
+            while (true) {
+                // chunks go to the waves as they free up
+                int j = 0;
+                if (lane == 0) j = atomicAdd(&next_chunk, 1);
+                j = __builtin_amdgcn_readfirstlane(j);
+                if (j >= T) break;
+                const int ch = j < nf ? j : kGMaxChunks - 1 - (j - nf);
                 const int k = __builtin_amdgcn_readfirstlane(chunk_key[ch]);
                 const int cp = __builtin_amdgcn_readfirstlane(chunk_pos[ch]);
                 const int cnt = cp >> 16, s0 = cp & 0xffff;
