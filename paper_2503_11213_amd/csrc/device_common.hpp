@@ -248,10 +248,12 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         if (EXACT) { if ((cond) && status == kAlive) status = (code); } \
         else alive = alive && !(cond);                           \
     } while (0)
-    // sphere, or a flat surface as a sphere of curvature 0
-    auto sphere = [&](const int s, const int code, const T c, const T semi2)
+    // sphere, or a flat surface as a sphere of curvature 0.  rho2 = x^2 + y^2
+    // of the current point on entry, of the hit on return (the clip test's
+    // value, reused by the next surface: a transfer along z leaves it).
+    auto sphere = [&](const int s, const int code, const T c, const T semi2, T& rho2)
                       __attribute__((always_inline)) {
-        const T F = c * (r.x * r.x + r.y * r.y + r.z * r.z) - T(2) * r.z;
+        const T F = c * fma(r.z, r.z, rho2) - T(2) * r.z;
         const T G = r.dz - c * (r.x * r.dx + r.y * r.dy + r.z * r.dz);
         const T disc = G * G - c * F;
         SDIRT_FAIL(disc < T(0), kMiss);
@@ -266,7 +268,8 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         r.x += t * r.dx;
         r.y += t * r.dy;
         r.z += t * r.dz;
-        SDIRT_FAIL(r.x * r.x + r.y * r.y > semi2, kClip);
+        rho2 = r.x * r.x + r.y * r.y;
+        SDIRT_FAIL(rho2 > semi2, kClip);
         // vector Snell with cos^2 I = disc: K = 1 - m^2 (1 - disc)
         const T m = (T)mu[s];
         const T m2 = m * m;
@@ -283,10 +286,11 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         // spheres and flats only: every surface but the aperture stop takes
         // the sphere path (no per-surface branches); the stop, a plane of
         // index ratio 1, is a transfer and a clip
+        T rho2 = r.x * r.x + r.y * r.y;
         auto surf = [&](const int s) __attribute__((always_inline)) {
             r.z -= (T)L.tprev[s];
             SDIRT_FAIL(!(r.dz > T(0)), kInvalid);
-            sphere(s, L.code[s], (T)L.c[s], (T)L.semi2[s]);
+            sphere(s, L.code[s], (T)L.c[s], (T)L.semi2[s], rho2);
             rec(s, r);
         };
         const int stop = L.stop;
@@ -298,7 +302,8 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
             r.x += tau * r.dx;
             r.y += tau * r.dy;
             r.z = T(0);
-            SDIRT_FAIL(r.x * r.x + r.y * r.y > (T)L.semi2[s0], kClip);
+            rho2 = r.x * r.x + r.y * r.y;
+            SDIRT_FAIL(rho2 > (T)L.semi2[s0], kClip);
             rec(s0, r);
             ++s0;
         }
@@ -312,7 +317,8 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         r.z -= (T)L.tprev[s];
         SDIRT_FAIL(!(r.dz > T(0)), kInvalid);
         if (kind == SDIRT_SPHERE) {
-            sphere(s, code, c, semi2);
+            T rho2 = r.x * r.x + r.y * r.y;
+            sphere(s, code, c, semi2, rho2);
         } else {
             const T tau = -r.z * rcp_t<T>(r.dz);
             r.x += tau * r.dx;
