@@ -276,6 +276,34 @@ int sdirt_mlp_forward(const sdirt_mlp_desc* desc, const float* params,
                       long long n_rows, const float* x, void* out, int out_dtype,
                       void* workspace, int ws_batch, void* stream);
 
+/* The surrogate render (Fig. 2(c); Sec. 3.2): every pixel of an image
+ * rendered with the PSF the network predicts for it, without the dense PSF
+ * map ever reaching memory.  For each image n, channel c and pixel (y, x)
+ * the network's softmax output P for the input (h_x, h_y, 1/d, lambda_c),
+ * read as [2][ks][ks], gives
+ *   out[n, s*C + c, y, x] = sum_{i,j} P[s][i][j]
+ *                           * img[n, c, clamp(y+pad-i), clamp(x+pad-j)],
+ * i.e. sdirt_mlp_forward into a float32 dense map followed by
+ * sdirt_render_dp with per-channel kernels, with the inputs formed in
+ * float32 as h_x = (x - (W-1)/2) * pitch, h_y = (y - (H-1)/2) * pitch,
+ * 1/d = 1.0f / depth[n, y, x] (depth in mm), lambda_c = wavelength[c] (um).
+ * The network must have width 256 and n_out = 2 ks ks (odd ks <= 65).
+ * img device [N][C][H][W] f32, depth device [N][H][W] f32, out device
+ * [N][2C][H][W] f32 (overwritten); workspace as for sdirt_mlp_forward with
+ * ws_batch rows (a multiple of 64; rows are processed 64 pixels, one 8 x 8
+ * tile of one channel, at a time). */
+typedef struct {
+    int N, C, H, W;          /* images, channels (1..4), rows, columns      */
+    int ks;                  /* PSF window (n_out = 2 ks ks)                 */
+    double pitch;            /* pixel pitch (mm)                              */
+    double wavelength[4];    /* wavelength of each channel (um)               */
+} sdirt_mlp_render_desc;
+
+int sdirt_mlp_render(const sdirt_mlp_desc* desc, const float* params,
+                     const sdirt_mlp_render_desc* render, const float* img,
+                     const float* depth, float* out, void* workspace, int ws_batch,
+                     void* stream);
+
 /* Loss and its gradient for one batch: grads_out device [n_params] f32,
  * loss_out device [1] f32 (either may be NULL); target device
  * [batch][n_out], each row a jointly sum-normalised PSF. */

@@ -138,3 +138,36 @@ def adam_init(params):
     return {"step": 0,
             "m": [[np.zeros_like(W), np.zeros_like(b)] for W, b in params],
             "v": [[np.zeros_like(W), np.zeros_like(b)] for W, b in params]}
+
+
+def pixel_inputs(N, C, H, W, pitch, depth, wavelengths):
+    """Network inputs of every pixel and channel, formed in float32 as the
+    surrogate render defines them: h_x = (x - (W - 1) / 2) * pitch, h_y
+    likewise, 1/d = 1 / depth (float32 division), lambda_c.  Returns
+    [N, H, W, C, 4] float32."""
+    f32 = np.float32
+    pitch = f32(pitch)
+    xs = (np.arange(W, dtype=np.float32) - f32(0.5) * f32(W - 1)) * pitch
+    ys = (np.arange(H, dtype=np.float32) - f32(0.5) * f32(H - 1)) * pitch
+    depth = np.asarray(depth, dtype=np.float32).reshape(N, H, W)
+    x = np.empty((N, H, W, C, 4), dtype=np.float32)
+    x[..., 0] = xs[None, None, :, None]
+    x[..., 1] = ys[None, :, None, None]
+    x[..., 2] = (f32(1.0) / depth)[..., None]
+    x[..., 3] = np.asarray(wavelengths, dtype=np.float32)[:C][None, None, None, :]
+    return x
+
+
+def render_surrogate(params, img, depth, wavelengths, pitch, norm, bf16=True):
+    """Fig. 2(c) / Sec. 3.2: the all-in-focus image rendered with the PSF the
+    network predicts for every pixel and channel: the softmax output of
+    forward() read as [2][ks][ks] is that pixel's per-channel kernel of the
+    dense renderer (oracle.render.render_dense).  img [N, C, H, W]."""
+    from oracle import render as R
+    img = np.asarray(img, dtype=np.float64)
+    N, C, H, W = img.shape
+    x = pixel_inputs(N, C, H, W, pitch, depth, wavelengths)
+    p, _ = forward(params, x.reshape(-1, 4).astype(np.float64), norm, bf16=bf16)
+    ks = int(round(np.sqrt(p.shape[1] // 2)))
+    K = p.reshape(N, H, W, C, 2, ks, ks)
+    return R.render_dense(img, K)

@@ -81,6 +81,11 @@ class MlpDesc(C.Structure):
                 ("lam_lo", C.c_double), ("lam_hi", C.c_double), ("loss", C.c_int)]
 
 
+class MlpRenderDesc(C.Structure):
+    _fields_ = [("N", C.c_int), ("C", C.c_int), ("H", C.c_int), ("W", C.c_int),
+                ("ks", C.c_int), ("pitch", C.c_double), ("wavelength", C.c_double * 4)]
+
+
 # exported symbol -> (restype, argtypes)
 SIGNATURES = {
     "sdirt_version": (C.c_int, []),
@@ -112,6 +117,9 @@ SIGNATURES = {
     "sdirt_mlp_forward": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_longlong,
                                     C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                                     C.c_int, C.c_void_p]),
+    "sdirt_mlp_render": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.POINTER(MlpRenderDesc),
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                   C.c_void_p]),
     "sdirt_mlp_backward": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_int,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),

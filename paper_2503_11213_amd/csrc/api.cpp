@@ -24,6 +24,8 @@ int mlp_n_params(const sdirt_mlp_desc*, long long*);
 int mlp_workspace_size(const sdirt_mlp_desc*, int, size_t*);
 int mlp_forward(const sdirt_mlp_desc*, const float*, long long, const float*, void*, int,
                 void*, int, hipStream_t);
+int mlp_render(const sdirt_mlp_desc*, const float*, const sdirt_mlp_render_desc*, const float*,
+               const float*, float*, void*, int, hipStream_t);
 int mlp_backward(const sdirt_mlp_desc*, const float*, int, const float*, const float*,
                  float*, float*, void*, hipStream_t);
 int mlp_adam(const sdirt_mlp_desc*, float*, float*, float*, const float*, int, float,
@@ -138,6 +140,14 @@ int sdirt_mlp_forward(const sdirt_mlp_desc* desc, const float* params, long long
                       int ws_batch, void* stream) {
     return mlp_forward(desc, params, n_rows, x, out, out_dtype, workspace, ws_batch,
                        (hipStream_t)stream);
+}
+
+int sdirt_mlp_render(const sdirt_mlp_desc* desc, const float* params,
+                     const sdirt_mlp_render_desc* render, const float* img,
+                     const float* depth, float* out, void* workspace, int ws_batch,
+                     void* stream) {
+    return mlp_render(desc, params, render, img, depth, out, workspace, ws_batch,
+                      (hipStream_t)stream);
 }
 
 int sdirt_mlp_backward(const sdirt_mlp_desc* desc, const float* params, int batch,

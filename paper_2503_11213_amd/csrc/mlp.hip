@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/sdirt.h"
+#include "mlp_fused.hpp"
 
 namespace sdirt {
 
@@ -601,19 +602,6 @@ int mlp_workspace_size(const sdirt_mlp_desc* d, int batch, size_t* out) {
     return SDIRT_OK;
 }
 
-struct FusedArgs {
-    long long n_rows;
-    int n_hidden, n_out, n_freq, feat_pad;
-    float x_half, y_half, iv_lo, iv_hi, lam_lo, lam_hi;
-    const float* x;
-    const float* params;
-    long long b_off[17];
-    const bf16_t* W[17];
-    void* out;
-    int out_bf16;
-};
-int launch_mlp_fused(const FusedArgs& A, bf16_t* hbuf, long long chunk, hipStream_t st);
-
 int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, const float* x,
                 void* out, int out_dtype, void* workspace, int ws_batch, hipStream_t st) {
     MlpDims m;
@@ -653,6 +641,42 @@ int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, 
         hipLaunchKernelGGL(softmax_loss_kernel, dim3(B), dim3(256), 0, st, s);
     }
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
+}
+
+int mlp_render(const sdirt_mlp_desc* d, const float* params, const sdirt_mlp_render_desc* rd,
+               const float* img, const float* depth, float* out, void* workspace, int ws_batch,
+               hipStream_t st) {
+    MlpDims m;
+    int rc = dims_of(d, &m);
+    if (rc) return rc;
+    if (!params || !rd || !img || !depth || !out || !workspace) return SDIRT_EINVAL;
+    if (ws_batch < 64 || ws_batch % 64) return SDIRT_EINVAL;
+    if (rd->N < 1 || rd->C < 1 || rd->H < 1 || rd->W < 1) return SDIRT_EINVAL;
+    if (rd->C > 4) return SDIRT_EUNSUPPORTED;
+    if (rd->ks < 1 || rd->ks % 2 == 0 || 2 * rd->ks * rd->ks != m.n_out) return SDIRT_EINVAL;
+    if (m.width != 256 || rd->ks > 65) return SDIRT_EUNSUPPORTED;
+    if (!std::isfinite(rd->pitch) || !(rd->pitch > 0)) return SDIRT_EINVAL;
+    for (int c = 0; c < rd->C; ++c)
+        if (!std::isfinite(rd->wavelength[c]) || !(rd->wavelength[c] > 0)) return SDIRT_EINVAL;
+    if ((long long)rd->H * rd->W > (1LL << 30)) return SDIRT_EUNSUPPORTED;
+    const MlpWs w = carve(m, ws_batch, (char*)workspace);
+    frag_all(m, w, params, st);
+    FusedArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.n_hidden = m.n_hidden; f.n_out = m.n_out; f.n_freq = m.n_freq;
+    f.feat_pad = feat_pad(m);
+    f.x_half = (float)d->x_half; f.y_half = (float)d->y_half;
+    f.iv_lo = (float)d->iv_lo; f.iv_hi = (float)d->iv_hi;
+    f.lam_lo = (float)d->lam_lo; f.lam_hi = (float)d->lam_hi;
+    f.params = params;
+    for (int l = 0; l < m.L; ++l) { f.b_off[l] = (long long)m.b_off(l); f.W[l] = w.WF[l]; }
+    f.depth = depth; f.img = img; f.rout = out;
+    f.img_n = rd->N; f.img_c = rd->C; f.img_h = rd->H; f.img_w = rd->W; f.ks = rd->ks;
+    f.tiles_x = (rd->W + 7) / 8; f.tiles_y = (rd->H + 7) / 8;
+    f.pitch = (float)rd->pitch;
+    for (int c = 0; c < rd->C; ++c) f.lam[c] = (float)rd->wavelength[c];
+    f.n_rows = (long long)rd->N * rd->C * f.tiles_x * f.tiles_y * 64;
+    return launch_mlp_render(f, w.H[m.n_hidden], ws_batch, st);
 }
 
 int mlp_backward(const sdirt_mlp_desc* d, const float* params, int batch, const float* x,

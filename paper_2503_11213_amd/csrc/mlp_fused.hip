@@ -22,10 +22,10 @@
 #include <type_traits>
 
 #include "../../include/sdirt.h"
+#include "mlp_fused.hpp"
 
 namespace sdirt {
 
-typedef uint16_t bf16_t;
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
@@ -34,17 +34,6 @@ constexpr int kFWidth = 256;           // hidden width (fixed)
 constexpr int kFStride = kFWidth + 8;  // LDS row stride in bf16 (bank spread)
 constexpr int kFThreads = 256;
 
-struct FusedArgs {
-    long long n_rows;
-    int n_hidden, n_out, n_freq, feat_pad;
-    float x_half, y_half, iv_lo, iv_hi, lam_lo, lam_hi;
-    const float* x;                 // [n_rows][4]
-    const float* params;            // float32 master (biases)
-    long long b_off[17];            // bias offsets per layer
-    const bf16_t* W[17];            // bf16 weights [out][in_pad]
-    void* out;                      // [n_rows][n_out]
-    int out_bf16;
-};
 
 // float -> bf16, round to nearest even (v_cvt_pk_bf16_f32)
 __device__ inline bf16_t f2bf_rne(float f) {
@@ -121,6 +110,38 @@ __device__ inline void frag_mma(const bf16_t* H, const bf16_t* WF, int KS, int c
     }
 }
 
+// Decoding of a pixel row (see FusedArgs): the image, channel and pixel; the
+// pixel is clamped into the image for the padding rows of edge tiles.
+struct PixelRow {
+    int n, c, x0, y0, x, y;
+};
+__device__ inline PixelRow pixel_row(const FusedArgs& A, long long gr) {
+    const long long T = (long long)A.tiles_x * A.tiles_y;
+    const long long blk = gr >> 6;
+    const int p = (int)(gr & 63);
+    const long long ic = blk / T;
+    const int tile = (int)(blk - ic * T);
+    PixelRow r;
+    r.n = (int)(ic / A.img_c);
+    r.c = (int)(ic - (long long)r.n * A.img_c);
+    const int ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
+    r.y0 = 8 * ty;
+    r.x0 = 8 * tx;
+    r.y = min(r.y0 + (p >> 3), A.img_h - 1);
+    r.x = min(r.x0 + (p & 7), A.img_w - 1);
+    return r;
+}
+
+// Input `part` of a pixel row, in float32: h_x = (x - (W - 1) / 2) pitch,
+// h_y likewise, 1 / depth, the channel's wavelength.
+__device__ inline float pixel_input(const FusedArgs& A, long long gr, int part) {
+    const PixelRow r = pixel_row(A, gr);
+    if (part == 0) return ((float)r.x - 0.5f * (float)(A.img_w - 1)) * A.pitch;
+    if (part == 1) return ((float)r.y - 0.5f * (float)(A.img_h - 1)) * A.pitch;
+    if (part == 2) return 1.0f / A.depth[((size_t)r.n * A.img_h + r.y) * A.img_w + r.x];
+    return A.lam[r.c];
+}
+
 // Trunk: encoding and hidden layers of 64 rows of the chunk [r_begin, r_end);
 // the last hidden activations go to hout ([rows of the chunk][256] bf16).
 __global__ __launch_bounds__(kFThreads, 2) void mlp_trunk_kernel(const FusedArgs A, long long r_begin,
@@ -135,7 +156,7 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_trunk_kernel(const FusedArgs
         const long long gr = row0 + row;
         float v = 0.f;
         if (gr < r_end) {
-            const float xv = A.x[gr * 4 + part];
+            const float xv = A.depth ? pixel_input(A, gr, part) : A.x[gr * 4 + part];
             if (part == 0) v = xv / A.x_half;
             else if (part == 1) v = xv / A.y_half;
             else if (part == 2) v = 2.f * (xv - A.iv_lo) / (A.iv_hi - A.iv_lo) - 1.f;
@@ -321,6 +342,168 @@ int launch_mlp_fused(const FusedArgs& A, bf16_t* hbuf, long long chunk, hipStrea
         else
             hipLaunchKernelGGL(mlp_head_kernel<false>, dim3((unsigned)blocks), dim3(kFThreads), 0, st, A, r0, r1,
                                (const bf16_t*)hbuf);
+    }
+    return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
+}
+
+// Fused surrogate render: the softmax layer of the 64 rows of one 8 x 8
+// pixel tile of one channel, reduced against the tile's image windows in the
+// same pass instead of being written out.  With the column k of a row taken
+// as (side s, tap (i, j)) and w_k the image value under that tap (clamped
+// image, staged in LDS), the row's outputs are
+//     out_s = sum_{k in side s} 2^(z_k - M) w_k / sum_k 2^(z_k - M),
+// so one pass keeps per row and lane a running max M, the sum S and the two
+// weighted sums (all rescaled together when M rises).
+__global__ __launch_bounds__(kFThreads, 2) void mlp_render_head_kernel(const FusedArgs A,
+                                                                     long long r_begin,
+                                                                     long long r_end,
+                                                                     const bf16_t* hin) {
+    __shared__ bf16_t Hs[kFRows * kFStride];
+    __shared__ float stat[4][kFRows][4];                 // per wave: M, S, a_left, a_right
+    extern __shared__ float halo[];                      // [8 + ks - 1]^2 image values
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g4 = (lane >> 4) * 4;
+    const long long row0 = r_begin + (long long)blockIdx.x * kFRows;
+    const PixelRow pr = pixel_row(A, row0);              // the tile (row0 is its pixel 0)
+    const int ks = A.ks, kk = ks * ks, pad = (ks - 1) / 2, hh = 8 + ks - 1;
+    for (int e = tid; e < kFRows * (kFWidth / 8); e += kFThreads) {
+        const int row = e / (kFWidth / 8), c8 = e % (kFWidth / 8);
+        const bf16x8_t zero = {};
+        *reinterpret_cast<bf16x8_t*>(Hs + row * kFStride + 8 * c8) =
+            row0 + row < r_end
+                ? *reinterpret_cast<const bf16x8_t*>(hin + (size_t)(row0 - r_begin + row) * kFWidth + 8 * c8)
+                : zero;
+    }
+    const float* im = A.img + ((size_t)pr.n * A.img_c + pr.c) * A.img_h * A.img_w;
+    for (int e = tid; e < hh * hh; e += kFThreads) {
+        const int r = e / hh, q = e - r * hh;
+        const int yy = min(max(pr.y0 - pad + r, 0), A.img_h - 1);
+        const int xx = min(max(pr.x0 - pad + q, 0), A.img_w - 1);
+        halo[e] = im[(size_t)yy * A.img_w + xx];
+    }
+    __syncthreads();
+    // the lane's rows 16 i + g4 + r are pixels (row / 8, row % 8); tap (i, j)
+    // of output pixel (py, px) reads halo[py + 2 pad - i][px + 2 pad - j]
+    int hb[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * i + g4 + r;
+            hb[4 * i + r] = ((row >> 3) + 2 * pad) * hh + (row & 7) + 2 * pad;
+        }
+    constexpr float kL2E = 1.4426950408889634f;
+    constexpr float kNone = -1e30f;
+    const int Lo = A.n_hidden;
+    const bf16_t* Wo = A.W[Lo];
+    const float* bo = A.params + A.b_off[Lo];
+    const int ntile = (A.n_out + 63) / 64;
+    floatx4_t acc[4][4];
+    float m[16], s[16], al[16], ar[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) { m[k] = kNone; s[k] = 0.f; al[k] = 0.f; ar[k] = 0.f; }
+    for (int t = wave; t < ntile; t += 4) {
+        frag_mma(Hs, Wo, kFWidth / 32, 64 * t, acc);
+        float bl[4], right[4];
+        int coff[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = 64 * t + 16 * j + r16;
+            const bool valid = n < A.n_out;
+            bl[j] = valid ? bo[n] * kL2E : kNone;
+            const int side = n >= kk;
+            const int tap = valid ? n - side * kk : 0;
+            const int ti = tap / ks;
+            coff[j] = ti * hh + (tap - ti * ks);
+            right[j] = side ? 1.f : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = 4 * i + r;
+                float z[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) z[j] = fmaf(acc[i][j][r], kL2E, bl[j]);
+                const float mn = fmaxf(fmaxf(m[k], fmaxf(z[0], z[1])), fmaxf(z[2], z[3]));
+                if (__ballot(mn > m[k])) {
+                    const float sc = __builtin_amdgcn_exp2f(m[k] - mn);
+                    s[k] *= sc; al[k] *= sc; ar[k] *= sc;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float e = __builtin_amdgcn_exp2f(z[j] - mn);
+                    const float ew = e * halo[hb[k] - coff[j]];
+                    s[k] += e;
+                    al[k] = fmaf(ew, 1.f - right[j], al[k]);
+                    ar[k] = fmaf(ew, right[j], ar[k]);
+                }
+                m[k] = mn;
+            }
+    }
+    // merge over the 16 lanes holding the same rows, then over the 4 waves
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const float m2 = __shfl_xor(m[k], o, 64);
+            const float s2 = __shfl_xor(s[k], o, 64);
+            const float l2 = __shfl_xor(al[k], o, 64);
+            const float q2 = __shfl_xor(ar[k], o, 64);
+            const float mn = fmaxf(m[k], m2);
+            const float f1 = __builtin_amdgcn_exp2f(m[k] - mn), f2 = __builtin_amdgcn_exp2f(m2 - mn);
+            s[k] = s[k] * f1 + s2 * f2;
+            al[k] = al[k] * f1 + l2 * f2;
+            ar[k] = ar[k] * f1 + q2 * f2;
+            m[k] = mn;
+        }
+    }
+    if (r16 == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float* st = stat[wave][16 * i + g4 + r];
+                const int k = 4 * i + r;
+                st[0] = m[k]; st[1] = s[k]; st[2] = al[k]; st[3] = ar[k];
+            }
+    }
+    __syncthreads();
+    if (tid < kFRows) {
+        const int row = tid;
+        float mm = stat[0][row][0], ss = stat[0][row][1], ll = stat[0][row][2], qq = stat[0][row][3];
+        for (int w = 1; w < 4; ++w) {
+            const float m2 = stat[w][row][0];
+            const float mn = fmaxf(mm, m2);
+            const float f1 = __builtin_amdgcn_exp2f(mm - mn), f2 = __builtin_amdgcn_exp2f(m2 - mn);
+            ss = ss * f1 + stat[w][row][1] * f2;
+            ll = ll * f1 + stat[w][row][2] * f2;
+            qq = qq * f1 + stat[w][row][3] * f2;
+            mm = mn;
+        }
+        const int y = pr.y0 + (row >> 3), x = pr.x0 + (row & 7);
+        if (row0 + row < r_end && y < A.img_h && x < A.img_w) {
+            const float inv = 1.f / ss;
+            const size_t plane = (size_t)A.img_h * A.img_w;
+            float* o = A.rout + ((size_t)pr.n * 2 * A.img_c + pr.c) * plane + (size_t)y * A.img_w + x;
+            o[0] = ll * inv;
+            o[(size_t)A.img_c * plane] = qq * inv;
+        }
+    }
+}
+
+int launch_mlp_render(const FusedArgs& A, bf16_t* hbuf, long long chunk, hipStream_t st) {
+    if (A.n_rows <= 0) return SDIRT_OK;
+    if (chunk < kFRows || chunk % kFRows) return SDIRT_EINVAL;
+    const int hh = 8 + A.ks - 1;
+    const size_t shm = (size_t)hh * hh * sizeof(float);
+    for (long long r0 = 0; r0 < A.n_rows; r0 += chunk) {
+        const long long r1 = std::min(A.n_rows, r0 + chunk);
+        const long long blocks = (r1 - r0 + kFRows - 1) / kFRows;
+        if (blocks > 0x7fffffffLL) return SDIRT_EUNSUPPORTED;
+        hipLaunchKernelGGL(mlp_trunk_kernel, dim3((unsigned)blocks), dim3(kFThreads), 0, st, A, r0, r1, hbuf);
+        hipLaunchKernelGGL(mlp_render_head_kernel, dim3((unsigned)blocks), dim3(kFThreads), shm, st, A, r0,
+                           r1, (const bf16_t*)hbuf);
     }
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
 }

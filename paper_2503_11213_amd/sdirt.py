@@ -261,6 +261,24 @@ def mlp_forward(desc, params, x, workspace, ws_batch, out_dtype=abi.F32, out=Non
     return out
 
 
+def mlp_render(desc, params, img, depth, wavelengths, pitch, workspace, ws_batch, out=None):
+    """Surrogate render: img [N][C][H][W] f32 rendered with the network's PSF
+    for every pixel and channel (depth [N][H][W] mm, wavelengths [C] um,
+    pitch mm); returns out [N][2C][H][W] f32."""
+    N, C_, H, W = img.shape
+    ks = int(round((desc.n_out // 2) ** 0.5))
+    rd = abi.MlpRenderDesc(N, C_, H, W, ks, float(pitch))
+    for c, lam in enumerate(wavelengths):
+        rd.wavelength[c] = float(lam)
+    if out is None:
+        out = torch.empty((N, 2 * C_, H, W), dtype=torch.float32, device=img.device)
+    rc = abi.lib().sdirt_mlp_render(C.byref(desc), _dptr(params), C.byref(rd),
+                                    _dptr(img.contiguous()), _dptr(depth.contiguous()),
+                                    _dptr(out), _dptr(workspace), int(ws_batch), _stream())
+    abi.check("sdirt_mlp_render", rc)
+    return out
+
+
 def mlp_backward(desc, params, x, target, workspace):
     grads = torch.empty_like(params)
     loss = torch.empty((1,), dtype=torch.float32, device=params.device)

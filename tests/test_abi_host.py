@@ -141,3 +141,30 @@ def test_mlp_desc_validation():
     d.loss = abi.LOSS_L2MAX
     d.width = 100
     assert lib.sdirt_mlp_n_params(C.byref(d), C.byref(n)) == abi.EINVAL
+
+
+def test_surrogate_render_argument_validation():
+    # rejected on the host before any device work
+    lib = abi.lib()
+    d = sdirt.make_mlp_desc(n_hidden=5, width=256, n_out=2178, n_freq=8, x_half=4.5,
+                            y_half=3.0, iv_lo=2e-4, iv_hi=2e-3, lam_lo=0.486, lam_hi=0.656)
+    p = C.c_void_p(16)     # never dereferenced: the call fails before any launch
+
+    def call(rd, ws=64, ptr=p):
+        return lib.sdirt_mlp_render(C.byref(d), ptr, C.byref(rd), ptr, ptr, ptr, ptr, ws, None)
+
+    good = dict(N=1, C=3, H=8, W=8, ks=33, pitch=0.005)
+    def desc(**kw):
+        a = dict(good); a.update(kw)
+        rd = abi.MlpRenderDesc(a["N"], a["C"], a["H"], a["W"], a["ks"], a["pitch"])
+        for c in range(4):
+            rd.wavelength[c] = 0.55
+        return rd
+    assert call(desc(ks=31)) == abi.EINVAL                 # 2 ks^2 != n_out
+    assert call(desc(C=5)) == abi.EUNSUPPORTED
+    assert call(desc(N=0)) == abi.EINVAL
+    assert call(desc(pitch=-1.0)) == abi.EINVAL
+    assert call(desc(), ws=100) == abi.EINVAL              # not a multiple of 64
+    assert call(desc(), ptr=None) == abi.EINVAL
+    rd = desc(); rd.wavelength[1] = float("nan")
+    assert call(rd) == abi.EINVAL

@@ -13,6 +13,9 @@ pytestmark = pytest.mark.gpu
 NORM = dict(x_half=4.5024, y_half=3.0016, iv_lo=1 / 5000, iv_hi=1 / 500, lam_lo=0.486,
             lam_hi=0.656)
 REL = 1e-2
+# the surrogate render averages the image under each PSF, which damps the
+# PSFs' own bf16-level differences (measured: 1e-4 .. 6e-4)
+REL_RENDER = 3e-3
 
 
 def _desc(n_out=2 * 33 * 33, width=256, n_hidden=5, loss=abi.LOSS_L2MAX):
@@ -168,3 +171,67 @@ def test_fused_forward_output_widths(n_out):
                               64, out_dtype=dt).float().cpu().numpy()
         assert _rel_l2(p, ref) <= REL
         assert np.allclose(p.sum(axis=1), 1.0, atol=2e-2 if dt == abi.BF16 else 1e-4)
+
+
+@pytest.mark.parametrize("ks,N,C,H,W,ws", [(9, 2, 3, 20, 27, 128), (33, 1, 3, 18, 21, 4096),
+                                          (5, 1, 1, 9, 8, 64)])
+def test_surrogate_render_matches_oracle(ks, N, C, H, W, ws):
+    # per-pixel network PSFs consumed by the renderer in one pass; ragged
+    # 8 x 8 tiles, several workspace chunks, one and three channels
+    widths = [64, 256, 256, 256, 256, 256, 2 * ks * ks]
+    layers, flat = _params(widths, 3)
+    rng = np.random.default_rng(4)
+    img = rng.uniform(0, 1, (N, C, H, W)).astype(np.float32)
+    depth = rng.uniform(500, 5000, (N, H, W)).astype(np.float32)
+    lams = [0.656, 0.55, 0.486][:C]
+    pitch = 0.3
+    d = _desc(n_out=2 * ks * ks)
+    ws_t = sdirt.mlp_workspace(d, ws)
+    out = sdirt.mlp_render(d, torch.from_numpy(flat).cuda(), torch.from_numpy(img).cuda(),
+                           torch.from_numpy(depth).cuda(), lams, pitch, ws_t, ws)
+    got = out.cpu().numpy()
+    ref = M.render_surrogate(_oracle_params(layers), img, depth, lams, pitch, NORM, bf16=True)
+    err = _rel_l2(got, ref)
+    print("surrogate render rel L2", err)
+    assert err <= REL_RENDER
+    # the two sides together average the window: totals match the box filter
+    # of a constant image exactly
+    one = torch.ones((N, C, H, W), device="cuda")
+    o1 = sdirt.mlp_render(d, torch.from_numpy(flat).cuda(), one, torch.from_numpy(depth).cuda(),
+                          lams, pitch, ws_t, ws).cpu().numpy()
+    assert np.allclose(o1[:, :C] + o1[:, C:], 1.0, atol=1e-5)
+
+
+def test_surrogate_render_full_size_sampled_pixels():
+    # the benchmarked launch shape: 1680 x 1120 RGB, ks 33, 65536-row chunks
+    ks, N, C, H, W, ps = 33, 1, 3, 1120, 1680, 0.00536
+    widths = [64, 256, 256, 256, 256, 256, 2 * ks * ks]
+    layers, flat = _params(widths, 5)
+    img = scenes.aif_blobs(H, W, C, n_blobs=300, seed=0)[None]
+    depth = scenes.depth_voronoi(H, W, 500.0, 5000.0, seed=100)[None].astype(np.float32)
+    lams = [0.656, 0.55, 0.486]
+    norm = dict(x_half=W * ps / 2, y_half=H * ps / 2, iv_lo=0.2e-3, iv_hi=2.0e-3,
+                lam_lo=0.486, lam_hi=0.656)
+    d = sdirt.make_mlp_desc(n_hidden=5, width=256, n_out=2 * ks * ks, n_freq=8, **norm)
+    ws_t = sdirt.mlp_workspace(d, 65536)
+    out = sdirt.mlp_render(d, torch.from_numpy(flat).cuda(), torch.from_numpy(img).cuda(),
+                           torch.from_numpy(depth).cuda(), lams, ps, ws_t, 65536).cpu().numpy()
+    x = M.pixel_inputs(N, C, H, W, ps, depth, lams)
+    rng = np.random.default_rng(8)
+    pix = [(0, 0), (H - 1, W - 1), (0, W - 1), (H - 1, 0), (560, 840), (7, 8)] + \
+          [(int(rng.integers(H)), int(rng.integers(W))) for _ in range(30)]
+    pad = (ks - 1) // 2
+    got, ref = [], []
+    for (y, xx) in pix:
+        p, _ = M.forward(_oracle_params(layers), x[0, y, xx].astype(np.float64), norm, bf16=True)
+        rows = np.clip(y + pad - np.arange(ks), 0, H - 1)
+        cols = np.clip(xx + pad - np.arange(ks), 0, W - 1)
+        for c in range(C):
+            win = img[0, c][rows][:, cols]
+            K = p[c].reshape(2, ks, ks)
+            ref.append([(K[s] * win).sum() for s in range(2)])
+            got.append([out[0, c, y, xx], out[0, C + c, y, xx]])
+    got, ref = np.array(got), np.array(ref)
+    err = _rel_l2(got, ref)
+    print("full-size surrogate render rel L2", err)
+    assert err <= REL_RENDER

@@ -137,3 +137,57 @@ def test_kl_loss_and_gradient_match_torch_library():
     for (gW, gb), (W, b) in zip(grads, tw):
         assert np.allclose(gW, W.grad.numpy(), rtol=1e-10, atol=1e-15)
         assert np.allclose(gb, b.grad.numpy(), rtol=1e-10, atol=1e-15)
+
+
+def _surrogate_case(ks, seed):
+    rng = np.random.default_rng(seed)
+    N, C, H, W = 1, 2, 11, 14
+    img = rng.uniform(0, 1, (N, C, H, W))
+    depth = rng.uniform(500, 5000, (N, H, W))
+    params = _params([64, 16, 2 * ks * ks], seed)
+    return img, depth, params
+
+
+def test_surrogate_render_uniform_psf_is_half_the_box_mean():
+    # zero output layer: every PSF is uniform, 1 / (2 ks^2) per tap, so each
+    # side is half the mean of the replicate-padded ks x ks window
+    from scipy.ndimage import uniform_filter
+    ks = 5
+    img, depth, params = _surrogate_case(ks, 1)
+    W_out, b_out = params[-1]
+    params[-1] = (np.zeros_like(W_out), np.zeros_like(b_out))
+    out = mlp.render_surrogate(params, img, depth, [0.5, 0.6], 0.01, NORM, bf16=False)
+    for c in range(2):
+        box = uniform_filter(img[0, c], size=ks, mode="nearest")
+        assert np.allclose(out[0, c], box / 2, atol=1e-12)
+        assert np.allclose(out[0, 2 + c], box / 2, atol=1e-12)
+
+
+@pytest.mark.parametrize("side,i,j", [(0, 2, 2), (1, 0, 0), (1, 4, 1)])
+def test_surrogate_render_delta_psf_shifts_the_image(side, i, j):
+    # one dominant logit: the PSF is a unit impulse at tap (i, j) of one side,
+    # which reads img[clamp(y + pad - i), clamp(x + pad - j)]
+    ks, pad = 5, 2
+    img, depth, params = _surrogate_case(ks, 2)
+    W_out, b_out = params[-1]
+    b = np.zeros_like(b_out)
+    b[side * ks * ks + i * ks + j] = 200.0
+    params[-1] = (np.zeros_like(W_out), b)
+    out = mlp.render_surrogate(params, img, depth, [0.5, 0.6], 0.01, NORM, bf16=False)
+    H, W = img.shape[2:]
+    rows = np.clip(np.arange(H) + pad - i, 0, H - 1)
+    cols = np.clip(np.arange(W) + pad - j, 0, W - 1)
+    for c in range(2):
+        shifted = img[0, c][rows][:, cols]
+        assert np.allclose(out[0, side * 2 + c], shifted, atol=1e-12)
+        assert np.allclose(out[0, (1 - side) * 2 + c], 0.0, atol=1e-12)
+
+
+def test_surrogate_pixel_inputs():
+    depth = np.full((1, 3, 5), 2000.0)
+    x = mlp.pixel_inputs(1, 2, 3, 5, 0.25, depth, [0.5, 0.6])
+    assert x.dtype == np.float32
+    assert np.array_equal(x[0, 1, :, 0, 0], np.float32([-0.5, -0.25, 0.0, 0.25, 0.5]))
+    assert np.array_equal(x[0, :, 2, 1, 1], np.float32([-0.25, 0.0, 0.25]))
+    assert np.all(x[..., 2] == np.float32(1.0) / np.float32(2000.0))
+    assert np.all(x[..., 0, 3] == np.float32(0.5)) and np.all(x[..., 1, 3] == np.float32(0.6))
