@@ -265,7 +265,9 @@ def mlp_render(desc, params, img, depth, wavelengths, pitch, workspace, ws_batch
     """Surrogate render: img [N][C][H][W] f32 rendered with the network's PSF
     for every pixel and channel (depth [N][H][W] mm, wavelengths [C] um,
     pitch mm); returns out [N][2C][H][W] f32."""
+    assert img.is_cuda and img.dtype == torch.float32 and depth.dtype == torch.float32
     N, C_, H, W = img.shape
+    assert tuple(depth.shape[-2:]) == (H, W) and depth.numel() == N * H * W
     ks = int(round((desc.n_out // 2) ** 0.5))
     rd = abi.MlpRenderDesc(N, C_, H, W, ks, float(pitch))
     for c, lam in enumerate(wavelengths):
