@@ -141,13 +141,19 @@ def extras(dev, stream):
     gi = sdirt.render_dp_backward(desc, K, gout)
     tf = timed(lambda: sdirt.render_dp(desc, img, K, out=o), stream, 3)
     tb = timed(lambda: sdirt.render_dp_backward(desc, K, gout, grad_img=gi), stream, 3)
+    # gradient with respect to the kernel map (written once: 10.6 GB)
+    gK = torch.empty_like(K)
+    sdirt.render_dp_psf_backward(desc, img, gout, grad_psf=gK)
+    tk = timed(lambda: sdirt.render_dp_psf_backward(desc, img, gout, grad_psf=gK), stream, 3)
     nbytes = K.numel() * 4
     out["render_dense"] = {"workload": "512x512 RGB, dense per-pixel per-channel 41x41 f32 map",
                            "fwd_ms": tf, "bwd_ms": tb, "fwd_gbs": nbytes / tf / 1e6,
                            "bwd_gbs": nbytes / tb / 1e6, "fwd_hbm_frac": nbytes / tf / 1e6 / PEAK_HBM_GBS,
                            "fwd_plus_bwd_over_fwd": (tf + tb) / tf,
-                           "mpix_per_s": H * W / tf / 1e3}
-    del K, gout, gi, o
+                           "mpix_per_s": H * W / tf / 1e3,
+                           "kernel_grad_ms": tk, "kernel_grad_gbs": nbytes / tk / 1e6,
+                           "kernel_grad_hbm_frac": nbytes / tk / 1e6 / PEAK_HBM_GBS}
+    del K, gK, gout, gi, o
     print("dense render done", file=sys.stderr, flush=True)
     # 3. MLP inference vs tracing at ks 33 (12-surface lens, 512^2 rays)
     lens, sensor, query = configs.config4()

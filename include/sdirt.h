@@ -234,6 +234,20 @@ int sdirt_render_dp_backward(const sdirt_render_desc* desc, const void* psf,
                              const float* depth, const float* grad_out,
                              float* grad_img, void* stream);
 
+/* Gradient with respect to a dense kernel map (the renderer of Sec. 3.2 /
+ * S1.3 is linear in its kernels): for every pixel, kernel channel c' and
+ * side s,
+ *   grad_psf[n, y, x, c', s, i, j] = sum over the image channels c that
+ *       read kernel c' of grad_out[n, s*C + c, y, x]
+ *                          * img[n, c, clamp(y+pad-i), clamp(x+pad-j)].
+ * Chains the render to whatever produced the map (the surrogate network, a
+ * differentiable tracer).  Dense source only (SDIRT_EUNSUPPORTED for the
+ * bank); grad_psf device [N][H][W][Cp][2][ks][ks] in desc->psf_dtype (bf16
+ * rounded to nearest even), overwritten; depth is not read (may be NULL). */
+int sdirt_render_dp_psf_backward(const sdirt_render_desc* desc, const float* img,
+                                 const float* depth, const float* grad_out,
+                                 void* grad_psf, void* stream);
+
 /* ---- PSF surrogate MLP (Sec. 3.2, Supplement S1.4) ---------------------
  * Maps an image-plane point, inverse depth and wavelength to the jointly
  * sum-normalised left/right PSF: Fourier encoding (sin / cos of

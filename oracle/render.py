@@ -81,6 +81,26 @@ def render_dense_adjoint(grad_out, K):
     return gin
 
 
+def render_dense_psf_adjoint(img, grad_out, Cp, ks):
+    """Transpose of render_dense with respect to the kernels (the render is
+    linear in K): [N, H, W, Cp, 2, ks, ks], kernel channel c' collecting the
+    image channels that read it (c' = c per channel, 0 when shared)."""
+    img = np.asarray(img, dtype=np.float64)
+    g = np.asarray(grad_out, dtype=np.float64)
+    N, C, H, W = img.shape
+    pad = (ks - 1) // 2
+    gK = np.zeros((N, H, W, Cp, 2, ks, ks))
+    for n in range(N):
+        for c in range(C):
+            cp = c if Cp == C else 0
+            for i in range(ks):
+                for j in range(ks):
+                    src = _shifted(img[n, c], pad - i, pad - j)
+                    for s in range(2):
+                        gK[n, :, :, cp, s, i, j] += g[n, s * C + c] * src
+    return gK
+
+
 def bank_thresholds(field_radii, inv_depths, pitch):
     """Squared-radius thresholds in half-pixel units (floored) and depth
     thresholds for the nearest-entry bank lookup."""

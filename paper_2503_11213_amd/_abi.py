@@ -111,6 +111,8 @@ SIGNATURES = {
     "sdirt_render_dp_backward": (C.c_int, [C.POINTER(RenderDesc), C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p]),
+    "sdirt_render_dp_psf_backward": (C.c_int, [C.POINTER(RenderDesc), C.c_void_p, C.c_void_p,
+                                               C.c_void_p, C.c_void_p, C.c_void_p]),
     "sdirt_mlp_n_params": (C.c_int, [C.POINTER(MlpDesc), C.POINTER(C.c_longlong)]),
     "sdirt_mlp_workspace_size": (C.c_int, [C.POINTER(MlpDesc), C.c_int,
                                            C.POINTER(C.c_size_t)]),

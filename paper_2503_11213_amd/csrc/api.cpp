@@ -20,6 +20,8 @@ int render_impl(const sdirt_render_desc*, const float*, const void*, const float
                 float*, hipStream_t);
 int render_backward_impl(const sdirt_render_desc*, const void*, const float*,
                          const float*, float*, hipStream_t);
+int render_psf_backward_impl(const sdirt_render_desc*, const float*, const float*, const float*,
+                             void*, hipStream_t);
 int mlp_n_params(const sdirt_mlp_desc*, long long*);
 int mlp_workspace_size(const sdirt_mlp_desc*, int, size_t*);
 int mlp_forward(const sdirt_mlp_desc*, const float*, long long, const float*, void*, int,
@@ -123,6 +125,12 @@ int sdirt_render_dp_backward(const sdirt_render_desc* desc, const void* psf,
                              const float* depth, const float* grad_out,
                              float* grad_img, void* stream) {
     return render_backward_impl(desc, psf, depth, grad_out, grad_img, (hipStream_t)stream);
+}
+
+int sdirt_render_dp_psf_backward(const sdirt_render_desc* desc, const float* img,
+                                 const float* depth, const float* grad_out,
+                                 void* grad_psf, void* stream) {
+    return render_psf_backward_impl(desc, img, depth, grad_out, grad_psf, (hipStream_t)stream);
 }
 
 int sdirt_mlp_n_params(const sdirt_mlp_desc* desc, long long* n_params) {

@@ -62,6 +62,13 @@ __device__ inline float psf_at(const typename PsfT<BF16>::type* p, int idx) {
     else return p[idx];
 }
 
+// float -> kernel storage (bf16: round to nearest even)
+template <bool BF16>
+__device__ inline typename PsfT<BF16>::type to_psf(float v) {
+    if constexpr (BF16) return __builtin_bit_cast(uint16_t, (__bf16)v);
+    else return v;
+}
+
 // Kernels of one output pixel: a pointer per channel c and side s (wave
 // uniform), and the bank mirrors (the side swap folded into the pointers).
 template <int NC, bool BF16>
@@ -272,6 +279,63 @@ __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A)
             for (int c = 0; c < NC; ++c)
                 if (acc[k][c] != 0.f)
                     atomicAdd(&A.gimg[(((size_t)n * NC + c) * A.H + yy) * A.W + xx], acc[k][c]);
+        }
+    }
+}
+
+// Gradient with respect to a dense per-pixel kernel map: for each pixel,
+// grad_K[c'][s][i][j] = sum over the channels c reading kernel c' of
+// grad_out[s C + c] * img[c][clamp(y + pad - i)][clamp(x + pad - j)].  The
+// tile's image halo is staged in LDS; one wave writes one pixel's 2 Cp ks^2
+// values with contiguous lanes (an HBM-bound stream, like the forward).
+template <int NC, bool SHARED, bool BF16>
+__global__ __launch_bounds__(kRBlock) void render_psf_grad_kernel(const RenderArgs A, void* grad) {
+    typedef typename PsfT<BF16>::type T;
+    extern __shared__ float halo[];
+    const int ks = A.ks, kk = ks * ks;
+    const int hh = kTH + ks - 1, hw = kTW + ks - 1;
+    const int tile = blockIdx.x;
+    const int n = tile / (A.tiles_x * A.tiles_y);
+    const int rem = tile - n * A.tiles_x * A.tiles_y;
+    const int y0 = (rem / A.tiles_x) * kTH, x0 = (rem % A.tiles_x) * kTW;
+    stage_halo(A, n, y0, x0, halo, hh, hw);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T* gk = reinterpret_cast<T*>(grad);
+    for (int p = wave; p < kTH * kTW; p += kWaves) {
+        const int y = y0 + p / kTW, x = x0 + p % kTW;
+        if (y >= A.H || x >= A.W) continue;
+        float g[2][NC];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                g[s][c] = A.gout[(((size_t)n * 2 * NC + s * NC + c) * A.H + y) * A.W + x];
+        const size_t pix = ((size_t)n * A.H + y) * A.W + x;
+        const int ly = y - y0 + ks - 1, lx = x - x0 + ks - 1;
+        for (int t = lane; t < kk; t += 64) {
+            const int i = t / ks, j = t - i * ks;
+            const int hoff = (ly - i) * hw + (lx - j);
+            if (SHARED) {
+                float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const float v = halo[c * hh * hw + hoff];
+                    a0 = fmaf(g[0][c], v, a0);
+                    a1 = fmaf(g[1][c], v, a1);
+                }
+                T* o = gk + pix * 2 * kk + t;
+                o[0] = (T)to_psf<BF16>(a0);
+                o[kk] = (T)to_psf<BF16>(a1);
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const float v = halo[c * hh * hw + hoff];
+                    T* o = gk + (pix * NC + c) * 2 * kk + t;
+                    o[0] = (T)to_psf<BF16>(g[0][c] * v);
+                    o[kk] = (T)to_psf<BF16>(g[1][c] * v);
+                }
+            }
         }
     }
 }
@@ -1020,6 +1084,44 @@ int render_backward_impl(const sdirt_render_desc* desc, const void* psf,
     if ((rc = launch_fill_zero(gimg, (size_t)A.N * A.C * A.H * A.W * sizeof(float), stream)))
         return rc;
     return dispatch_render<true>(A, stream);
+}
+
+template <int NC>
+static void launch_psf_grad(const RenderArgs& A, void* grad, hipStream_t st) {
+    const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
+    const size_t shm = (size_t)NC * hh * hw * sizeof(float);
+    const dim3 grid((unsigned)((long long)A.N * A.tiles_x * A.tiles_y));
+#define SDIRT_PSFG(SH, BF)                                                                   \
+    do {                                                                                     \
+        auto k = render_psf_grad_kernel<NC, SH, BF>;                                         \
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); \
+        hipLaunchKernelGGL(k, grid, dim3(kRBlock), shm, st, A, grad);                        \
+    } while (0)
+    if (A.Cp == 1 && A.bf16) SDIRT_PSFG(true, true);
+    else if (A.Cp == 1) SDIRT_PSFG(true, false);
+    else if (A.bf16) SDIRT_PSFG(false, true);
+    else SDIRT_PSFG(false, false);
+#undef SDIRT_PSFG
+}
+
+int render_psf_backward_impl(const sdirt_render_desc* desc, const float* img, const float* depth,
+                             const float* gout, void* grad_psf, hipStream_t stream) {
+    RenderArgs A;
+    int rc = pack_render(desc, &A);
+    if (rc) return rc;
+    if (!img || !gout || !grad_psf) return SDIRT_EINVAL;
+    if (A.source != SDIRT_SRC_DENSE) return SDIRT_EUNSUPPORTED;
+    (void)depth;
+    const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
+    if ((size_t)A.C * hh * hw * sizeof(float) > 160 * 1024) return SDIRT_EUNSUPPORTED;
+    A.img = img; A.gout = gout;
+    switch (A.C) {
+        case 1: launch_psf_grad<1>(A, grad_psf, stream); break;
+        case 2: launch_psf_grad<2>(A, grad_psf, stream); break;
+        case 3: launch_psf_grad<3>(A, grad_psf, stream); break;
+        default: launch_psf_grad<4>(A, grad_psf, stream); break;
+    }
+    return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
 }
 
 }  // namespace sdirt

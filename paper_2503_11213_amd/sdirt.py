@@ -224,6 +224,21 @@ def render_dp_backward(desc, psf, grad_out, depth=None, grad_img=None):
 
 # ---- PSF surrogate MLP ------------------------------------------------------
 
+def render_dp_psf_backward(desc, img, grad_out, grad_psf=None):
+    """Gradient of the dense render with respect to its kernel map:
+    [N][H][W][Cp][2][ks][ks] in the descriptor's kernel dtype."""
+    assert img.is_cuda and img.dtype == torch.float32
+    if grad_psf is None:
+        dt = torch.bfloat16 if desc.psf_dtype == abi.BF16 else torch.float32
+        grad_psf = torch.empty((desc.N, desc.H, desc.W, desc.psf_channels, 2, desc.ks, desc.ks),
+                               dtype=dt, device=img.device)
+    rc = abi.lib().sdirt_render_dp_psf_backward(C.byref(desc), _dptr(img.contiguous()), None,
+                                                _dptr(grad_out.contiguous()), _dptr(grad_psf),
+                                                _stream())
+    abi.check("sdirt_render_dp_psf_backward", rc)
+    return grad_psf
+
+
 def make_mlp_desc(n_hidden=5, width=256, n_out=2 * 33 * 33, n_freq=8, x_half=1.0,
                   y_half=1.0, iv_lo=0.0, iv_hi=1.0, lam_lo=0.4, lam_hi=0.7,
                   loss=abi.LOSS_L2MAX):

@@ -199,3 +199,49 @@ def test_dense_full_size_sampled_pixels():
         gref = R.render_dense_adjoint(g[:, :, sl[0], sl[1]], K[:, sl[0], sl[1]])
         assert _rel(out[:, :, y, x], ref[:, :, y - ya, x - xa]) <= REL_TOL, (y, x)
         assert _rel(gi[:, :, y, x], gref[:, :, y - ya, x - xa]) <= REL_TOL, (y, x)
+
+
+@pytest.mark.parametrize("shape", [(1, 3, 19, 37, 7, 3), (2, 3, 17, 9, 5, 1),
+                                   (1, 2, 23, 21, 9, 2), (1, 1, 8, 8, 1, 1)])
+def test_dense_kernel_gradient(shape):
+    # gradient with respect to the per-pixel kernel map: one product per
+    # element (a sum of C products for shared kernels), float32
+    N, C, H, W, ks, Cp = shape
+    img, _ = _dense(N, C, H, W, ks, Cp, 21)
+    g = np.random.default_rng(22).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, psf_channels=Cp)
+    gk = sdirt.render_dp_psf_backward(desc, torch.from_numpy(img).cuda(),
+                                      torch.from_numpy(g).cuda()).cpu().numpy()
+    ref = R.render_dense_psf_adjoint(img, g, Cp, ks)
+    assert gk.shape == ref.shape
+    assert np.max(np.abs(gk - ref)) <= 1e-6 * max(np.abs(ref).max(), 1e-30)
+
+
+def test_dense_kernel_gradient_bf16_and_full_size_sample():
+    # bf16 kernel map: each element rounded once to nearest even; and the
+    # 512 x 512 RGB, 41 x 41 per-channel launch on sampled pixels
+    N, C, H, W, ks, Cp = 1, 3, 512, 512, 41, 3
+    rng = np.random.default_rng(23)
+    img = rng.uniform(0, 1, (N, C, H, W)).astype(np.float32)
+    g = rng.normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    it, gt = torch.from_numpy(img).cuda(), torch.from_numpy(g).cuda()
+    pix = [(0, 0), (H - 1, W - 1), (0, W - 1), (200, 311), (17, 500)] + \
+          [(int(rng.integers(H)), int(rng.integers(W))) for _ in range(10)]
+    pad = (ks - 1) // 2
+    for dt in (abi.F32, abi.BF16):
+        desc, keep = sdirt.make_render_desc(N, C, H, W, ks, psf_channels=Cp, psf_dtype=dt)
+        gk = sdirt.render_dp_psf_backward(desc, it, gt)
+        for (y, x) in pix:
+            got = gk[0, y, x].float().cpu().numpy()                 # [C, 2, ks, ks]
+            rows = np.clip(y + pad - np.arange(ks), 0, H - 1)
+            cols = np.clip(x + pad - np.arange(ks), 0, W - 1)
+            for c in range(C):
+                win = img[0, c][rows][:, cols].astype(np.float64)
+                for s in range(2):
+                    ref = g[0, s * C + c, y, x] * win
+                    if dt == abi.BF16:
+                        ref = to_bf16(ref)
+                        assert np.max(np.abs(got[c, s] - ref)) <= 1e-6 * np.abs(ref).max()
+                    else:
+                        assert np.max(np.abs(got[c, s] - ref)) <= 1e-6 * np.abs(ref).max()
+        del gk

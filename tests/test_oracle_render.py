@@ -115,3 +115,31 @@ def test_bank_render_uses_mirror_rules():
     assert K[0, 0, 0, 0, 1, 1, 0] == 1.0      # x<0,y<0: right <- flipped left
     assert K[0, 0, 0, 0, 0, 2, 1] == 1.0      # left <- row-flipped right
     assert K[0, 4, 5, 0, 0, 1, 2] == 1.0      # x>0,y>0: unchanged
+
+
+@pytest.mark.parametrize("Cp", [1, 3])
+def test_kernel_gradient_matches_torch_autograd(Cp):
+    # library gradient: torch autograd through the replicate-pad / unfold
+    # expression of the render, with respect to the kernels
+    N, C, H, W, ks = 1, 3, 9, 11, 5
+    img = _rand((N, C, H, W), 11)
+    g = _rand((N, 2 * C, H, W), 12) - 0.5
+    pad = ks // 2
+    K = torch.from_numpy(_rand((N, H, W, Cp, 2, ks, ks), 13)).requires_grad_(True)
+    t = torch.from_numpy(img)
+    patches = torch.nn.functional.unfold(
+        torch.nn.functional.pad(t, (pad, pad, pad, pad), mode="replicate"), ks)
+    patches = patches.view(N, C, ks * ks, H * W)
+    Kt = K.flip(-1).flip(-2).reshape(N, H * W, Cp, 2, ks * ks)
+    outs = []
+    for s in range(2):
+        w = Kt[:, :, :, s, :].permute(0, 2, 3, 1)                 # [N,Cp,T,P]
+        outs.append((patches * w).sum(2).view(N, C, H, W))
+    out = torch.cat(outs, 1)
+    (out * torch.from_numpy(g)).sum().backward()
+    gK = R.render_dense_psf_adjoint(img, g, Cp, ks)
+    assert np.allclose(gK, K.grad.numpy(), atol=1e-12)
+    # and the adjoint identity against the forward
+    D = _rand(K.shape, 14)
+    lhs = np.sum(R.render_dense(img, D) * g)
+    assert lhs == pytest.approx(np.sum(D * gK), rel=1e-12)
