@@ -206,19 +206,36 @@ int sdirt_trace_dp_psf_backward(const sdirt_lens* lens,
  *          inverse depth of depth[n][y][x] are taken, channel c uses
  *          wavelength slot lambda_of_channel[c]; pixels left of the centre
  *          use the column-flipped kernel with sides swapped, pixels below
- *          it the row-flipped kernel (an approximation off the x axis). */
-enum { SDIRT_SRC_DENSE = 0, SDIRT_SRC_BANK = 1 };
+ *          it the row-flipped kernel (an approximation off the x axis).
+ *   BANK2D: psf device [Fy][Fx][D][L][2][ks][ks] f32 traced on a 2-D grid
+ *          of the first quadrant (h_x = field_radii[fx] >= 0, h_y =
+ *          field_y[fy] >= 0) and reused in the others through the flip
+ *          symmetries of DP PSFs about both axes (Sec. 5.1): per pixel the
+ *          nearest grid point to (|h_x|, |h_y|), the same column flip with
+ *          side swap for h_x < 0 and row flip for h_y < 0, and linear
+ *          interpolation in inverse depth, in float32: iv = 1 / depth,
+ *          d0 = the last plane k <= D-2 with (float)inv_depths[k] <= iv (0
+ *          if none), w = clamp((iv - iv_d0) / (iv_d0+1 - iv_d0), 0, 1) (0 when
+ *          D = 1); K = (1 - w) K[d0] + w K[d0 + 1].  h_x of pixel x is
+ *          (x - (W-1)/2) * pitch (h_y likewise); nearest-point decisions are
+ *          made exactly on the integer |2x - (W-1)| against
+ *          floor(2 * midpoint / pitch).  Only window sizes 21, 31, 33, 41, 63
+ *          and 65 (SDIRT_EUNSUPPORTED otherwise). */
+enum { SDIRT_SRC_DENSE = 0, SDIRT_SRC_BANK = 1, SDIRT_SRC_BANK2D = 2 };
 
 typedef struct {
     int N, C, H, W, ks;
     int source;               /* SDIRT_SRC_*                               */
     int psf_channels;         /* DENSE: Cp = 1 or C                        */
-    int psf_dtype;            /* DENSE: SDIRT_F32 or SDIRT_BF16; BANK: F32 */
+    int psf_dtype;            /* DENSE: SDIRT_F32 or SDIRT_BF16; banks: F32 */
     int bank_fields, bank_depths, bank_lambdas;
-    const double* field_radii;   /* host [F], strictly increasing (mm)     */
+    const double* field_radii;   /* host [F], strictly increasing (mm); the
+                                    x grid (Fx = bank_fields) for BANK2D    */
     const double* inv_depths;    /* host [D], strictly increasing (1/mm)   */
-    int lambda_of_channel[4];    /* BANK: slot per image channel           */
-    double pitch;                /* BANK: pixel pitch (mm)                 */
+    int lambda_of_channel[4];    /* banks: slot per image channel          */
+    double pitch;                /* banks: pixel pitch (mm)                */
+    int bank_fields_y;           /* BANK2D: Fy                             */
+    const double* field_y;       /* BANK2D: host [Fy], strictly increasing */
 } sdirt_render_desc;
 
 /* img device [N][C][H][W] f32; depth device [N][H][W] f32 (BANK only, may

@@ -26,6 +26,8 @@ Kernel sources
           left of the centre use the mirror image (columns flipped, left and
           right swapped), pixels below it flip rows.  This lookup is an
           approximation for pixels off the x axis (it ignores azimuth).
+  bank2d: a first-quadrant 2-D grid with linear interpolation in inverse
+          depth (see the section at the end).
 """
 
 import numpy as np
@@ -192,3 +194,83 @@ def render_bank_pixels(img, bank, depth_maps, field_radii, inv_depths, lam_of_c,
             for s in range(2):
                 out[k, s * C + c] = np.sum(kern[s] * patch)
     return out
+
+
+# ---- 2-D (exact-azimuth) bank -------------------------------------------
+# A bank traced on a first-quadrant grid (h_x = xs[fx] >= 0, h_y = ys[fy] >= 0)
+# is reused in the other quadrants through the flip symmetry of DP PSFs
+# about both axes (Sec. 5.1): a pixel takes the grid point nearest to
+# (|h_x|, |h_y|), mirrored in columns with the sides swapped when h_x < 0
+# and in rows when h_y < 0, and blends the two depth planes that bracket its
+# inverse depth linearly.  Readings: h_x of pixel x is (x - (W-1)/2) * pitch;
+# the nearest grid point is decided on the exact half-pixel integer
+# |2x - (W-1)| against floor(2 * midpoint / pitch); the inverse depth and the
+# blend weight are float32 computations (iv = 1/depth, planes as float32),
+# d0 = the last plane k <= D-2 with iv_k <= iv (0 if none) and
+# w = clamp((iv - iv_d0) / (iv_d0+1 - iv_d0), 0, 1), w = 0 for one plane.
+
+def bank2d_lookup(H, W, depth, xs, ys, inv_depths, pitch):
+    """Per pixel: fx, fy, d0, w (float32), mirror-x flag, mirror-y flag."""
+    yy, xx = np.meshgrid(np.arange(H, dtype=np.int64), np.arange(W, dtype=np.int64),
+                         indexing="ij")
+    X2 = 2 * xx - (W - 1)
+    Y2 = 2 * yy - (H - 1)
+    xs, ys = np.asarray(xs, dtype=np.float64), np.asarray(ys, dtype=np.float64)
+    tx = np.floor((xs[:-1] + xs[1:]) / pitch)
+    ty = np.floor((ys[:-1] + ys[1:]) / pitch)
+    fx = np.zeros((H, W), dtype=np.int64)
+    fy = np.zeros((H, W), dtype=np.int64)
+    for t in tx:
+        fx += np.abs(X2) > t
+    for t in ty:
+        fy += np.abs(Y2) > t
+    ivk = np.asarray(inv_depths, dtype=np.float32)
+    D = len(ivk)
+    iv = np.float32(1.0) / np.asarray(depth, dtype=np.float32)
+    d0 = np.zeros((H, W), dtype=np.int64)
+    for k in range(1, D - 1):
+        d0 += iv >= ivk[k]
+    if D > 1:
+        with np.errstate(all="ignore"):
+            w = (iv - ivk[d0]) / (ivk[d0 + 1] - ivk[d0])
+        w = np.minimum(np.maximum(w, np.float32(0)), np.float32(1)).astype(np.float32)
+    else:
+        w = np.zeros((H, W), dtype=np.float32)
+    return fx, fy, d0, w, X2 < 0, Y2 < 0
+
+
+def dense_from_bank2d(bank, depth_maps, xs, ys, inv_depths, lam_of_c, pitch):
+    """Expand a 2-D bank [Fy][Fx][D][L][2][ks][ks] to dense per-pixel kernels
+    [N][H][W][C][2][ks][ks] by the rule above."""
+    bank = np.asarray(bank, dtype=np.float64)
+    N, H, W = depth_maps.shape
+    C = len(lam_of_c)
+    ks = bank.shape[-1]
+    D = bank.shape[2]
+    K = np.zeros((N, H, W, C, 2, ks, ks))
+    for n in range(N):
+        fx, fy, d0, w, mx, my = bank2d_lookup(H, W, depth_maps[n], xs, ys, inv_depths, pitch)
+        for y in range(H):
+            for x in range(W):
+                wt = float(w[y, x])
+                for c in range(C):
+                    e = bank[fy[y, x], fx[y, x], :, lam_of_c[c]]
+                    k = (1.0 - wt) * e[d0[y, x]]
+                    if D > 1:
+                        k = k + wt * e[d0[y, x] + 1]
+                    if mx[y, x]:
+                        k = k[::-1, :, ::-1]     # swap L/R, flip columns
+                    if my[y, x]:
+                        k = k[:, ::-1, :]        # flip rows
+                    K[n, y, x, c] = k
+    return K
+
+
+def render_bank2d(img, bank, depth_maps, xs, ys, inv_depths, lam_of_c, pitch):
+    return render_dense(img, dense_from_bank2d(bank, depth_maps, xs, ys, inv_depths,
+                                               lam_of_c, pitch))
+
+
+def render_bank2d_adjoint(grad_out, bank, depth_maps, xs, ys, inv_depths, lam_of_c, pitch):
+    return render_dense_adjoint(grad_out, dense_from_bank2d(bank, depth_maps, xs, ys,
+                                                            inv_depths, lam_of_c, pitch))

@@ -31,8 +31,12 @@ struct RenderArgs {
     int N, C, H, W, ks, pad;
     int source, Cp, bf16;
     int F, D, L;
-    long long t_r[SDIRT_MAX_BANK_F];   // squared-radius thresholds (half px)
+    long long t_r[SDIRT_MAX_BANK_F];   // squared-radius thresholds (half px); 2-D bank: |2x - W + 1|
     float t_z[SDIRT_MAX_BANK_D];       // depth thresholds (rounded up)
+    int bank2d, Fy;                    // 2-D bank: F = Fx, Fy rows of the field grid
+    long long t_y[SDIRT_MAX_BANK_F];   // 2-D bank: |2y - H + 1| thresholds (half px)
+    float ivk[SDIRT_MAX_BANK_D];       // 2-D bank: inverse depths (float32)
+    int pass;                          // 2-D bank: 0 = plane d0, weight 1 - w; 1 = d0 + 1, w
     int lam_of_c[4];
     int tiles_x, tiles_y;
     int use_fast;        // bank source: grouped kernels when ks allows
@@ -397,17 +401,56 @@ __device__ inline int wave_min_int(int v) {
     return v;
 }
 
-// Bank key of pixel (y, x): ((fi * D + di) * 2 + flip_x) * 2 + flip_y.
+// 2-D bank: the planes bracketing the pixel's inverse depth and the weight
+// of the farther one, in float32 (see the BANK2D source).
+__device__ inline void depth_bracket(const RenderArgs& A, float z, int* d0, float* w) {
+    const float iv = 1.0f / z;
+    int d = 0;
+    for (int k = 1; k < A.D - 1; ++k) d += iv >= A.ivk[k];
+    float t = 0.f;
+    if (A.D > 1) t = fminf(fmaxf((iv - A.ivk[d]) / (A.ivk[d + 1] - A.ivk[d]), 0.f), 1.f);
+    *d0 = d;
+    *w = t;
+}
+
+// Weight of pixel (y, x) in the current pass: 1 for the radial bank; 1 - w
+// or w for the 2-D bank.
+__device__ inline float pass_weight(const RenderArgs& A, int n, int y, int x) {
+    if (!A.bank2d) return 1.f;
+    int d0;
+    float w;
+    depth_bracket(A, A.depth[((size_t)n * A.H + y) * A.W + x], &d0, &w);
+    return A.pass ? w : 1.f - w;
+}
+
+// Bank key of pixel (y, x): ((entry * 2 + flip_x) * 2 + flip_y), the entry
+// fi * D + di (radial bank: nearest radius and inverse depth) or
+// (fy * Fx + fx) * D + d (2-D bank: nearest grid point, plane d0 + pass);
+// 0x7fffffff for a pixel with nothing to add in the 2-D bank's second pass.
 __device__ inline int bank_key(const RenderArgs& A, int n, int y, int x) {
     const long long X2 = 2LL * x - (A.W - 1);
     const long long Y2 = 2LL * y - (A.H - 1);
-    const long long R2 = X2 * X2 + Y2 * Y2;
-    int fi = 0;
-    for (int k = 0; k < A.F - 1; ++k) fi += R2 > A.t_r[k];
     const float z = A.depth[((size_t)n * A.H + y) * A.W + x];
-    int di = 0;
-    for (int k = 0; k < A.D - 1; ++k) di += z < A.t_z[k];
-    return ((fi * A.D + di) * 2 + (X2 < 0 ? 1 : 0)) * 2 + (Y2 < 0 ? 1 : 0);
+    int entry;
+    if (A.bank2d) {
+        const long long ax = X2 < 0 ? -X2 : X2, ay = Y2 < 0 ? -Y2 : Y2;
+        int fx = 0, fy = 0;
+        for (int k = 0; k < A.F - 1; ++k) fx += ax > A.t_r[k];
+        for (int k = 0; k < A.Fy - 1; ++k) fy += ay > A.t_y[k];
+        int d0;
+        float w;
+        depth_bracket(A, z, &d0, &w);
+        if (A.pass && !(w > 0.f)) return 0x7fffffff;
+        entry = (fy * A.F + fx) * A.D + d0 + A.pass;
+    } else {
+        const long long R2 = X2 * X2 + Y2 * Y2;
+        int fi = 0;
+        for (int k = 0; k < A.F - 1; ++k) fi += R2 > A.t_r[k];
+        int di = 0;
+        for (int k = 0; k < A.D - 1; ++k) di += z < A.t_z[k];
+        entry = fi * A.D + di;
+    }
+    return (entry * 2 + (X2 < 0 ? 1 : 0)) * 2 + (Y2 < 0 ? 1 : 0);
 }
 
 // One lane's share of staging a kernel row pair into a row buffer of ROW
@@ -629,15 +672,25 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
                 const size_t side_ofs = (g >> 1) ? (size_t)A.C * A.H * A.W : 0;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    if (u >= ng) break;
-                    const bool valid = 16 * u + (lane & 15) < cnt;
+                    const bool valid = u < ng && 16 * u + (lane & 15) < cnt;
                     const unsigned msk = valid ? (unsigned)its[u] >> 9 : 0u;
                     const int sid = its[u] & 511;
                     const int y = y0 + (sid >> 3), xs = x0 + (sid & 7) * kStrip + 4 * (g & 1);
                     const size_t o = (((size_t)n * 2 * A.C + c) * A.H + y) * A.W + xs + side_ofs;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (msk & (1u << (4 * (g & 1) + r))) A.out[o + r] = acc[u][r];
+                    for (int r = 0; r < 4; ++r) {
+                        if (msk & (1u << (4 * (g & 1) + r))) {
+                            if (!A.bank2d) {
+                                A.out[o + r] = acc[u][r];
+                            } else {
+                                // 2-D bank: the pass's share of the depth
+                                // blend, written by the first pass, added by
+                                // the second
+                                const float wt = pass_weight(A, n, y, xs + r);
+                                A.out[o + r] = A.pass ? fmaf(wt, acc[u][r], A.out[o + r]) : wt * acc[u][r];
+                            }
+                        }
+                    }
                 }
             }
             __syncthreads();
@@ -892,9 +945,11 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
 #pragma unroll
                     for (int kq = 0; kq < 4; ++kq) {
                         const int q = 4 * (kq & 1) + g;
-                        const size_t o = orow + min(x0 + tc * kStrip + q, A.W - 1) + (kq >> 1) * plane;
+                        const int xq = min(x0 + tc * kStrip + q, A.W - 1);
+                        const size_t o = orow + xq + (kq >> 1) * plane;
                         const float v = A.gout[o];                   // in bounds even if masked
-                        gb[u][kq] = (msk >> q) & 1u ? v : 0.f;
+                        const float wt = A.bank2d ? pass_weight(A, n, y, xq) : 1.f;
+                        gb[u][kq] = (msk >> q) & 1u ? v * wt : 0.f;
                     }
                 }
                 switch (np) {
@@ -942,9 +997,7 @@ static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
 }
 
 template <bool BWD>
-static bool try_bank_fast(const RenderArgs& A, hipStream_t st) {
-    if (A.source != SDIRT_SRC_BANK) return false;
-    if ((long long)A.F * A.D * 4 >= 0x7fffffffLL) return false;
+static bool try_bank_fast_pass(const RenderArgs& A, hipStream_t st) {
     switch (A.ks) {
         case 21: return launch_bank_fast<21, BWD>(A, st);
         case 31: return launch_bank_fast<31, BWD>(A, st);
@@ -954,6 +1007,23 @@ static bool try_bank_fast(const RenderArgs& A, hipStream_t st) {
         case 65: return launch_bank_fast<65, BWD>(A, st);
         default: return false;
     }
+}
+
+// The 2-D bank renders its depth blend in two passes over entry-grouped
+// pixels: plane d0 weighted 1 - w (writing the output), then plane d0 + 1
+// weighted w (adding to it); the adjoint's passes both add into the image
+// gradient.
+template <bool BWD>
+static bool try_bank_fast(const RenderArgs& A, hipStream_t st) {
+    if (A.source != SDIRT_SRC_BANK && A.source != SDIRT_SRC_BANK2D) return false;
+    const long long cells = A.bank2d ? (long long)A.F * A.Fy : A.F;
+    if (cells * A.D * 4 >= 0x7fffffffLL) return false;
+    if (!A.bank2d) return try_bank_fast_pass<BWD>(A, st);
+    RenderArgs B = A;
+    B.pass = 0;
+    if (!try_bank_fast_pass<BWD>(B, st)) return false;
+    B.pass = 1;
+    return try_bank_fast_pass<BWD>(B, st);
 }
 
 // ---- host ----------------------------------------------------------------
@@ -974,7 +1044,7 @@ static int pack_render(const sdirt_render_desc* d, RenderArgs* A) {
         A->Cp = d->psf_channels;
         if (d->psf_dtype == SDIRT_BF16) A->bf16 = 1;
         else if (d->psf_dtype != SDIRT_F32) return SDIRT_EUNSUPPORTED;
-    } else if (d->source == SDIRT_SRC_BANK) {
+    } else if (d->source == SDIRT_SRC_BANK || d->source == SDIRT_SRC_BANK2D) {
         if (d->psf_dtype != SDIRT_F32) return SDIRT_EUNSUPPORTED;
         A->Cp = d->C;
         A->F = d->bank_fields; A->D = d->bank_depths; A->L = d->bank_lambdas;
@@ -990,12 +1060,35 @@ static int pack_render(const sdirt_render_desc* d, RenderArgs* A) {
             if (!std::isfinite(d->inv_depths[k]) || !(d->inv_depths[k] > 0)) return SDIRT_EINVAL;
             if (k && !(d->inv_depths[k] > d->inv_depths[k - 1])) return SDIRT_EINVAL;
         }
-        // nearest field radius: R2 (exact integer, half-pixel units) against
-        // floor((2 * midpoint / pitch)^2)
-        for (int k = 0; k + 1 < A->F; ++k) {
-            const double mid = 0.5 * (d->field_radii[k] + d->field_radii[k + 1]);
-            const double t = std::floor((2.0 * mid / d->pitch) * (2.0 * mid / d->pitch));
-            A->t_r[k] = t < 0 ? -1 : (long long)t;
+        if (d->source == SDIRT_SRC_BANK2D) {
+            // first-quadrant grid: nearest |2x - W + 1| (exact integer, half
+            // pixels) against floor(2 * midpoint / pitch), likewise in y;
+            // inverse depths as float32, strictly increasing
+            A->bank2d = 1;
+            A->Fy = d->bank_fields_y;
+            if (A->Fy < 1 || !d->field_y) return SDIRT_EINVAL;
+            if (A->Fy > SDIRT_MAX_BANK_F) return SDIRT_EUNSUPPORTED;
+            if (!(d->field_radii[0] >= 0)) return SDIRT_EINVAL;
+            for (int k = 0; k < A->Fy; ++k) {
+                if (!std::isfinite(d->field_y[k]) || !(d->field_y[k] >= 0)) return SDIRT_EINVAL;
+                if (k && !(d->field_y[k] > d->field_y[k - 1])) return SDIRT_EINVAL;
+            }
+            for (int k = 0; k + 1 < A->F; ++k)
+                A->t_r[k] = (long long)std::floor((d->field_radii[k] + d->field_radii[k + 1]) / d->pitch);
+            for (int k = 0; k + 1 < A->Fy; ++k)
+                A->t_y[k] = (long long)std::floor((d->field_y[k] + d->field_y[k + 1]) / d->pitch);
+            for (int k = 0; k < A->D; ++k) {
+                A->ivk[k] = (float)d->inv_depths[k];
+                if (k && !(A->ivk[k] > A->ivk[k - 1])) return SDIRT_EINVAL;
+            }
+        } else {
+            // nearest field radius: R2 (exact integer, half-pixel units)
+            // against floor((2 * midpoint / pitch)^2)
+            for (int k = 0; k + 1 < A->F; ++k) {
+                const double mid = 0.5 * (d->field_radii[k] + d->field_radii[k + 1]);
+                const double t = std::floor((2.0 * mid / d->pitch) * (2.0 * mid / d->pitch));
+                A->t_r[k] = t < 0 ? -1 : (long long)t;
+            }
         }
         // nearest inverse depth: depth < 1 / midpoint(1/d), threshold rounded
         // up to float so the float comparison decides exactly as in float64
@@ -1050,6 +1143,7 @@ template <bool BWD>
 static int dispatch_render(const RenderArgs& A, hipStream_t st) {
     if (A.use_fast && try_bank_fast<BWD>(A, st))
         return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
+    if (A.bank2d) return SDIRT_EUNSUPPORTED;           // grouped kernels only
     const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
     if (!BWD && (size_t)A.C * hh * hw * sizeof(float) > 160 * 1024) return SDIRT_EUNSUPPORTED;
     switch (A.C) {
@@ -1067,7 +1161,7 @@ int render_impl(const sdirt_render_desc* desc, const float* img, const void* psf
     int rc = pack_render(desc, &A);
     if (rc) return rc;
     if (!img || !psf || !out) return SDIRT_EINVAL;
-    if (A.source == SDIRT_SRC_BANK && !depth) return SDIRT_EINVAL;
+    if (A.source != SDIRT_SRC_DENSE && !depth) return SDIRT_EINVAL;
     A.img = img; A.psf = psf; A.depth = depth; A.out = out;
     return dispatch_render<false>(A, stream);
 }
@@ -1079,7 +1173,7 @@ int render_backward_impl(const sdirt_render_desc* desc, const void* psf,
     int rc = pack_render(desc, &A);
     if (rc) return rc;
     if (!gout || !psf || !gimg) return SDIRT_EINVAL;
-    if (A.source == SDIRT_SRC_BANK && !depth) return SDIRT_EINVAL;
+    if (A.source != SDIRT_SRC_DENSE && !depth) return SDIRT_EINVAL;
     A.psf = psf; A.depth = depth; A.gout = gout; A.gimg = gimg;
     if ((rc = launch_fill_zero(gimg, (size_t)A.N * A.C * A.H * A.W * sizeof(float), stream)))
         return rc;

@@ -177,14 +177,21 @@ def trace_dp_psf_backward(lens, sensor, query, grad_psf, math=abi.F64):
 
 def make_render_desc(N, C_, H, W, ks, source=abi.SRC_DENSE, psf_channels=None,
                      psf_dtype=abi.F32, field_radii=None, inv_depths=None,
-                     bank_lambdas=1, lambda_of_channel=None, pitch=0.0):
+                     bank_lambdas=1, lambda_of_channel=None, pitch=0.0, field_y=None):
+    """Render descriptor; for the banks, field_radii is the radial grid
+    (SRC_BANK) or the x grid (SRC_BANK2D, with field_y the y grid)."""
     d = abi.RenderDesc()
     d.N, d.C, d.H, d.W, d.ks = int(N), int(C_), int(H), int(W), int(ks)
     d.source = int(source)
     d.psf_channels = int(psf_channels if psf_channels is not None else C_)
     d.psf_dtype = int(psf_dtype)
     keep = []
-    if source == abi.SRC_BANK:
+    if source == abi.SRC_BANK2D:
+        fy = _darr(field_y)
+        keep.append(fy)
+        d.bank_fields_y = len(field_y)
+        d.field_y = C.cast(fy, C.POINTER(C.c_double))
+    if source in (abi.SRC_BANK, abi.SRC_BANK2D):
         fr, iv = _darr(field_radii), _darr(inv_depths)
         keep += [fr, iv]
         d.bank_fields = len(field_radii)

@@ -245,3 +245,56 @@ def test_dense_kernel_gradient_bf16_and_full_size_sample():
                     else:
                         assert np.max(np.abs(got[c, s] - ref)) <= 1e-6 * np.abs(ref).max()
         del gk
+
+
+def _bank2d_case(N, C, H, W, ks, Fx, Fy, D, L, ps, seed, noise=False):
+    rng = np.random.default_rng(seed)
+    img = rng.uniform(0, 1, (N, C, H, W)).astype(np.float32)
+    bank = rng.uniform(0, 1, (Fy, Fx, D, L, 2, ks, ks)).astype(np.float32)
+    xs = np.linspace(0, W * ps / 2, Fx)
+    ys = np.linspace(0, H * ps / 2, Fy)
+    iv = np.linspace(1 / 5000.0, 1 / 500.0, D)
+    if noise:
+        dmap = (1.0 / rng.uniform(1 / 6000.0, 1 / 400.0, (N, H, W))).astype(np.float32)
+    else:
+        dmap = np.stack([scenes.depth_voronoi(H, W, 450.0, 5500.0, seed=140 + n)
+                         for n in range(N)]).astype(np.float32)
+    return img, bank, xs, ys, iv, dmap
+
+
+@pytest.mark.parametrize("ks,noise", [(21, False), (33, True), (63, False)])
+def test_bank2d_forward_and_adjoint(ks, noise):
+    # exact-azimuth bank: first-quadrant grid, flips, linear in 1/d (two
+    # passes of the grouped kernels); depths beyond both ends of the planes
+    N, C, H, W, Fx, Fy, D, L, ps = 2, 3, 45, 150, 5, 4, 4, 3, 0.01
+    img, bank, xs, ys, iv, dmap = _bank2d_case(N, C, H, W, ks, Fx, Fy, D, L, ps, 41, noise)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK2D,
+                                        field_radii=xs, field_y=ys, inv_depths=iv,
+                                        bank_lambdas=L, lambda_of_channel=loc, pitch=ps)
+    bt, dt = torch.from_numpy(bank).cuda(), torch.from_numpy(dmap).cuda()
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), bt, depth=dt)
+    ref = R.render_bank2d(img, bank, dmap, xs, ys, iv, loc, ps)
+    assert _rel(out.cpu().numpy(), ref) <= REL_TOL
+    g = np.random.default_rng(42).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, bt, torch.from_numpy(g).cuda(), depth=dt)
+    gref = R.render_bank2d_adjoint(g, bank, dmap, xs, ys, iv, loc, ps)
+    assert _rel(gi.cpu().numpy(), gref) <= REL_TOL
+
+
+def test_bank2d_single_plane_and_unsupported_window():
+    N, C, H, W, ks, ps = 1, 1, 20, 30, 21, 0.01
+    img, bank, xs, ys, iv, dmap = _bank2d_case(N, C, H, W, ks, 3, 2, 1, 1, ps, 43)
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK2D,
+                                        field_radii=xs, field_y=ys, inv_depths=iv,
+                                        bank_lambdas=1, lambda_of_channel=[0], pitch=ps)
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), torch.from_numpy(bank).cuda(),
+                          depth=torch.from_numpy(dmap).cuda())
+    ref = R.render_bank2d(img, bank, dmap, xs, ys, iv, [0], ps)
+    assert _rel(out.cpu().numpy(), ref) <= REL_TOL
+    desc7, keep7 = sdirt.make_render_desc(N, C, H, W, 7, source=abi.SRC_BANK2D,
+                                          field_radii=xs, field_y=ys, inv_depths=iv,
+                                          bank_lambdas=1, lambda_of_channel=[0], pitch=ps)
+    with pytest.raises(abi.SdirtError):
+        sdirt.render_dp(desc7, torch.from_numpy(img).cuda(), torch.zeros((2, 3, 1, 1, 2, 7, 7)).cuda(),
+                        depth=torch.from_numpy(dmap).cuda())

@@ -143,3 +143,60 @@ def test_kernel_gradient_matches_torch_autograd(Cp):
     D = _rand(K.shape, 14)
     lhs = np.sum(R.render_dense(img, D) * g)
     assert lhs == pytest.approx(np.sum(D * gK), rel=1e-12)
+
+
+def _delta_bank2d(Fx, Fy, D, ks, i0, j0):
+    bank = np.zeros((Fy, Fx, D, 1, 2, ks, ks))
+    bank[..., 0, i0, j0] = 1.0
+    return bank
+
+
+def test_bank2d_flip_rules_by_quadrant():
+    # a left-side impulse at tap (i0, j0) everywhere: each quadrant shows the
+    # image shifted by the mirrored tap on the side the mirror rules give
+    H, W, ks, i0, j0 = 12, 14, 5, 1, 3
+    pad = ks // 2
+    img = _rand((1, 1, H, W), 31)
+    depth = np.full((1, H, W), 2000.0, dtype=np.float32)
+    bank = _delta_bank2d(2, 2, 1, ks, i0, j0)
+    out = R.render_bank2d(img, bank, depth, [0.0, 1.0], [0.0, 1.0], [1 / 2000.0], [0], 0.1)
+    for y in range(H):
+        for x in range(W):
+            mx, my = 2 * x - (W - 1) < 0, 2 * y - (H - 1) < 0
+            i = ks - 1 - i0 if my else i0
+            j = ks - 1 - j0 if mx else j0
+            side = 1 if mx else 0
+            src = img[0, 0, min(max(y + pad - i, 0), H - 1), min(max(x + pad - j, 0), W - 1)]
+            assert out[0, side, y, x] == pytest.approx(src, abs=1e-14)
+            assert out[0, 1 - side, y, x] == 0.0
+
+
+def test_bank2d_linear_in_inverse_depth():
+    # plane 0 an identity kernel, plane 1 zero: the output is (1 - w) img with
+    # w the float32 position of 1/depth between the planes (exact here)
+    H, W, ks = 6, 7, 3
+    img = _rand((1, 1, H, W), 32)
+    bank = np.zeros((1, 1, 3, 1, 2, ks, ks))
+    bank[0, 0, 0, 0, 0, 1, 1] = 1.0
+    iv = [0.25, 1.0, 2.0]                     # planes (1/mm), exact in float32
+    for depth, expect in ((4.0, 1.0), (2.0, 2.0 / 3.0), (1.0, 0.0), (8.0, 1.0), (0.5, 0.0)):
+        dm = np.full((1, H, W), depth, dtype=np.float32)
+        out = R.render_bank2d(img, bank, dm, [0.0], [0.0], iv, [0], 0.1)
+        # the centre tap is its own mirror image; the side swaps left of the
+        # centre, so the two sides together carry it
+        assert np.allclose(out[0, 0] + out[0, 1], expect * img[0, 0], atol=1e-7), depth
+    fx, fy, d0, w, _, _ = R.bank2d_lookup(H, W, np.full((H, W), 0.8, dtype=np.float32),
+                                           [0.0], [0.0], iv, 0.1)
+    assert np.all(d0 == 1) and np.allclose(w, 0.25, atol=1e-7)     # 1/0.8 = 1.25
+
+
+def test_bank2d_nearest_grid_point_equals_search():
+    H, W, pitch = 40, 52, 0.013
+    xs, ys = [0.0, 0.071, 0.2, 0.31], [0.0, 0.104, 0.22]
+    fx, fy, *_ = R.bank2d_lookup(H, W, np.ones((H, W), dtype=np.float32), xs, ys, [1.0], pitch)
+    hx = np.abs((np.arange(W) - (W - 1) / 2) * pitch)
+    hy = np.abs((np.arange(H) - (H - 1) / 2) * pitch)
+    bx = np.argmin(np.abs(hx[:, None] - np.array(xs)[None]), axis=1)
+    by = np.argmin(np.abs(hy[:, None] - np.array(ys)[None]), axis=1)
+    assert np.array_equal(fx, np.broadcast_to(bx[None, :], (H, W)))
+    assert np.array_equal(fy, np.broadcast_to(by[:, None], (H, W)))
