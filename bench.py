@@ -261,6 +261,36 @@ def extras(dev, stream):
         "render_s": t_r * 1e-3, "paper_render_s": 0.2,
         "paper_hardware": "i7-12700K + RTX 3090 (Sec. 5.1)"}
     print("paper workload done", file=sys.stderr, flush=True)
+    # 4b. exact-azimuth bank: the 12-surface lens traced on a 16 x 11
+    #     first-quadrant field grid, then the 1680 x 1120 RGB render and its
+    #     adjoint with flips and depth interpolation
+    lens, sensor, query, pts2, xs, ys = configs.config2_bank2d()
+    H, W, ps = sensor.height_px, sensor.width_px, sensor.pitch
+    P2 = pts2.shape[0]
+    pts2 = torch.from_numpy(pts2).to(dev)
+    b2 = torch.empty((P2, 2, query.ks, query.ks), dtype=torch.float32, device=dev)
+    tr = lambda: sdirt.trace_dp_psf(lens, sensor, query, points=pts2, out=b2, stats=False)
+    tr()
+    t_tr = timed(tr, stream, 2)
+    img2 = torch.from_numpy(scenes.aif_blobs(H, W, 3, n_blobs=2000, seed=0)[None]).to(dev)
+    dm2 = torch.from_numpy(scenes.depth_voronoi(H, W, 500.0, 5000.0, seed=100)[None]).to(dev)
+    desc2, keep2 = sdirt.make_render_desc(1, 3, H, W, query.ks, source=abi.SRC_BANK2D,
+                                          field_radii=xs, field_y=ys,
+                                          inv_depths=[1.0 / d for d in query.depths],
+                                          bank_lambdas=3, lambda_of_channel=list(configs.LAMBDA_OF_RGB),
+                                          pitch=ps)
+    o2 = sdirt.render_dp(desc2, img2, b2, depth=dm2)
+    g2 = torch.randn_like(o2)
+    gi2 = sdirt.render_dp_backward(desc2, b2, g2, depth=dm2)
+    tf = timed(lambda: sdirt.render_dp(desc2, img2, b2, depth=dm2, out=o2), stream, 3)
+    tb = timed(lambda: sdirt.render_dp_backward(desc2, b2, g2, depth=dm2, grad_img=gi2), stream, 3)
+    out["bank2d"] = {"workload": "12-surface lens, 16 x 11 first-quadrant fields x 16 depths x 3 "
+                                 "wavelengths (8448 PSFs, 512^2 rays, ks 63); 1680x1120 RGB "
+                                 "render + adjoint with flips and linear 1/d interpolation",
+                     "trace_ms": t_tr, "psfs_per_s": P2 / (t_tr * 1e-3),
+                     "render_fwd_ms": tf, "render_bwd_ms": tb}
+    del b2, o2, g2, gi2
+    print("bank2d done", file=sys.stderr, flush=True)
     # 5. smartphone-like 16-surface aspheric lens: 64 x 32 x 3 PSFs, 1024^2
     #    rays each, ks 65; then its render batch: 16 RGB 4032 x 3024 images
     #    (one AiF image, four depth maps, each used four times) from that

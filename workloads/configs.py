@@ -56,6 +56,21 @@ def config2(rays=512):
     return lens, sensor, query
 
 
+def config2_bank2d(rays=512, fx=16, fy=11):
+    """The 12-surface lens of config2 traced on a first-quadrant 2-D field
+    grid (fx x fy points from the centre to the sensor edges, y-major) for
+    the exact-azimuth bank render: the same depths, wavelengths and window.
+    Returns lens, sensor, query, list-mode points [P][4], x grid, y grid."""
+    lens, sensor, query = config2(rays)
+    W, H, ps = sensor.width_px, sensor.height_px, sensor.pitch
+    xs = [k * (W * ps / 2) / (fx - 1) for k in range(fx)]
+    ys = [m * (H * ps / 2) / (fy - 1) for m in range(fy)]
+    # list-mode points in bank order [fy][fx][depth][wavelength]
+    points = np.array([(x, y, d, l) for y in ys for x in xs for d in query.depths
+                       for l in range(len(query.wavelengths))], dtype=np.float64)
+    return lens, sensor, query, points, xs, ys
+
+
 def config3(rays=256):
     lens = config2_lens()
     W, H, ps = 1680, 1120, 0.00536
