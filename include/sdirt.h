@@ -251,16 +251,19 @@ int sdirt_render_dp_backward(const sdirt_render_desc* desc, const void* psf,
                              const float* depth, const float* grad_out,
                              float* grad_img, void* stream);
 
-/* Gradient with respect to a dense kernel map (the renderer of Sec. 3.2 /
- * S1.3 is linear in its kernels): for every pixel, kernel channel c' and
+/* Gradient with respect to the kernels (the renderer of Sec. 3.2 / S1.3 is
+ * linear in them).  Dense source: for every pixel, kernel channel c' and
  * side s,
  *   grad_psf[n, y, x, c', s, i, j] = sum over the image channels c that
  *       read kernel c' of grad_out[n, s*C + c, y, x]
- *                          * img[n, c, clamp(y+pad-i), clamp(x+pad-j)].
- * Chains the render to whatever produced the map (the surrogate network, a
- * differentiable tracer).  Dense source only (SDIRT_EUNSUPPORTED for the
- * bank); grad_psf device [N][H][W][Cp][2][ks][ks] in desc->psf_dtype (bf16
- * rounded to nearest even), overwritten; depth is not read (may be NULL). */
+ *                          * img[n, c, clamp(y+pad-i), clamp(x+pad-j)],
+ * device [N][H][W][Cp][2][ks][ks] in desc->psf_dtype (bf16 rounded to
+ * nearest even); depth is not read (may be NULL).  Bank sources: the sum of
+ * those per-pixel gradients over the pixels that read each bank entry, the
+ * lookup's mirrors undone and (BANK2D) weighted by the depth blend, device
+ * f32 in the bank's own layout; depth required; window sizes 21, 31, 33,
+ * 41, 63 and 65 only.  Chains the render to whatever produced the kernels
+ * (the surrogate network, the tracer's adjoint).  grad_psf is overwritten. */
 int sdirt_render_dp_psf_backward(const sdirt_render_desc* desc, const float* img,
                                  const float* depth, const float* grad_out,
                                  void* grad_psf, void* stream);

@@ -274,3 +274,56 @@ def render_bank2d(img, bank, depth_maps, xs, ys, inv_depths, lam_of_c, pitch):
 def render_bank2d_adjoint(grad_out, bank, depth_maps, xs, ys, inv_depths, lam_of_c, pitch):
     return render_dense_adjoint(grad_out, dense_from_bank2d(bank, depth_maps, xs, ys,
                                                             inv_depths, lam_of_c, pitch))
+
+
+def _bank_scatter(gK, bank_shape, entries):
+    """Adjoint of a bank expansion: gK [N][H][W][C][2][ks][ks] per-pixel
+    kernel gradients summed back into the bank entries they were read from;
+    entries(n) yields, per pixel and channel, (index tuple, weight, mx, my)."""
+    out = np.zeros(bank_shape)
+    N, H, W, C = gK.shape[:4]
+    for n in range(N):
+        for (y, x, c, idx, wt, mx, my) in entries(n):
+            k = gK[n, y, x, c]
+            if my:
+                k = k[:, ::-1, :]
+            if mx:
+                k = k[::-1, :, ::-1]
+            out[idx] += wt * k
+    return out
+
+
+def render_bank_psf_adjoint(img, grad_out, bank_shape, depth_maps, field_radii, inv_depths,
+                            lam_of_c, pitch):
+    """Transpose of render_bank with respect to the bank [F][Dn][L][2][ks][ks]."""
+    N, C, H, W = np.asarray(img).shape
+    gK = render_dense_psf_adjoint(img, grad_out, C, bank_shape[-1])
+
+    def entries(n):
+        fi, di, mx, my = bank_lookup(H, W, depth_maps[n], field_radii, inv_depths, pitch)
+        for y in range(H):
+            for x in range(W):
+                for c in range(C):
+                    yield (y, x, c, (fi[y, x], di[y, x], lam_of_c[c]), 1.0, mx[y, x], my[y, x])
+    return _bank_scatter(gK, bank_shape, entries)
+
+
+def render_bank2d_psf_adjoint(img, grad_out, bank_shape, depth_maps, xs, ys, inv_depths,
+                              lam_of_c, pitch):
+    """Transpose of render_bank2d with respect to the bank [Fy][Fx][D][L][2][ks][ks]."""
+    N, C, H, W = np.asarray(img).shape
+    D = bank_shape[2]
+    gK = render_dense_psf_adjoint(img, grad_out, C, bank_shape[-1])
+
+    def entries(n):
+        fx, fy, d0, w, mx, my = bank2d_lookup(H, W, depth_maps[n], xs, ys, inv_depths, pitch)
+        for y in range(H):
+            for x in range(W):
+                wt = float(w[y, x])
+                for c in range(C):
+                    yield (y, x, c, (fy[y, x], fx[y, x], d0[y, x], lam_of_c[c]), 1.0 - wt,
+                           mx[y, x], my[y, x])
+                    if D > 1:
+                        yield (y, x, c, (fy[y, x], fx[y, x], d0[y, x] + 1, lam_of_c[c]), wt,
+                               mx[y, x], my[y, x])
+    return _bank_scatter(gK, bank_shape, entries)

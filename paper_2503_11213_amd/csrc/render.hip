@@ -536,9 +536,106 @@ __device__ inline void bank_mfma_rows(const float* __restrict__ kl, int rstep, b
     for (int u = 0; u < NG; ++u) out[u] = acc[0][u] + acc[1][u];
 }
 
+// Kernel gradient of one chunk (cnt <= 64 strips of one entry, in 16 k-steps
+// of 4 strips): for kernel row i, the Toeplitz-shaped gradient
+//     D[(side, q)][p] = sum over the strips of g[side][q] * window_i[p]
+// is a matrix product with the strips as the contraction (A: the strips'
+// output gradients, fixed over the rows; B: their image windows from the
+// LDS halo), in 16-column blocks of p.  The kernel gradient is its diagonal
+// sum, grad_K[side][i][j] = sum_q D[(side, q)][q + KS - 1 - j]: each block
+// goes through a per-wave LDS scratch and the partial diagonal sums collect
+// in a second one, then 2 KS lanes add a row into the bank entry (mirrors
+// applied) with global atomics.
 template <int KS>
+struct KGradGeom {
+    static constexpr int NB = (KS + kStrip - 1 + 15) / 16;    // 16-column blocks of p
+    static constexpr int BLK = 16 * 17;                        // one block, padded rows
+    static constexpr int SUMS = 2 * 16 * NB;                   // partial sums [2][16 NB]
+    static constexpr int SCR = BLK + SUMS;
+    static_assert(kGT - kStrip + KS + kStrip - 1 <= GroupGeom<KS>::HW, "window reads stay in the halo row");
+};
+
+template <int KS>
+__device__ inline void bank_kgrad_chunk(const RenderArgs& A, int n, int c, int y0, int x0,
+                                        const int* items, int cnt, int fxb, int fyb, float* ge,
+                                        const float* halo, float* scr, int lane) {
+    using G = GroupGeom<KS>;
+    using KG = KGradGeom<KS>;
+    const int kk = KS * KS;
+    const int m = lane & 15, kq = lane >> 4;          // A: row (side, q) = m, k = kq
+    const int side = m >> 3, q = m & 7;
+    const int nks = (cnt + 3) >> 2;                   // k-steps of 4 strips
+    float ga[16];
+    int bofs[16];
+    const size_t plane = (size_t)A.C * A.H * A.W;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int j = 4 * t + kq;
+        const int it = items[min(j, cnt - 1)];
+        const int sid = it & 511;
+        const unsigned msk = j < cnt ? (unsigned)it >> 9 : 0u;
+        const int y = y0 + (sid >> 3), xs = x0 + (sid & 7) * kStrip;
+        // B operand of this lane: window column p = 16 b + m of strip j
+        bofs[t] = ((sid >> 3) + KS - 1) * G::HW + (sid & 7) * kStrip;
+        float g = 0.f;
+        if ((msk >> q) & 1u) {
+            g = A.gout[(((size_t)n * 2 * A.C + c) * A.H + y) * A.W + xs + q + side * plane];
+            if (A.bank2d) g *= pass_weight(A, n, y, xs + q);
+        }
+        ga[t] = g;
+    }
+    float* blk = scr;                                 // [16][17]
+    float* sums = scr + KG::BLK;                      // [2][16 NB]
+    for (int i = 0; i < KS; ++i) {
+        for (int e = lane; e < KG::SUMS; e += 64) sums[e] = 0.f;
+        for (int b = 0; b < KG::NB; ++b) {
+            floatx4_t d = {0.f, 0.f, 0.f, 0.f};
+            // columns past the window (p > KS + 6) are never summed: those
+            // lanes read the last window column instead
+            const int pofs = min(16 * b + m, KS + kStrip - 2) - i * G::HW;
+            for (int t = 0; t < nks; ++t)
+                d = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[t], halo[bofs[t] + pofs], d, 0, 0, 0);
+            // the lane holds D[4 kq + r][16 b + m]
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) blk[(4 * kq + r) * 17 + m] = d[r];
+            __builtin_amdgcn_wave_barrier();
+            // partial diagonal sums c = p - q in [16 b - 7, 16 b + 15]
+            if (lane < 46) {
+                const int sd = lane / 23;
+                const int cc = 16 * b - 7 + lane % 23;
+                if (cc >= 0 && cc < KS) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int qq = 0; qq < kStrip; ++qq) {
+                        const int col = cc + qq - 16 * b;
+                        if (col >= 0 && col < 16) acc += blk[(sd * 8 + qq) * 17 + col];
+                    }
+                    sums[sd * 16 * KG::NB + cc] += acc;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // row i of both sides into the entry: tap j = KS - 1 - c, mirrored
+        const int si = fyb ? KS - 1 - i : i;
+        for (int e = lane; e < 2 * KS; e += 64) {
+            const int sd = e / KS, cc = e - sd * KS;
+            const int j = KS - 1 - cc;
+            const int sj = fxb ? KS - 1 - j : j;
+            const int ss = fxb ? 1 - sd : sd;
+            const float v = sums[sd * 16 * KG::NB + cc];
+            if (v != 0.f) atomicAdd(&ge[(size_t)ss * kk + si * KS + sj], v);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// KGRAD: instead of the output, the gradient with respect to the bank
+// entries (see bank_kgrad_chunk); grad is the bank-shaped accumulator.
+template <int KS, bool KGRAD>
 __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderArgs A,
-                                                                 const float* __restrict__ bank) {
+                                                                 const float* __restrict__ bank,
+                                                                 float* __restrict__ grad) {
     using G = GroupGeom<KS>;
     using M = MfmaGeom<KS>;
     extern __shared__ __align__(16) float halo[];        // [HH][HW]
@@ -546,7 +643,10 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
     __shared__ int chunk_key[kGMaxChunks], chunk_pos[kGMaxChunks];
     __shared__ int red[kRBlock / 64];
     __shared__ int n_items, n_full, n_part, next_chunk;
-    __shared__ __align__(16) float arows[kRBlock / 64][4 * M::ROW];   // per wave: 2 buffers x 2 sides
+    // per wave: kernel-row staging (2 buffers x 2 sides), or for KGRAD the
+    // block and diagonal-sum scratch of bank_kgrad_chunk
+    constexpr int kWaveScratch = KGRAD ? KGradGeom<KS>::SCR : 4 * M::ROW;
+    __shared__ __align__(16) float arows[kRBlock / 64][kWaveScratch];
     const int pad = (KS - 1) / 2;
     const int kk = KS * KS;
     const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
@@ -558,7 +658,7 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
     const int y0 = (rem / tilesx) * kGT, x0 = (rem % tilesx) * kGT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     float* arow = arows[wave];
-    for (int e = lane; e < 4 * M::ROW; e += 64) arow[e] = 0.f;   // margins stay zero
+    for (int e = lane; e < kWaveScratch; e += 64) arow[e] = 0.f;   // margins stay zero
     // keys of the two strips this thread lists (strip sid: row sid / 8, column block sid % 8)
     int key[2][kStrip];
 #pragma unroll
@@ -649,6 +749,11 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
                 const int cp = __builtin_amdgcn_readfirstlane(chunk_pos[ch]);
                 const int cnt = cp >> 16, s0 = cp & 0xffff;
                 const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
+                if (KGRAD) {
+                    bank_kgrad_chunk<KS>(A, n, c, y0, x0, items + s0, cnt, fxb, fyb,
+                                         grad + ((size_t)fd * A.L + lam) * 2 * kk, halo, arow, lane);
+                    continue;
+                }
                 // left output side reads the stored right kernel when mirrored
                 const float* kl = bank + ((size_t)fd * A.L + lam) * 2 * kk + (fxb ? kk : 0);
                 int its[4], bofs[4];
@@ -989,11 +1094,34 @@ static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
         const size_t shm = (size_t)G::HH * G::HW * sizeof(float);
         const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
         const dim3 grid((unsigned)((long long)A.C * A.N * tilesx * tilesy));
-        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL(render_bank_fast_kernel<KS>, grid, dim3(kRBlock), shm, st, A,
-                           reinterpret_cast<const float*>(A.psf));
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL((render_bank_fast_kernel<KS, false>), grid, dim3(kRBlock), shm, st, A,
+                           reinterpret_cast<const float*>(A.psf), (float*)nullptr);
     }
     return true;
+}
+
+template <int KS>
+static void launch_bank_kgrad(const RenderArgs& A, float* grad, hipStream_t st) {
+    using G = GroupGeom<KS>;
+    const size_t shm = (size_t)G::HH * G::HW * sizeof(float);
+    const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
+    const dim3 grid((unsigned)((long long)A.C * A.N * tilesx * tilesy));
+    if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((render_bank_fast_kernel<KS, true>), grid, dim3(kRBlock), shm, st, A,
+                       (const float*)nullptr, grad);
+}
+
+static bool bank_kgrad_pass(const RenderArgs& A, float* grad, hipStream_t st) {
+    switch (A.ks) {
+        case 21: launch_bank_kgrad<21>(A, grad, st); return true;
+        case 31: launch_bank_kgrad<31>(A, grad, st); return true;
+        case 33: launch_bank_kgrad<33>(A, grad, st); return true;
+        case 41: launch_bank_kgrad<41>(A, grad, st); return true;
+        case 63: launch_bank_kgrad<63>(A, grad, st); return true;
+        case 65: launch_bank_kgrad<65>(A, grad, st); return true;
+        default: return false;
+    }
 }
 
 template <bool BWD>
@@ -1204,7 +1332,25 @@ int render_psf_backward_impl(const sdirt_render_desc* desc, const float* img, co
     int rc = pack_render(desc, &A);
     if (rc) return rc;
     if (!img || !gout || !grad_psf) return SDIRT_EINVAL;
-    if (A.source != SDIRT_SRC_DENSE) return SDIRT_EUNSUPPORTED;
+    if (A.source != SDIRT_SRC_DENSE) {
+        // bank sources: gradient with respect to the bank entries,
+        // accumulated over the pixels that read them (mirrors undone)
+        if (!depth) return SDIRT_EINVAL;
+        A.img = img; A.gout = gout; A.depth = depth;
+        const long long cells = A.bank2d ? (long long)A.F * A.Fy : A.F;
+        if (cells * A.D * 4 >= 0x7fffffffLL) return SDIRT_EUNSUPPORTED;
+        if (A.ks != 21 && A.ks != 31 && A.ks != 33 && A.ks != 41 && A.ks != 63 && A.ks != 65)
+            return SDIRT_EUNSUPPORTED;
+        const size_t n = (size_t)cells * A.D * A.L * 2 * A.ks * A.ks;
+        if ((rc = launch_fill_zero(grad_psf, n * sizeof(float), stream))) return rc;
+        float* g = reinterpret_cast<float*>(grad_psf);
+        for (int pass = 0; pass < (A.bank2d ? 2 : 1); ++pass) {
+            RenderArgs B = A;
+            B.pass = pass;
+            bank_kgrad_pass(B, g, stream);
+        }
+        return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
+    }
     (void)depth;
     const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
     if ((size_t)A.C * hh * hw * sizeof(float) > 160 * 1024) return SDIRT_EUNSUPPORTED;

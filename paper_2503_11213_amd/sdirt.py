@@ -231,15 +231,26 @@ def render_dp_backward(desc, psf, grad_out, depth=None, grad_img=None):
 
 # ---- PSF surrogate MLP ------------------------------------------------------
 
-def render_dp_psf_backward(desc, img, grad_out, grad_psf=None):
-    """Gradient of the dense render with respect to its kernel map:
-    [N][H][W][Cp][2][ks][ks] in the descriptor's kernel dtype."""
+def render_dp_psf_backward(desc, img, grad_out, depth=None, grad_psf=None):
+    """Gradient of the render with respect to its kernels: the dense map
+    [N][H][W][Cp][2][ks][ks] (the descriptor's kernel dtype) or the bank in
+    its own layout (float32; depth required)."""
     assert img.is_cuda and img.dtype == torch.float32
     if grad_psf is None:
-        dt = torch.bfloat16 if desc.psf_dtype == abi.BF16 else torch.float32
-        grad_psf = torch.empty((desc.N, desc.H, desc.W, desc.psf_channels, 2, desc.ks, desc.ks),
-                               dtype=dt, device=img.device)
-    rc = abi.lib().sdirt_render_dp_psf_backward(C.byref(desc), _dptr(img.contiguous()), None,
+        ks = desc.ks
+        if desc.source == abi.SRC_DENSE:
+            dt = torch.bfloat16 if desc.psf_dtype == abi.BF16 else torch.float32
+            shape = (desc.N, desc.H, desc.W, desc.psf_channels, 2, ks, ks)
+        elif desc.source == abi.SRC_BANK2D:
+            dt = torch.float32
+            shape = (desc.bank_fields_y, desc.bank_fields, desc.bank_depths, desc.bank_lambdas,
+                     2, ks, ks)
+        else:
+            dt = torch.float32
+            shape = (desc.bank_fields, desc.bank_depths, desc.bank_lambdas, 2, ks, ks)
+        grad_psf = torch.empty(shape, dtype=dt, device=img.device)
+    rc = abi.lib().sdirt_render_dp_psf_backward(C.byref(desc), _dptr(img.contiguous()),
+                                                _dptr(depth),
                                                 _dptr(grad_out.contiguous()), _dptr(grad_psf),
                                                 _stream())
     abi.check("sdirt_render_dp_psf_backward", rc)

@@ -298,3 +298,34 @@ def test_bank2d_single_plane_and_unsupported_window():
     with pytest.raises(abi.SdirtError):
         sdirt.render_dp(desc7, torch.from_numpy(img).cuda(), torch.zeros((2, 3, 1, 1, 2, 7, 7)).cuda(),
                         depth=torch.from_numpy(dmap).cuda())
+
+
+@pytest.mark.parametrize("ks,two_d", [(21, False), (63, False), (33, True), (65, True)])
+def test_bank_kernel_gradient(ks, two_d):
+    # gradient with respect to the bank entries: per-pixel kernel gradients
+    # summed over the pixels reading each entry, mirrors undone, 2-D bank
+    # weights applied (matrix-core correlation, atomic accumulation)
+    N, C, H, W, L, ps = 1, 3, 45, 150, 3, 0.01
+    loc = [2, 1, 0]
+    rng = np.random.default_rng(61)
+    g = rng.normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    if two_d:
+        img, bank, xs, ys, iv, dmap = _bank2d_case(N, C, H, W, ks, 4, 3, 3, L, ps, 62)
+        desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK2D,
+                                            field_radii=xs, field_y=ys, inv_depths=iv,
+                                            bank_lambdas=L, lambda_of_channel=loc, pitch=ps)
+        ref = R.render_bank2d_psf_adjoint(img, g, bank.shape, dmap, xs, ys, iv, loc, ps)
+    else:
+        F, D = 6, 5
+        img, bank, radii, iv, dmap = _bank_case(N, C, H, W, ks, F, D, L, ps, 63)
+        desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                            field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                            lambda_of_channel=loc, pitch=ps)
+        ref = R.render_bank_psf_adjoint(img, g, bank.shape, dmap, radii, iv, loc, ps)
+    got = sdirt.render_dp_psf_backward(desc, torch.from_numpy(img).cuda(),
+                                       torch.from_numpy(g).cuda(),
+                                       depth=torch.from_numpy(dmap).cuda()).cpu().numpy()
+    assert got.shape == ref.shape
+    err = np.max(np.abs(got - ref)) / np.abs(ref).max()
+    print("bank kernel gradient max err / max", err)
+    assert err <= 1e-5

@@ -200,3 +200,22 @@ def test_bank2d_nearest_grid_point_equals_search():
     by = np.argmin(np.abs(hy[:, None] - np.array(ys)[None]), axis=1)
     assert np.array_equal(fx, np.broadcast_to(bx[None, :], (H, W)))
     assert np.array_equal(fy, np.broadcast_to(by[:, None], (H, W)))
+
+
+def test_bank_gradients_satisfy_the_adjoint_identity():
+    # the render is linear in the bank: <render(B), g> = <B, grad_bank(g)>
+    N, C, H, W, ks, L = 1, 2, 10, 13, 5, 2
+    img = _rand((N, C, H, W), 51)
+    g = _rand((N, 2 * C, H, W), 52) - 0.5
+    depth = np.random.default_rng(53).uniform(400, 6000, (N, H, W)).astype(np.float32)
+    loc = [1, 0]
+    radii, iv = [0.0, 0.03, 0.07], [1 / 5000.0, 1 / 1000.0, 1 / 450.0]
+    B = _rand((3, 3, L, 2, ks, ks), 54)
+    gB = R.render_bank_psf_adjoint(img, g, B.shape, depth, radii, iv, loc, 0.01)
+    lhs = np.sum(R.render_bank(img, B, depth, radii, iv, loc, 0.01) * g)
+    assert lhs == pytest.approx(np.sum(B * gB), rel=1e-12)
+    xs, ys = [0.0, 0.04], [0.0, 0.02, 0.05]
+    B2 = _rand((3, 2, 3, L, 2, ks, ks), 55)
+    gB2 = R.render_bank2d_psf_adjoint(img, g, B2.shape, depth, xs, ys, iv, loc, 0.01)
+    lhs = np.sum(R.render_bank2d(img, B2, depth, xs, ys, iv, loc, 0.01) * g)
+    assert lhs == pytest.approx(np.sum(B2 * gB2), rel=1e-12)
