@@ -284,12 +284,16 @@ def extras(dev, stream):
     gi2 = sdirt.render_dp_backward(desc2, b2, g2, depth=dm2)
     tf = timed(lambda: sdirt.render_dp(desc2, img2, b2, depth=dm2, out=o2), stream, 3)
     tb = timed(lambda: sdirt.render_dp_backward(desc2, b2, g2, depth=dm2, grad_img=gi2), stream, 3)
+    gb2 = torch.empty_like(b2)
+    kg2 = lambda: sdirt.render_dp_psf_backward(desc2, img2, g2, depth=dm2, grad_psf=gb2)
+    kg2()
+    tk2 = timed(kg2, stream, 3)
     out["bank2d"] = {"workload": "12-surface lens, 16 x 11 first-quadrant fields x 16 depths x 3 "
                                  "wavelengths (8448 PSFs, 512^2 rays, ks 63); 1680x1120 RGB "
                                  "render + adjoint with flips and linear 1/d interpolation",
                      "trace_ms": t_tr, "psfs_per_s": P2 / (t_tr * 1e-3),
-                     "render_fwd_ms": tf, "render_bwd_ms": tb}
-    del b2, o2, g2, gi2
+                     "render_fwd_ms": tf, "render_bwd_ms": tb, "bank_grad_ms": tk2}
+    del b2, o2, g2, gi2, gb2
     print("bank2d done", file=sys.stderr, flush=True)
     # 5. smartphone-like 16-surface aspheric lens: 64 x 32 x 3 PSFs, 1024^2
     #    rays each, ks 65; then its render batch: 16 RGB 4032 x 3024 images
@@ -405,6 +409,13 @@ def main():
     ms_trace = timed(trace, stream, reps)
     ms_render = timed(render, stream, reps)
     ms_rbwd = timed(render_bwd, stream, reps)
+    # gradient with respect to the bank (not part of the step: the chain to
+    # the tracer's adjoint for end-to-end lens optimisation)
+    gbank = torch.empty_like(bank)
+    kgrad = lambda: sdirt.render_dp_psf_backward(desc, img, gout, depth=dmap, grad_psf=gbank)
+    kgrad()
+    ms_kgrad = timed(kgrad, stream, reps)
+    del gbank
     _, st = sdirt.trace_dp_psf(lens, sensor, query, out=bank, stats=True)
     st = st.cpu().numpy()
 
@@ -443,7 +454,8 @@ def main():
                   "transmitted_fraction": float(st[:, 2].sum() / st[:, 0].sum())},
         "render": {"fwd_ms": ms_render, "bwd_ms": ms_rbwd,
                    "fwd_mpix_per_s": H * W / (ms_render * 1e-3) / 1e6,
-                   "fwd_plus_bwd_over_fwd": (ms_render + ms_rbwd) / ms_render},
+                   "fwd_plus_bwd_over_fwd": (ms_render + ms_rbwd) / ms_render,
+                   "bank_grad_ms": ms_kgrad},
     }
     if not args.no_extras:
         line.update(extras(dev, stream))
