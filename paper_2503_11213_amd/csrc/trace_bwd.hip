@@ -57,14 +57,14 @@ __device__ __forceinline__ void refract_bwd(double mu, const double d[3], const 
                                    const double ob[3], double db[3], double nb[3]) {
     const double cosI = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
     const double K = 1.0 - mu * mu * (1.0 - cosI * cosI);
-    const double sK = sqrt(K > 0.0 ? K : 0.0);
+    const double sK = sqrt_t<double>(K);
     const double g = sK - mu * cosI;
     const double gb = ob[0] * n[0] + ob[1] * n[1] + ob[2] * n[2];
     for (int k = 0; k < 3; ++k) {
         nb[k] += ob[k] * g;
         db[k] += ob[k] * mu;
     }
-    const double Kb = sK > 0.0 ? gb * 0.5 / sK : 0.0;
+    const double Kb = sK > 0.0 ? gb * 0.5 * rcp_d(sK) : 0.0;
     const double cb = -mu * gb + Kb * mu * mu * 2.0 * cosI;
     for (int k = 0; k < 3; ++k) {
         db[k] += cb * n[k];
@@ -113,7 +113,8 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
     // ---- forward recompute -------------------------------------------
     const double dx = in.dx, dy = in.dy, dz = in.dz;
     const double z1 = in.z - tprev;
-    const double tau = -z1 / dz;
+    const double idz = rcp_d(dz);
+    const double tau = -z1 * idz;
     const double x1 = in.x + tau * dx, y1 = in.y + tau * dy;
     double D = 0.0, F = 0.0, G = 0.0, den = 1.0, sq = 0.0;
     double xh = x1, yh = y1, zh = 0.0;
@@ -123,9 +124,9 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
         F = c * (x1 * x1 + y1 * y1);
         G = dz - c * (x1 * dx + y1 * dy);
         const double disc = G * G - c * F;
-        sq = sqrt(disc > 0.0 ? disc : 0.0);
+        sq = sqrt_t<double>(disc);
         den = G + sq;
-        D = F / den;
+        D = F * rcp_d(den);
     } else if (kind == SDIRT_ASPHERE) {
         const double kk = co[0];
         const double FF = c * (x1 * x1 + y1 * y1);
@@ -190,11 +191,12 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
         const double Db = xhb * dx + yhb * dy + zhb * dz;
         db[0] += xhb * D; db[1] += yhb * D; db[2] += zhb * D;
         double x1b = xhb, y1b = yhb;
-        const double Fb0 = Db / den;
-        const double denb = -Db * D / den;
+        const double iden = rcp_d(den);
+        const double Fb0 = Db * iden;
+        const double denb = -Db * D * iden;
         double Gb = denb;
         const double sqb = denb;
-        const double discb = sq > 0.0 ? sqb * 0.5 / sq : 0.0;
+        const double discb = sq > 0.0 ? sqb * 0.5 * rcp_d(sq) : 0.0;
         Gb += discb * 2.0 * G;
         const double Fb = Fb0 - c * discb;
         pg[0] += -F * discb;
@@ -256,8 +258,8 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
     const double taub = xhb * dx + yhb * dy;
     db[0] += xhb * tau;
     db[1] += yhb * tau;
-    const double z1b = -taub / dz;
-    db[2] += taub * z1 / (dz * dz);
+    const double z1b = -taub * idz;
+    db[2] += taub * z1 * idz * idz;
     ib.x = xhb;
     ib.y = yhb;
     ib.z = z1b;
@@ -288,6 +290,9 @@ __device__ inline St path_get(const float* v, int s, int lane) {
     return St{o[0], o[64], o[128], o[192], o[256], o[320]};
 }
 
+// GENERAL = false: spheres, planes and stops only (the forward re-trace then
+// takes the branch-free surface loop).
+template <bool GENERAL>
 __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
     __shared__ double gsh[kPerSurf * kMaxS + 1];
     extern __shared__ float path[];     // [(S + 1) * 6][64]
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             const double inv = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
             ray = Ray<double>{ex, ey, zep, ddx * inv, ddy * inv, ddz * inv};
             path_put(path, 0, lane, ray);
-            const int st = trace_ray<double, PathRec, false>(A.lens, mu, ray, PathRec{path, lane});
+            const int st = trace_ray<double, PathRec, false, GENERAL>(A.lens, mu, ray, PathRec{path, lane});
             live = st == kAlive;
         }
         // ---- splat adjoint: dL/dO, dL/dD, dL/dk -----------------------
@@ -457,7 +462,11 @@ int trace_backward_impl(const sdirt_lens* lens, const sdirt_sensor* sensor,
     A.smp.chunks = chunks;
     A.smp.rays_per_chunk = (n_rays + chunks - 1) / chunks;
     const size_t shm = (size_t)(R.S + 1) * 6 * kBBlock * sizeof(float);
-    hipLaunchKernelGGL(trace_bwd_kernel, dim3((unsigned)((long long)chunks * P)),
+    bool general = false;
+    for (int s = 0; s < R.S; ++s)
+        general = general || R.kind[s] == SDIRT_ASPHERE || R.kind[s] == SDIRT_IDEAL;
+    hipLaunchKernelGGL(general ? trace_bwd_kernel<true> : trace_bwd_kernel<false>,
+                       dim3((unsigned)((long long)chunks * P)),
                        dim3(kBBlock), shm, stream, A);
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
 }
