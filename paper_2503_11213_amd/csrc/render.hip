@@ -678,7 +678,8 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
     bool more = true;
     while (more) {
         // ---- list a batch of entries, grouped, in chunks of <= 64 items
-        if (tid == 0) { n_items = 0; n_full = 0; n_part = 0; }
+        // the chunk counter starts at 0 even when the batch lists nothing
+        if (tid == 0) { n_items = 0; n_full = 0; n_part = 0; next_chunk = 0; }
         __syncthreads();
         while (true) {
             int mine = 0x7fffffff;
@@ -722,7 +723,6 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
                     chunk_key[slot] = k;
                     chunk_pos[slot] = s0 | (cnt << 16);
                 }
-                next_chunk = 0;
             }
             __syncthreads();
         }
