@@ -39,9 +39,10 @@ FLOP_SPHERE, FLOP_STOP, FLOP_RAY = 56, 10, 60
 # for the kernel sources with this digest only; otherwise traffic is null.
 TRACE_SOURCES = ("paper_2503_11213_amd/csrc/device_common.hpp",
                  "paper_2503_11213_amd/csrc/trace.hip",
-                 "paper_2503_11213_amd/csrc/pack.hpp")
-TRACE_TRAFFIC = {"sources_sha256": "a0070704e226e155a7a32ba040823c51059fcc12cbaf32189a545d9ea91c058c",
-                 "bytes": 65724250}
+                 "paper_2503_11213_amd/csrc/pack.hpp",
+                 "paper_2503_11213_amd/csrc/pack.cpp")
+TRACE_TRAFFIC = {"sources_sha256": "5bfdb29c607979479748fabdd7839405bc368005f758b59c657c1067925cabd7",
+                 "bytes": 65723181}
 
 
 def sources_digest():
