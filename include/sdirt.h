@@ -345,6 +345,22 @@ int sdirt_mlp_backward(const sdirt_mlp_desc* desc, const float* params, int batc
                        const float* x, const float* target, float* grads_out,
                        float* loss_out, void* workspace, void* stream);
 
+/* Vector-Jacobian product of the network (Sec. 3.2): for n_rows inputs x
+ * (device [n_rows][4], as for sdirt_mlp_forward) and an upstream gradient
+ * grad_psf = dL/dP of a scalar L with respect to the softmax outputs
+ * (device [n_rows][n_out] f32, e.g. the kernel-map gradient of
+ * sdirt_render_dp_psf_backward for a map the network predicted), the
+ * gradient of L with respect to the parameters, summed over the rows:
+ * through the softmax, dL/dz_i = P_i (g_i - sum_j P_j g_j); then as
+ * sdirt_mlp_backward.  grads_out device [n_params] f32 and value_out
+ * device [1] f32 (sum over rows of <g, P>; may be NULL) are overwritten.
+ * Rows are processed in chunks of ws_batch (a multiple of 64) with a
+ * workspace sized for ws_batch; a ragged last chunk is padded in the
+ * workspace with rows that contribute nothing.  n_rows = 0 gives zeros. */
+int sdirt_mlp_vjp(const sdirt_mlp_desc* desc, const float* params, long long n_rows,
+                  const float* x, const float* grad_psf, float* grads_out, float* value_out,
+                  void* workspace, int ws_batch, void* stream);
+
 /* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) of
  * params with moments m, v (device [n_params] f32 each, updated). */
 int sdirt_mlp_adam(const sdirt_mlp_desc* desc, float* params, float* m, float* v,

@@ -87,6 +87,10 @@ def forward(params, x, norm, bf16=False):
 
 
 def loss(p, t, kind="l2max"):
+    """kind "vjp": t is an upstream gradient dL/dp; the value is the sum
+    over rows of <t, p> (not averaged)."""
+    if kind == "vjp":
+        return float(np.sum(p * t))
     if kind == "kl":
         tl = np.where(t > 0.0, t * np.log(np.where(t > 0.0, t, 1.0)), 0.0)
         return float(np.mean(np.sum(tl - t * np.log(p), axis=1)))
@@ -98,7 +102,10 @@ def backward(params, p, cache, t, bf16=False, kind="l2max"):
     """Gradients [(dW, db)] of loss(p, t, kind) through softmax and the layers."""
     rnd = to_bf16 if bf16 else (lambda a: a)
     B = p.shape[0]
-    if kind == "kl":
+    if kind == "vjp":
+        # softmax Jacobian applied to the upstream gradient t = dL/dp
+        dz = p * (t - np.sum(p * t, axis=1, keepdims=True))
+    elif kind == "kl":
         dz = (p * t.sum(axis=1, keepdims=True) - t) / B
     else:
         m = t.max(axis=1, keepdims=True)

@@ -126,6 +126,9 @@ SIGNATURES = {
     "sdirt_mlp_backward": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_int,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),
+    "sdirt_mlp_vjp": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_longlong, C.c_void_p,
+                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                C.c_void_p]),
     "sdirt_mlp_adam": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_int, C.c_float, C.c_void_p]),
     "sdirt_mlp_train": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_void_p, C.c_void_p,

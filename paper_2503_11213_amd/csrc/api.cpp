@@ -30,6 +30,8 @@ int mlp_render(const sdirt_mlp_desc*, const float*, const sdirt_mlp_render_desc*
                const float*, float*, void*, int, hipStream_t);
 int mlp_backward(const sdirt_mlp_desc*, const float*, int, const float*, const float*,
                  float*, float*, void*, hipStream_t);
+int mlp_vjp(const sdirt_mlp_desc*, const float*, long long, const float*, const float*,
+            float*, float*, void*, int, hipStream_t);
 int mlp_adam(const sdirt_mlp_desc*, float*, float*, float*, const float*, int, float,
              hipStream_t);
 int mlp_train(const sdirt_mlp_desc*, float*, float*, float*, int, int, float, float, int, int,
@@ -163,6 +165,13 @@ int sdirt_mlp_backward(const sdirt_mlp_desc* desc, const float* params, int batc
                        float* loss_out, void* workspace, void* stream) {
     return mlp_backward(desc, params, batch, x, target, grads_out, loss_out, workspace,
                         (hipStream_t)stream);
+}
+
+int sdirt_mlp_vjp(const sdirt_mlp_desc* desc, const float* params, long long n_rows,
+                  const float* x, const float* grad_psf, float* grads_out, float* value_out,
+                  void* workspace, int ws_batch, void* stream) {
+    return mlp_vjp(desc, params, n_rows, x, grad_psf, grads_out, value_out, workspace,
+                   ws_batch, (hipStream_t)stream);
 }
 
 int sdirt_mlp_adam(const sdirt_mlp_desc* desc, float* params, float* m, float* v,

@@ -324,6 +324,7 @@ struct SoftArgs {
     int B, n_out, n_out_pad;
     float inv_batch;
     int kl;                  // Kullback-Leibler loss instead of max-scaled L2
+    int vjp;                 // target is an upstream gradient dL/dp (no loss)
     const float* logits;
     const float* target;     // null: inference
     void* out;               // inference output [B][n_out] (f32 or bf16) or null
@@ -368,6 +369,27 @@ __global__ __launch_bounds__(256) void softmax_loss_kernel(const SoftArgs a) {
         return;
     }
     const float* t = a.target + (size_t)b * a.n_out;
+    if (a.vjp) {
+        // upstream gradient t = dL/dp through the softmax:
+        // dz_i = p_i (t_i - sum_j p_j t_j); the row's value sum_i p_i t_i
+        float pg = 0.f;
+        for (int i = threadIdx.x; i < a.n_out; i += blockDim.x)
+            pg += __expf(z[i] - mx) * inv * t[i];
+        pg = block_reduce(pg, red, false);
+        if (threadIdx.x == 0) atomicAdd(a.loss, pg);
+        for (int i = threadIdx.x; i < a.n_out_pad; i += blockDim.x) {
+            float g = 0.f;
+            if (i < a.n_out) {
+                const float p = __expf(z[i] - mx) * inv;
+                g = p * (t[i] - pg);
+                a.dz[(size_t)b * a.n_out + i] = g;
+            }
+            const bf16_t gb = f2bf(g);
+            a.dzb[(size_t)b * a.n_out_pad + i] = gb;
+            a.dzT[(size_t)i * a.B + b] = gb;
+        }
+        return;
+    }
     if (a.kl) {
         // KL(t || p) = sum_i t_i (log t_i - log p_i); d/dz_i = p_i sum(t) - t_i
         const float lse = mx + __logf(sum);
@@ -419,6 +441,13 @@ __global__ __launch_bounds__(256) void softmax_loss_kernel(const SoftArgs a) {
         a.dzb[(size_t)b * a.n_out_pad + i] = gb;
         a.dzT[(size_t)i * a.B + b] = gb;
     }
+}
+
+// y += x (float32, n elements)
+__global__ void accumulate_kernel(float* y, const float* x, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        y[i] += x[i];
 }
 
 // column sums of a float32 [B][N] matrix (bias gradient)
@@ -528,11 +557,13 @@ static void forward_rows(const MlpDims& m, const sdirt_mlp_desc* d, const MlpWs&
 
 // loss gradient for the batch already in w.H / w.logits; grads into w.grads
 static void backward_rows(const MlpDims& m, const MlpWs& w, const float* params, int B,
-                          const float* target, hipStream_t st) {
+                          const float* target, hipStream_t st, bool vjp = false) {
     SoftArgs s;
     std::memset(&s, 0, sizeof(s));
-    s.B = B; s.n_out = m.n_out; s.n_out_pad = m.n_out_pad; s.inv_batch = 1.f / B;
-    s.kl = m.loss == SDIRT_LOSS_KL;
+    s.B = B; s.n_out = m.n_out; s.n_out_pad = m.n_out_pad;
+    s.inv_batch = vjp ? 1.f : 1.f / B;
+    s.vjp = vjp;
+    s.kl = !vjp && m.loss == SDIRT_LOSS_KL;
     s.logits = w.logits; s.target = target; s.dz = w.dz; s.dzb = w.dzb; s.dzT = w.dzT;
     s.loss = w.loss;
     hipLaunchKernelGGL(softmax_loss_kernel, dim3(B), dim3(256), 0, st, s);
@@ -697,6 +728,50 @@ int mlp_backward(const sdirt_mlp_desc* d, const float* params, int batch, const 
         (void)hipMemcpyAsync(grads_out, w.grads, m.n_params() * 4, hipMemcpyDeviceToDevice, st);
     if (loss_out)
         (void)hipMemcpyAsync(loss_out, w.loss, 4, hipMemcpyDeviceToDevice, st);
+    return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
+}
+
+int mlp_vjp(const sdirt_mlp_desc* d, const float* params, long long n_rows, const float* x,
+            const float* grad_psf, float* grads_out, float* value_out, void* workspace,
+            int ws_batch, hipStream_t st) {
+    MlpDims m;
+    int rc = dims_of(d, &m);
+    if (rc) return rc;
+    if (!params || !grads_out || !workspace || n_rows < 0) return SDIRT_EINVAL;
+    if (n_rows > 0 && (!x || !grad_psf)) return SDIRT_EINVAL;
+    if (ws_batch < 64 || ws_batch % 64) return SDIRT_EINVAL;
+    const MlpWs w = carve(m, ws_batch, (char*)workspace);
+    const size_t np = m.n_params();
+    if ((rc = launch_fill_zero(grads_out, np * 4, st))) return rc;
+    if (value_out && (rc = launch_fill_zero(value_out, 4, st))) return rc;
+    if (n_rows == 0) return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
+    cast_all(m, w, params, st);
+    const int gblocks = (int)std::min<size_t>((np + 255) / 256, 2048);
+    for (long long r0 = 0; r0 < n_rows; r0 += ws_batch) {
+        const long long nb = std::min<long long>(ws_batch, n_rows - r0);
+        const int B = (int)((nb + 63) / 64 * 64);
+        const float* xb = x + r0 * 4;
+        const float* gb = grad_psf + r0 * m.n_out;
+        if (nb < B) {
+            // ragged tail: rows padded with zero inputs and zero gradients,
+            // which add nothing
+            if ((rc = launch_fill_zero(w.xb, (size_t)B * 16, st))) return rc;
+            if ((rc = launch_fill_zero(w.target, (size_t)B * m.n_out * 4, st))) return rc;
+            (void)hipMemcpyAsync(w.xb, xb, (size_t)nb * 16, hipMemcpyDeviceToDevice, st);
+            (void)hipMemcpyAsync(w.target, gb, (size_t)nb * m.n_out * 4, hipMemcpyDeviceToDevice, st);
+            xb = w.xb;
+            gb = w.target;
+        }
+        if ((rc = launch_fill_zero(w.loss, 4, st))) return rc;
+        zero_bias_grads(m, w, st);
+        forward_rows(m, d, w, params, B, xb, st, true);
+        backward_rows(m, w, params, B, gb, st, true);
+        hipLaunchKernelGGL(accumulate_kernel, dim3(gblocks), dim3(256), 0, st, grads_out,
+                           (const float*)w.grads, np);
+        if (value_out)
+            hipLaunchKernelGGL(accumulate_kernel, dim3(1), dim3(64), 0, st, value_out,
+                               (const float*)w.loss, (size_t)1);
+    }
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
 }
 

@@ -324,6 +324,21 @@ def mlp_backward(desc, params, x, target, workspace):
     return grads, loss
 
 
+def mlp_vjp(desc, params, x, grad_psf, workspace, ws_batch):
+    """Gradient of sum_rows <grad_psf, P(x)> with respect to the parameters
+    (float32 [n_params]) and that sum ([1])."""
+    assert x.dtype == torch.float32 and grad_psf.dtype == torch.float32
+    n = int(x.shape[0])
+    assert grad_psf.shape[0] == n and grad_psf.numel() == n * desc.n_out
+    grads = torch.empty_like(params)
+    value = torch.empty((1,), dtype=torch.float32, device=params.device)
+    rc = abi.lib().sdirt_mlp_vjp(C.byref(desc), _dptr(params), n, _dptr(x.contiguous()),
+                                 _dptr(grad_psf.contiguous()), _dptr(grads), _dptr(value),
+                                 _dptr(workspace), int(ws_batch), _stream())
+    abi.check("sdirt_mlp_vjp", rc)
+    return grads, value
+
+
 def mlp_adam(desc, params, m, v, grads, step, lr):
     rc = abi.lib().sdirt_mlp_adam(C.byref(desc), _dptr(params), _dptr(m), _dptr(v),
                                   _dptr(grads), int(step), float(lr), _stream())

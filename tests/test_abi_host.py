@@ -168,3 +168,27 @@ def test_surrogate_render_argument_validation():
     assert call(desc(), ptr=None) == abi.EINVAL
     rd = desc(); rd.wavelength[1] = float("nan")
     assert call(rd) == abi.EINVAL
+
+
+@pytest.mark.parametrize("idx", [1, 2])
+def test_lens_theta_round_trip(idx):
+    # the autograd wrapper's parameter vector: a lens rebuilt from its own
+    # theta (stop radius and sensor distance fixed, no f-number or focus)
+    # resolves to the same first-order data
+    from paper_2503_11213_amd.autograd import lens_theta, lens_at, PER_SURFACE
+    lens = _lenses()[idx]
+    sensor = Sensor(pitch=0.005, sigmoid_k=17.0)
+    th = lens_theta(lens, sensor)
+    S = len(lens.surfaces)
+    assert th.shape == (PER_SURFACE * S + 1,)
+    assert th.shape[0] == sdirt.n_params(lens)
+    a = sdirt.resolve_lens(lens)
+    assert th[PER_SURFACE * (S - 1) + 1].item() == a["sensor_distance"]
+    assert th[-1].item() == 17.0
+    l2, s2 = lens_at(lens, sensor, th)
+    assert l2.f_number == 0.0 and l2.focus_depth == 0.0 and s2.sigmoid_k == 17.0
+    b = sdirt.resolve_lens(l2)
+    for k in ("efl", "sensor_distance", "stop_radius", "z_ep", "rho_ep", "m_num", "sensor_z"):
+        assert b[k] == pytest.approx(a[k], rel=1e-12, abs=1e-12), k
+    with pytest.raises(ValueError):
+        lens_at(lens, sensor, th[:-1])

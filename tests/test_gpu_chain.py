@@ -1,0 +1,141 @@
+"""End-to-end gradients of an image-space loss through torch.autograd:
+with respect to the lens, TraceDPPSF (trace, trace adjoint) chained with
+RenderDP (bank render, its gradient with respect to the bank), against
+float64 central differences of the oracle's frozen-framing estimator driven
+by the oracle's transpose of the bank render; with respect to the
+surrogate network's weights, MlpPSF chained with the dense render, against
+the oracle's bf16 mirror of the same chain."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import configs
+from workloads.lens import Sensor, PsfQuery, SPLAT_TENT, DP_SIGMOID
+from oracle import adjoint as A, render as R
+from paper_2503_11213_amd import sdirt, _abi as abi
+from paper_2503_11213_amd.autograd import TraceDPPSF, RenderDP, lens_theta
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-4
+
+
+def _case():
+    lens = configs.config2_lens()
+    sensor = Sensor(pitch=0.00536, dp_mode=DP_SIGMOID, sigmoid_k=20.0)
+    N, C, H, W, ks = 1, 2, 40, 48, 21
+    radii = [0.0, 0.09, 0.18]
+    depths = [1000.0, 850.0]                   # inverse depths ascending
+    lams = [0.486, 0.656]
+    query = PsfQuery(fields=[(r, 0.0) for r in radii], depths=depths, wavelengths=lams,
+                     rays_x=40, rays_y=40, seed=3, jitter=True, ks=ks, splat=SPLAT_TENT)
+    rng = np.random.default_rng(71)
+    img = rng.uniform(size=(N, C, H, W)).astype(np.float32)
+    dmap = rng.uniform(800.0, 1100.0, size=(N, H, W)).astype(np.float32)
+    wts = rng.normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    return lens, sensor, query, img, dmap, wts, radii, [1.0 / d for d in depths], [1, 0]
+
+
+def test_image_loss_gradient_wrt_lens_matches_oracle_differences():
+    lens, sensor, query, img, dmap, wts, radii, iv, loc = _case()
+    N, C, H, W = img.shape
+    ks = query.ks
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv,
+                                        bank_lambdas=len(query.wavelengths),
+                                        lambda_of_channel=loc, pitch=sensor.pitch)
+    theta = lens_theta(lens, sensor).requires_grad_(True)
+    psf = TraceDPPSF.apply(theta, lens, sensor, query)
+    out = RenderDP.apply(torch.from_numpy(img).cuda(), psf, desc, torch.from_numpy(dmap).cuda())
+    loss = (out * torch.from_numpy(wts).cuda()).sum()
+    loss.backward()
+    g_gpu = theta.grad.numpy()
+
+    # the oracle's chain: dL/dPSF by the render transpose, then central
+    # differences of <dL/dPSF, PSF(theta)> per parameter
+    est = A.FrozenEstimator(lens, sensor, query)
+    shape = (len(radii), len(iv), len(query.wavelengths), 2, ks, ks)
+    G = R.render_bank_psf_adjoint(img.astype(np.float64), wts.astype(np.float64), shape,
+                                  dmap.astype(np.float64), radii, iv, loc,
+                                  sensor.pitch).reshape(-1, 2, ks, ks)
+    assert np.abs(G).max() > 0
+    S = len(lens.surfaces)
+    params = [0, 1, 8 * 3, 8 * 6 + 1, 8 * 11, 8 * (S - 1) + 1, 8 * S]
+    fd = {}
+    for p in params:
+        sens = est.landing_sensitivity(p, 1e-7 * max(abs(est.theta0[p]), 1e-3))
+        h = 1e-6 / max(sens, 1e-12) if p != 8 * S else 1.0
+        fd[p] = (est.ray_fd_gradient(G, p, h), est.ray_fd_gradient(G, p, h / 2))
+    scale = max(abs(v[1]) for v in fd.values())
+    for p, (a, b) in fd.items():
+        print("param", p, "gpu", g_gpu[p], "fd", b)
+        assert abs(a - b) <= 0.1 * REL * max(abs(b), 1e-3 * scale), (p, a, b)
+        assert abs(g_gpu[p] - b) <= REL * max(abs(b), 1e-3 * scale), (p, g_gpu[p], b)
+
+
+def test_render_autograd_matches_the_adjoint_entry_points():
+    # RenderDP's backward is the image adjoint and the kernel gradient of
+    # the library (dense f32 map here): autograd agrees with the plain entry
+    # points (the image adjoint folds tile halos with float atomics, so up
+    # to the order of those additions)
+    N, C, H, W, ks = 1, 3, 24, 40, 9
+    rng = np.random.default_rng(72)
+    img = torch.from_numpy(rng.uniform(size=(N, C, H, W)).astype(np.float32)).cuda()
+    K = torch.from_numpy(rng.uniform(size=(N, H, W, C, 2, ks, ks)).astype(np.float32)).cuda()
+    g = torch.from_numpy(rng.normal(size=(N, 2 * C, H, W)).astype(np.float32)).cuda()
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks)
+    x = img.clone().requires_grad_(True)
+    k = K.clone().requires_grad_(True)
+    out = RenderDP.apply(x, k, desc, None)
+    assert torch.equal(out, sdirt.render_dp(desc, img, K))
+    out.backward(g)
+    gi = sdirt.render_dp_backward(desc, K, g)
+    assert torch.allclose(x.grad, gi, rtol=1e-5, atol=1e-6 * gi.abs().max().item())
+    assert torch.equal(k.grad, sdirt.render_dp_psf_backward(desc, img, g))
+
+
+def test_image_loss_gradient_wrt_network_matches_oracle():
+    # network PSFs per pixel and channel -> dense render -> <W, out>; the
+    # gradient with respect to the weights through the kernel-map gradient
+    # and the network's vector-Jacobian product, against the oracle's bf16
+    # mirror of the same chain
+    from oracle import mlp as M
+    from workloads import scenes
+    ks, N, C, H, W, pitch = 9, 1, 3, 13, 22, 0.2
+    norm = dict(x_half=2.5, y_half=1.5, iv_lo=1 / 5000, iv_hi=1 / 500, lam_lo=0.486,
+                lam_hi=0.656)
+    widths = [64, 256, 256, 256, 256, 256, 2 * ks * ks]
+    layers = scenes.mlp_init(widths, 21)
+    flat = np.concatenate([np.concatenate([Wm.ravel(), b]) for Wm, b in layers]).astype(np.float32)
+    rng = np.random.default_rng(22)
+    yy, xx = np.mgrid[0:H, 0:W]
+    img = np.stack([0.2 + 0.03 * xx + 0.01 * (c + 1) * yy for c in range(C)])[None]
+    img = img.astype(np.float32)
+    depth = rng.uniform(500.0, 5000.0, size=(N, H, W)).astype(np.float32)
+    wts = rng.uniform(size=(N, 2 * C, H, W)).astype(np.float32)
+    lams = [0.656, 0.55, 0.486]
+    x = M.pixel_inputs(N, C, H, W, pitch, depth, lams).reshape(-1, 4)
+    d = sdirt.make_mlp_desc(n_hidden=5, width=256, n_out=2 * ks * ks, n_freq=8, **norm)
+    ws = 128                                   # 858 rows: 6 full chunks and a ragged one
+    wsp = sdirt.mlp_workspace(d, ws)
+    params = torch.from_numpy(flat).cuda().requires_grad_(True)
+    from paper_2503_11213_amd.autograd import MlpPSF
+    psf = MlpPSF.apply(params, torch.from_numpy(x).cuda(), d, wsp, ws)
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks)
+    out = RenderDP.apply(torch.from_numpy(img).cuda(), psf.reshape(N, H, W, C, 2, ks, ks), desc,
+                         None)
+    (out * torch.from_numpy(wts).cuda()).sum().backward()
+    got = params.grad.cpu().numpy()
+    # the composition of the plain entry points, on the same inputs
+    gk = sdirt.render_dp_psf_backward(desc, torch.from_numpy(img).cuda(),
+                                      torch.from_numpy(wts).cuda())
+    direct, _ = sdirt.mlp_vjp(d, params.detach(), torch.from_numpy(x).cuda(),
+                              gk.reshape(-1, 2 * ks * ks), wsp, ws)
+    direct = direct.cpu().numpy()
+    assert np.linalg.norm(got - direct) <= 1e-5 * np.linalg.norm(direct)
+    # against the oracle's chain, with the bars of the network's own test
+    from vjp_bars import vjp_bars, compare_flat
+    P = [(Wm.astype(np.float64), b.astype(np.float64)) for Wm, b in layers]
+    G = R.render_dense_psf_adjoint(img.astype(np.float64), wts.astype(np.float64), C, ks)
+    _, ref, bars = vjp_bars(P, x.astype(np.float64), G.reshape(x.shape[0], -1), norm)
+    compare_flat(got, layers, ref, bars)

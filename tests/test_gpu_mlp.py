@@ -7,6 +7,7 @@ import torch
 from workloads import scenes
 from oracle import mlp as M
 from paper_2503_11213_amd import sdirt, _abi as abi
+from vjp_bars import vjp_bars, compare_flat
 
 pytestmark = pytest.mark.gpu
 
@@ -96,6 +97,74 @@ def test_gradients_match_bf16_mirror(loss):
         assert _rel_l2(g[off:off + b.size], gb) <= REL
         off += b.size
     assert off == g.size
+
+
+@pytest.mark.parametrize("n,ws,coherent", [(200, 128, True), (64, 4096, False)])
+def test_vjp_matches_bf16_mirror(n, ws, coherent):
+    # gradient of sum_rows <g, P(x)> for an upstream gradient g: rows that
+    # share most of g (well conditioned), and independent rows (the sums
+    # over rows cancel)
+    widths = [64, 256, 256, 256, 256, 256, 2178]
+    layers, flat = _params(widths, 8)
+    x = _inputs(n, 9)
+    rng = np.random.default_rng(10)
+    g = rng.normal(size=(n, 2178))
+    if coherent:
+        g = rng.normal(size=(1, 2178)) + 0.2 * g
+    g = g.astype(np.float32)
+    d = _desc()
+    ws_t = sdirt.mlp_workspace(d, ws)
+    grads, val = sdirt.mlp_vjp(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(),
+                               torch.from_numpy(g).cuda(), ws_t, ws)
+    g64 = g.astype(np.float64)
+    p, ref, bars = vjp_bars(_oracle_params(layers), x.astype(np.float64), g64, NORM)
+    assert abs(val.item() - M.loss(p, g64, kind="vjp")) <= 1e-3 * np.abs(p * g64).sum()
+    compare_flat(grads.cpu().numpy(), layers, ref, bars)
+
+
+def test_vjp_chunks_add_up():
+    # rows are independent up to the weight-gradient sums: one chunk, two
+    # chunks with a ragged tail padded in the workspace, four chunks with a
+    # tail of 8 rows give the same gradient up to float32 summation order
+    widths = [64, 256, 256, 256, 256, 256, 2178]
+    layers, flat = _params(widths, 13)
+    n = 200
+    x = torch.from_numpy(_inputs(n, 14)).cuda()
+    g = torch.from_numpy(np.random.default_rng(15).normal(size=(n, 2178)).astype(np.float32)).cuda()
+    d = _desc()
+    pt = torch.from_numpy(flat).cuda()
+    res = []
+    for ws in (4096, 128, 64):
+        gr, val = sdirt.mlp_vjp(d, pt, x, g, sdirt.mlp_workspace(d, ws), ws)
+        res.append((gr.cpu().numpy(), val.item()))
+    for gr, val in res[1:]:
+        assert _rel_l2(gr, res[0][0]) <= 1e-5
+        assert val == pytest.approx(res[0][1], rel=1e-5, abs=1e-5)
+    # dropping one row is far outside that agreement
+    g2 = g.clone()
+    g2[137] = 0
+    gd, _ = sdirt.mlp_vjp(d, pt, x, g2, sdirt.mlp_workspace(d, 128), 128)
+    assert _rel_l2(gd.cpu().numpy(), res[0][0]) > 1e-3
+
+
+def test_vjp_empty_and_constant_gradient():
+    widths = [64, 256, 256, 256, 256, 256, 2178]
+    layers, flat = _params(widths, 8)
+    d = _desc()
+    ws_t = sdirt.mlp_workspace(d, 64)
+    pt = torch.from_numpy(flat).cuda()
+    e, ev = sdirt.mlp_vjp(d, pt, torch.zeros((0, 4), device="cuda"),
+                          torch.zeros((0, 2178), device="cuda"), ws_t, 64)
+    assert torch.count_nonzero(e).item() == 0 and ev.item() == 0.0
+    # a gradient constant along each row does not pass the softmax
+    x = torch.from_numpy(_inputs(100, 11)).cuda()
+    g = torch.from_numpy(np.random.default_rng(12).normal(size=(100, 2178)).astype(np.float32)).cuda()
+    full, _ = sdirt.mlp_vjp(d, pt, x, g, ws_t, 64)
+    const, cv = sdirt.mlp_vjp(d, pt, x, torch.full((100, 2178), 2.5, device="cuda"), ws_t, 64)
+    assert cv.item() == pytest.approx(250.0, rel=1e-4)
+    assert const.abs().max().item() <= 1e-3 * full.abs().max().item()
+    with pytest.raises(abi.SdirtError):
+        sdirt.mlp_vjp(d, pt, x, g, ws_t, 100)
 
 
 def test_adam_matches_oracle():

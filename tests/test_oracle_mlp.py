@@ -65,6 +65,32 @@ def test_forward_backward_match_torch_autograd():
         assert np.allclose(gb, b.grad.numpy(), rtol=1e-10, atol=1e-15)
 
 
+def test_upstream_gradient_backward_matches_torch_autograd():
+    # vector-Jacobian product of the network for an upstream gradient
+    # dL/dp (the render's kernel-map gradient): torch autograd of <g, p>
+    widths = [64, 16, 16, 16, 16, 16, 50]
+    params = _params(widths, 5)
+    x = _inputs(9, 6)
+    g = np.random.default_rng(7).normal(size=(9, 50))
+    p, cache = mlp.forward(params, x, NORM)
+    grads = mlp.backward(params, p, cache, g, kind="vjp")
+    h = torch.from_numpy(mlp.encode(x, NORM))
+    tw = [(torch.tensor(W, requires_grad=True), torch.tensor(b, requires_grad=True)) for W, b in params]
+    for li, (W, b) in enumerate(tw):
+        h = torch.nn.functional.linear(h, W, b)
+        if li < len(tw) - 1:
+            h = torch.relu(h)
+    lt = (torch.softmax(h, dim=1) * torch.from_numpy(g)).sum()
+    lt.backward()
+    assert mlp.loss(p, g, kind="vjp") == pytest.approx(lt.item(), rel=1e-13)
+    for (gW, gb), (W, b) in zip(grads, tw):
+        assert np.allclose(gW, W.grad.numpy(), rtol=1e-10, atol=1e-15)
+        assert np.allclose(gb, b.grad.numpy(), rtol=1e-10, atol=1e-15)
+    # a constant upstream gradient has no effect through the softmax
+    zero = mlp.backward(params, p, cache, np.full_like(g, 3.0), kind="vjp")
+    assert max(np.abs(gW).max() for gW, _ in zero) < 1e-12
+
+
 def test_width8_finite_differences():
     widths = [64, 8, 8, 8, 8, 8, 12]
     params = _params(widths, 4)
