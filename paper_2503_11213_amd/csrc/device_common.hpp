@@ -75,26 +75,36 @@ __device__ inline double rcp_d(double v) {
     return fma(r, fma(-v, r, 1.0), r);
 }
 
+// a * b + c with c in scalar registers: one v_fma_f64.  (Left to itself
+// the compiler keeps loop-invariant float64 constants in vector registers
+// and evaluates a Horner step as a register copy of the constant followed
+// by an accumulating fma.)
+__device__ __forceinline__ double fma_sc(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
 // sin and cos for |x| <= pi/4 from their Taylor series through x^15 and
 // x^16 (truncation below 1e-16 on that interval), in float64.  sin is odd
 // and cos even bit for bit.
 __device__ inline void sincos_quarter(double x, double* s, double* c) {
     const double x2 = x * x;
     double p = -1.0 / 1307674368000.0;           // -1/15!
-    p = fma(p, x2, 1.0 / 6227020800.0);          //  1/13!
-    p = fma(p, x2, -1.0 / 39916800.0);           // -1/11!
-    p = fma(p, x2, 1.0 / 362880.0);              //  1/9!
-    p = fma(p, x2, -1.0 / 5040.0);               // -1/7!
-    p = fma(p, x2, 1.0 / 120.0);                 //  1/5!
-    p = fma(p, x2, -1.0 / 6.0);                  // -1/3!
+    p = fma_sc(p, x2, 1.0 / 6227020800.0);       //  1/13!
+    p = fma_sc(p, x2, -1.0 / 39916800.0);        // -1/11!
+    p = fma_sc(p, x2, 1.0 / 362880.0);           //  1/9!
+    p = fma_sc(p, x2, -1.0 / 5040.0);            // -1/7!
+    p = fma_sc(p, x2, 1.0 / 120.0);              //  1/5!
+    p = fma_sc(p, x2, -1.0 / 6.0);               // -1/3!
     *s = fma(x * x2, p, x);
     double q = 1.0 / 20922789888000.0;           //  1/16!
-    q = fma(q, x2, -1.0 / 87178291200.0);        // -1/14!
-    q = fma(q, x2, 1.0 / 479001600.0);           //  1/12!
-    q = fma(q, x2, -1.0 / 3628800.0);            // -1/10!
-    q = fma(q, x2, 1.0 / 40320.0);               //  1/8!
-    q = fma(q, x2, -1.0 / 720.0);                // -1/6!
-    q = fma(q, x2, 1.0 / 24.0);                  //  1/4!
+    q = fma_sc(q, x2, -1.0 / 87178291200.0);     // -1/14!
+    q = fma_sc(q, x2, 1.0 / 479001600.0);        //  1/12!
+    q = fma_sc(q, x2, -1.0 / 3628800.0);         // -1/10!
+    q = fma_sc(q, x2, 1.0 / 40320.0);            //  1/8!
+    q = fma_sc(q, x2, -1.0 / 720.0);             // -1/6!
+    q = fma_sc(q, x2, 1.0 / 24.0);               //  1/4!
     q = fma(q, x2, -0.5);                        // -1/2!
     *c = fma(x2, q, 1.0);
 }
@@ -174,6 +184,19 @@ template <> __device__ inline double sqrt_live<double>(double v) {
 }
 template <> __device__ inline float sqrt_live<float>(float v) {
     return __builtin_amdgcn_sqrtf(fmaxf(v, 1e-30f));
+}
+
+// sqrt of an argument that is positive on every path of a live ray: the
+// caller has already marked a ray with a non-positive (or NaN) argument as
+// lost, and the NaN it gets here stays in that ray's unused state.
+template <typename T> __device__ inline T sqrt_pos(T v);
+template <> __device__ inline double sqrt_pos<double>(double v) {
+    const double y = __builtin_amdgcn_rsq(v);
+    const double s = v * y;
+    return fma(0.5 * y, fma(-s, s, v), s);
+}
+template <> __device__ inline float sqrt_pos<float>(float v) {
+    return __builtin_amdgcn_sqrtf(v);
 }
 
 // Even-asphere surface constants, read once per surface.
@@ -256,10 +279,11 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         const T F = c * fma(r.z, r.z, rho2) - T(2) * r.z;
         const T G = r.dz - c * (r.x * r.dx + r.y * r.dy + r.z * r.dz);
         const T disc = G * G - c * F;
-        SDIRT_FAIL(disc < T(0), kMiss);
+        // a ray that misses the sphere or only grazes it is lost
+        SDIRT_FAIL(!(disc > T(0)), kMiss);
         // sqrt(disc) is also the cosine of the incidence angle at the
         // hit: with n = (-c x, -c y, 1 - c z) there, d.n = G - c t
-        const T cosI = sqrt_live<T>(disc);
+        const T cosI = sqrt_pos<T>(disc);
         T t;
         if (sizeof(T) == sizeof(double) && (code & 0x80))
             t = (G - cosI) * (T)L.inv_c[s];
@@ -274,8 +298,9 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         const T m = (T)mu[s];
         const T m2 = m * m;
         const T K = fma(m2, disc, T(1) - m2);
-        SDIRT_FAIL(K < T(0), kTir);
-        const T g = sqrt_live<T>(K) - m * cosI;
+        // total internal reflection, or an exit ray along the surface
+        SDIRT_FAIL(!(K > T(0)), kTir);
+        const T g = sqrt_pos<T>(K) - m * cosI;
         const T gc = g * c;
         r.dx = fma(-gc, r.x, m * r.dx);
         r.dy = fma(-gc, r.y, m * r.dy);

@@ -85,9 +85,18 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
     float e_vig = 0.f, e_tr = 0.f, e_l = 0.f, e_r = 0.f, e_miss = 0.f, e_out = 0.f;
     __syncthreads();
 
+    // grid cell (ci, cj) of ray r = cj nx + ci, advanced at the top of each
+    // pass by the loop stride kBlock = step_j nx + step_i with one carry
+    // (0 <= ci < nx); it starts one stride before the first ray
+    const int step_j = kBlock / nx, step_i = kBlock - step_j * nx;
+    int cj = (int)(((uint64_t)(uint32_t)(r0 + tid) * A.smp.div_magic) >> A.smp.div_shift);
+    int ci = r0 + tid - cj * nx - step_i;
+    cj -= step_j;
+    if (ci < 0) { ci += nx; --cj; }
     for (int r = r0 + tid; r < r1 && slot_ok; r += kBlock) {
-        const int cj = (int)(((uint64_t)(uint32_t)r * A.smp.div_magic) >> A.smp.div_shift);
-        const int ci = r - cj * nx;
+        ci += step_i;
+        cj += step_j;
+        if (ci >= nx) { ci -= nx; ++cj; }
         double x1 = 0.5, x2 = 0.5;
         if (A.smp.jitter) {
             x1 = jitter01(key, (uint32_t)r, 0u);
@@ -140,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
         }
         if (SPLAT == SDIRT_SPLAT_BOX) {
             if (ib >= 0 && ib < ks && jb >= 0 && jb < ks) {
-                const int o = ib * ks + jb;
+                const int o = __mul24(ib, ks) + jb;
                 if (wl != 0.f) atomicAdd(&tile[o], wl);
                 if (wr != 0.f) atomicAdd(&tile[kk + o], wr);
                 e_l += wl;
