@@ -236,6 +236,12 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_head_kernel(const FusedArgs 
     const bf16_t* Wo = A.W[Lo];
     const float* bo = A.params + A.b_off[Lo];
     const int ntile = (A.n_out + 63) / 64;
+    // m[k]: the reference of row k's running sum s[k] = sum 2^(z - m[k]),
+    // kept at or above every logit of the row seen so far and raised (to
+    // kSlack above the new maximum) only when a logit passes it, so that
+    // between raises a tile costs one exponential per logit, no maximum and
+    // no rescaling; the terms stay in (0, 1] and far from underflow
+    constexpr float kSlack = 32.f;
     float m[16], s[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) { m[k] = kNone; s[k] = 0.f; }
@@ -247,19 +253,35 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_head_kernel(const FusedArgs 
             const int n = 64 * t + 16 * j + r16;
             bl[j] = n < A.n_out ? bo[n] * kL2E : kNone;
         }
+        bool raise = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl[j]);
+                    raise |= acc[i][j][r] > m[4 * i + r];
+                }
+        if (__ballot(raise)) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 4 * i + r;
+                    const float zm = fmaxf(fmaxf(acc[i][0][r], acc[i][1][r]), fmaxf(acc[i][2][r], acc[i][3][r]));
+                    const float mn = fmaxf(m[k], zm + kSlack);
+                    s[k] *= __builtin_amdgcn_exp2f(m[k] - mn);
+                    m[k] = mn;
+                }
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int k = 4 * i + r;
-                float z[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) z[j] = fmaf(acc[i][j][r], kL2E, bl[j]);
-                const float mn = fmaxf(fmaxf(m[k], fmaxf(z[0], z[1])), fmaxf(z[2], z[3]));
-                // rescale the sum only when some lane of the wave raised its max
-                if (__ballot(mn > m[k])) s[k] *= __builtin_amdgcn_exp2f(m[k] - mn);
-                s[k] += (__builtin_amdgcn_exp2f(z[0] - mn) + __builtin_amdgcn_exp2f(z[1] - mn)) + (__builtin_amdgcn_exp2f(z[2] - mn) + __builtin_amdgcn_exp2f(z[3] - mn));
-                m[k] = mn;
+                s[k] += (__builtin_amdgcn_exp2f(acc[i][0][r] - m[k]) + __builtin_amdgcn_exp2f(acc[i][1][r] - m[k])) +
+                        (__builtin_amdgcn_exp2f(acc[i][2][r] - m[k]) + __builtin_amdgcn_exp2f(acc[i][3][r] - m[k]));
             }
     }
     // merge over the 16 lanes holding the same rows, then over the 4 waves
