@@ -239,7 +239,11 @@ typedef struct {
 } sdirt_render_desc;
 
 /* img device [N][C][H][W] f32; depth device [N][H][W] f32 (BANK only, may
- * be NULL for DENSE); out device [N][2C][H][W] f32, overwritten. */
+ * be NULL for DENSE); out device [N][2C][H][W] f32, overwritten.  The
+ * dense source, and the radial bank at window sizes other than those of
+ * the matrix-core path, stage C (ks + 7)^2 image floats per 8 x 8 pixel
+ * tile in LDS: SDIRT_EUNSUPPORTED when that exceeds 160 KB (ks > 109 at
+ * C = 3; every ks <= SDIRT_MAX_KS fits at C = 1). */
 int sdirt_render_dp(const sdirt_render_desc* desc, const float* img,
                     const void* psf, const float* depth, float* out,
                     void* stream);
@@ -258,7 +262,8 @@ int sdirt_render_dp_backward(const sdirt_render_desc* desc, const void* psf,
  *       read kernel c' of grad_out[n, s*C + c, y, x]
  *                          * img[n, c, clamp(y+pad-i), clamp(x+pad-j)],
  * device [N][H][W][Cp][2][ks][ks] in desc->psf_dtype (bf16 rounded to
- * nearest even); depth is not read (may be NULL).  Bank sources: the sum of
+ * nearest even); depth is not read (may be NULL); the same LDS limit as the
+ * dense forward (C (ks + 7)^2 floats <= 160 KB).  Bank sources: the sum of
  * those per-pixel gradients over the pixels that read each bank entry, the
  * lookup's mirrors undone and (BANK2D) weighted by the depth blend, device
  * f32 in the bank's own layout; depth required; window sizes 21, 31, 33,
