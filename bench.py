@@ -41,8 +41,8 @@ TRACE_SOURCES = ("paper_2503_11213_amd/csrc/device_common.hpp",
                  "paper_2503_11213_amd/csrc/trace.hip",
                  "paper_2503_11213_amd/csrc/pack.hpp",
                  "paper_2503_11213_amd/csrc/pack.cpp")
-TRACE_TRAFFIC = {"sources_sha256": "5bfdb29c607979479748fabdd7839405bc368005f758b59c657c1067925cabd7",
-                 "bytes": 65723181}
+TRACE_TRAFFIC = {"sources_sha256": "f649b99e406df527afaf7e18022e649f2c23676b58f28026e69600a52a0eb6c1",
+                 "bytes": 65727277}
 
 
 def sources_digest():
