@@ -205,9 +205,59 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_trunk_kernel(const FusedArgs
     }
 }
 
+// Head products of one 64-column output tile t, transposed: acc[i][j]
+// holds C[column 16 j + 4 (l / 16) + r][row 16 i + l % 16], so lane l owns
+// rows 16 i + l % 16 and, in each column block j, four consecutive
+// columns.  A operands: weight fragments (fragment order, as in frag_mma)
+// held for all eight k-steps: on entry ring holds, or has in flight, tile
+// t's; each k-step's slot is refilled, as soon as its products are issued,
+// with the same k-step of tile tn (the wave's next tile, if tn >= 0).  All
+// of the next tile's weight loads are thus issued before this tile's
+// output stores, so that waiting for them never waits for those stores
+// (loads and stores share one in-order counter).  B operands: hidden rows
+// from LDS.
+__device__ inline void head_prefetch(const bf16_t* WF, int t, bf16x8_t (&ring)[8][4], int lane) {
+    constexpr int KS = kFWidth / 32;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ring[ks][j] = load_frag(WF, KS, 4 * t + j, ks, lane);
+}
+
+__device__ inline void head_tile_mma(const bf16_t* Hs, const bf16_t* WF, int t, int tn,
+                                     bf16x8_t (&ring)[8][4], floatx4_t (&acc)[4][4], int lane) {
+    constexpr int KS = kFWidth / 32;
+    const int r16 = lane & 15, kg = (lane >> 4) * 8;
+    const bf16_t* hp = Hs + r16 * kFStride + kg;
+    // the hidden rows are the same for every tile: keep the compiler from
+    // hoisting their reads out of the tile loop (128 registers)
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        bf16x8_t h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            h[i] = *reinterpret_cast<const bf16x8_t*>(hp + 16 * i * kFStride + 32 * ks);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    ring[ks][j], h[i],
+                    ks == 0 ? floatx4_t{0.f, 0.f, 0.f, 0.f} : acc[i][j], 0, 0, 0);
+        if (tn >= 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) ring[ks][j] = load_frag(WF, KS, 4 * tn + j, ks, lane);
+        }
+    }
+}
+
 // Head: the softmax output layer of 64 rows of the chunk, from the trunk's
 // activations.  Two passes over the output tiles (the logits are recomputed
-// rather than stored); two workgroups share a compute unit.
+// rather than stored); two workgroups share a compute unit.  In the
+// transposed tile layout a lane holds 4 rows x 16 columns of a tile, so the
+// softmax statistics take 4 registers per quantity and the output leaves
+// in runs of four consecutive columns per lane.
 template <bool BF16>
 __global__ __launch_bounds__(kFThreads, 2) void mlp_head_kernel(const FusedArgs A, long long r_begin,
                                                               long long r_end, const bf16_t* hin) {
@@ -216,6 +266,12 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_head_kernel(const FusedArgs 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g4 = (lane >> 4) * 4;
     const long long row0 = r_begin + (long long)blockIdx.x * kFRows;
+    const int Lo = A.n_hidden;
+    const bf16_t* Wo = A.W[Lo];
+    const float* bo = A.params + A.b_off[Lo];
+    const int ntile = (A.n_out + 63) / 64;
+    bf16x8_t ring[8][4];
+    if (wave < ntile) head_prefetch(Wo, wave, ring, lane);
     for (int e = tid; e < kFRows * (kFWidth / 8); e += kFThreads) {
         const int row = e / (kFWidth / 8), c8 = e % (kFWidth / 8);
         const bf16x8_t zero = {};
@@ -226,127 +282,144 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_head_kernel(const FusedArgs 
     }
     __syncthreads();
     floatx4_t acc[4][4];
-    // ---- output layer: pass 1, running max / sum per row ---------------------
+    // ---- output layer: pass 1, running reference / sum per row ---------------
     // Logits are carried in base 2 (z log2 e) so that every exponential is
     // one v_exp_f32; -1e30 stands for "no column yet" (finite, so no
-    // special cases: its exponentials vanish).
+    // special cases: its exponentials vanish).  m[i], the reference of row
+    // 16 i + l % 16's running sum s[i] = sum 2^(z - m[i]), is kept at or
+    // above every logit of the row seen so far and raised (to kSlack above
+    // the new maximum) only when a logit passes it, so that between raises a
+    // tile costs one exponential per logit and no rescaling; the terms stay
+    // in (0, 1] and far from underflow.
     constexpr float kL2E = 1.4426950408889634f;
     constexpr float kNone = -1e30f;
-    const int Lo = A.n_hidden;
-    const bf16_t* Wo = A.W[Lo];
-    const float* bo = A.params + A.b_off[Lo];
-    const int ntile = (A.n_out + 63) / 64;
-    // m[k]: the reference of row k's running sum s[k] = sum 2^(z - m[k]),
-    // kept at or above every logit of the row seen so far and raised (to
-    // kSlack above the new maximum) only when a logit passes it, so that
-    // between raises a tile costs one exponential per logit, no maximum and
-    // no rescaling; the terms stay in (0, 1] and far from underflow
     constexpr float kSlack = 32.f;
-    float m[16], s[16];
+    float m[4], s[4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) { m[k] = kNone; s[k] = 0.f; }
+    for (int i = 0; i < 4; ++i) { m[i] = kNone; s[i] = 0.f; }
     for (int t = wave; t < ntile; t += 4) {
-        frag_mma(Hs, Wo, kFWidth / 32, 64 * t, acc);
-        float bl[4];
+        // the last tile of this pass prefetches the first of the next
+        head_tile_mma(Hs, Wo, t, t + 4 < ntile ? t + 4 : wave, ring, acc, lane);
+        float bl[4][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = 64 * t + 16 * j + r16;
-            bl[j] = n < A.n_out ? bo[n] * kL2E : kNone;
-        }
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 64 * t + 16 * j + g4 + r;
+                bl[j][r] = n < A.n_out ? bo[n] * kL2E : kNone;
+            }
         bool raise = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl[j]);
-                    raise |= acc[i][j][r] > m[4 * i + r];
+                for (int r = 0; r < 4; ++r) {
+                    acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl[j][r]);
+                    raise |= acc[i][j][r] > m[i];
                 }
         if (__ballot(raise)) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i) {
+                float zm = kNone;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int k = 4 * i + r;
-                    const float zm = fmaxf(fmaxf(acc[i][0][r], acc[i][1][r]), fmaxf(acc[i][2][r], acc[i][3][r]));
-                    const float mn = fmaxf(m[k], zm + kSlack);
-                    s[k] *= __builtin_amdgcn_exp2f(m[k] - mn);
-                    m[k] = mn;
-                }
+                for (int j = 0; j < 4; ++j)
+                    zm = fmaxf(zm, fmaxf(fmaxf(acc[i][j][0], acc[i][j][1]), fmaxf(acc[i][j][2], acc[i][j][3])));
+                const float mn = fmaxf(m[i], zm + kSlack);
+                s[i] *= __builtin_amdgcn_exp2f(m[i] - mn);
+                m[i] = mn;
+            }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i) {
+            float a = 0.f;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int k = 4 * i + r;
-                s[k] += (__builtin_amdgcn_exp2f(acc[i][0][r] - m[k]) + __builtin_amdgcn_exp2f(acc[i][1][r] - m[k])) +
-                        (__builtin_amdgcn_exp2f(acc[i][2][r] - m[k]) + __builtin_amdgcn_exp2f(acc[i][3][r] - m[k]));
-            }
-    }
-    // merge over the 16 lanes holding the same rows, then over the 4 waves
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-            const float m2 = __shfl_xor(m[k], o, 64);
-            const float s2 = __shfl_xor(s[k], o, 64);
-            const float mn = fmaxf(m[k], m2);
-            s[k] = s[k] * __builtin_amdgcn_exp2f(m[k] - mn) + s2 * __builtin_amdgcn_exp2f(m2 - mn);
-            m[k] = mn;
+            for (int j = 0; j < 4; ++j)
+                a += (__builtin_amdgcn_exp2f(acc[i][j][0] - m[i]) + __builtin_amdgcn_exp2f(acc[i][j][1] - m[i])) +
+                     (__builtin_amdgcn_exp2f(acc[i][j][2] - m[i]) + __builtin_amdgcn_exp2f(acc[i][j][3] - m[i]));
+            s[i] += a;
         }
     }
-    if (r16 == 0) {
+    // merge over the 4 lanes holding the same rows, then over the 4 waves
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                stat_m[wave][16 * i + g4 + r] = m[4 * i + r];
-                stat_s[wave][16 * i + g4 + r] = s[4 * i + r];
-            }
+        for (int o = 16; o < 64; o <<= 1) {
+            const float m2 = __shfl_xor(m[i], o, 64);
+            const float s2 = __shfl_xor(s[i], o, 64);
+            const float mn = fmaxf(m[i], m2);
+            s[i] = s[i] * __builtin_amdgcn_exp2f(m[i] - mn) + s2 * __builtin_amdgcn_exp2f(m2 - mn);
+            m[i] = mn;
+        }
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            stat_m[wave][16 * i + r16] = m[i];
+            stat_s[wave][16 * i + r16] = s[i];
+        }
     }
     __syncthreads();
     // per row: M + log2(S), so that p = 2^(z - M - log2 S)
-    float mls[16];
+    float mls[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = 16 * i + g4 + r;
-            float mm = stat_m[0][row], ss = stat_s[0][row];
-            for (int w = 1; w < 4; ++w) {
-                const float m2 = stat_m[w][row], s2 = stat_s[w][row];
-                const float mn = fmaxf(mm, m2);
-                ss = ss * __builtin_amdgcn_exp2f(mm - mn) + s2 * __builtin_amdgcn_exp2f(m2 - mn);
-                mm = mn;
-            }
-            mls[4 * i + r] = ss > 0.f ? mm + __builtin_amdgcn_logf(ss) : 1e30f;
+    for (int i = 0; i < 4; ++i) {
+        const int row = 16 * i + r16;
+        float mm = stat_m[0][row], ss = stat_s[0][row];
+        for (int w = 1; w < 4; ++w) {
+            const float m2 = stat_m[w][row], s2 = stat_s[w][row];
+            const float mn = fmaxf(mm, m2);
+            ss = ss * __builtin_amdgcn_exp2f(mm - mn) + s2 * __builtin_amdgcn_exp2f(m2 - mn);
+            mm = mn;
         }
+        mls[i] = ss > 0.f ? mm + __builtin_amdgcn_logf(ss) : 1e30f;
+    }
     // ---- pass 2: recompute and write probabilities ---------------------------
+    // each lane writes four consecutive columns per block: two 4-byte words
+    // of bf16 pairs (the row pitch keeps words aligned when n_out is even),
+    // or four floats
     typedef typename std::conditional<BF16, __bf16, float>::type OutT;
     OutT* outp = reinterpret_cast<OutT*>(A.out);
+    const bool words = !BF16 || (A.n_out & 1) == 0;
     for (int t = wave; t < ntile; t += 4) {
-        frag_mma(Hs, Wo, kFWidth / 32, 64 * t, acc);
-        float bl[4];
+        head_tile_mma(Hs, Wo, t, t + 4 < ntile ? t + 4 : -1, ring, acc, lane);
+        float bl[4][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = 64 * t + 16 * j + r16;
-            bl[j] = n < A.n_out ? bo[n] * kL2E : 0.f;
-        }
-        const bool full = 64 * t + 64 <= A.n_out;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const long long gr = row0 + 16 * i + g4 + r;
-                if (gr >= r_end) continue;
-                OutT* rowp = outp + gr * A.n_out + 64 * t + r16;
+                const int n = 64 * t + 16 * j + g4 + r;
+                bl[j][r] = n < A.n_out ? bo[n] * kL2E : 0.f;
+            }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float p = __builtin_amdgcn_exp2f(fmaf(acc[i][j][r], kL2E, bl[j]) - mls[4 * i + r]);
-                    if (full || 64 * t + 16 * j + r16 < A.n_out) rowp[16 * j] = (OutT)p;
+        for (int i = 0; i < 4; ++i) {
+            const long long gr = row0 + 16 * i + r16;
+            if (gr >= r_end) continue;
+            OutT* rowp = outp + gr * A.n_out + 64 * t + g4;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float p[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    p[r] = __builtin_amdgcn_exp2f(fmaf(acc[i][j][r], kL2E, bl[j][r]) - mls[i]);
+                const int n0 = 64 * t + 16 * j + g4;
+                OutT* q = rowp + 16 * j;
+                if (words && n0 + 3 < A.n_out) {
+                    if (BF16) {
+                        uint32_t* w = reinterpret_cast<uint32_t*>(q);
+                        w[0] = (uint32_t)f2bf_rne(p[0]) | ((uint32_t)f2bf_rne(p[1]) << 16);
+                        w[1] = (uint32_t)f2bf_rne(p[2]) | ((uint32_t)f2bf_rne(p[3]) << 16);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) q[r] = (OutT)p[r];
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (n0 + r < A.n_out) q[r] = (OutT)p[r];
                 }
             }
+        }
     }
 }
 
