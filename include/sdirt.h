@@ -139,6 +139,7 @@ typedef struct {
     int normalize;              /* SDIRT_NORM_*                            */
     int out_dtype;              /* SDIRT_F32 or SDIRT_F64                  */
     int math;                   /* SDIRT_F64 (default) or SDIRT_F32 trace  */
+    int deterministic;          /* 1: bitwise reproducible PSFs (below)    */
 } sdirt_psf_query;
 
 /* Resolve stop size, sensor position and pupil on the host (no device
@@ -172,7 +173,15 @@ int sdirt_trace_rays(const sdirt_lens* lens, double wavelength, int math,
  *              transmitted, left-in-window, right-in-window,
  *              missed-sub-pixel, outside-window energies (before
  *              normalisation).
- * Both buffers are overwritten. */
+ * Both buffers are overwritten.  By default the rays of a point are split
+ * over several workgroups whose float32 tiles are added with atomics, so
+ * PSF values vary from run to run in the last bits (~1e-7 relative).  With
+ * query->deterministic = 1 each ray's weight is rounded to a multiple of
+ * 2^-32 and summed in 64-bit integers (order-free, exact), and each point
+ * is traced by a single workgroup, so repeated calls give identical bits;
+ * the integer tile needs 16 ks^2 bytes of LDS, so ks <= 101 in that mode
+ * (SDIRT_EUNSUPPORTED above), and the chunk count of
+ * sdirt_trace_dp_psf_chunks is ignored. */
 int sdirt_trace_dp_psf(const sdirt_lens* lens, const sdirt_sensor* sensor,
                        const sdirt_psf_query* query, void* psf_out,
                        double* stats_out, void* stream);

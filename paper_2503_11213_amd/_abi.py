@@ -60,7 +60,8 @@ class PsfQuery(C.Structure):
                 ("n_points", C.c_int), ("points", C.c_void_p),
                 ("rays_x", C.c_int), ("rays_y", C.c_int), ("seed", C.c_uint32),
                 ("jitter", C.c_int), ("ks", C.c_int), ("splat", C.c_int),
-                ("normalize", C.c_int), ("out_dtype", C.c_int), ("math", C.c_int)]
+                ("normalize", C.c_int), ("out_dtype", C.c_int), ("math", C.c_int),
+                ("deterministic", C.c_int)]
 
 
 class RenderDesc(C.Structure):

@@ -97,6 +97,10 @@ int check_query(const sdirt_psf_query* q, const Resolved& R, PointArgs* P,
     if (q->normalize < SDIRT_NORM_NONE || q->normalize > SDIRT_NORM_MAX) return SDIRT_EINVAL;
     if (q->out_dtype != SDIRT_F32 && q->out_dtype != SDIRT_F64) return SDIRT_EUNSUPPORTED;
     if (q->math != SDIRT_F32 && q->math != SDIRT_F64) return SDIRT_EUNSUPPORTED;
+    if (q->deterministic != 0 && q->deterministic != 1) return SDIRT_EINVAL;
+    // the integer tile [2][ks][ks] of 64-bit sums plus the kernel's own
+    // 128 bytes of statistics scratch within the 160 KB of LDS
+    if (q->deterministic && 16LL * q->ks * q->ks > 160LL * 1024 - 256) return SDIRT_EUNSUPPORTED;
     if (!q->wavelengths || q->n_wavelengths < 1) return SDIRT_EINVAL;
     if (q->n_wavelengths > kMaxL) return SDIRT_EUNSUPPORTED;
     std::memset(P, 0, sizeof(*P));
@@ -134,6 +138,7 @@ int check_query(const sdirt_psf_query* q, const Resolved& R, PointArgs* P,
     div_magic_for((uint32_t)q->rays_x, &S->div_magic, &S->div_shift);
     S->seed = q->seed;
     S->jitter = q->jitter ? 1 : 0;
+    S->det = q->deterministic;
     return SDIRT_OK;
 }
 

@@ -30,6 +30,7 @@ struct SampleArgs {
     int rays_per_chunk;
     uint64_t div_magic;              // r / nx == (r * div_magic) >> div_shift
     uint32_t div_shift;
+    int det;                         // fixed-point tiles, one workgroup per point
 };
 
 // Multiplier and shift for exact unsigned division by d of every n < 2^30.

@@ -54,9 +54,19 @@ __device__ inline void point_of(const PointArgs& P, int q, double* hx, double* h
     }
 }
 
+// A weight in [0, 1] as an integer multiple of 2^-32 (round to nearest):
+// sums of these are exact and independent of the order of the additions.
+__device__ inline unsigned long long fixed_weight(float w) {
+    return (unsigned long long)__builtin_rintf(w * 4294967296.0f);
+}
+
 template <typename T, int SPLAT, int DP, typename OutT, bool GENERAL>
 __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) {
-    extern __shared__ float tile[];          // [2][ks][ks]
+    // [2][ks][ks] float32 sums, or (deterministic mode) 64-bit integer sums
+    // of weights in units of 2^-32
+    extern __shared__ float tile[];
+    unsigned long long* tile_q = reinterpret_cast<unsigned long long*>(tile);
+    const bool det = A.smp.det != 0;
     __shared__ float red[kBlock / 64][8];
     const int ks = A.sen.ks;
     const int kk = ks * ks;
@@ -64,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
     const int q = blockIdx.x / A.smp.chunks;
     const int chunk = blockIdx.x - q * A.smp.chunks;
     const int tid = threadIdx.x;
-    for (int i = tid; i < 2 * kk; i += kBlock) tile[i] = 0.0f;
+    for (int i = tid; i < (det ? 4 : 2) * kk; i += kBlock) tile[i] = 0.0f;
 
     double hx, hy, depth;
     int slot;
@@ -150,8 +160,13 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
         if (SPLAT == SDIRT_SPLAT_BOX) {
             if (ib >= 0 && ib < ks && jb >= 0 && jb < ks) {
                 const int o = __mul24(ib, ks) + jb;
-                if (wl != 0.f) atomicAdd(&tile[o], wl);
-                if (wr != 0.f) atomicAdd(&tile[kk + o], wr);
+                if (det) {
+                    if (wl != 0.f) atomicAdd(&tile_q[o], fixed_weight(wl));
+                    if (wr != 0.f) atomicAdd(&tile_q[kk + o], fixed_weight(wr));
+                } else {
+                    if (wl != 0.f) atomicAdd(&tile[o], wl);
+                    if (wr != 0.f) atomicAdd(&tile[kk + o], wr);
+                }
                 e_l += wl;
                 e_r += wr;
             } else {
@@ -168,8 +183,13 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
                 const int ii = i0 + (t >> 1), jj = j0 + (t & 1);
                 if (ii >= 0 && ii < ks && jj >= 0 && jj < ks) {
                     const int o = ii * ks + jj;
-                    atomicAdd(&tile[o], wl * wt[t]);
-                    atomicAdd(&tile[kk + o], wr * wt[t]);
+                    if (det) {
+                        atomicAdd(&tile_q[o], fixed_weight(wl * wt[t]));
+                        atomicAdd(&tile_q[kk + o], fixed_weight(wr * wt[t]));
+                    } else {
+                        atomicAdd(&tile[o], wl * wt[t]);
+                        atomicAdd(&tile[kk + o], wr * wt[t]);
+                    }
                     e_l += wl * wt[t];
                     e_r += wr * wt[t];
                 } else {
@@ -197,6 +217,12 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
             if (tot[k] != 0.0) atomicAdd(&st[k + 1], tot[k]);
     }
     OutT* out = reinterpret_cast<OutT*>(A.out) + (size_t)q * 2 * kk;
+    if (det) {
+        // the point's only workgroup: exact sums, one store per element
+        for (int i = tid; i < 2 * kk; i += kBlock)
+            out[i] = (OutT)((double)tile_q[i] * (1.0 / 4294967296.0));
+        return;
+    }
     for (int i = tid; i < 2 * kk; i += kBlock) {
         const float v = tile[i];
         if (v != 0.0f) atomicAdd(&out[i], (OutT)v);
@@ -331,11 +357,13 @@ int trace_dp_psf_impl(const sdirt_lens* lens, const sdirt_sensor* sensor,
     const size_t elt = query->out_dtype == SDIRT_F64 ? 8 : 4;
     if ((rc = launch_fill_zero(psf_out, (size_t)P * 2 * kk * elt, stream))) return rc;
     if (stats_out && (rc = launch_fill_zero(stats_out, (size_t)P * 7 * 8, stream))) return rc;
-    const int chunks = chunks_override > 0 ? std::min(chunks_override, n_rays) : chunks_for(P, n_rays);
+    // deterministic mode: one workgroup per point, integer tile
+    const int chunks = A.smp.det ? 1
+                       : chunks_override > 0 ? std::min(chunks_override, n_rays) : chunks_for(P, n_rays);
     A.smp.chunks = chunks;
     A.smp.rays_per_chunk = (n_rays + chunks - 1) / chunks;
     const dim3 grid((unsigned)((long long)chunks * P));
-    const size_t shm = (size_t)2 * kk * sizeof(float);
+    const size_t shm = (size_t)2 * kk * (A.smp.det ? sizeof(unsigned long long) : sizeof(float));
     const bool f64math = query->math == SDIRT_F64;
     if (query->out_dtype == SDIRT_F64) {
         if (f64math) dispatch_splat<double, double>(A, grid, shm, stream);

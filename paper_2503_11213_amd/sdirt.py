@@ -98,6 +98,7 @@ def make_query(query, math=abi.F64, points=None):
     q.normalize = int(query.normalize)
     q.out_dtype = abi.F64 if query.out_f64 else abi.F32
     q.math = int(math)
+    q.deterministic = 1 if getattr(query, "deterministic", False) else 0
     return q, keep
 
 

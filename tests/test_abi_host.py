@@ -98,6 +98,15 @@ def test_invalid_queries_are_rejected():
     s = Sensor(pitch=0.0)
     assert _call_trace(lens, s, query) == abi.EINVAL
     assert _call_trace(lens, sensor, query, out_ptr=0) == abi.EINVAL
+    # deterministic mode: a flag, and its integer tile must fit in LDS
+    q = copy.deepcopy(query); q.deterministic = True; q.ks = 103
+    assert _call_trace(lens, sensor, q) == abi.EUNSUPPORTED
+    qs, keep = sdirt.make_query(query)
+    qs.deterministic = 2
+    L, keepl = sdirt.make_lens(lens)
+    rc = abi.lib().sdirt_trace_dp_psf(C.byref(L), C.byref(sdirt.make_sensor(sensor)), C.byref(qs),
+                                      C.c_void_p(1), C.c_void_p(0), C.c_void_p(0))
+    assert rc == abi.EINVAL
 
 
 def test_invalid_render_descs_are_rejected():

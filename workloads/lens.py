@@ -106,6 +106,7 @@ class PsfQuery:
     splat: int = SPLAT_BOX
     normalize: int = NORM_NONE
     out_f64: bool = False
+    deterministic: bool = False     # bitwise reproducible PSFs (the kernels' mode)
 
     @property
     def n_points(self):
