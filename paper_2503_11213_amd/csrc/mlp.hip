@@ -56,7 +56,9 @@ struct GemmArgs {
     float* Cf; int ldcf;          // float32 result or null
     bf16_t* Cb; int ldcb;         // bf16 result or null
     bf16_t* CbT; int ldcbt;       // bf16 transposed result [N][M] or null
-    float* colsum;                // += sum over m of the result, or null
+    float* colpart;               // partial column sums of the result or null:
+                                  // row 2 (m / 128) + (m % 128) / 64 of
+                                  // [2 ceil(M / 128)][N], each written once
 };
 
 __global__ __launch_bounds__(kGB) void gemm_nt_kernel(const GemmArgs g) {
@@ -141,11 +143,13 @@ __global__ __launch_bounds__(kGB) void gemm_nt_kernel(const GemmArgs g) {
                 if (g.CbT) g.CbT[(size_t)n * g.ldcbt + m] = vb;
             }
         }
-        if (g.colsum) {
-            // lanes l, l+16, l+32, l+48 share the column
+        if (g.colpart) {
+            // lanes l, l+16, l+32, l+48 share the column: the wave's 64 rows
+            // of it, stored (not accumulated) so that the final sum over
+            // the parts has a fixed order
             csum += __shfl_xor(csum, 16, 64);
             csum += __shfl_xor(csum, 32, 64);
-            if (nok && lane < 16 && csum != 0.f) atomicAdd(&g.colsum[n], csum);
+            if (nok && lane < 16) g.colpart[(size_t)(2 * bm + (wave >> 1)) * g.N + n] = csum;
         }
     }
 }
@@ -202,6 +206,7 @@ struct MlpWs {
     bf16_t* dA[2];   // ping-pong [B][width]
     bf16_t* dAT[2];  // [width][B]
     float* grads;    // [n_params]
+    float* part;     // [2 ceil(B / 128)][width] partial bias-gradient sums
     float* target;   // [B][n_out] (training gather)
     float* xb;       // [B][4]
     float* loss;     // [1]
@@ -239,6 +244,7 @@ static MlpWs carve(const MlpDims& m, int B, char* base) {
         w.dAT[k] = (bf16_t*)take((size_t)m.width * B * 2);
     }
     w.grads = (float*)take(m.n_params() * 4);
+    w.part = (float*)take((size_t)2 * ((B + 127) / 128) * m.width * 4);
     w.target = (float*)take((size_t)B * m.n_out * 4);
     w.xb = (float*)take((size_t)B * 4 * 4);
     w.loss = (float*)take(256);
@@ -568,7 +574,10 @@ static void backward_rows(const MlpDims& m, const MlpWs& w, const float* params,
     s.loss = w.loss;
     hipLaunchKernelGGL(softmax_loss_kernel, dim3(B), dim3(256), 0, st, s);
     const int Lh = m.L - 1;
-    // last layer: db = colsum(dz), dW = dz^T H, dH = dz W (masked by H > 0)
+    const int nparts = 2 * ((B + 127) / 128);   // partial bias sums per column
+    // last layer: db = colsum(dz), dW = dz^T H, dH = dz W (masked by H > 0);
+    // every bias gradient is a fixed-order sum (no atomics), so training is
+    // bitwise reproducible
     hipLaunchKernelGGL(colsum_kernel, dim3((m.n_out + 255) / 256), dim3(256), 0, st,
                        w.dz, B, m.n_out, w.grads + m.b_off(Lh));
     {
@@ -585,8 +594,10 @@ static void backward_rows(const MlpDims& m, const MlpWs& w, const float* params,
         g.M = B; g.N = m.width; g.K = m.n_out_pad;
         g.mask = w.H[Lh]; g.ldm = m.width;
         g.Cb = w.dA[cur]; g.ldcb = m.width; g.CbT = w.dAT[cur]; g.ldcbt = B;
-        g.colsum = w.grads + m.b_off(Lh - 1);
+        g.colpart = w.part;
         gemm(g, st);
+        hipLaunchKernelGGL(colsum_kernel, dim3((m.width + 255) / 256), dim3(256), 0, st,
+                           (const float*)w.part, nparts, m.width, w.grads + m.b_off(Lh - 1));
     }
     for (int l = Lh - 1; l >= 0; --l) {
         const int in_pad = l == 0 ? feat_pad(m) : m.width;
@@ -603,18 +614,16 @@ static void backward_rows(const MlpDims& m, const MlpWs& w, const float* params,
             g.M = B; g.N = m.width; g.K = m.width;
             g.mask = w.H[l]; g.ldm = m.width;
             g.Cb = w.dA[1 - cur]; g.ldcb = m.width; g.CbT = w.dAT[1 - cur]; g.ldcbt = B;
-            g.colsum = w.grads + m.b_off(l - 1);
+            g.colpart = w.part;
             gemm(g, st);
+            hipLaunchKernelGGL(colsum_kernel, dim3((m.width + 255) / 256), dim3(256), 0, st,
+                               (const float*)w.part, nparts, m.width, w.grads + m.b_off(l - 1));
             cur = 1 - cur;
         }
         (void)in_pad;
     }
 }
 
-static void zero_bias_grads(const MlpDims& m, const MlpWs& w, hipStream_t st) {
-    for (int l = 0; l < m.L - 1; ++l)
-        launch_fill_zero(w.grads + m.b_off(l), (size_t)m.out_of(l) * 4, st);
-}
 
 int mlp_n_params(const sdirt_mlp_desc* d, long long* out) {
     MlpDims m;
@@ -721,7 +730,6 @@ int mlp_backward(const sdirt_mlp_desc* d, const float* params, int batch, const 
     const MlpWs w = carve(m, batch, (char*)workspace);
     cast_all(m, w, params, st);
     if ((rc = launch_fill_zero(w.loss, 4, st))) return rc;
-    zero_bias_grads(m, w, st);
     forward_rows(m, d, w, params, batch, x, st, true);
     backward_rows(m, w, params, batch, target, st);
     if (grads_out)
@@ -763,7 +771,6 @@ int mlp_vjp(const sdirt_mlp_desc* d, const float* params, long long n_rows, cons
             gb = w.target;
         }
         if ((rc = launch_fill_zero(w.loss, 4, st))) return rc;
-        zero_bias_grads(m, w, st);
         forward_rows(m, d, w, params, B, xb, st, true);
         backward_rows(m, w, params, B, gb, st, true);
         hipLaunchKernelGGL(accumulate_kernel, dim3(gblocks), dim3(256), 0, st, grads_out,
@@ -815,7 +822,6 @@ int mlp_train(const sdirt_mlp_desc* d, float* params, float* m1, float* m2, int 
                            (int)n_samples, m.n_out, seed, (uint32_t)step, batch, w.xb, w.target);
         cast_all(m, w, params, st);
         launch_fill_zero(w.loss, 4, st);
-        zero_bias_grads(m, w, st);
         forward_rows(m, d, w, params, batch, w.xb, st, true);
         backward_rows(m, w, params, batch, w.target, st);
         adam_launch(m.n_params(), params, m1, m2, w.grads, step + 1, lr, st);

@@ -8,6 +8,7 @@ Python or in torch.
 """
 
 import ctypes as C
+import json
 
 import torch
 
@@ -355,3 +356,33 @@ def mlp_train(desc, params, m, v, x_all, t_all, workspace, batch, step0, n_steps
                                    int(seed) & 0xFFFFFFFF, _dptr(loss_trace),
                                    _dptr(workspace), _stream())
     abi.check("sdirt_mlp_train", rc)
+
+
+# ---- trainer checkpoints ------------------------------------------------------
+
+def mlp_save_checkpoint(path, desc, params, m, v, step, seed, total_steps):
+    """Trainer state to a safetensors file: the float32 master parameters and
+    Adam moments, and as metadata the next step, the data seed, the schedule
+    length and the network description.  sdirt_mlp_train draws its batches
+    by a counter hash of (seed, step, row) and sets the learning rate from
+    the step, so this is all a resumed run needs."""
+    from safetensors.torch import save_file
+    meta = {"step": str(int(step)), "seed": str(int(seed)), "total_steps": str(int(total_steps)),
+            "desc": json.dumps({n: getattr(desc, n) for n, _ in desc._fields_})}
+    save_file({"params": params.detach().float().cpu().contiguous(),
+               "m": m.detach().float().cpu().contiguous(),
+               "v": v.detach().float().cpu().contiguous()}, path, metadata=meta)
+
+
+def mlp_load_checkpoint(path, device="cuda"):
+    """(desc, params, m, v, step, seed, total_steps) from mlp_save_checkpoint."""
+    from safetensors import safe_open
+    with safe_open(path, framework="pt") as f:
+        meta = f.metadata()
+        t = {k: f.get_tensor(k).to(device) for k in f.keys()}
+    dd = json.loads(meta["desc"])
+    desc = abi.MlpDesc()
+    for n, _ in abi.MlpDesc._fields_:
+        setattr(desc, n, dd[n])
+    return (desc, t["params"], t["m"], t["v"], int(meta["step"]), int(meta["seed"]),
+            int(meta["total_steps"]))

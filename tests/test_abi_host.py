@@ -201,3 +201,21 @@ def test_lens_theta_round_trip(idx):
         assert b[k] == pytest.approx(a[k], rel=1e-12, abs=1e-12), k
     with pytest.raises(ValueError):
         lens_at(lens, sensor, th[:-1])
+
+
+def test_trainer_checkpoint_round_trip(tmp_path):
+    # parameters, Adam moments, step, seed, schedule and network description
+    # survive a save / load unchanged (host tensors; no device work)
+    import torch
+    d = sdirt.make_mlp_desc(n_hidden=3, width=64, n_out=50, n_freq=8, x_half=2.0, y_half=1.0,
+                            iv_lo=1e-4, iv_hi=2e-3, lam_lo=0.45, lam_hi=0.7, loss=abi.LOSS_KL)
+    n = sdirt.mlp_n_params(d)
+    g = torch.Generator().manual_seed(0)
+    p, m, v = (torch.randn(n, generator=g) for _ in range(3))
+    path = str(tmp_path / "trainer.safetensors")
+    sdirt.mlp_save_checkpoint(path, d, p, m, v, step=1234, seed=77, total_steps=5000)
+    d2, p2, m2, v2, step, seed, total = sdirt.mlp_load_checkpoint(path, device="cpu")
+    assert torch.equal(p, p2) and torch.equal(m, m2) and torch.equal(v, v2)
+    assert (step, seed, total) == (1234, 77, 5000)
+    for name, _ in abi.MlpDesc._fields_:
+        assert getattr(d2, name) == getattr(d, name), name

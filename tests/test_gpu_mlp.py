@@ -219,6 +219,48 @@ def test_training_reduces_loss():
     assert tr[-50:].mean() < 0.2 * tr[:10].mean()
 
 
+def test_training_resumes_from_a_checkpoint(tmp_path):
+    # train 300 steps in one call; then 150, checkpoint to disk, reload and
+    # 150 more: training reductions have a fixed order (no atomics in the
+    # gradients), so the resumed run lands on the uninterrupted one's bits
+    widths = [64, 256, 256, 256, 256, 256, 2 * 9 * 9]
+    d = _desc(n_out=2 * 9 * 9, loss=abi.LOSS_KL)
+    layers, flat = _params(widths, 9)
+    n, B, steps = 4096, 256, 300
+    x = torch.from_numpy(_inputs(n, 10)).cuda()
+    t = torch.from_numpy(_targets(n, 2 * 9 * 9, 11)).cuda()
+    ws_t = sdirt.mlp_workspace(d, B)
+
+    def fresh():
+        p = torch.from_numpy(flat).cuda()
+        return p, torch.zeros_like(p), torch.zeros_like(p)
+
+    runs = []
+    for _ in range(2):
+        p, m, v = fresh()
+        tr = torch.zeros((steps,), device="cuda")
+        sdirt.mlp_train(d, p, m, v, x, t, ws_t, B, 0, steps, total_steps=steps, seed=5,
+                        loss_trace=tr)
+        runs.append((p.cpu(), m.cpu(), v.cpu(), tr.cpu()))
+    p, m, v = fresh()
+    tr1 = torch.zeros((steps // 2,), device="cuda")
+    sdirt.mlp_train(d, p, m, v, x, t, ws_t, B, 0, steps // 2, total_steps=steps, seed=5,
+                    loss_trace=tr1)
+    path = str(tmp_path / "trainer.safetensors")
+    sdirt.mlp_save_checkpoint(path, d, p, m, v, step=steps // 2, seed=5, total_steps=steps)
+    del p, m, v
+    d2, p, m, v, step, seed, total = sdirt.mlp_load_checkpoint(path)
+    tr2 = torch.zeros((steps - step,), device="cuda")
+    sdirt.mlp_train(d2, p, m, v, x, t, ws_t, B, step, steps - step, total_steps=total, seed=seed,
+                    loss_trace=tr2)
+    ref, ref_m, ref_v, ref_tr = runs[0]
+    assert all(torch.equal(a, b) for a, b in zip(runs[0][:3], runs[1][:3]))
+    assert torch.equal(p.cpu(), ref) and torch.equal(m.cpu(), ref_m) and torch.equal(v.cpu(), ref_v)
+    # the reported losses are sums over rows in atomic order: equal to rounding
+    resumed = torch.cat([tr1.cpu(), tr2.cpu()])
+    assert torch.allclose(resumed, ref_tr, rtol=1e-5, atol=1e-7)
+
+
 def test_invalid_batch_is_rejected():
     d = _desc()
     with pytest.raises(RuntimeError):
