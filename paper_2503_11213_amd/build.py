@@ -62,7 +62,8 @@ def build(verbose=False):
         raise RuntimeError("HIP build failed")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + \
-        [j[1] for j in jobs]
+        [j[1] for j in jobs] + ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
+                                "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
