@@ -3,14 +3,14 @@
 Sec. 3.2 / Supplement S1.4: ray-traced DP PSFs at random points of the
 valid imaging region are the training set of an MLP that then predicts the
 PSF of every pixel of a depth map, which feeds the pixel-wise renderer; the
-tracer stays the judge of the network's error.
+tracer at many rays remains the reference for the network's error.
 
     python -m paper_2503_11213_amd.surrogate [--samples N] [--steps S]
 
 traces the training set, trains (Kullback-Leibler loss by default; the
 paper's L2 loss with --loss l2max), measures the held-out energy L1 against
 high-ray traces (8192^2 rays: their own noise is ~0.1 %), the error of
-plain tracing at several ray counts against the same judge, the paper's
+plain tracing at several ray counts against the same reference, the paper's
 per-element L1 / L2 figures, times MLP inference against tracing at the
 same window size and prints one JSON line.
 """
@@ -55,7 +55,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--judge-rays", type=int, default=8192)
+    ap.add_argument("--reference-rays", type=int, default=8192)
     ap.add_argument("--loss", choices=["kl", "l2max"], default="kl")
     args = ap.parse_args()
     dev = torch.device("cuda", 0)
@@ -99,27 +99,27 @@ def main():
                     "loss_first": float(trace[:10].mean()), "loss_last": float(trace[-100:].mean())}
     del targets
     torch.cuda.empty_cache()
-    # held-out error, judged by the tracer at more rays
+    # held-out error, against the tracer at more rays
     hpts, hx = configs.surrogate_points(args.heldout, seed=2)
     hpts_t = torch.from_numpy(hpts).to(dev)
-    judge = trace_points(lens, sensor, query, hpts_t, rays=args.judge_rays, chunk=4096)
+    reference = trace_points(lens, sensor, query, hpts_t, rays=args.reference_rays, chunk=4096)
     hx_t = torch.from_numpy(hx).to(dev)
     ws_inf = sdirt.mlp_workspace(desc, 4096)
     pred = sdirt.mlp_forward(desc, params, hx_t, ws_inf, 4096)
-    e_mlp = energy_l1(pred, judge)
+    e_mlp = energy_l1(pred, reference)
     kk2 = pred.shape[1]
-    rec["heldout"] = {"points": args.heldout, "judge_rays": args.judge_rays ** 2,
+    rec["heldout"] = {"points": args.heldout, "reference_rays": args.reference_rays ** 2,
                       "mlp_energy_l1_mean": float(e_mlp.mean()),
                       "mlp_energy_l1_median": float(e_mlp.median()),
                       # the paper's Table S3 figures: mean |p - t| and (p - t)^2 per element
-                      "mlp_l1_per_element": float((pred.float() - judge).abs().mean()),
-                      "mlp_l2_per_element": float(((pred.float() - judge) ** 2).mean()),
+                      "mlp_l1_per_element": float((pred.float() - reference).abs().mean()),
+                      "mlp_l2_per_element": float(((pred.float() - reference) ** 2).mean()),
                       "outputs_per_psf": kk2}
-    # plain tracing: error against the same judge and speed, per ray count
+    # plain tracing: error against the same reference and speed, per ray count
     rec["trace_error"] = {}
     for rays in (128, 256, 512, 1024, 2048):
         same = trace_points(lens, sensor, query, hpts_t, rays=rays)
-        rec["trace_error"][str(rays)] = float(energy_l1(same, judge).mean())
+        rec["trace_error"][str(rays)] = float(energy_l1(same, reference).mean())
     print("held-out energy L1: mlp %.4f; trace %s" % (rec["heldout"]["mlp_energy_l1_mean"],
                                                    rec["trace_error"]), flush=True)
     # throughput at ks 33: MLP inference vs tracing (512^2 rays)

@@ -27,9 +27,9 @@ def test_trained_surrogate_beats_tracing_at_equal_error():
     params = torch.from_numpy(flat).to(dev)
     hpts, hx = configs.surrogate_points(256, seed=12)
     hpts_t, hx_t = torch.from_numpy(hpts).to(dev), torch.from_numpy(hx).to(dev)
-    judge = trace_points(lens, sensor, query, hpts_t, rays=2048)
+    reference = trace_points(lens, sensor, query, hpts_t, rays=2048)
     ws_inf = sdirt.mlp_workspace(desc, 256)
-    e0 = float(energy_l1(sdirt.mlp_forward(desc, params, hx_t, ws_inf, 256), judge).mean())
+    e0 = float(energy_l1(sdirt.mlp_forward(desc, params, hx_t, ws_inf, 256), reference).mean())
     m, v = torch.zeros_like(params), torch.zeros_like(params)
     B, steps = 512, 3000
     ws = sdirt.mlp_workspace(desc, B)
@@ -37,13 +37,13 @@ def test_trained_surrogate_beats_tracing_at_equal_error():
     sdirt.mlp_train(desc, params, m, v, torch.from_numpy(x).to(dev), targets, ws, B, 0, steps,
                     lr0=1e-3, lr_min=1e-5, total_steps=steps, seed=7, loss_trace=trace)
     pred = sdirt.mlp_forward(desc, params, hx_t, ws_inf, 256)
-    e1 = float(energy_l1(pred, judge).mean())
+    e1 = float(energy_l1(pred, reference).mean())
     print("held-out energy L1: untrained %.3f, trained %.3f" % (e0, e1))
     assert np.isfinite(trace.cpu().numpy()).all()
     assert e1 < 0.4 * e0 and e1 < 0.3
     # the ray count at which plain tracing is no worse than the network
     rays = next(r for r in (64, 128, 256, 512, 1024)
-                if float(energy_l1(trace_points(lens, sensor, query, hpts_t, rays=r), judge).mean()) <= e1)
+                if float(energy_l1(trace_points(lens, sensor, query, hpts_t, rays=r), reference).mean()) <= e1)
     n = 65536
     tp = torch.from_numpy(configs.surrogate_points(n, seed=13)[0]).to(dev)
     xp = torch.from_numpy(configs.surrogate_points(n, seed=13)[1]).to(dev)
