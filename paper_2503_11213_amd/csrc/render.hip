@@ -541,17 +541,15 @@ __device__ inline void bank_mfma_rows(const float* __restrict__ kl, int rstep, b
 //     D[(side, q)][p] = sum over the strips of g[side][q] * window_i[p]
 // is a matrix product with the strips as the contraction (A: the strips'
 // output gradients, fixed over the rows; B: their image windows from the
-// LDS halo), in 16-column blocks of p.  The kernel gradient is its diagonal
-// sum, grad_K[side][i][j] = sum_q D[(side, q)][q + KS - 1 - j]: each block
-// goes through a per-wave LDS scratch and the partial diagonal sums collect
-// in a second one, then 2 KS lanes add a row into the bank entry (mirrors
-// applied) with global atomics.
+// LDS halo), in 16-column blocks of p computed as independent chains.  The
+// kernel gradient is its diagonal sum, grad_K[side][i][j] =
+// sum_q D[(side, q)][q + KS - 1 - j], formed in registers with lane
+// shuffles; one lane per diagonal adds it into the bank entry (mirrors
+// applied) with a global atomic.
 template <int KS>
 struct KGradGeom {
     static constexpr int NB = (KS + kStrip - 1 + 15) / 16;    // 16-column blocks of p
-    static constexpr int BLK = 16 * 17;                        // one block, padded rows
-    static constexpr int SUMS = 2 * 16 * NB;                   // partial sums [2][16 NB]
-    static constexpr int SCR = BLK + SUMS;
+    static constexpr int SCR = 4;                              // per-wave scratch (unused)
     static_assert(kGT - kStrip + KS + kStrip - 1 <= GroupGeom<KS>::HW, "window reads stay in the halo row");
 };
 
@@ -584,49 +582,59 @@ __device__ inline void bank_kgrad_chunk(const RenderArgs& A, int n, int c, int y
         }
         ga[t] = g;
     }
-    float* blk = scr;                                 // [16][17]
-    float* sums = scr + KG::BLK;                      // [2][16 NB]
+    (void)scr;
     for (int i = 0; i < KS; ++i) {
-        for (int e = lane; e < KG::SUMS; e += 64) sums[e] = 0.f;
+        // the NB column blocks as independent accumulation chains, k-step
+        // by k-step, so that consecutive products do not wait on each other
+        floatx4_t dd[KG::NB];
+        int pofs[KG::NB];
+#pragma unroll
         for (int b = 0; b < KG::NB; ++b) {
-            floatx4_t d = {0.f, 0.f, 0.f, 0.f};
+            dd[b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
             // columns past the window (p > KS + 6) are never summed: those
             // lanes read the last window column instead
-            const int pofs = min(16 * b + m, KS + kStrip - 2) - i * G::HW;
-            for (int t = 0; t < nks; ++t)
-                d = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[t], halo[bofs[t] + pofs], d, 0, 0, 0);
-            // the lane holds D[4 kq + r][16 b + m]
-            __builtin_amdgcn_wave_barrier();
+            pofs[b] = min(16 * b + m, KS + kStrip - 2) - i * G::HW;
+        }
+        for (int t = 0; t < nks; ++t) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) blk[(4 * kq + r) * 17 + m] = d[r];
-            __builtin_amdgcn_wave_barrier();
-            // partial diagonal sums c = p - q in [16 b - 7, 16 b + 15]
-            if (lane < 46) {
-                const int sd = lane / 23;
-                const int cc = 16 * b - 7 + lane % 23;
-                if (cc >= 0 && cc < KS) {
-                    float acc = 0.f;
+            for (int b = 0; b < KG::NB; ++b)
+                dd[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[t], halo[bofs[t] + pofs[b]], dd[b], 0, 0, 0);
+        }
+        // diagonal sums in registers.  Lane (m, kq) holds D[(s, 4 h + r)][16 b + m]
+        // (s = kq / 2, h = kq % 2): first u_b[m] = sum_r D[(s, 4 h + r)][16 b + m + r]
+        // (diagonal c = 16 b + m - 4 h; columns past 15 from block b + 1), then
+        // S[s][16 b + m] = u_b[m] of h = 0 + u_b[m + 4] of h = 1
+        float uu[KG::NB];
 #pragma unroll
-                    for (int qq = 0; qq < kStrip; ++qq) {
-                        const int col = cc + qq - 16 * b;
-                        if (col >= 0 && col < 16) acc += blk[(sd * 8 + qq) * 17 + col];
-                    }
-                    sums[sd * 16 * KG::NB + cc] += acc;
-                }
+        for (int b = 0; b < KG::NB; ++b) {
+            float u = dd[b][0];
+#pragma unroll
+            for (int r = 1; r < 4; ++r) {
+                const float a = __shfl_down(dd[b][r], r, 16);
+                float nx = 0.f;
+                if (b + 1 < KG::NB) nx = __shfl_up(dd[b + 1][r], 16 - r, 16);
+                u += m + r < 16 ? a : nx;
             }
-            __builtin_amdgcn_wave_barrier();
+            uu[b] = u;
         }
-        // row i of both sides into the entry: tap j = KS - 1 - c, mirrored
         const int si = fyb ? KS - 1 - i : i;
-        for (int e = lane; e < 2 * KS; e += 64) {
-            const int sd = e / KS, cc = e - sd * KS;
-            const int j = KS - 1 - cc;
-            const int sj = fxb ? KS - 1 - j : j;
-            const int ss = fxb ? 1 - sd : sd;
-            const float v = sums[sd * 16 * KG::NB + cc];
-            if (v != 0.f) atomicAdd(&ge[(size_t)ss * kk + si * KS + sj], v);
+        const int sd = kq >> 1;
+#pragma unroll
+        for (int b = 0; b < KG::NB; ++b) {
+            const float a = __shfl_down(uu[b], 4, 16);
+            float nx = 0.f;
+            if (b + 1 < KG::NB) nx = __shfl_up(uu[b + 1], 12, 16);
+            const float w = __shfl_xor(m + 4 < 16 ? a : nx, 16, 64);   // h = 1's, on h = 0 lanes
+            const float v = uu[b] + w;
+            // row i of side sd into the entry: tap j = KS - 1 - c, mirrored
+            const int cc = 16 * b + m;
+            if ((kq & 1) == 0 && cc < KS && v != 0.f) {
+                const int j = KS - 1 - cc;
+                const int sj = fxb ? KS - 1 - j : j;
+                const int ss = fxb ? 1 - sd : sd;
+                atomicAdd(&ge[(size_t)ss * kk + si * KS + sj], v);
+            }
         }
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
