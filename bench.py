@@ -41,8 +41,8 @@ TRACE_SOURCES = ("paper_2503_11213_amd/csrc/device_common.hpp",
                  "paper_2503_11213_amd/csrc/trace.hip",
                  "paper_2503_11213_amd/csrc/pack.hpp",
                  "paper_2503_11213_amd/csrc/pack.cpp")
-TRACE_TRAFFIC = {"sources_sha256": "f649b99e406df527afaf7e18022e649f2c23676b58f28026e69600a52a0eb6c1",
-                 "bytes": 65727277}
+TRACE_TRAFFIC = {"sources_sha256": "efd856cf901a745ab96df7348f5a220c028fac42a5e373f8b7523e19ea27af8a",
+                 "bytes": 65716014}
 
 
 def sources_digest():
