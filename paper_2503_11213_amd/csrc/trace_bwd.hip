@@ -270,14 +270,18 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
 }
 
 // The state entering every surface, kept in LDS as float32 (structure of
-// arrays: entry (s, k) of lane l at [(6 s + k) * 64 + l], conflict-free).
+// arrays: entry (s, k) of lane l at [(5 s + k) * 64 + l], conflict-free):
+// x, y, z, dx, dy; dz is the positive root of |d| = 1 (a live ray always
+// travels toward +z), which saves a sixth of the LDS and so raises the
+// number of resident workgroups.
+constexpr int kPathVals = 5;
 struct PathRec {
     float* v;
     int lane;
     __device__ void operator()(int s, const Ray<double>& r) const {
-        float* o = v + 6 * (s + 1) * 64 + lane;
+        float* o = v + kPathVals * (s + 1) * 64 + lane;
         o[0] = (float)r.x; o[64] = (float)r.y; o[128] = (float)r.z;
-        o[192] = (float)r.dx; o[256] = (float)r.dy; o[320] = (float)r.dz;
+        o[192] = (float)r.dx; o[256] = (float)r.dy;
     }
 };
 
@@ -286,8 +290,9 @@ __device__ inline void path_put(float* v, int s, int lane, const Ray<double>& r)
 }
 
 __device__ inline St path_get(const float* v, int s, int lane) {
-    const float* o = v + 6 * s * 64 + lane;
-    return St{o[0], o[64], o[128], o[192], o[256], o[320]};
+    const float* o = v + kPathVals * s * 64 + lane;
+    const double dx = o[192], dy = o[256];
+    return St{o[0], o[64], o[128], dx, dy, sqrt_t<double>(1.0 - dx * dx - dy * dy)};
 }
 
 // GENERAL = false: spheres, planes and stops only (the forward re-trace then
@@ -295,7 +300,7 @@ __device__ inline St path_get(const float* v, int s, int lane) {
 template <bool GENERAL>
 __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
     __shared__ double gsh[kPerSurf * kMaxS + 1];
-    extern __shared__ float path[];     // [(S + 1) * 6][64]
+    extern __shared__ float path[];     // [(S + 1) * kPathVals][64]
     const int S = A.lens.S;
     const int np = kPerSurf * S + 1;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -461,7 +466,7 @@ int trace_backward_impl(const sdirt_lens* lens, const sdirt_sensor* sensor,
     int chunks = std::max(1, std::min((16384 + P - 1) / P, n_rays / (kBBlock * 4)));
     A.smp.chunks = chunks;
     A.smp.rays_per_chunk = (n_rays + chunks - 1) / chunks;
-    const size_t shm = (size_t)(R.S + 1) * 6 * kBBlock * sizeof(float);
+    const size_t shm = (size_t)(R.S + 1) * kPathVals * kBBlock * sizeof(float);
     bool general = false;
     for (int s = 0; s < R.S; ++s)
         general = general || R.kind[s] == SDIRT_ASPHERE || R.kind[s] == SDIRT_IDEAL;
