@@ -46,9 +46,32 @@ struct St {
     double x, y, z, dx, dy, dz;
 };
 
+// v of a lane moved by one DPP pattern (each 32-bit half); lanes without a
+// source read 0
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the wave's 64 lanes, returned on every lane.  Within each row of
+// 16 lanes two quad permutations and two row rotations leave the row's sum
+// in every lane; two row broadcasts then carry rows 0..2 into the later
+// rows, so that lane 63 holds the total.  All steps are VALU data movement
+// (no LDS round trips).
 __device__ inline double wave_sum_d(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_move<0xb1>(v);     // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4e>(v);     // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x124>(v);    // row_ror:4
+    v += dpp_move<0x128>(v);    // row_ror:8
+    v += dpp_move<0x142>(v);    // row_bcast:15
+    v += dpp_move<0x143>(v);    // row_bcast:31
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // Adjoint of vector Snell refraction d' = mu d + g N, g = sqrt(K) - mu cosI,
