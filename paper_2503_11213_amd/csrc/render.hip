@@ -553,6 +553,32 @@ struct KGradGeom {
     static_assert(kGT - kStrip + KS + kStrip - 1 <= GroupGeom<KS>::HW, "window reads stay in the halo row");
 };
 
+// Within each row of 16 lanes: the value of lane l + k (row_shl) or l - k
+// (row_shr), by DPP; lanes whose source falls outside the row read 0 and
+// are not used by the callers.
+__device__ inline float row_shl(float v, int k) {
+    int r = 0;
+    const int x = __builtin_bit_cast(int, v);
+    switch (k) {
+        case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x101, 0xf, 0xf, false); break;
+        case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x102, 0xf, 0xf, false); break;
+        case 3: r = __builtin_amdgcn_update_dpp(0, x, 0x103, 0xf, 0xf, false); break;
+        default: r = __builtin_amdgcn_update_dpp(0, x, 0x104, 0xf, 0xf, false); break;
+    }
+    return __builtin_bit_cast(float, r);
+}
+__device__ inline float row_shr(float v, int k) {
+    int r = 0;
+    const int x = __builtin_bit_cast(int, v);
+    switch (k) {
+        case 15: r = __builtin_amdgcn_update_dpp(0, x, 0x11f, 0xf, 0xf, false); break;
+        case 14: r = __builtin_amdgcn_update_dpp(0, x, 0x11e, 0xf, 0xf, false); break;
+        case 13: r = __builtin_amdgcn_update_dpp(0, x, 0x11d, 0xf, 0xf, false); break;
+        default: r = __builtin_amdgcn_update_dpp(0, x, 0x11c, 0xf, 0xf, false); break;
+    }
+    return __builtin_bit_cast(float, r);
+}
+
 template <int KS>
 __device__ inline void bank_kgrad_chunk(const RenderArgs& A, int n, int c, int y0, int x0,
                                         const int* items, int cnt, int fxb, int fyb, float* ge,
@@ -610,9 +636,9 @@ __device__ inline void bank_kgrad_chunk(const RenderArgs& A, int n, int c, int y
             float u = dd[b][0];
 #pragma unroll
             for (int r = 1; r < 4; ++r) {
-                const float a = __shfl_down(dd[b][r], r, 16);
+                const float a = row_shl(dd[b][r], r);                    // lane m + r
                 float nx = 0.f;
-                if (b + 1 < KG::NB) nx = __shfl_up(dd[b + 1][r], 16 - r, 16);
+                if (b + 1 < KG::NB) nx = row_shr(dd[b + 1][r], 16 - r);  // lane m + r - 16
                 u += m + r < 16 ? a : nx;
             }
             uu[b] = u;
@@ -621,9 +647,9 @@ __device__ inline void bank_kgrad_chunk(const RenderArgs& A, int n, int c, int y
         const int sd = kq >> 1;
 #pragma unroll
         for (int b = 0; b < KG::NB; ++b) {
-            const float a = __shfl_down(uu[b], 4, 16);
+            const float a = row_shl(uu[b], 4);
             float nx = 0.f;
-            if (b + 1 < KG::NB) nx = __shfl_up(uu[b + 1], 12, 16);
+            if (b + 1 < KG::NB) nx = row_shr(uu[b + 1], 12);
             const float w = __shfl_xor(m + 4 < 16 ? a : nx, 16, 64);   // h = 1's, on h = 0 lanes
             const float v = uu[b] + w;
             // row i of side sd into the entry: tap j = KS - 1 - c, mirrored
