@@ -489,6 +489,7 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_render_head_kernel(const Fus
         }
     constexpr float kL2E = 1.4426950408889634f;
     constexpr float kNone = -1e30f;
+    constexpr float kSlack = 32.f;
     const int Lo = A.n_hidden;
     const bf16_t* Wo = A.W[Lo];
     const float* bo = A.params + A.b_off[Lo];
@@ -512,29 +513,67 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_render_head_kernel(const Fus
             coff[j] = ti * hh + (tap - ti * ks);
             right[j] = side ? 1.f : 0.f;
         }
+        // the reference m[k] is raised only when a logit passes it (to
+        // kSlack above the new maximum), as in the inference head
+        bool raise = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int k = 4 * i + r;
-                float z[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) z[j] = fmaf(acc[i][j][r], kL2E, bl[j]);
-                const float mn = fmaxf(fmaxf(m[k], fmaxf(z[0], z[1])), fmaxf(z[2], z[3]));
-                if (__ballot(mn > m[k])) {
-                    const float sc = __builtin_amdgcn_exp2f(m[k] - mn);
-                    s[k] *= sc; al[k] *= sc; ar[k] *= sc;
-                }
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const float e = __builtin_amdgcn_exp2f(z[j] - mn);
-                    const float ew = e * halo[hb[k] - coff[j]];
-                    s[k] += e;
-                    al[k] = fmaf(ew, 1.f - right[j], al[k]);
-                    ar[k] = fmaf(ew, right[j], ar[k]);
+                    acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl[j]);
+                    raise |= acc[i][j][r] > m[4 * i + r];
                 }
-                m[k] = mn;
-            }
+        if (__ballot(raise)) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 4 * i + r;
+                    const float zm = fmaxf(fmaxf(acc[i][0][r], acc[i][1][r]), fmaxf(acc[i][2][r], acc[i][3][r]));
+                    const float mn = fmaxf(m[k], zm + kSlack);
+                    const float sc = __builtin_amdgcn_exp2f(m[k] - mn);
+                    s[k] *= sc; al[k] *= sc; ar[k] *= sc;
+                    m[k] = mn;
+                }
+        }
+        // a tile on one side only (all but the one that straddles the
+        // sides) adds its weighted terms to that side's sum directly
+        const int side0 = 64 * t >= kk, side1 = 64 * t + 63 >= kk;
+        if (side0 == side1) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 4 * i + r;
+                    float es = 0.f, ews = 0.f;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float e = __builtin_amdgcn_exp2f(acc[i][j][r] - m[k]);
+                        es += e;
+                        ews = fmaf(e, halo[hb[k] - coff[j]], ews);
+                    }
+                    s[k] += es;
+                    if (side0) ar[k] += ews;
+                    else al[k] += ews;
+                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = 4 * i + r;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float e = __builtin_amdgcn_exp2f(acc[i][j][r] - m[k]);
+                        const float ew = e * halo[hb[k] - coff[j]];
+                        s[k] += e;
+                        al[k] = fmaf(ew, 1.f - right[j], al[k]);
+                        ar[k] = fmaf(ew, right[j], ar[k]);
+                    }
+                }
+        }
     }
     // merge over the 16 lanes holding the same rows, then over the 4 waves
 #pragma unroll
