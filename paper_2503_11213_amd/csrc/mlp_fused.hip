@@ -538,8 +538,10 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_render_head_kernel(const Fus
                     m[k] = mn;
                 }
         }
-        // a tile on one side only (all but the one that straddles the
-        // sides) adds its weighted terms to that side's sum directly
+        // outputs [0, ks^2) are the left kernel's taps, [ks^2, 2 ks^2) the
+        // right's: a tile wholly inside one of them (every tile but the one
+        // that holds output ks^2 - 1 and ks^2) adds its weighted terms to
+        // that kernel's sum alone
         const int side0 = 64 * t >= kk, side1 = 64 * t + 63 >= kk;
         if (side0 == side1) {
 #pragma unroll
