@@ -313,8 +313,11 @@ def test_surrogate_render_matches_oracle(ks, N, C, H, W, ws):
     assert np.allclose(o1[:, :C] + o1[:, C:], 1.0, atol=1e-5)
 
 
-def test_surrogate_render_full_size_sampled_pixels():
-    # the benchmarked launch shape: 1680 x 1120 RGB, ks 33, 65536-row chunks
+@pytest.mark.parametrize("chunk", [65536, 262144])
+def test_surrogate_render_full_size_sampled_pixels(chunk):
+    # 1680 x 1120 RGB, ks 33 (5,644,800 pixel rows): 65536-row chunks, and
+    # the benchmarked launch of 262144-row chunks (21 full chunks and a
+    # 139,776-row tail)
     ks, N, C, H, W, ps = 33, 1, 3, 1120, 1680, 0.00536
     widths = [64, 256, 256, 256, 256, 256, 2 * ks * ks]
     layers, flat = _params(widths, 5)
@@ -324,9 +327,9 @@ def test_surrogate_render_full_size_sampled_pixels():
     norm = dict(x_half=W * ps / 2, y_half=H * ps / 2, iv_lo=0.2e-3, iv_hi=2.0e-3,
                 lam_lo=0.486, lam_hi=0.656)
     d = sdirt.make_mlp_desc(n_hidden=5, width=256, n_out=2 * ks * ks, n_freq=8, **norm)
-    ws_t = sdirt.mlp_workspace(d, 65536)
+    ws_t = sdirt.mlp_workspace(d, chunk)
     out = sdirt.mlp_render(d, torch.from_numpy(flat).cuda(), torch.from_numpy(img).cuda(),
-                           torch.from_numpy(depth).cuda(), lams, ps, ws_t, 65536).cpu().numpy()
+                           torch.from_numpy(depth).cuda(), lams, ps, ws_t, chunk).cpu().numpy()
     x = M.pixel_inputs(N, C, H, W, ps, depth, lams)
     rng = np.random.default_rng(8)
     pix = [(0, 0), (H - 1, W - 1), (0, W - 1), (H - 1, 0), (560, 840), (7, 8)] + \
