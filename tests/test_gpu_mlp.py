@@ -284,6 +284,31 @@ def test_fused_forward_output_widths(n_out):
         assert np.allclose(p.sum(axis=1), 1.0, atol=2e-2 if dt == abi.BF16 else 1e-4)
 
 
+def test_inference_full_size_sampled_rows():
+    # the benchmarked launch: 2^20 rows in 65536-row chunks, ks 33, bf16
+    # out; sampled rows (chunk edges among them) against the bf16 mirror,
+    # and every row's probabilities summing to one
+    from workloads import configs
+    n, chunk, n_out = 1 << 20, 65536, 2 * 33 * 33
+    norm = configs.config4_desc_kwargs()
+    d = sdirt.make_mlp_desc(n_out=n_out, **norm)
+    layers, flat = _params([64, 256, 256, 256, 256, 256, n_out], 0)
+    _, x = configs.surrogate_points(n, seed=9)
+    ws_t = sdirt.mlp_workspace(d, chunk)
+    ob = torch.empty((n, n_out), dtype=torch.bfloat16, device="cuda")
+    sdirt.mlp_forward(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(), ws_t, chunk,
+                      out_dtype=abi.BF16, out=ob)
+    sums = torch.sum(ob, dim=1, dtype=torch.float32).cpu().numpy()
+    assert np.all(np.abs(sums - 1.0) <= 2e-2)
+    rng = np.random.default_rng(10)
+    rows = np.concatenate([[0, chunk - 1, chunk, n - 1], rng.integers(0, n, 60)])
+    got = ob[torch.from_numpy(rows).cuda()].float().cpu().numpy()
+    ref, _ = M.forward(_oracle_params(layers), x[rows].astype(np.float64), norm, bf16=True)
+    err = _rel_l2(got, ref)
+    print("full-size inference rel L2", err)
+    assert err <= REL
+
+
 @pytest.mark.parametrize("ks,N,C,H,W,ws", [(9, 2, 3, 20, 27, 128), (33, 1, 3, 18, 21, 4096),
                                           (5, 1, 1, 9, 8, 64)])
 def test_surrogate_render_matches_oracle(ks, N, C, H, W, ws):
