@@ -186,6 +186,20 @@ int sdirt_trace_dp_psf(const sdirt_lens* lens, const sdirt_sensor* sensor,
                        const sdirt_psf_query* query, void* psf_out,
                        double* stats_out, void* stream);
 
+/* sdirt_trace_dp_psf with the number of ray chunks per point given by the
+ * caller instead of chosen by the library (Sec. 3.1; the result is the same
+ * estimator, Eq. (3), for any chunk count).  A point's pupil grid is cut
+ * into `chunks` contiguous ranges of ray indices, each traced by one
+ * workgroup whose LDS tile is added into psf_out with float32 atomics; the
+ * launch has chunks * P workgroups.  chunks >= 1 (SDIRT_EINVAL otherwise);
+ * values above the ray count are clamped to it; ignored in deterministic
+ * mode (one workgroup per point).  Other arguments, layouts, ownership and
+ * errors as sdirt_trace_dp_psf.  For sweeping launch shapes and for tests
+ * that the chunking does not change the PSFs. */
+int sdirt_trace_dp_psf_chunks(const sdirt_lens* lens, const sdirt_sensor* sensor,
+                              const sdirt_psf_query* query, void* psf_out,
+                              double* stats_out, int chunks, void* stream);
+
 /* Number of parameters of the trace adjoint: 8 * n_surfaces + 1. */
 int sdirt_n_params(const sdirt_lens* lens);
 
@@ -379,6 +393,21 @@ int sdirt_mlp_vjp(const sdirt_mlp_desc* desc, const float* params, long long n_r
  * params with moments m, v (device [n_params] f32 each, updated). */
 int sdirt_mlp_adam(const sdirt_mlp_desc* desc, float* params, float* m, float* v,
                    const float* grads, int step, float lr, void* stream);
+
+/* One training step on a caller-given batch (Sec. 3.2, Eq. (4); Supplement
+ * S1.4): forward, the loss of desc->loss and its gradient (as
+ * sdirt_mlp_backward), then one Adam update of params with moments m, v (as
+ * sdirt_mlp_adam, bias correction of step `step` >= 1, learning rate lr).
+ *   x       device [batch][4] inputs, target device [batch][n_out] jointly
+ *           sum-normalised PSFs (batch a multiple of 64);
+ *   params, m, v  device [n_params] f32, updated in place;
+ *   loss_out device [1] f32, the batch loss before the update (may be NULL);
+ *   workspace as for sdirt_mlp_backward (sdirt_mlp_workspace_size(batch)).
+ * SDIRT_EINVAL for NULL buffers, a batch that is not a positive multiple of
+ * 64, step < 1 or a non-finite lr. */
+int sdirt_mlp_train_step(const sdirt_mlp_desc* desc, float* params, float* m, float* v,
+                         int step, float lr, int batch, const float* x, const float* target,
+                         float* loss_out, void* workspace, void* stream);
 
 /* n_steps training steps on a device-resident dataset (x_all [n][4],
  * t_all [n][n_out]): each step draws `batch` samples by a counter hash of

@@ -132,6 +132,9 @@ SIGNATURES = {
                                 C.c_void_p]),
     "sdirt_mlp_adam": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_int, C.c_float, C.c_void_p]),
+    "sdirt_mlp_train_step": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_int, C.c_float, C.c_int, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]),
     "sdirt_mlp_train": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_int, C.c_int, C.c_float, C.c_float, C.c_int,
                                   C.c_int, C.c_longlong, C.c_void_p, C.c_void_p,

@@ -38,6 +38,8 @@ int mlp_adam(const sdirt_mlp_desc*, float*, float*, float*, const float*, int, f
              hipStream_t);
 int mlp_train(const sdirt_mlp_desc*, float*, float*, float*, int, int, float, float, int, int,
               long long, const float*, const float*, uint32_t, float*, void*, hipStream_t);
+int mlp_train_step(const sdirt_mlp_desc*, float*, float*, float*, int, float, int, const float*,
+                   const float*, float*, void*, hipStream_t);
 }  // namespace sdirt
 
 using namespace sdirt;
@@ -115,8 +117,6 @@ int sdirt_trace_dp_psf(const sdirt_lens* lens, const sdirt_sensor* sensor,
                              (hipStream_t)stream, 0);
 }
 
-// Same as sdirt_trace_dp_psf with an explicit number of ray chunks per
-// point (workgroups per PSF point); used to sweep launch shapes.
 int sdirt_trace_dp_psf_chunks(const sdirt_lens* lens, const sdirt_sensor* sensor,
                               const sdirt_psf_query* query, void* psf_out,
                               double* stats_out, int chunks, void* stream) {
@@ -201,6 +201,14 @@ int sdirt_mlp_adam(const sdirt_mlp_desc* desc, float* params, float* m, float* v
                    const float* grads, int step, float lr, void* stream) {
     Range r("sdirt_mlp_adam");
     return mlp_adam(desc, params, m, v, grads, step, lr, (hipStream_t)stream);
+}
+
+int sdirt_mlp_train_step(const sdirt_mlp_desc* desc, float* params, float* m, float* v,
+                         int step, float lr, int batch, const float* x, const float* target,
+                         float* loss_out, void* workspace, void* stream) {
+    Range r("sdirt_mlp_train_step");
+    return mlp_train_step(desc, params, m, v, step, lr, batch, x, target, loss_out, workspace,
+                          (hipStream_t)stream);
 }
 
 int sdirt_mlp_train(const sdirt_mlp_desc* desc, float* params, float* m, float* v,

@@ -363,7 +363,10 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
                 // previous one: Newton is then in its quadratic regime and the
                 // next step would be under r^2 |step| < 1e-13 mm (r the ratio),
                 // so that step is skipped.
-                bool conv = false, bad = false;
+                // a ray already lost (bookkeeping mode) takes no Newton
+                // step: its state is never used, and its iterations, which
+                // need not converge, would hold the whole wave
+                bool conv = !alive, bad = false;
                 T prev = T(1e30);
                 for (int it = 0; it < 50 && !conv && !bad; ++it) {
                     const T xr = r.x + delta * r.dx;

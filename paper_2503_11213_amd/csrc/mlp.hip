@@ -642,6 +642,27 @@ int mlp_workspace_size(const sdirt_mlp_desc* d, int batch, size_t* out) {
     return SDIRT_OK;
 }
 
+// Fused inference of a width-256 network (every layer and the softmax in one
+// pass over the rows): fragment-ordered weights into w.WF, then chunks of
+// `chunk` rows whose last hidden activations pass through hbuf.
+static int forward_fused(const MlpDims& m, const sdirt_mlp_desc* d, const MlpWs& w,
+                         bf16_t* hbuf, long long chunk, const float* params, long long n_rows,
+                         const float* x, void* out, int out_dtype, hipStream_t st) {
+    frag_all(m, w, params, st);
+    FusedArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.n_rows = n_rows;
+    f.n_hidden = m.n_hidden; f.n_out = m.n_out; f.n_freq = m.n_freq;
+    f.feat_pad = feat_pad(m);
+    f.x_half = (float)d->x_half; f.y_half = (float)d->y_half;
+    f.iv_lo = (float)d->iv_lo; f.iv_hi = (float)d->iv_hi;
+    f.lam_lo = (float)d->lam_lo; f.lam_hi = (float)d->lam_hi;
+    f.x = x; f.params = params;
+    for (int l = 0; l < m.L; ++l) { f.b_off[l] = (long long)m.b_off(l); f.W[l] = w.WF[l]; }
+    f.out = out; f.out_bf16 = out_dtype == SDIRT_BF16;
+    return launch_mlp_fused(f, hbuf, chunk, st);
+}
+
 int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, const float* x,
                 void* out, int out_dtype, void* workspace, int ws_batch, hipStream_t st) {
     MlpDims m;
@@ -651,22 +672,9 @@ int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, 
     if (ws_batch < 64 || ws_batch % 64) return SDIRT_EINVAL;
     if (out_dtype != SDIRT_F32 && out_dtype != SDIRT_BF16) return SDIRT_EUNSUPPORTED;
     const MlpWs w = carve(m, ws_batch, (char*)workspace);
-    if (m.width == 256) {
-        frag_all(m, w, params, st);
-        // fused kernel: every layer and the softmax in one pass over the rows
-        FusedArgs f;
-        std::memset(&f, 0, sizeof(f));
-        f.n_rows = n_rows;
-        f.n_hidden = m.n_hidden; f.n_out = m.n_out; f.n_freq = m.n_freq;
-        f.feat_pad = feat_pad(m);
-        f.x_half = (float)d->x_half; f.y_half = (float)d->y_half;
-        f.iv_lo = (float)d->iv_lo; f.iv_hi = (float)d->iv_hi;
-        f.lam_lo = (float)d->lam_lo; f.lam_hi = (float)d->lam_hi;
-        f.x = x; f.params = params;
-        for (int l = 0; l < m.L; ++l) { f.b_off[l] = (long long)m.b_off(l); f.W[l] = w.WF[l]; }
-        f.out = out; f.out_bf16 = out_dtype == SDIRT_BF16;
-        return launch_mlp_fused(f, w.H[m.n_hidden], ws_batch, st);
-    }
+    if (m.width == 256)
+        return forward_fused(m, d, w, w.H[m.n_hidden], ws_batch, params, n_rows, x, out,
+                             out_dtype, st);
     cast_all(m, w, params, st);
     const size_t esz = out_dtype == SDIRT_BF16 ? 2 : 4;
     for (long long r0 = 0; r0 < n_rows; r0 += ws_batch) {
@@ -799,6 +807,25 @@ int mlp_adam(const sdirt_mlp_desc* d, float* params, float* m1, float* m2, const
     if (rc) return rc;
     if (!params || !m1 || !m2 || !grads || step < 1 || !std::isfinite(lr)) return SDIRT_EINVAL;
     adam_launch(m.n_params(), params, m1, m2, grads, step, lr, st);
+    return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
+}
+
+int mlp_train_step(const sdirt_mlp_desc* d, float* params, float* m1, float* m2, int step,
+                   float lr, int batch, const float* x, const float* target, float* loss_out,
+                   void* workspace, hipStream_t st) {
+    MlpDims m;
+    int rc = dims_of(d, &m);
+    if (rc) return rc;
+    if (!params || !m1 || !m2 || !x || !target || !workspace) return SDIRT_EINVAL;
+    if (batch < 64 || batch % 64 || step < 1 || !std::isfinite(lr)) return SDIRT_EINVAL;
+    const MlpWs w = carve(m, batch, (char*)workspace);
+    cast_all(m, w, params, st);
+    if ((rc = launch_fill_zero(w.loss, 4, st))) return rc;
+    forward_rows(m, d, w, params, batch, x, st, true);
+    backward_rows(m, w, params, batch, target, st);
+    adam_launch(m.n_params(), params, m1, m2, w.grads, step, lr, st);
+    if (loss_out)
+        (void)hipMemcpyAsync(loss_out, w.loss, 4, hipMemcpyDeviceToDevice, st);
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
 }
 

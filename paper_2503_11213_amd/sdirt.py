@@ -23,6 +23,48 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _expect(t, name, dtype, numel, required=True):
+    """Raise ValueError unless t is a contiguous device tensor of the given
+    dtype and element count (the layout the C call will read or write)."""
+    if t is None:
+        if required:
+            raise ValueError("%s is required" % name)
+        return
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() != numel:
+        raise ValueError("%s must hold %d elements, got %d" % (name, numel, t.numel()))
+
+
+def _psf_layout(desc):
+    """(dtype, element count) of the kernels a render descriptor reads."""
+    ks2 = 2 * desc.ks * desc.ks
+    if desc.source == abi.SRC_DENSE:
+        dt = torch.bfloat16 if desc.psf_dtype == abi.BF16 else torch.float32
+        return dt, desc.N * desc.H * desc.W * desc.psf_channels * ks2
+    n = desc.bank_fields * desc.bank_depths * desc.bank_lambdas * ks2
+    if desc.source == abi.SRC_BANK2D:
+        n *= desc.bank_fields_y
+    return torch.float32, n
+
+
+def _check_render(desc, psf=None, depth=None, img=None, out=None, grad_out=None,
+                  grad_img=None, grad_psf=None):
+    N, C_, H, W = desc.N, desc.C, desc.H, desc.W
+    pdt, pn = _psf_layout(desc)
+    _expect(psf, "psf", pdt, pn, required=False)
+    _expect(grad_psf, "grad_psf", pdt, pn, required=False)
+    _expect(depth, "depth", torch.float32, N * H * W, required=desc.source != abi.SRC_DENSE)
+    _expect(img, "img", torch.float32, N * C_ * H * W, required=False)
+    _expect(grad_img, "grad_img", torch.float32, N * C_ * H * W, required=False)
+    _expect(out, "out", torch.float32, N * 2 * C_ * H * W, required=False)
+    _expect(grad_out, "grad_out", torch.float32, N * 2 * C_ * H * W, required=False)
+
+
 def _material(m):
     kind, p0, p1 = m
     return int(kind), float(p0), float(p1)
@@ -148,8 +190,11 @@ def trace_dp_psf(lens, sensor, query, math=abi.F64, points=None, out=None,
     q, keep2 = make_query(query, math, points)
     P = q.n_points if points is not None else q.n_fields * q.n_depths * q.n_wavelengths
     dt = torch.float64 if query.out_f64 else torch.float32
+    if points is not None:
+        _expect(points, "points", torch.float64, 4 * P)
     if out is None:
         out = torch.empty((P, 2, query.ks, query.ks), dtype=dt, device=device)
+    _expect(out, "out", dt, P * 2 * query.ks * query.ks)
     st = torch.empty((P, 7), dtype=torch.float64, device=out.device) if stats else None
     if chunks is None:
         rc = abi.lib().sdirt_trace_dp_psf(C.byref(L), C.byref(s), C.byref(q),
@@ -168,7 +213,9 @@ def trace_dp_psf_backward(lens, sensor, query, grad_psf, math=abi.F64):
     L, keep = make_lens(lens)
     s = make_sensor(sensor)
     q, keep2 = make_query(query, math)
+    P = q.n_fields * q.n_depths * q.n_wavelengths
     g = grad_psf.contiguous().float()
+    _expect(g, "grad_psf", torch.float32, P * 2 * query.ks * query.ks)
     n = abi.lib().sdirt_n_params(C.byref(L))
     out = torch.empty((n,), dtype=torch.float64, device=g.device)
     rc = abi.lib().sdirt_trace_dp_psf_backward(C.byref(L), C.byref(s), C.byref(q),
@@ -210,23 +257,25 @@ def make_render_desc(N, C_, H, W, ks, source=abi.SRC_DENSE, psf_channels=None,
 
 def render_dp(desc, img, psf, depth=None, out=None):
     """out [N][2C][H][W] float32."""
-    assert img.is_cuda and img.dtype == torch.float32
+    img = img.contiguous()
     if out is None:
         out = torch.empty((desc.N, 2 * desc.C, desc.H, desc.W), dtype=torch.float32,
                           device=img.device)
-    rc = abi.lib().sdirt_render_dp(C.byref(desc), _dptr(img.contiguous()),
+    _check_render(desc, psf=psf, depth=depth, img=img, out=out)
+    rc = abi.lib().sdirt_render_dp(C.byref(desc), _dptr(img),
                                    _dptr(psf), _dptr(depth), _dptr(out), _stream())
     abi.check("sdirt_render_dp", rc)
     return out
 
 
 def render_dp_backward(desc, psf, grad_out, depth=None, grad_img=None):
+    grad_out = grad_out.contiguous()
     if grad_img is None:
         grad_img = torch.empty((desc.N, desc.C, desc.H, desc.W), dtype=torch.float32,
                                device=grad_out.device)
+    _check_render(desc, psf=psf, depth=depth, grad_out=grad_out, grad_img=grad_img)
     rc = abi.lib().sdirt_render_dp_backward(C.byref(desc), _dptr(psf), _dptr(depth),
-                                            _dptr(grad_out.contiguous()),
-                                            _dptr(grad_img), _stream())
+                                            _dptr(grad_out), _dptr(grad_img), _stream())
     abi.check("sdirt_render_dp_backward", rc)
     return grad_img
 
@@ -237,7 +286,8 @@ def render_dp_psf_backward(desc, img, grad_out, depth=None, grad_psf=None):
     """Gradient of the render with respect to its kernels: the dense map
     [N][H][W][Cp][2][ks][ks] (the descriptor's kernel dtype) or the bank in
     its own layout (float32; depth required)."""
-    assert img.is_cuda and img.dtype == torch.float32
+    img = img.contiguous()
+    grad_out = grad_out.contiguous()
     if grad_psf is None:
         ks = desc.ks
         if desc.source == abi.SRC_DENSE:
@@ -251,10 +301,9 @@ def render_dp_psf_backward(desc, img, grad_out, depth=None, grad_psf=None):
             dt = torch.float32
             shape = (desc.bank_fields, desc.bank_depths, desc.bank_lambdas, 2, ks, ks)
         grad_psf = torch.empty(shape, dtype=dt, device=img.device)
-    rc = abi.lib().sdirt_render_dp_psf_backward(C.byref(desc), _dptr(img.contiguous()),
-                                                _dptr(depth),
-                                                _dptr(grad_out.contiguous()), _dptr(grad_psf),
-                                                _stream())
+    _check_render(desc, depth=depth, img=img, grad_out=grad_out, grad_psf=grad_psf)
+    rc = abi.lib().sdirt_render_dp_psf_backward(C.byref(desc), _dptr(img), _dptr(depth),
+                                                _dptr(grad_out), _dptr(grad_psf), _stream())
     abi.check("sdirt_render_dp_psf_backward", rc)
     return grad_psf
 
@@ -284,12 +333,26 @@ def mlp_workspace(desc, batch, device="cuda"):
     return torch.empty((n.value,), dtype=torch.uint8, device=device)
 
 
+def _check_mlp(desc, params, workspace=None, ws_batch=None):
+    _expect(params, "params", torch.float32, mlp_n_params(desc))
+    if workspace is not None:
+        n = C.c_size_t()
+        abi.check("sdirt_mlp_workspace_size",
+                  abi.lib().sdirt_mlp_workspace_size(C.byref(desc), int(ws_batch), C.byref(n)))
+        if workspace.numel() * workspace.element_size() < n.value or not workspace.is_cuda:
+            raise ValueError("workspace must be a device buffer of at least %d bytes" % n.value)
+
+
 def mlp_forward(desc, params, x, workspace, ws_batch, out_dtype=abi.F32, out=None):
     n = x.shape[0]
+    x = x.contiguous()
+    dt = torch.bfloat16 if out_dtype == abi.BF16 else torch.float32
     if out is None:
-        dt = torch.bfloat16 if out_dtype == abi.BF16 else torch.float32
         out = torch.empty((n, desc.n_out), dtype=dt, device=x.device)
-    rc = abi.lib().sdirt_mlp_forward(C.byref(desc), _dptr(params), int(n), _dptr(x.contiguous()),
+    _check_mlp(desc, params, workspace, ws_batch)
+    _expect(x, "x", torch.float32, 4 * n)
+    _expect(out, "out", dt, n * desc.n_out)
+    rc = abi.lib().sdirt_mlp_forward(C.byref(desc), _dptr(params), int(n), _dptr(x),
                                      _dptr(out), int(out_dtype), _dptr(workspace),
                                      int(ws_batch), _stream())
     abi.check("sdirt_mlp_forward", rc)
@@ -307,20 +370,30 @@ def mlp_render(desc, params, img, depth, wavelengths, pitch, workspace, ws_batch
     rd = abi.MlpRenderDesc(N, C_, H, W, ks, float(pitch))
     for c, lam in enumerate(wavelengths):
         rd.wavelength[c] = float(lam)
+    img = img.contiguous()
+    depth = depth.contiguous()
     if out is None:
         out = torch.empty((N, 2 * C_, H, W), dtype=torch.float32, device=img.device)
+    _check_mlp(desc, params, workspace, ws_batch)
+    _expect(out, "out", torch.float32, N * 2 * C_ * H * W)
     rc = abi.lib().sdirt_mlp_render(C.byref(desc), _dptr(params), C.byref(rd),
-                                    _dptr(img.contiguous()), _dptr(depth.contiguous()),
+                                    _dptr(img), _dptr(depth),
                                     _dptr(out), _dptr(workspace), int(ws_batch), _stream())
     abi.check("sdirt_mlp_render", rc)
     return out
 
 
 def mlp_backward(desc, params, x, target, workspace):
+    B = int(x.shape[0])
+    x = x.contiguous()
+    target = target.contiguous()
+    _check_mlp(desc, params, workspace, B)
+    _expect(x, "x", torch.float32, 4 * B)
+    _expect(target, "target", torch.float32, B * desc.n_out)
     grads = torch.empty_like(params)
     loss = torch.empty((1,), dtype=torch.float32, device=params.device)
-    rc = abi.lib().sdirt_mlp_backward(C.byref(desc), _dptr(params), int(x.shape[0]),
-                                      _dptr(x.contiguous()), _dptr(target.contiguous()),
+    rc = abi.lib().sdirt_mlp_backward(C.byref(desc), _dptr(params), B,
+                                      _dptr(x), _dptr(target),
                                       _dptr(grads), _dptr(loss), _dptr(workspace), _stream())
     abi.check("sdirt_mlp_backward", rc)
     return grads, loss
@@ -329,27 +402,57 @@ def mlp_backward(desc, params, x, target, workspace):
 def mlp_vjp(desc, params, x, grad_psf, workspace, ws_batch):
     """Gradient of sum_rows <grad_psf, P(x)> with respect to the parameters
     (float32 [n_params]) and that sum ([1])."""
-    assert x.dtype == torch.float32 and grad_psf.dtype == torch.float32
     n = int(x.shape[0])
-    assert grad_psf.shape[0] == n and grad_psf.numel() == n * desc.n_out
+    x = x.contiguous()
+    grad_psf = grad_psf.contiguous()
+    _check_mlp(desc, params, workspace, ws_batch)
+    _expect(x, "x", torch.float32, 4 * n)
+    _expect(grad_psf, "grad_psf", torch.float32, n * desc.n_out)
     grads = torch.empty_like(params)
     value = torch.empty((1,), dtype=torch.float32, device=params.device)
-    rc = abi.lib().sdirt_mlp_vjp(C.byref(desc), _dptr(params), n, _dptr(x.contiguous()),
-                                 _dptr(grad_psf.contiguous()), _dptr(grads), _dptr(value),
+    rc = abi.lib().sdirt_mlp_vjp(C.byref(desc), _dptr(params), n, _dptr(x),
+                                 _dptr(grad_psf), _dptr(grads), _dptr(value),
                                  _dptr(workspace), int(ws_batch), _stream())
     abi.check("sdirt_mlp_vjp", rc)
     return grads, value
 
 
 def mlp_adam(desc, params, m, v, grads, step, lr):
+    n = mlp_n_params(desc)
+    for t, name in ((params, "params"), (m, "m"), (v, "v"), (grads, "grads")):
+        _expect(t, name, torch.float32, n)
     rc = abi.lib().sdirt_mlp_adam(C.byref(desc), _dptr(params), _dptr(m), _dptr(v),
                                   _dptr(grads), int(step), float(lr), _stream())
     abi.check("sdirt_mlp_adam", rc)
 
 
+def mlp_train_step(desc, params, m, v, x, target, workspace, step, lr, loss_out=None):
+    """One step on the batch (x, target): forward, loss gradient and the Adam
+    update of step `step` (from 1); params, m and v are updated in place."""
+    B = int(x.shape[0])
+    n = mlp_n_params(desc)
+    for t, name in ((params, "params"), (m, "m"), (v, "v")):
+        _expect(t, name, torch.float32, n)
+    _check_mlp(desc, params, workspace, B)
+    _expect(x, "x", torch.float32, 4 * B)
+    _expect(target, "target", torch.float32, B * desc.n_out)
+    _expect(loss_out, "loss_out", torch.float32, 1, required=False)
+    rc = abi.lib().sdirt_mlp_train_step(C.byref(desc), _dptr(params), _dptr(m), _dptr(v),
+                                        int(step), float(lr), B, _dptr(x), _dptr(target),
+                                        _dptr(loss_out), _dptr(workspace), _stream())
+    abi.check("sdirt_mlp_train_step", rc)
+
+
 def mlp_train(desc, params, m, v, x_all, t_all, workspace, batch, step0, n_steps,
               lr0=1e-3, lr_min=1e-5, total_steps=None, seed=1, loss_trace=None):
     total = int(total_steps if total_steps is not None else step0 + n_steps)
+    n = mlp_n_params(desc)
+    for t, name in ((params, "params"), (m, "m"), (v, "v")):
+        _expect(t, name, torch.float32, n)
+    _check_mlp(desc, params, workspace, batch)
+    _expect(x_all, "x_all", torch.float32, 4 * int(x_all.shape[0]))
+    _expect(t_all, "t_all", torch.float32, int(x_all.shape[0]) * desc.n_out)
+    _expect(loss_trace, "loss_trace", torch.float32, int(n_steps), required=False)
     rc = abi.lib().sdirt_mlp_train(C.byref(desc), _dptr(params), _dptr(m), _dptr(v),
                                    int(step0), int(n_steps), float(lr0), float(lr_min), total,
                                    int(batch), int(x_all.shape[0]), _dptr(x_all), _dptr(t_all),
@@ -360,14 +463,16 @@ def mlp_train(desc, params, m, v, x_all, t_all, workspace, batch, step0, n_steps
 
 # ---- trainer checkpoints ------------------------------------------------------
 
-def mlp_save_checkpoint(path, desc, params, m, v, step, seed, total_steps):
+def mlp_save_checkpoint(path, desc, params, m, v, step, seed, total_steps, lr0, lr_min, batch):
     """Trainer state to a safetensors file: the float32 master parameters and
-    Adam moments, and as metadata the next step, the data seed, the schedule
-    length and the network description.  sdirt_mlp_train draws its batches
-    by a counter hash of (seed, step, row) and sets the learning rate from
-    the step, so this is all a resumed run needs."""
+    Adam moments, and as metadata the next step, the data seed, the learning
+    rate schedule (lr0, lr_min, total_steps), the batch size and the network
+    description.  sdirt_mlp_train draws its batches by a counter hash of
+    (seed, step, row) and sets the learning rate from the step and the
+    schedule, so with these a resumed run continues the interrupted one."""
     from safetensors.torch import save_file
     meta = {"step": str(int(step)), "seed": str(int(seed)), "total_steps": str(int(total_steps)),
+            "lr0": repr(float(lr0)), "lr_min": repr(float(lr_min)), "batch": str(int(batch)),
             "desc": json.dumps({n: getattr(desc, n) for n, _ in desc._fields_})}
     save_file({"params": params.detach().float().cpu().contiguous(),
                "m": m.detach().float().cpu().contiguous(),
@@ -375,7 +480,8 @@ def mlp_save_checkpoint(path, desc, params, m, v, step, seed, total_steps):
 
 
 def mlp_load_checkpoint(path, device="cuda"):
-    """(desc, params, m, v, step, seed, total_steps) from mlp_save_checkpoint."""
+    """(desc, params, m, v, step, seed, total_steps, schedule) from
+    mlp_save_checkpoint; schedule = {"lr0", "lr_min", "batch"}."""
     from safetensors import safe_open
     with safe_open(path, framework="pt") as f:
         meta = f.metadata()
@@ -384,5 +490,7 @@ def mlp_load_checkpoint(path, device="cuda"):
     desc = abi.MlpDesc()
     for n, _ in abi.MlpDesc._fields_:
         setattr(desc, n, dd[n])
+    schedule = {"lr0": float(meta["lr0"]), "lr_min": float(meta["lr_min"]),
+                "batch": int(meta["batch"])}
     return (desc, t["params"], t["m"], t["v"], int(meta["step"]), int(meta["seed"]),
-            int(meta["total_steps"]))
+            int(meta["total_steps"]), schedule)

@@ -32,6 +32,25 @@ def test_library_exports_every_declared_symbol():
     assert lib.sdirt_status_string(abi.EINVAL) == b"invalid argument"
 
 
+def exported_symbols():
+    """sdirt_* functions the built library exports (its dynamic symbol table)."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", abi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    return sorted({ln.split()[-1] for ln in out.splitlines()
+                   if len(ln.split()) == 3 and ln.split()[1] == "T" and
+                   ln.split()[-1].startswith("sdirt_")})
+
+
+def test_library_exports_only_declared_symbols():
+    # the header is the whole boundary: nothing callable that it does not declare
+    exported = exported_symbols()
+    declared = set(declared_symbols())
+    assert len(exported) >= 10
+    assert [n for n in exported if n not in declared] == []
+    assert set(abi.SIGNATURES) == declared
+
+
 def _lenses():
     L1 = lenses.rf50(); L1.f_number = 4.0; L1.focus_depth = 1000.0
     return [lenses.singlet(), L1, configs.config2_lens(), lenses.rf35(),
@@ -213,9 +232,11 @@ def test_trainer_checkpoint_round_trip(tmp_path):
     g = torch.Generator().manual_seed(0)
     p, m, v = (torch.randn(n, generator=g) for _ in range(3))
     path = str(tmp_path / "trainer.safetensors")
-    sdirt.mlp_save_checkpoint(path, d, p, m, v, step=1234, seed=77, total_steps=5000)
-    d2, p2, m2, v2, step, seed, total = sdirt.mlp_load_checkpoint(path, device="cpu")
+    sdirt.mlp_save_checkpoint(path, d, p, m, v, step=1234, seed=77, total_steps=5000,
+                              lr0=1.5e-3, lr_min=2.5e-5, batch=1024)
+    d2, p2, m2, v2, step, seed, total, sched = sdirt.mlp_load_checkpoint(path, device="cpu")
     assert torch.equal(p, p2) and torch.equal(m, m2) and torch.equal(v, v2)
     assert (step, seed, total) == (1234, 77, 5000)
+    assert sched == {"lr0": 1.5e-3, "lr_min": 2.5e-5, "batch": 1024}
     for name, _ in abi.MlpDesc._fields_:
         assert getattr(d2, name) == getattr(d, name), name

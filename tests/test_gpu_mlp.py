@@ -7,16 +7,18 @@ import torch
 from workloads import scenes
 from oracle import mlp as M
 from paper_2503_11213_amd import sdirt, _abi as abi
-from vjp_bars import vjp_bars, compare_flat
+from vjp_bars import vjp_reference, clustered_inputs, compare_flat
 
 pytestmark = pytest.mark.gpu
 
 NORM = dict(x_half=4.5024, y_half=3.0016, iv_lo=1 / 5000, iv_hi=1 / 500, lam_lo=0.486,
             lam_hi=0.656)
 REL = 1e-2
-# the surrogate render averages the image under each PSF, which damps the
-# PSFs' own bf16-level differences (measured: 1e-4 .. 6e-4)
-REL_RENDER = 3e-3
+# Surrogate render, per output pixel: |out - ref| / max(|ref|, 1e-3) against
+# the bf16 mirror's composition.  A rendered pixel is an average of the image
+# under the pixel's PSF, so a bf16-level change of a few PSF elements (see
+# ELT below) moves it by much less than their own 2^-8; 3e-3 bounds it.
+RENDER_ELT = 3e-3
 
 
 def _desc(n_out=2 * 33 * 33, width=256, n_hidden=5, loss=abi.LOSS_L2MAX):
@@ -65,10 +67,13 @@ def test_forward_matches_bf16_mirror(B, ws):
     p = p.cpu().numpy()
     ref, _ = M.forward(_oracle_params(layers), x.astype(np.float64), NORM, bf16=True)
     assert np.allclose(p.sum(axis=1), 1.0, atol=1e-4)
-    assert _rel_l2(p, ref) <= REL
+    print("forward f32 out: max elementwise %.2e, rel L2 %.2e" % (_elementwise(p, ref),
+                                                                  _rel_l2(p, ref)))
+    assert _elementwise(p, ref) <= ELT
     pb = sdirt.mlp_forward(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(), ws_t,
                            ws, out_dtype=abi.BF16).float().cpu().numpy()
-    assert _rel_l2(pb, ref) <= REL
+    print("forward bf16 out: max elementwise %.2e" % _elementwise(pb, ref))
+    assert _elementwise(pb, ref) <= ELT
 
 
 @pytest.mark.parametrize("loss", ["l2max", "kl"])
@@ -99,27 +104,24 @@ def test_gradients_match_bf16_mirror(loss):
     assert off == g.size
 
 
-@pytest.mark.parametrize("n,ws,coherent", [(200, 128, True), (64, 4096, False)])
-def test_vjp_matches_bf16_mirror(n, ws, coherent):
-    # gradient of sum_rows <g, P(x)> for an upstream gradient g: rows that
-    # share most of g (well conditioned), and independent rows (the sums
-    # over rows cancel)
+@pytest.mark.parametrize("n,ws,spread", [(200, 128, 0.02), (256, 4096, 0.05)])
+def test_vjp_matches_bf16_mirror(n, ws, spread):
+    # gradient of sum_rows <g, P(x)> for inputs near one point and an upstream
+    # gradient shared by the rows up to 20 % (sums over rows that add up; the
+    # independent-row case is the chunk test below)
     widths = [64, 256, 256, 256, 256, 256, 2178]
     layers, flat = _params(widths, 8)
-    x = _inputs(n, 9)
+    x = clustered_inputs(n, 9, spread=spread)
     rng = np.random.default_rng(10)
-    g = rng.normal(size=(n, 2178))
-    if coherent:
-        g = rng.normal(size=(1, 2178)) + 0.2 * g
-    g = g.astype(np.float32)
+    g = (rng.normal(size=(1, 2178)) + 0.2 * rng.normal(size=(n, 2178))).astype(np.float32)
     d = _desc()
     ws_t = sdirt.mlp_workspace(d, ws)
     grads, val = sdirt.mlp_vjp(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(),
                                torch.from_numpy(g).cuda(), ws_t, ws)
     g64 = g.astype(np.float64)
-    p, ref, bars = vjp_bars(_oracle_params(layers), x.astype(np.float64), g64, NORM)
+    p, ref = vjp_reference(_oracle_params(layers), x.astype(np.float64), g64, NORM)
     assert abs(val.item() - M.loss(p, g64, kind="vjp")) <= 1e-3 * np.abs(p * g64).sum()
-    compare_flat(grads.cpu().numpy(), layers, ref, bars)
+    compare_flat(grads.cpu().numpy(), layers, ref)
 
 
 def test_vjp_chunks_add_up():
@@ -235,23 +237,30 @@ def test_training_resumes_from_a_checkpoint(tmp_path):
         p = torch.from_numpy(flat).cuda()
         return p, torch.zeros_like(p), torch.zeros_like(p)
 
+    # a schedule other than the trainer's defaults, which the resumed run
+    # must take from the checkpoint
+    lr0, lr_min = 2e-3, 3e-5
     runs = []
     for _ in range(2):
         p, m, v = fresh()
         tr = torch.zeros((steps,), device="cuda")
-        sdirt.mlp_train(d, p, m, v, x, t, ws_t, B, 0, steps, total_steps=steps, seed=5,
-                        loss_trace=tr)
+        sdirt.mlp_train(d, p, m, v, x, t, ws_t, B, 0, steps, lr0=lr0, lr_min=lr_min,
+                        total_steps=steps, seed=5, loss_trace=tr)
         runs.append((p.cpu(), m.cpu(), v.cpu(), tr.cpu()))
     p, m, v = fresh()
     tr1 = torch.zeros((steps // 2,), device="cuda")
-    sdirt.mlp_train(d, p, m, v, x, t, ws_t, B, 0, steps // 2, total_steps=steps, seed=5,
-                    loss_trace=tr1)
+    sdirt.mlp_train(d, p, m, v, x, t, ws_t, B, 0, steps // 2, lr0=lr0, lr_min=lr_min,
+                    total_steps=steps, seed=5, loss_trace=tr1)
     path = str(tmp_path / "trainer.safetensors")
-    sdirt.mlp_save_checkpoint(path, d, p, m, v, step=steps // 2, seed=5, total_steps=steps)
+    sdirt.mlp_save_checkpoint(path, d, p, m, v, step=steps // 2, seed=5, total_steps=steps,
+                              lr0=lr0, lr_min=lr_min, batch=B)
     del p, m, v
-    d2, p, m, v, step, seed, total = sdirt.mlp_load_checkpoint(path)
+    d2, p, m, v, step, seed, total, sched = sdirt.mlp_load_checkpoint(path)
+    assert sched == {"lr0": lr0, "lr_min": lr_min, "batch": B}
+    B2 = sched["batch"]
     tr2 = torch.zeros((steps - step,), device="cuda")
-    sdirt.mlp_train(d2, p, m, v, x, t, ws_t, B, step, steps - step, total_steps=total, seed=seed,
+    sdirt.mlp_train(d2, p, m, v, x, t, sdirt.mlp_workspace(d2, B2), B2, step, steps - step,
+                    lr0=sched["lr0"], lr_min=sched["lr_min"], total_steps=total, seed=seed,
                     loss_trace=tr2)
     ref, ref_m, ref_v, ref_tr = runs[0]
     assert all(torch.equal(a, b) for a, b in zip(runs[0][:3], runs[1][:3]))
@@ -280,7 +289,7 @@ def test_fused_forward_output_widths(n_out):
     for dt in (abi.F32, abi.BF16):
         p = sdirt.mlp_forward(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(), ws_t,
                               64, out_dtype=dt).float().cpu().numpy()
-        assert _rel_l2(p, ref) <= REL
+        assert _elementwise(p, ref) <= ELT
         assert np.allclose(p.sum(axis=1), 1.0, atol=2e-2 if dt == abi.BF16 else 1e-4)
 
 
@@ -304,9 +313,9 @@ def test_inference_full_size_sampled_rows():
     rows = np.concatenate([[0, chunk - 1, chunk, n - 1], rng.integers(0, n, 60)])
     got = ob[torch.from_numpy(rows).cuda()].float().cpu().numpy()
     ref, _ = M.forward(_oracle_params(layers), x[rows].astype(np.float64), norm, bf16=True)
-    err = _rel_l2(got, ref)
-    print("full-size inference rel L2", err)
-    assert err <= REL
+    err = _elementwise(got, ref)
+    print("full-size inference max elementwise", err, "rel L2", _rel_l2(got, ref))
+    assert err <= ELT
 
 
 @pytest.mark.parametrize("ks,N,C,H,W,ws", [(9, 2, 3, 20, 27, 128), (33, 1, 3, 18, 21, 4096),
@@ -327,9 +336,9 @@ def test_surrogate_render_matches_oracle(ks, N, C, H, W, ws):
                            torch.from_numpy(depth).cuda(), lams, pitch, ws_t, ws)
     got = out.cpu().numpy()
     ref = M.render_surrogate(_oracle_params(layers), img, depth, lams, pitch, NORM, bf16=True)
-    err = _rel_l2(got, ref)
-    print("surrogate render rel L2", err)
-    assert err <= REL_RENDER
+    err = float((np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3)).max())
+    print("surrogate render max per-pixel rel err", err, "rel L2", _rel_l2(got, ref))
+    assert err <= RENDER_ELT
     # the two sides together average the window: totals match the box filter
     # of a constant image exactly
     one = torch.ones((N, C, H, W), device="cuda")
@@ -371,6 +380,93 @@ def test_surrogate_render_full_size_sampled_pixels(chunk):
             ref.append([(K[s] * win).sum() for s in range(2)])
             got.append([out[0, c, y, xx], out[0, C + c, y, xx]])
     got, ref = np.array(got), np.array(ref)
-    err = _rel_l2(got, ref)
-    print("full-size surrogate render rel L2", err)
-    assert err <= REL_RENDER
+    err = float((np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3)).max())
+    print("full-size surrogate render max per-pixel rel err", err, "rel L2", _rel_l2(got, ref))
+    assert err <= RENDER_ELT
+
+
+# ---- softmax reference raises (large logit spreads) -----------------------
+# The fused heads keep a per-row running reference for the softmax that is
+# raised whenever a logit passes it; with the He-initialised weights above a
+# row's logits spread over about 10 log2 units and the reference rises once.
+# These networks shift the output layer's biases so that the row maxima sit
+# in later tiles and in tiles of other waves, with spreads of 80-115 log2
+# units, so the reference is raised again and again.  (Scaling the output
+# weights up instead would scale the logits' bf16-level differences with
+# them, and test the bar rather than the raises.)
+#
+# Per-element bar against the bf16 mirror: the kernels and the mirror round
+# the same operands to bf16; they differ only where a float32 sum lands on
+# the other side of a bf16 rounding boundary than the float64 sum (one
+# element moves by 2^-8 of itself), plus, for bf16 outputs, the output's own
+# rounding (2^-9).  A logit moved by d changes its probability by the factor
+# exp(d); the bar allows 2^-5 of the row's largest probability per element.
+ELT = 2.0 ** -5
+
+
+def _shaped_layers(widths, seed, kind):
+    layers = scenes.mlp_init(widths, seed)
+    W, b = layers[-1]
+    n = W.shape[0]
+    if kind == "ramp":            # rising bias: maxima in the last tiles, 110 log2 units
+        b = b + np.linspace(0.0, 110.0 / np.log2(np.e), n)
+    elif kind == "peaks":         # four competing outputs in tiles of three waves;
+        b = b - 50.0              # the row decides which wins (~80 log2 units)
+        for t in (2, 11, 20, (n - 1) // 64):
+            b[min(64 * t + 5, n - 1)] += 50.0
+    elif kind == "late_tile":     # only the last 64-output tile is competitive
+        b = b - 60.0
+        b[64 * ((n - 1) // 64):] += 60.0
+    layers[-1] = (W.astype(np.float32), b.astype(np.float32))
+    flat = np.concatenate([np.concatenate([Wm.ravel(), bb]) for Wm, bb in layers]).astype(np.float32)
+    return layers, flat
+
+
+def _elementwise(got, ref):
+    """max |got - ref| over each row, relative to the row's largest ref."""
+    return float(np.max(np.abs(got - ref).max(axis=1) / ref.max(axis=1)))
+
+
+@pytest.mark.parametrize("kind", ["ramp", "peaks", "late_tile"])
+def test_inference_head_softmax_raises(kind):
+    widths = [64, 256, 256, 256, 256, 256, 2178]
+    layers, flat = _shaped_layers(widths, 40, kind)
+    x = _inputs(192, 41)
+    d = _desc()
+    ws_t = sdirt.mlp_workspace(d, 128)
+    ref, cache = M.forward(_oracle_params(layers), x.astype(np.float64), NORM, bf16=True)
+    z = cache[-1][1] * np.log2(np.e)
+    spread = float(np.median(z.max(axis=1) - z.min(axis=1)))
+    print(kind, "median logit spread (log2 units) %.1f" % spread)
+    assert spread > 64
+    for dt in (abi.F32, abi.BF16):
+        p = sdirt.mlp_forward(d, torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda(), ws_t,
+                              128, out_dtype=dt).float().cpu().numpy()
+        e = _elementwise(p, ref)
+        print(kind, "bf16 out" if dt == abi.BF16 else "f32 out", "max elementwise %.2e" % e,
+              "rel L2 %.2e" % _rel_l2(p, ref))
+        assert e <= ELT
+        assert np.allclose(p.sum(axis=1), 1.0, atol=2e-2 if dt == abi.BF16 else 1e-4)
+
+
+@pytest.mark.parametrize("kind", ["ramp", "peaks", "late_tile"])
+def test_render_head_softmax_raises(kind):
+    ks, N, C, H, W, ws = 33, 1, 3, 12, 17, 128
+    widths = [64, 256, 256, 256, 256, 256, 2 * ks * ks]
+    layers, flat = _shaped_layers(widths, 42, kind)
+    rng = np.random.default_rng(43)
+    img = rng.uniform(0, 1, (N, C, H, W)).astype(np.float32)
+    depth = rng.uniform(500, 5000, (N, H, W)).astype(np.float32)
+    lams = [0.656, 0.55, 0.486]
+    pitch = 0.3
+    d = _desc(n_out=2 * ks * ks)
+    out = sdirt.mlp_render(d, torch.from_numpy(flat).cuda(), torch.from_numpy(img).cuda(),
+                           torch.from_numpy(depth).cuda(), lams, pitch,
+                           sdirt.mlp_workspace(d, ws), ws).cpu().numpy()
+    ref = M.render_surrogate(_oracle_params(layers), img, depth, lams, pitch, NORM, bf16=True)
+    # these PSFs concentrate on a few taps, so a rendered pixel carries the
+    # bf16-level error of its largest PSF elements instead of averaging it
+    # out: the per-element PSF bar applies per pixel
+    err = float((np.abs(out - ref) / np.maximum(np.abs(ref), 1e-3)).max())
+    print(kind, "render max per-pixel rel err %.2e" % err)
+    assert err <= ELT

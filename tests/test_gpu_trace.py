@@ -330,3 +330,16 @@ def test_deterministic_mode(splat):
     n1, _ = sdirt.trace_dp_psf(lens, sensor, q3)
     n2, _ = sdirt.trace_dp_psf(lens, sensor, q3)
     assert torch.equal(n1, n2)
+
+
+@pytest.mark.parametrize("name", ["clip", "tir", "miss", "conic", "invalid", "first_failure"])
+def test_failure_status_at_its_closed_form_boundary(name):
+    # the status codes of rays just inside / outside each failure condition,
+    # against the answer the case's geometry fixes (pinned on the oracle too)
+    from workloads import status_cases as sc
+    L, o, d, expect = sc.CASES[name]()
+    print("status case", name, flush=True)
+    hits, status = sdirt.trace_rays(L, 0.55, torch.from_numpy(o).cuda(),
+                                    torch.from_numpy(d).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(status.cpu().numpy(), expect), (status.cpu().numpy(), expect)

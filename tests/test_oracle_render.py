@@ -219,3 +219,27 @@ def test_bank_gradients_satisfy_the_adjoint_identity():
     gB2 = R.render_bank2d_psf_adjoint(img, g, B2.shape, depth, xs, ys, iv, loc, 0.01)
     lhs = np.sum(R.render_bank2d(img, B2, depth, xs, ys, iv, loc, 0.01) * g)
     assert lhs == pytest.approx(np.sum(B2 * gB2), rel=1e-12)
+
+
+@pytest.mark.parametrize("H,W", [(9, 12), (10, 11)])
+def test_bank_pixels_equal_the_bank_render_everywhere(H, W):
+    # the per-pixel evaluation used for sampled full-size parity is the bank
+    # render itself: every pixel of images with an exact centre row (H odd)
+    # or centre column (W odd), all four quadrants and all borders
+    N, C, ks, ps = 2, 2, 5, 0.01
+    rng = np.random.default_rng(31)
+    img = rng.uniform(0, 1, (N, C, H, W))
+    bank = rng.uniform(0, 1, (4, 3, 2, 2, ks, ks))
+    radii = [0.0, 0.02, 0.04, 0.06]
+    iv = [1 / 5000.0, 1 / 2000.0, 1 / 500.0]
+    dmap = rng.uniform(500, 5000, (N, H, W)).astype(np.float32)
+    loc = [1, 0]
+    full = R.render_bank(img, bank, dmap, radii, iv, loc, ps)
+    pix = [(n, y, x) for n in range(N) for y in range(H) for x in range(W)]
+    got = R.render_bank_pixels(img, bank, dmap, radii, iv, loc, ps, pix)
+    ref = np.stack([full[n, :, y, x] for (n, y, x) in pix])
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    # the lookup reaches every mirror combination in these images
+    fi, di, mx, my = R.bank_lookup(H, W, dmap[0], radii, iv, ps)
+    assert {(a, b) for a, b in zip(mx.ravel(), my.ravel())} == {(False, False), (False, True),
+                                                                (True, False), (True, True)}
