@@ -49,6 +49,7 @@ extern "C" {
 #define SDIRT_EUNSUPPORTED   -2   /* valid but unsupported mode/dtype/size */
 #define SDIRT_ELAUNCH        -3   /* a HIP launch or runtime call failed   */
 #define SDIRT_ENODEVICE      -4   /* no HIP device available               */
+#define SDIRT_ESCRATCH       -5   /* needs more than the static scratch    */
 
 /* ---- limits ----------------------------------------------------------- */
 #define SDIRT_MAX_SURFACES    24  /* rows of the prescription incl. stop   */
@@ -337,6 +338,28 @@ int sdirt_mlp_workspace_size(const sdirt_mlp_desc* desc, int batch, size_t* byte
 int sdirt_mlp_forward(const sdirt_mlp_desc* desc, const float* params,
                       long long n_rows, const float* x, void* out, int out_dtype,
                       void* workspace, int ws_batch, void* stream);
+
+/* Allocation-free sdirt_mlp_forward, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same result as sdirt_mlp_forward (the same
+ * kernels; rows are independent, so the chunking does not change any
+ * value), but its working memory (the bf16 weights in fragment order and one
+ * chunk of hidden activations) is a static device array of
+ * SDIRT_NOALLOC_SCRATCH_BYTES inside the library instead of a caller
+ * workspace; the call allocates nothing.  Each device the library runs on
+ * holds its own copy of that array until the process ends.  All calls on one
+ * device share it: calls that overlap on one device (other streams or host
+ * threads) race and must be serialised by the caller.  Only width-256
+ * networks (the fused kernels), SDIRT_EUNSUPPORTED otherwise; a network
+ * whose bf16 weights plus 64 rows of activations exceed the array returns
+ * SDIRT_ESCRATCH (the 5 x 256 network with 2 x 33 x 33 outputs needs
+ * 1.8 MB; rows are processed in chunks of up to 65536).
+ *   x device [n_rows][4] f32, out device [n_rows][n_out] f32 or bf16
+ *   (out_dtype), params device f32 as for sdirt_mlp_forward. */
+#define SDIRT_NOALLOC_SCRATCH_BYTES (16u << 20)
+int sdirt_mlp_forward_noalloc(const sdirt_mlp_desc* desc, const float* params,
+                              long long n_rows, const float* x, void* out, int out_dtype,
+                              void* stream);
 
 /* The surrogate render (Fig. 2(c); Sec. 3.2): every pixel of an image
  * rendered with the PSF the network predicts for it, without the dense PSF

@@ -10,7 +10,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsdirt.so")
 
-OK, EINVAL, EUNSUPPORTED, ELAUNCH, ENODEVICE = 0, -1, -2, -3, -4
+OK, EINVAL, EUNSUPPORTED, ELAUNCH, ENODEVICE, ESCRATCH = 0, -1, -2, -3, -4, -5
+NOALLOC_SCRATCH_BYTES = 16 << 20
 SPHERE, PLANE, STOP, ASPHERE, IDEAL = 0, 1, 2, 3, 4
 MAT_CAUCHY, MAT_ABBE = 0, 1
 DP_SIGMOID, DP_MICROLENS = 0, 1
@@ -121,6 +122,8 @@ SIGNATURES = {
     "sdirt_mlp_forward": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_longlong,
                                     C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                                     C.c_int, C.c_void_p]),
+    "sdirt_mlp_forward_noalloc": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_longlong,
+                                            C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "sdirt_mlp_render": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.POINTER(MlpRenderDesc),
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                    C.c_void_p]),

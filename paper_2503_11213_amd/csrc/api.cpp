@@ -30,6 +30,8 @@ int mlp_forward(const sdirt_mlp_desc*, const float*, long long, const float*, vo
                 void*, int, hipStream_t);
 int mlp_render(const sdirt_mlp_desc*, const float*, const sdirt_mlp_render_desc*, const float*,
                const float*, float*, void*, int, hipStream_t);
+int mlp_forward_noalloc(const sdirt_mlp_desc*, const float*, long long, const float*, void*, int,
+                        hipStream_t);
 int mlp_backward(const sdirt_mlp_desc*, const float*, int, const float*, const float*,
                  float*, float*, void*, hipStream_t);
 int mlp_vjp(const sdirt_mlp_desc*, const float*, long long, const float*, const float*,
@@ -65,6 +67,7 @@ const char* sdirt_status_string(int status) {
         case SDIRT_EUNSUPPORTED: return "unsupported mode, dtype or size";
         case SDIRT_ELAUNCH: return "HIP launch or runtime failure";
         case SDIRT_ENODEVICE: return "no HIP device";
+        case SDIRT_ESCRATCH: return "needs more memory than the library's static scratch array";
         default: return "unknown status";
     }
 }
@@ -170,6 +173,13 @@ int sdirt_mlp_forward(const sdirt_mlp_desc* desc, const float* params, long long
     Range r("sdirt_mlp_forward");
     return mlp_forward(desc, params, n_rows, x, out, out_dtype, workspace, ws_batch,
                        (hipStream_t)stream);
+}
+
+int sdirt_mlp_forward_noalloc(const sdirt_mlp_desc* desc, const float* params,
+                              long long n_rows, const float* x, void* out, int out_dtype,
+                              void* stream) {
+    Range r("sdirt_mlp_forward_noalloc");
+    return mlp_forward_noalloc(desc, params, n_rows, x, out, out_dtype, (hipStream_t)stream);
 }
 
 int sdirt_mlp_render(const sdirt_mlp_desc* desc, const float* params,

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/sdirt.h"
@@ -689,6 +690,67 @@ int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, 
         hipLaunchKernelGGL(softmax_loss_kernel, dim3(B), dim3(256), 0, st, s);
     }
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
+}
+
+// ---- allocation-free inference ----------------------------------------------
+// The fused inference above with its working memory (the fragment-ordered
+// weights and one chunk of last hidden activations) in a static device array
+// instead of a caller workspace, for callers that cannot allocate device
+// memory.  Each device holds its own copy of the array for the life of the
+// process; its device address is looked up once per device, with that device
+// current, and only that address is handed to kernels.  Nothing in it needs
+// clearing: every call rewrites the weights (padding included) and each
+// chunk's activations before reading them.  Calls that overlap on one
+// device (other streams, other host threads) share the array and race.
+constexpr size_t kNoAllocBytes = (size_t)SDIRT_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+static int scratch_address(void** addr) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SDIRT_ENODEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return SDIRT_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return SDIRT_ELAUNCH;
+        g_scratch_addr[dev] = p;
+    }
+    *addr = g_scratch_addr[dev];
+    return SDIRT_OK;
+}
+
+int mlp_forward_noalloc(const sdirt_mlp_desc* d, const float* params, long long n_rows,
+                        const float* x, void* out, int out_dtype, hipStream_t st) {
+    MlpDims m;
+    int rc = dims_of(d, &m);
+    if (rc) return rc;
+    if (!params || !x || !out || n_rows < 0) return SDIRT_EINVAL;
+    if (out_dtype != SDIRT_F32 && out_dtype != SDIRT_BF16) return SDIRT_EUNSUPPORTED;
+    if (m.width != 256) return SDIRT_EUNSUPPORTED;
+    // layout: the layers' fragment-ordered weights, then the chunk buffer
+    const int fp = feat_pad(m);
+    size_t wf_off[17], off = 0;
+    for (int l = 0; l < m.L; ++l) {
+        const int in_pad = l == 0 ? fp : m.width;
+        wf_off[l] = off;
+        off += align256((size_t)((m.out_of(l) + 63) / 64) * 64 * in_pad * 2);
+    }
+    const size_t row_bytes = (size_t)m.width * sizeof(bf16_t);   // one row of hbuf
+    if (off + 64 * row_bytes > kNoAllocBytes) return SDIRT_ESCRATCH;
+    const long long chunk =
+        std::min<long long>(65536, (long long)((kNoAllocBytes - off) / row_bytes) / 64 * 64);
+    void* base = nullptr;
+    if ((rc = scratch_address(&base))) return rc;
+    MlpWs w;
+    std::memset(&w, 0, sizeof(w));
+    for (int l = 0; l < m.L; ++l) w.WF[l] = (bf16_t*)((char*)base + wf_off[l]);
+    bf16_t* hbuf = (bf16_t*)((char*)base + off);
+    return forward_fused(m, d, w, hbuf, chunk, params, n_rows, x, out, out_dtype, st);
 }
 
 int mlp_render(const sdirt_mlp_desc* d, const float* params, const sdirt_mlp_render_desc* rd,

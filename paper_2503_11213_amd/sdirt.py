@@ -359,6 +359,24 @@ def mlp_forward(desc, params, x, workspace, ws_batch, out_dtype=abi.F32, out=Non
     return out
 
 
+def mlp_forward_noalloc(desc, params, x, out_dtype=abi.F32, out=None):
+    """mlp_forward without a workspace: the library's static scratch array
+    holds the working memory (allocation-free; calls that overlap on one
+    device race).  Width-256 networks only."""
+    n = x.shape[0]
+    x = x.contiguous()
+    dt = torch.bfloat16 if out_dtype == abi.BF16 else torch.float32
+    if out is None:
+        out = torch.empty((n, desc.n_out), dtype=dt, device=x.device)
+    _check_mlp(desc, params)
+    _expect(x, "x", torch.float32, 4 * n)
+    _expect(out, "out", dt, n * desc.n_out)
+    rc = abi.lib().sdirt_mlp_forward_noalloc(C.byref(desc), _dptr(params), int(n), _dptr(x),
+                                             _dptr(out), int(out_dtype), _stream())
+    abi.check("sdirt_mlp_forward_noalloc", rc)
+    return out
+
+
 def mlp_render(desc, params, img, depth, wavelengths, pitch, workspace, ws_batch, out=None):
     """Surrogate render: img [N][C][H][W] f32 rendered with the network's PSF
     for every pixel and channel (depth [N][H][W] mm, wavelengths [C] um,
