@@ -2,15 +2,19 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-One step = the whole hot path over one batch of the 12-surface lens workload
-(32 radial fields x 16 depths x 3 wavelengths = 1536 DP PSFs, 512 x 512 rays
-each, ks 63, sensor 1680 x 1120 at 5.36 um):
-  1. trace_dp_psf  -- pupil sampling, sequential trace, DP split, box splat;
-  2. render_dp     -- 1680 x 1120 RGB image rendered from that PSF bank and a
-                      piecewise-planar depth map (bank source);
+One step = the whole hot path over one batch of the largest workload, the
+16-surface aspheric phone lens (EFL 4.3 mm, f/1.8; sensor 4032 x 3024 at
+1.0 um): 64 radial fields x 32 depths (0.1-5 m, uniform in 1/d) x 3
+wavelengths = 6144 DP PSFs of 1024 x 1024 rays each, ks 65:
+  1. trace_dp_psf  -- pupil sampling, sequential trace (10 spheres, the stop,
+                      6 even aspheres), DP split, box splat;
+  2. render_dp     -- a batch of 16 RGB 4032 x 3024 images rendered from that
+                      PSF bank and piecewise-planar depth maps (bank source);
   3. render_dp_backward -- image adjoint of the same render.
-Inputs (lens, image, depth map, upstream gradient) are resident on the GPU
-before timing starts.  Prints one JSON line.
+Inputs (lens, images, depth maps, upstream gradient) are resident on the GPU
+before timing starts.  Prints one JSON line; the other parts of the metric
+(the 12-surface lens step, trace adjoint, dense render, surrogate network,
+the paper's PSF-map workload, the exact-azimuth bank) ride along in it.
 """
 
 import argparse
@@ -26,23 +30,52 @@ METRIC = ("rays·surfaces/s and DP PSFs/s; render Mpix/s; fwd+bwd vs fwd time; "
           "MLP vs trace PSFs/s")
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
 
-# Algorithmic FLOPs of the float64 trace (add/mul = 1, fma = 2, div/sqrt = 1):
-# per refracting spherical surface 56 (transfer 7, intersection 20, clip 3,
-# normal 4, vector Snell 22), per aperture-only surface 10, and 60 per ray for
-# pupil sampling, sensor transfer, DP split and binning.
-FLOP_SPHERE, FLOP_STOP, FLOP_RAY = 56, 10, 60
+# Algorithmic FLOPs of the float64 trace (add/mul = 1, fma = 2, div/sqrt/
+# rsqrt = 1), counted on the surfaces a ray reaches alive:
+#   60 per launched ray: pupil sampling, sensor transfer, DP split, binning;
+#   56 per spherical surface (transfer 7, intersection 20, clip 3, normal 4,
+#      vector Snell 22); 10 per aperture stop (transfer and clip);
+#   78 per even asphere (transfer to the vertex plane 5, base-conic start 19,
+#      hit point 5, clip 4, sag slope at the hit 14, unit normal 12, vector
+#      Snell 19) plus 48 per Newton iteration (ray point 4, rho 3, sag 20,
+#      slope 11, residual 2, derivative 6, step 2).
+FLOP_RAY, FLOP_SPHERE, FLOP_STOP, FLOP_ASPH, FLOP_NEWTON = 60, 56, 10, 78, 48
+FLOP_OF_KIND = {0: FLOP_SPHERE, 1: FLOP_STOP, 2: FLOP_STOP, 3: FLOP_ASPH, 4: FLOP_STOP}
 
-# HBM bytes of one trace launch, from two rocprofv3 --pmc runs of
-# `bench.py --pmc-target` (FETCH_SIZE, then WRITE_SIZE), each scaled by what
-# the counter reads on a 1 GiB device copy in the same run.  The figure holds
-# for the kernel sources with this digest only; otherwise traffic is null.
+# Fraction of launched rays alive at each surface and Newton iterations per
+# launched ray (summed over the aspheres, at the kernels' stopping rule),
+# counted by tests/flop_counts.py on the oracle (64 x 64 rays at 96 of the
+# workload's points) and checked against it by tests/test_flop_model.py.
+TRACE_COUNTS = {
+    "config5": {"alive": [1.0, 0.9861, 0.9659, 0.9659, 0.9173, 0.9173, 0.9173, 0.8989,
+                          0.8695, 0.829, 0.8278, 0.8278, 0.8278, 0.8278, 0.8278, 0.8278,
+                          0.8278],
+                "newton_per_ray": 10.937},
+    "config2": {"alive": [1.0, 1.0, 1.0, 0.9998, 0.9998, 0.9998, 0.9998, 0.9929, 0.9929,
+                          0.9929, 0.9928, 0.9928, 0.9928],
+                "newton_per_ray": 0.0},
+}
+
+
+def trace_flop_per_ray(kinds, alive, newton_per_ray):
+    """Algorithmic FLOPs per launched ray of a prescription (surface kinds),
+    given the alive fraction per surface and Newton iterations per ray."""
+    return (FLOP_RAY + FLOP_NEWTON * newton_per_ray +
+            sum(a * FLOP_OF_KIND[k] for k, a in zip(kinds, alive)))
+
+
+# HBM bytes of one trace launch of the headline step, from two rocprofv3
+# --pmc runs of `bench.py --pmc-target` (FETCH_SIZE, then WRITE_SIZE), each
+# scaled by what the counter reads on a 1 GiB device copy in the same run.
+# The figure holds for the kernel sources with this digest only; otherwise
+# traffic is null.
 TRACE_SOURCES = ("paper_2503_11213_amd/csrc/device_common.hpp",
                  "paper_2503_11213_amd/csrc/trace.hip",
                  "paper_2503_11213_amd/csrc/pack.hpp",
                  "paper_2503_11213_amd/csrc/pack.cpp")
-TRACE_TRAFFIC = {"sources_sha256": "efd856cf901a745ab96df7348f5a220c028fac42a5e373f8b7523e19ea27af8a",
-                 "bytes": 65716014}
+TRACE_TRAFFIC = {"sources_sha256": None, "bytes": None}
 
 
 def sources_digest():
@@ -79,37 +112,98 @@ def timed(fn, stream, reps):
     return s.elapsed_time(e) / reps
 
 
-def cpu_baseline(lens, sensor, query, img, dmap, radii, iv, loc, ps, total_rs,
-                 H, W):
-    """The float64 oracle on a bounded sample of the same step, scaled to
-    the full step and reported in rays*surfaces/s."""
-    import numpy as np
+def _oracle_trace_point(args):
+    """One PSF point through the float64 oracle (a pool worker's task);
+    returns its time only (the bank it fills is not sent back)."""
+    lens, sensor, query, point = args
     import oracle.psf as opsf
-    import oracle.render as orender
-    n_surf = 12
-    picks = [(f, (5 * f + 3 * k) % 16, (f + k) % 3) for f in range(32) for k in range(2)]
     t0 = time.perf_counter()
-    bank, _ = opsf.trace_dp_psf(lens, sensor, query, points=picks)
-    t_trace = time.perf_counter() - t0
-    sample_rays = len(picks) * query.n_rays
-    crop = 160
-    ks = query.ks
-    bank6 = bank.reshape(len(query.fields), len(query.depths), len(query.wavelengths), 2, ks, ks)
-    y0, x0 = H // 2 - crop // 2, W // 2 - crop // 2
-    pix = [(0, y, x) for y in range(y0, y0 + crop) for x in range(x0, x0 + crop)]
+    opsf.trace_dp_psf(lens, sensor, query, points=[point])
+    return time.perf_counter() - t0
+
+
+def _oracle_render_rows(args):
+    """Bank-render pixels of an image crop through the float64 oracle (a
+    pool worker's task); the bank is the workload's shape, zero-filled here
+    (the oracle's cost does not depend on the kernel values)."""
+    img, dmap, bank_shape, radii, iv, loc, ps, pix = args
+    import numpy as np
+    import oracle.render as orender
+    bank6 = np.zeros(bank_shape)
     t0 = time.perf_counter()
     orender.render_bank_pixels(img, bank6, dmap, radii, iv, loc, ps, pix)
-    t_render = time.perf_counter() - t0
-    # the image adjoint reads the same kernels once more: same cost model
-    est_step = (t_trace * (query.n_points * query.n_rays) / sample_rays +
-                2.0 * t_render * (H * W) / len(pix))
-    return {"value": total_rs / est_step, "unit": "rays*surfaces/s", "cores": 1,
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(lens, sensor, query, step_rs, img1, dmap1, n_images):
+    """The float64 oracle on a bounded sample of the step, timed on the
+    host's cores (a process pool, one PSF point or pixel block per task) and
+    on one core, scaled to the whole step, in the step's unit."""
+    import multiprocessing as mp
+    import numpy as np
+    import copy
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    F, D, L = len(query.fields), len(query.depths), len(query.wavelengths)
+    picks = [(f, (7 * f + 3 * k) % D, (f + k) % L) for f in range(0, F, 2) for k in range(2)]
+    # 512 x 512 of each point's 1024 x 1024 rays: the oracle's cost is
+    # linear in the ray count (whole-bundle array operations)
+    q = copy.copy(query)
+    q.rays_x = q.rays_y = 512
+    ray_scale = query.n_rays / q.n_rays
+    H, W = dmap1.shape
+    ks = query.ks
+    bank_shape = (F, D, L, 2, ks, ks)
+    radii = [f[0] for f in query.fields]
+    iv = [1.0 / d for d in query.depths]
+    from workloads import configs
+    loc = list(configs.LAMBDA_OF_RGB)
+    # render sample: 8 x 128 pixels per process, inside a 256 x 256 crop of
+    # the image and depth map away from its borders (a pixel's cost does not
+    # depend on where it is)
+    cy, cx = H // 2 - 128, W // 2 - 128
+    crop_img = np.ascontiguousarray(img1[None, :, cy:cy + 256, cx:cx + 256])
+    crop_dm = np.ascontiguousarray(dmap1[None, cy:cy + 256, cx:cx + 256])
+    blocks = [[(0, y, x) for y in range(64 + 8 * k, 72 + 8 * k) for x in range(64, 192)]
+              for k in range(cores)]
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env:
+        os.environ[k] = "1"
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        pool.map(_oracle_trace_point, [(lens, sensor, q, p) for p in picks])
+        t_trace = time.perf_counter() - t0
+        args = [(crop_img, crop_dm, bank_shape, radii, iv, loc, sensor.pitch, blk)
+                for blk in blocks]
+        t0 = time.perf_counter()
+        pool.map(_oracle_render_rows, args)
+        t_render = time.perf_counter() - t0
+    for k, v in env.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+    # one core: one PSF point and one pixel block in this process
+    t1_trace = _oracle_trace_point((lens, sensor, q, picks[0]))
+    t1_render = _oracle_render_rows(args[0])
+    n_pix_sample = sum(len(b) for b in blocks)
+    full_pixels = n_images * H * W
+    # forward and image adjoint read the same kernels: twice the forward
+    est = (t_trace * ray_scale * query.n_points / len(picks) +
+           2.0 * t_render * full_pixels / n_pix_sample)
+    est1 = (t1_trace * ray_scale * query.n_points +
+            2.0 * t1_render * full_pixels / len(blocks[0]))
+    return {"value": step_rs / est, "unit": "rays*surfaces/s", "cores": cores,
             "kind": "oracle",
-            "sample": ("float64 NumPy oracle, one process: %d of 1536 PSF points at "
-                       "512x512 rays (%.1f s) and a %dx%d-pixel crop of the bank "
-                       "render (%.1f s, counted twice for forward + adjoint); step "
-                       "time extrapolated linearly to %.0f s" %
-                       (len(picks), t_trace, crop, crop, t_render, est_step))}
+            "one_core_value": step_rs / est1,
+            "sample": ("float64 NumPy oracle in a pool of %d processes: %d of %d PSF points "
+                       "at 512x512 of their 1024x1024 rays (%.1f s) and %d pixels of the bank "
+                       "render (%.1f s, counted twice for forward + adjoint), scaled linearly "
+                       "to the step's %d PSFs x 1024^2 rays and %d x %dx%d pixels: %.0f s per "
+                       "step; one core (one point %.2f s, %d pixels %.2f s): %.0f s per step" %
+                       (cores, len(picks), query.n_points, t_trace, n_pix_sample, t_render,
+                        query.n_points, n_images, W, H, est, t1_trace, len(blocks[0]),
+                        t1_render, est1))}
 
 
 def extras(dev, stream):
@@ -296,50 +390,65 @@ def extras(dev, stream):
                      "render_fwd_ms": tf, "render_bwd_ms": tb, "bank_grad_ms": tk2}
     del b2, o2, g2, gi2, gb2
     print("bank2d done", file=sys.stderr, flush=True)
-    # 5. smartphone-like 16-surface aspheric lens: 64 x 32 x 3 PSFs, 1024^2
-    #    rays each, ks 65; then its render batch: 16 RGB 4032 x 3024 images
-    #    (one AiF image, four depth maps, each used four times) from that
-    #    bank, forward plus image adjoint
-    lens, sensor, query = configs.config5()
-    b5 = torch.empty((query.n_points, 2, 65, 65), device=dev)
-    tr = lambda: sdirt.trace_dp_psf(lens, sensor, query, out=b5, stats=False)
-    tr()
-    t5 = timed(tr, stream, 2)
-    n_surf = sum(1 for s_ in lens.surfaces if s_.kind != 2)
-    out["phone_lens_trace"] = {
-        "workload": "16-surface aspheric lens (EFL 4.3 mm, f/1.8), 6144 PSFs x 1024^2 rays, ks 65",
-        "ms": t5, "psfs_per_s": query.n_points / (t5 * 1e-3),
-        "rays_surfaces_per_s": query.n_points * query.n_rays * n_surf / (t5 * 1e-3)}
-    H5, W5, N5 = sensor.height_px, sensor.width_px, 16
-    img1 = torch.from_numpy(scenes.aif_blobs(H5, W5, 3, n_blobs=2000, seed=0)).to(dev)
-    imgs = img1.unsqueeze(0).expand(N5, -1, -1, -1).contiguous()
-    del img1
-    dms = [torch.from_numpy(scenes.depth_voronoi(H5, W5, 100.0, 5000.0, seed=200 + k)).to(dev)
-           for k in range(4)]
-    dmap5 = torch.stack([dms[k % 4] for k in range(N5)])
-    del dms
-    desc5, keep5 = sdirt.make_render_desc(N5, 3, H5, W5, query.ks, source=abi.SRC_BANK,
-                                          field_radii=[f[0] for f in query.fields],
-                                          inv_depths=[1.0 / d for d in query.depths],
-                                          bank_lambdas=3, lambda_of_channel=list(configs.LAMBDA_OF_RGB),
-                                          pitch=sensor.pitch)
-    o5 = torch.empty((N5, 6, H5, W5), device=dev)
-    g5 = torch.randn((N5, 6, H5, W5), device=dev)
-    gi5 = torch.empty_like(imgs)
-    rf = lambda: sdirt.render_dp(desc5, imgs, b5, depth=dmap5, out=o5)
-    rb = lambda: sdirt.render_dp_backward(desc5, b5, g5, depth=dmap5, grad_img=gi5)
-    rf()
-    rb()
-    tf, tb = timed(rf, stream, 2), timed(rb, stream, 2)
-    npx = N5 * H5 * W5
-    out["phone_lens_render"] = {
-        "workload": "16 x 4032x3024 RGB from the 6144-PSF bank (ks 65), forward + image adjoint",
-        "fwd_ms": tf, "bwd_ms": tb, "fwd_mpix_per_s": npx / (tf * 1e-3) / 1e6,
-        "fwd_tflops": npx * 4.0 * 3 * query.ks ** 2 / (tf * 1e-3) / 1e12,
-        "fwd_plus_bwd_over_fwd": (tf + tb) / tf}
-    del imgs, dmap5, o5, g5, gi5, b5
-    print("phone lens done", file=sys.stderr, flush=True)
+    # 5. the 12-surface spherical lens: 32 radial fields x 16 depths x 3
+    #    wavelengths (1536 PSFs, 512^2 rays, ks 63), then a 1680 x 1120 RGB
+    #    render from that bank and its image adjoint
+    out["config2"] = config2_step(dev, stream)
+    print("12-surface lens done", file=sys.stderr, flush=True)
     return out
+
+
+def config2_step(dev, stream, reps=5):
+    import numpy as np
+    import torch
+    from workloads import configs, scenes
+    from paper_2503_11213_amd import sdirt, _abi as abi
+    lens, sensor, query = configs.config2()
+    H, W, ps = sensor.height_px, sensor.width_px, sensor.pitch
+    img = torch.from_numpy(scenes.aif_blobs(H, W, 3, n_blobs=2000, seed=0)[None]).to(dev)
+    dmap = torch.from_numpy(scenes.depth_voronoi(H, W, 500.0, 5000.0, seed=100)[None]).to(dev)
+    gout = torch.from_numpy(np.random.default_rng(1).normal(
+        size=(1, 6, H, W)).astype(np.float32)).to(dev)
+    desc, keep = sdirt.make_render_desc(1, 3, H, W, query.ks, source=abi.SRC_BANK,
+                                        field_radii=[f[0] for f in query.fields],
+                                        inv_depths=[1.0 / d for d in query.depths],
+                                        bank_lambdas=3, lambda_of_channel=list(configs.LAMBDA_OF_RGB),
+                                        pitch=ps)
+    P = query.n_points
+    bank = torch.empty((P, 2, query.ks, query.ks), dtype=torch.float32, device=dev)
+    out = torch.empty((1, 6, H, W), dtype=torch.float32, device=dev)
+    gimg = torch.empty((1, 3, H, W), dtype=torch.float32, device=dev)
+    tr = lambda: sdirt.trace_dp_psf(lens, sensor, query, out=bank, stats=False)
+    rf = lambda: sdirt.render_dp(desc, img, bank, depth=dmap, out=out)
+    rb = lambda: sdirt.render_dp_backward(desc, bank, gout, depth=dmap, grad_img=gimg)
+    tr(); rf(); rb()
+    t_tr, t_rf, t_rb = timed(tr, stream, reps), timed(rf, stream, reps), timed(rb, stream, reps)
+    gbank = torch.empty_like(bank)
+    kg = lambda: sdirt.render_dp_psf_backward(desc, img, gout, depth=dmap, grad_psf=gbank)
+    kg()
+    t_kg = timed(kg, stream, reps)
+    _, st = sdirt.trace_dp_psf(lens, sensor, query, out=bank, stats=True)
+    st = st.cpu().numpy()
+    kinds = [s_.kind for s_ in lens.surfaces]
+    n_surf = sum(1 for k in kinds if k != 2)
+    rays = P * query.n_rays
+    c = TRACE_COUNTS["config2"]
+    flop = rays * trace_flop_per_ray(kinds, c["alive"], c["newton_per_ray"])
+    return {"workload": "12-surface double-Gauss-like lens (seed 0, f/2, focus 0.909 m); 32 "
+                        "radial fields x 16 depths (0.5-5 m, uniform 1/d) x 3 wavelengths = "
+                        "1536 DP PSFs, 512x512 rays each, ks 63, sigmoid response, box splat; "
+                        "render + image adjoint of a 1680x1120 RGB image from the PSF bank",
+            "step_ms": t_tr + t_rf + t_rb,
+            "rays_surfaces_per_s_step": rays * n_surf / ((t_tr + t_rf + t_rb) * 1e-3),
+            "trace_ms": t_tr, "trace_rays_surfaces_per_s": rays * n_surf / (t_tr * 1e-3),
+            "trace_psfs_per_s": P / (t_tr * 1e-3),
+            "trace_tflops": flop / (t_tr * 1e-3) / 1e12,
+            "trace_fp64_frac": flop / (t_tr * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "in_window_energy_fraction": float((st[:, 3] + st[:, 4]).sum() / st[:, 0].sum()),
+            "render_fwd_ms": t_rf, "render_bwd_ms": t_rb,
+            "render_fwd_mpix_per_s": H * W / (t_rf * 1e-3) / 1e6,
+            "render_fwd_plus_bwd_over_fwd": (t_rf + t_rb) / t_rf,
+            "bank_grad_ms": t_kg}
 
 
 def main():
@@ -356,31 +465,34 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
-    lens, sensor, query = configs.config2()
+    lens, sensor, query = configs.config5()
+    P, ks = query.n_points, query.ks
+    bank = torch.empty((P, 2, ks, ks), dtype=torch.float32, device=dev)
     if args.pmc_target:
         src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)
         torch.empty_like(src).copy_(src)
-        sdirt.trace_dp_psf(lens, sensor, query)
+        sdirt.trace_dp_psf(lens, sensor, query, out=bank, stats=False)
         torch.cuda.synchronize()
         return
-    H, W, ps = sensor.height_px, sensor.width_px, sensor.pitch
-    img_np = scenes.aif_blobs(H, W, 3, n_blobs=2000, seed=0)[None]
-    dmap_np = scenes.depth_voronoi(H, W, 500.0, 5000.0, seed=100)[None]
-    img = torch.from_numpy(img_np).to(dev)
-    dmap = torch.from_numpy(dmap_np).to(dev)
-    gout = torch.from_numpy(np.random.default_rng(1).normal(
-        size=(1, 6, H, W)).astype(np.float32)).to(dev)
-    radii = [f[0] for f in query.fields]
-    iv = [1.0 / d for d in query.depths]
-    loc = list(configs.LAMBDA_OF_RGB)
-    desc, keep = sdirt.make_render_desc(1, 3, H, W, query.ks, source=abi.SRC_BANK,
-                                        field_radii=radii, inv_depths=iv,
-                                        bank_lambdas=3, lambda_of_channel=loc, pitch=ps)
-    P = query.n_points
-    bank = torch.empty((P, 2, query.ks, query.ks), dtype=torch.float32, device=dev)
-    stats = torch.empty((P, 7), dtype=torch.float64, device=dev)
-    out = torch.empty((1, 6, H, W), dtype=torch.float32, device=dev)
-    gimg = torch.empty((1, 3, H, W), dtype=torch.float32, device=dev)
+    H, W, N = sensor.height_px, sensor.width_px, 16
+    # the batch: one all-in-focus image and four depth maps, each used four
+    # times (the render's cost does not depend on the image content)
+    img1_np = scenes.aif_blobs(H, W, 3, n_blobs=2000, seed=0)
+    dms_np = [scenes.depth_voronoi(H, W, 100.0, 5000.0, seed=200 + k) for k in range(4)]
+    img1 = torch.from_numpy(img1_np).to(dev)
+    img = img1.unsqueeze(0).expand(N, -1, -1, -1).contiguous()
+    del img1
+    dms = [torch.from_numpy(d).to(dev) for d in dms_np]
+    dmap = torch.stack([dms[k % 4] for k in range(N)])
+    del dms
+    gout = torch.randn((N, 6, H, W), device=dev, generator=torch.Generator(dev).manual_seed(1))
+    desc, keep = sdirt.make_render_desc(N, 3, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=[f[0] for f in query.fields],
+                                        inv_depths=[1.0 / d for d in query.depths],
+                                        bank_lambdas=3, lambda_of_channel=list(configs.LAMBDA_OF_RGB),
+                                        pitch=sensor.pitch)
+    out = torch.empty((N, 6, H, W), dtype=torch.float32, device=dev)
+    gimg = torch.empty((N, 3, H, W), dtype=torch.float32, device=dev)
 
     def trace():
         sdirt.trace_dp_psf(lens, sensor, query, out=bank, stats=False)
@@ -391,42 +503,44 @@ def main():
     def render_bwd():
         sdirt.render_dp_backward(desc, bank, gout, depth=dmap, grad_img=gimg)
 
-    def step():
+    for _ in range(args.warmup):
         trace()
         render()
         render_bwd()
-
-    for _ in range(args.warmup):
-        step()
     torch.cuda.synchronize()
+    # the timed steps, with HIP events on the launch stream around each of
+    # the step's three calls
+    laps = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        evs[0].record(stream)
+        trace()
+        evs[1].record(stream)
+        render()
+        evs[2].record(stream)
+        render_bwd()
+        evs[3].record(stream)
+        laps.append(evs)
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
-
-    # per-kernel averages with HIP events on the launch stream
-    reps = max(2, args.steps)
-    ms_trace = timed(trace, stream, reps)
-    ms_render = timed(render, stream, reps)
-    ms_rbwd = timed(render_bwd, stream, reps)
-    # gradient with respect to the bank (not part of the step: the chain to
-    # the tracer's adjoint for end-to-end lens optimisation)
-    gbank = torch.empty_like(bank)
-    kgrad = lambda: sdirt.render_dp_psf_backward(desc, img, gout, depth=dmap, grad_psf=gbank)
-    kgrad()
-    ms_kgrad = timed(kgrad, stream, reps)
-    del gbank
+    ms_trace = float(np.mean([e[0].elapsed_time(e[1]) for e in laps]))
+    ms_render = float(np.mean([e[1].elapsed_time(e[2]) for e in laps]))
+    ms_rbwd = float(np.mean([e[2].elapsed_time(e[3]) for e in laps]))
     _, st = sdirt.trace_dp_psf(lens, sensor, query, out=bank, stats=True)
     st = st.cpu().numpy()
 
-    n_rays = P * query.n_rays
-    n_surf = sum(1 for s in lens.surfaces if s.kind != 2)      # refracting
-    n_stop = len(lens.surfaces) - n_surf
-    rs = n_rays * n_surf
+    kinds = [s.kind for s in lens.surfaces]
+    n_surf = sum(1 for k in kinds if k != 2)          # refracting surfaces
+    rays = P * query.n_rays
+    rs = rays * n_surf
     value = rs / (ms_step * 1e-3)
-    flop = n_rays * (FLOP_SPHERE * n_surf + FLOP_STOP * n_stop + FLOP_RAY)
+    c = TRACE_COUNTS["config5"]
+    flop_ray = trace_flop_per_ray(kinds, c["alive"], c["newton_per_ray"])
+    flop = rays * flop_ray
     achieved = flop / (ms_trace * 1e-3) / 1e12
+    npx = N * H * W
+    render_flop = npx * 4.0 * 3 * ks * ks
     line = {
         "metric": METRIC,
         "value": value,
@@ -436,33 +550,38 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "12-surface double-Gauss-like lens (seed 0, f/2, focus 0.909 m); "
-                               "32 radial fields x 16 depths (0.5-5 m, uniform 1/d) x 3 "
-                               "wavelengths = 1536 DP PSFs, 512x512 rays each, ks 63, "
-                               "sigmoid DP response, box splat; render + image adjoint of a "
-                               "1680x1120 RGB image from the PSF bank",
+        "config": {"workload": "16-surface aspheric phone lens (seeded even aspheres to r^10, "
+                               "EFL 4.3 mm, f/1.8, focus 0.196 m); 64 radial fields x 32 "
+                               "depths (0.1-5 m, uniform 1/d) x 3 wavelengths = 6144 DP PSFs, "
+                               "1024x1024 rays each, ks 65, sigmoid DP response, box splat; "
+                               "render + image adjoint of 16 RGB 4032x3024 images (1.0 um "
+                               "pixels) from the PSF bank and piecewise-planar depth maps",
                    "psfs": P, "rays_per_psf": query.n_rays, "surfaces": n_surf,
-                   "ks": query.ks, "image": [H, W, 3]},
-        "roofline": {"kernel": "trace_splat_kernel<double, box, sigmoid, float, spheres and flats>",
+                   "ks": ks, "images": [N, 3, H, W]},
+        "roofline": {"kernel": "trace_splat_kernel<double, box, sigmoid, float, general surface loop>",
                      "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": (TRACE_TRAFFIC["bytes"]
                                  if TRACE_TRAFFIC["sources_sha256"] == sources_digest() else None),
-                     "flop_per_launch": flop},
+                     "flop_per_launch": flop, "flop_per_ray": flop_ray,
+                     "launch_ms": ms_trace},
         "trace": {"ms": ms_trace, "rays_surfaces_per_s": rs / (ms_trace * 1e-3),
                   "psfs_per_s": P / (ms_trace * 1e-3),
                   "in_window_energy_fraction": float((st[:, 3] + st[:, 4]).sum() / st[:, 0].sum()),
                   "transmitted_fraction": float(st[:, 2].sum() / st[:, 0].sum())},
         "render": {"fwd_ms": ms_render, "bwd_ms": ms_rbwd,
-                   "fwd_mpix_per_s": H * W / (ms_render * 1e-3) / 1e6,
-                   "fwd_plus_bwd_over_fwd": (ms_render + ms_rbwd) / ms_render,
-                   "bank_grad_ms": ms_kgrad},
+                   "fwd_mpix_per_s": npx / (ms_render * 1e-3) / 1e6,
+                   "fwd_tflops": render_flop / (ms_render * 1e-3) / 1e12,
+                   "fwd_fp32_mfma_frac": render_flop / (ms_render * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                   "bwd_tflops": render_flop / (ms_rbwd * 1e-3) / 1e12,
+                   "fwd_plus_bwd_over_fwd": (ms_render + ms_rbwd) / ms_render},
     }
+    del img, dmap, gout, out, gimg
+    torch.cuda.empty_cache()
     if not args.no_extras:
         line.update(extras(dev, stream))
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(lens, sensor, query, img_np, dmap_np, radii,
-                                            iv, loc, ps, rs, H, W)
+        line["cpu_baseline"] = cpu_baseline(lens, sensor, query, rs, img1_np, dms_np[0], N)
     print(json.dumps(line), flush=True)
 
 

@@ -53,7 +53,7 @@ def asphere_sag(surf, rho):
     return sag, dsag, ok
 
 
-def _intersect_asphere(surf, x, y, dx, dy, dz, status):
+def _intersect_asphere(surf, x, y, dx, dy, dz, status, steps_log=None):
     c, k = surf.c, surf.conic
     F = c * (x * x + y * y)
     G = dz - c * (x * dx + y * dy)
@@ -62,6 +62,7 @@ def _intersect_asphere(surf, x, y, dx, dy, dz, status):
     delta = np.where(disc >= 0.0, F / (G + np.sqrt(np.maximum(disc, 0.0))), 0.0)
     conv = np.zeros(x.shape, dtype=bool)
     bad = np.zeros(x.shape, dtype=bool)
+    steps = []                      # (|step|, |Delta|) per iteration (NaN once a ray stopped)
     for _ in range(NEWTON_MAXIT):
         xr = x + delta * dx
         yr = y + delta * dy
@@ -74,9 +75,13 @@ def _intersect_asphere(surf, x, y, dx, dy, dz, status):
         bad |= active & ~ok
         upd = active & ok
         delta = np.where(upd, delta - step, delta)
+        steps.append(np.stack([np.where(upd, np.abs(step), np.nan),
+                               np.where(upd, np.abs(delta), np.nan)]))
         conv |= upd & (np.abs(step) < NEWTON_TOL)
         if np.all(conv | bad):
             break
+    if steps_log is not None:
+        steps_log.append(np.array(steps))
     status[(~conv | bad) & (status == ALIVE)] = NEWTON
     xr = x + delta * dx
     yr = y + delta * dy
@@ -93,13 +98,19 @@ def _refract(d, N, mu, status):
     return mu * d + (sq - mu * cosI)[:, None] * N
 
 
-def trace(prep, lam, o, d, record=False):
+def trace(prep, lam, o, d, record=False, log=None):
     """Trace rays (global origin o, unit direction d; z = 0 at vertex 1).
 
     Returns dict with landing point O (n, 2) on the sensor, direction D
     (n, 3), status (n,) and, if record, hits (n, S+1, 6): per surface the
     vertex-local hit point (x, y, z) and the direction after refraction;
     the last entry is the sensor plane.
+
+    log: optional dict that receives log["alive"][s], the rays still alive
+    when they reach surface s (after its transfer), and for every asphere
+    log["steps"][s], the |step| and the updated |Delta| of each Newton
+    iteration per ray ([iterations, 2, n], NaN once a ray stopped).  Bookkeeping only: the trace
+    is unchanged.
     """
     lens = prep.lens
     S = prep.S
@@ -117,6 +128,8 @@ def trace(prep, lam, o, d, record=False):
                 z = z - prep.thickness[s - 1]
             dx, dy, dz = d[:, 0], d[:, 1], d[:, 2]
             status[(dz <= 0.0) & (status == ALIVE)] = INVALID
+            if log is not None:
+                log.setdefault("alive", []).append(status == ALIVE)
             tau = -z / dz
             x = x + tau * dx
             y = y + tau * dy
@@ -132,7 +145,10 @@ def trace(prep, lam, o, d, record=False):
                 y = y + delta * dy
                 z = delta * dz
             elif surf.kind == ASPHERE:
-                delta, x, y = _intersect_asphere(surf, x, y, dx, dy, dz, status)
+                steps = [] if log is not None else None
+                delta, x, y = _intersect_asphere(surf, x, y, dx, dy, dz, status, steps)
+                if log is not None:
+                    log.setdefault("steps", {})[s] = steps[0]
                 z = delta * dz
             r2 = x * x + y * y
             semi = prep.semi[s]
