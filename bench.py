@@ -94,9 +94,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--pmc-target", action="store_true",
-                    help="for counter runs: a 1 GiB device copy (calibration), then one "
-                         "trace_dp_psf call of the step; prints nothing")
+    ap.add_argument("--pmc-target", default=None,
+                    choices=["calib", "trace", "trace_paper", "render", "render_bwd", "dense",
+                             "mlp_head"],
+                    help="for counter runs: a 1 GiB device copy (calibration of the memory "
+                         "counters), then one launch of the named kernel; prints nothing")
     return ap.parse_args()
 
 
@@ -451,6 +453,76 @@ def config2_step(dev, stream, reps=5):
             "bank_grad_ms": t_kg}
 
 
+def pmc_target(name, dev):
+    """One launch of a kernel for a profiler counter pass, after a 1 GiB
+    device copy whose FETCH_SIZE / WRITE_SIZE scale the memory counters:
+      calib       sdirt_calib_fma64, 2^20 threads x 1000 iterations
+                  (8.39e9 float64 FMAs);
+      trace       the step's trace (16-surface aspheric lens, 6144 PSFs);
+      trace_paper the paper's PSF map (RF50, 393,216 PSFs x 4096 rays);
+      render, render_bwd  the step's bank render and image adjoint;
+      dense       dense render of 512 x 512 RGB with a 41 x 41 f32 map;
+      mlp_head    surrogate inference of 2^20 rows (ks 33, bf16 out)."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    from workloads import configs, scenes
+    from paper_2503_11213_amd import sdirt, _abi as abi
+    src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)
+    torch.empty_like(src).copy_(src)
+    del src
+    torch.cuda.synchronize()
+    if name == "calib":
+        out = torch.empty((1 << 20,), dtype=torch.float64, device=dev)
+        abi.check("sdirt_calib_fma64", abi.lib().sdirt_calib_fma64(
+            1 << 20, 1000, C.c_void_p(out.data_ptr()),
+            C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    elif name == "trace":
+        lens, sensor, query = configs.config5()
+        sdirt.trace_dp_psf(lens, sensor, query, stats=False)
+    elif name == "trace_paper":
+        lens, sensor, query, (H, W) = configs.paper_psf_map()
+        dmap = scenes.depth_uniform_inverse(H, W, 500.0, 20000.0, seed=100)
+        pts = torch.from_numpy(configs.pixel_points(H, W, sensor.pitch, dmap)).to(dev)
+        sdirt.trace_dp_psf(lens, sensor, query, points=pts, stats=False)
+    elif name in ("render", "render_bwd"):
+        lens, sensor, query = configs.config5()
+        bank, _ = sdirt.trace_dp_psf(lens, sensor, query, stats=False)
+        H, W, N = sensor.height_px, sensor.width_px, 16
+        img = torch.from_numpy(scenes.aif_blobs(H, W, 3, n_blobs=2000, seed=0)).to(dev)
+        img = img.unsqueeze(0).expand(N, -1, -1, -1).contiguous()
+        dms = [torch.from_numpy(scenes.depth_voronoi(H, W, 100.0, 5000.0, seed=200 + k)).to(dev)
+               for k in range(4)]
+        dmap = torch.stack([dms[k % 4] for k in range(N)])
+        desc, keep = sdirt.make_render_desc(N, 3, H, W, query.ks, source=abi.SRC_BANK,
+                                            field_radii=[f[0] for f in query.fields],
+                                            inv_depths=[1.0 / d for d in query.depths],
+                                            bank_lambdas=3,
+                                            lambda_of_channel=list(configs.LAMBDA_OF_RGB),
+                                            pitch=sensor.pitch)
+        if name == "render":
+            sdirt.render_dp(desc, img, bank, depth=dmap)
+        else:
+            g = torch.randn((N, 6, H, W), device=dev)
+            sdirt.render_dp_backward(desc, bank, g, depth=dmap)
+    elif name == "dense":
+        N, C_, H, W, ks = 1, 3, 512, 512, 41
+        K = torch.rand((N, H, W, C_, 2, ks, ks), device=dev)
+        img = torch.rand((N, C_, H, W), device=dev)
+        desc, keep = sdirt.make_render_desc(N, C_, H, W, ks)
+        sdirt.render_dp(desc, img, K)
+    elif name == "mlp_head":
+        desc = sdirt.make_mlp_desc(n_out=2 * 33 * 33, **configs.config4_desc_kwargs())
+        layers = scenes.mlp_init([64, 256, 256, 256, 256, 256, 2178], seed=0)
+        params = torch.from_numpy(np.concatenate([np.concatenate([Wt.ravel(), bt])
+                                                  for Wt, bt in layers]).astype(np.float32)).to(dev)
+        _, x = configs.surrogate_points(1 << 20, seed=3)
+        ws = sdirt.mlp_workspace(desc, 1 << 20)
+        sdirt.mlp_forward(desc, params, torch.from_numpy(x).to(dev), ws, 1 << 20,
+                          out_dtype=abi.BF16)
+    torch.cuda.synchronize()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -465,15 +537,12 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
+    if args.pmc_target:
+        pmc_target(args.pmc_target, dev)
+        return
     lens, sensor, query = configs.config5()
     P, ks = query.n_points, query.ks
     bank = torch.empty((P, 2, ks, ks), dtype=torch.float32, device=dev)
-    if args.pmc_target:
-        src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)
-        torch.empty_like(src).copy_(src)
-        sdirt.trace_dp_psf(lens, sensor, query, out=bank, stats=False)
-        torch.cuda.synchronize()
-        return
     H, W, N = sensor.height_px, sensor.width_px, 16
     # the batch: one all-in-focus image and four depth maps, each used four
     # times (the render's cost does not depend on the image content)

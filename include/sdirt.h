@@ -361,6 +361,37 @@ int sdirt_mlp_forward_noalloc(const sdirt_mlp_desc* desc, const float* params,
                               long long n_rows, const float* x, void* out, int out_dtype,
                               void* stream);
 
+/* DP PSFs of a list-mode query from the surrogate network, with the ray
+ * tracer as its fallback (Sec. 3.2, Supplement S1.4: the network is trained
+ * on traced PSFs, and the tracer remains the reference that judges its
+ * error).  The caller gives the network's measured error per band of
+ * inverse depth (e.g. its held-out energy L1 against many-ray traces):
+ * band_edges host [n_bands + 1] strictly increasing inverse depths (1/mm),
+ * band_error host [n_bands].  Every point whose 1/depth lies in a band with
+ * band_error <= max_error takes the network's PSF (softmax output, float32,
+ * as sdirt_mlp_forward); every other point (in a band above the bar, or
+ * outside [band_edges[0], band_edges[n_bands]]) is ray traced as by
+ * sdirt_trace_dp_psf.  Band b of a point is the one with
+ * band_edges[b] <= 1/depth < band_edges[b + 1] (the last band includes its
+ * upper edge), 1/depth computed in float64.
+ *   query     list mode (points != NULL, device [P][4]: h_x, h_y, depth,
+ *             slot), normalize = SDIRT_NORM_SUM, out_dtype = SDIRT_F32
+ *             (SDIRT_EUNSUPPORTED otherwise), 2 ks^2 = desc->n_out; the
+ *             network input of a point is (h_x, h_y, 1/depth,
+ *             wavelengths[slot]) in float32;
+ *   psf_out   device [P][2][ks][ks] f32, overwritten;
+ *   source_out device [P] int32, overwritten: 0 network, 1 traced;
+ *   workspace as for sdirt_mlp_forward with ws_batch rows.
+ * The network must have width 256.  SDIRT_EINVAL for NULL buffers, bands
+ * that are not increasing or finite, n_bands outside [1, 64], a negative or
+ * non-finite max_error. */
+int sdirt_psf_hybrid(const sdirt_mlp_desc* desc, const float* params,
+                     const sdirt_lens* lens, const sdirt_sensor* sensor,
+                     const sdirt_psf_query* query, int n_bands,
+                     const double* band_edges, const double* band_error,
+                     double max_error, float* psf_out, int* source_out,
+                     void* workspace, int ws_batch, void* stream);
+
 /* The surrogate render (Fig. 2(c); Sec. 3.2): every pixel of an image
  * rendered with the PSF the network predicts for it, without the dense PSF
  * map ever reaching memory.  For each image n, channel c and pixel (y, x)
@@ -442,6 +473,17 @@ int sdirt_mlp_train(const sdirt_mlp_desc* desc, float* params, float* m, float* 
                     int batch, long long n_samples, const float* x_all,
                     const float* t_all, uint32_t seed, float* loss_trace,
                     void* workspace, void* stream);
+
+/* ---- measurement ------------------------------------------------------
+ * Not part of the method: a kernel of known float64 FMA count, for
+ * calibrating the profiler's float64 FLOP and VALU counters against the
+ * trace, whose FLOPs are counted from its algorithm.  n_threads threads
+ * (workgroups of 256) each run 8 independent chains of `iters` dependent
+ * fused multiply-adds: exactly 8 * iters * n_threads v_fma_f64
+ * (16 * iters * n_threads FLOPs).  out device [n_threads] doubles
+ * (overwritten, one value per thread).  SDIRT_EINVAL for NULL out,
+ * n_threads < 1 or iters < 1. */
+int sdirt_calib_fma64(long long n_threads, int iters, double* out, void* stream);
 
 /* ---- misc ------------------------------------------------------------- */
 const char* sdirt_status_string(int status);

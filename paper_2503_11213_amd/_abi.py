@@ -138,6 +138,11 @@ SIGNATURES = {
     "sdirt_mlp_train_step": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int, C.c_float, C.c_int, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sdirt_psf_hybrid": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.POINTER(Lens),
+                                   C.POINTER(Sensor), C.POINTER(PsfQuery), C.c_int,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "sdirt_calib_fma64": (C.c_int, [C.c_longlong, C.c_int, C.c_void_p, C.c_void_p]),
     "sdirt_mlp_train": (C.c_int, [C.POINTER(MlpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_int, C.c_int, C.c_float, C.c_float, C.c_int,
                                   C.c_int, C.c_longlong, C.c_void_p, C.c_void_p,

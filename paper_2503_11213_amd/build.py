@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsdirt.so")
 
-HIP_SOURCES = ["trace.hip", "trace_bwd.hip", "render.hip", "mlp.hip", "mlp_fused.hip"]
+HIP_SOURCES = ["trace.hip", "trace_bwd.hip", "render.hip", "mlp.hip", "mlp_fused.hip", "calib.hip"]
 CPP_SOURCES = ["host_optics.cpp", "pack.cpp", "api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -13,7 +13,7 @@
 
 namespace sdirt {
 int trace_dp_psf_impl(const sdirt_lens*, const sdirt_sensor*, const sdirt_psf_query*,
-                      void*, double*, hipStream_t, int);
+                      void*, double*, hipStream_t, int, const int*);
 int trace_rays_impl(const sdirt_lens*, double, int, int, const double*, const double*,
                     double*, int*, hipStream_t);
 int trace_backward_impl(const sdirt_lens*, const sdirt_sensor*, const sdirt_psf_query*,
@@ -42,6 +42,10 @@ int mlp_train(const sdirt_mlp_desc*, float*, float*, float*, int, int, float, fl
               long long, const float*, const float*, uint32_t, float*, void*, hipStream_t);
 int mlp_train_step(const sdirt_mlp_desc*, float*, float*, float*, int, float, int, const float*,
                    const float*, float*, void*, hipStream_t);
+int calib_fma64(long long, int, double*, hipStream_t);
+int psf_hybrid(const sdirt_mlp_desc*, const float*, const sdirt_lens*, const sdirt_sensor*,
+               const sdirt_psf_query*, int, const double*, const double*, double, float*, int*,
+               void*, int, hipStream_t);
 }  // namespace sdirt
 
 using namespace sdirt;
@@ -117,7 +121,7 @@ int sdirt_trace_dp_psf(const sdirt_lens* lens, const sdirt_sensor* sensor,
                        double* stats_out, void* stream) {
     Range r("sdirt_trace_dp_psf");
     return trace_dp_psf_impl(lens, sensor, query, psf_out, stats_out,
-                             (hipStream_t)stream, 0);
+                             (hipStream_t)stream, 0, nullptr);
 }
 
 int sdirt_trace_dp_psf_chunks(const sdirt_lens* lens, const sdirt_sensor* sensor,
@@ -126,7 +130,7 @@ int sdirt_trace_dp_psf_chunks(const sdirt_lens* lens, const sdirt_sensor* sensor
     Range r("sdirt_trace_dp_psf_chunks");
     if (chunks < 1) return SDIRT_EINVAL;
     return trace_dp_psf_impl(lens, sensor, query, psf_out, stats_out,
-                             (hipStream_t)stream, chunks);
+                             (hipStream_t)stream, chunks, nullptr);
 }
 
 int sdirt_trace_dp_psf_backward(const sdirt_lens* lens, const sdirt_sensor* sensor,
@@ -230,6 +234,21 @@ int sdirt_mlp_train(const sdirt_mlp_desc* desc, float* params, float* m, float* 
     return mlp_train(desc, params, m, v, step0, n_steps, lr0, lr_min, total_steps, batch,
                      n_samples, x_all, t_all, seed, loss_trace, workspace,
                      (hipStream_t)stream);
+}
+
+int sdirt_psf_hybrid(const sdirt_mlp_desc* desc, const float* params, const sdirt_lens* lens,
+                     const sdirt_sensor* sensor, const sdirt_psf_query* query, int n_bands,
+                     const double* band_edges, const double* band_error, double max_error,
+                     float* psf_out, int* source_out, void* workspace, int ws_batch,
+                     void* stream) {
+    Range r("sdirt_psf_hybrid");
+    return psf_hybrid(desc, params, lens, sensor, query, n_bands, band_edges, band_error,
+                      max_error, psf_out, source_out, workspace, ws_batch, (hipStream_t)stream);
+}
+
+int sdirt_calib_fma64(long long n_threads, int iters, double* out, void* stream) {
+    Range r("sdirt_calib_fma64");
+    return calib_fma64(n_threads, iters, out, (hipStream_t)stream);
 }
 
 }  // extern "C"
