@@ -196,6 +196,54 @@ def render_bank_pixels(img, bank, depth_maps, field_radii, inv_depths, lam_of_c,
     return out
 
 
+def render_bank_adjoint_pixels(grad_out, bank, depth_maps, field_radii, inv_depths,
+                               lam_of_c, pitch, pixels):
+    """The image adjoint of the bank render (render_bank_adjoint) evaluated
+    only at the listed image pixels (n, y, x): returns [len(pixels), C].
+    Image pixel (y, x) collects K[s][i][j] * grad_out[s C + c] of every
+    output pixel (y', x') and tap (i, j) with clamp(y' + pad - i) = y and
+    clamp(x' + pad - j) = x; those outputs lie within pad of (y, x)."""
+    g = np.asarray(grad_out, dtype=np.float64)
+    bank = np.asarray(bank, dtype=np.float64)
+    N, C2, H, W = g.shape
+    C = C2 // 2
+    ks = bank.shape[-1]
+    pad = (ks - 1) // 2
+    taps = np.arange(ks)
+    out = np.zeros((len(pixels), C))
+    looked = {}
+    for k, (n, y, x) in enumerate(pixels):
+        if n not in looked:
+            looked[n] = bank_lookup(H, W, depth_maps[n], field_radii, inv_depths, pitch)
+        fi, di, mx, my = looked[n]
+        ys, ii, xs, jj = [], [], [], []
+        for yo in range(max(0, y - pad), min(H - 1, y + pad) + 1):
+            hit = np.nonzero(np.clip(yo + pad - taps, 0, H - 1) == y)[0]
+            ys += [yo] * len(hit)
+            ii += list(hit)
+        for xo in range(max(0, x - pad), min(W - 1, x + pad) + 1):
+            hit = np.nonzero(np.clip(xo + pad - taps, 0, W - 1) == x)[0]
+            xs += [xo] * len(hit)
+            jj += list(hit)
+        yo = np.repeat(np.asarray(ys), len(xs))
+        io = np.repeat(np.asarray(ii), len(xs))
+        xo = np.tile(np.asarray(xs), len(ys))
+        jo = np.tile(np.asarray(jj), len(ys))
+        # tap (i, j) of side s of the output pixel's kernel, in the stored
+        # entry: rows flipped below the centre, columns flipped and sides
+        # swapped left of it
+        fy, fx = my[yo, xo], mx[yo, xo]
+        si = np.where(fy, ks - 1 - io, io)
+        sj = np.where(fx, ks - 1 - jo, jo)
+        for c in range(C):
+            e = bank[fi[yo, xo], di[yo, xo], lam_of_c[c]]          # [m, 2, ks, ks]
+            m = np.arange(len(yo))
+            for s in range(2):
+                ss = np.where(fx, 1 - s, s)
+                out[k, c] += np.sum(e[m, ss, si, sj] * g[n, s * C + c, yo, xo])
+    return out
+
+
 # ---- 2-D (exact-azimuth) bank -------------------------------------------
 # A bank traced on a first-quadrant grid (h_x = xs[fx] >= 0, h_y = ys[fy] >= 0)
 # is reused in the other quadrants through the flip symmetry of DP PSFs

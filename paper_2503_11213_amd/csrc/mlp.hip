@@ -648,8 +648,9 @@ int mlp_workspace_size(const sdirt_mlp_desc* d, int batch, size_t* out) {
 // `chunk` rows whose last hidden activations pass through hbuf.
 static int forward_fused(const MlpDims& m, const sdirt_mlp_desc* d, const MlpWs& w,
                          bf16_t* hbuf, long long chunk, const float* params, long long n_rows,
-                         const float* x, void* out, int out_dtype, hipStream_t st) {
-    frag_all(m, w, params, st);
+                         const float* x, void* out, int out_dtype, hipStream_t st,
+                         bool convert_weights = true) {
+    if (convert_weights) frag_all(m, w, params, st);
     FusedArgs f;
     std::memset(&f, 0, sizeof(f));
     f.n_rows = n_rows;
@@ -751,6 +752,103 @@ int mlp_forward_noalloc(const sdirt_mlp_desc* d, const float* params, long long 
     for (int l = 0; l < m.L; ++l) w.WF[l] = (bf16_t*)((char*)base + wf_off[l]);
     bf16_t* hbuf = (bf16_t*)((char*)base + off);
     return forward_fused(m, d, w, hbuf, chunk, params, n_rows, x, out, out_dtype, st);
+}
+
+// ---- network with the tracer as fallback --------------------------------
+// Per point of a list-mode query: the band of its inverse depth among the
+// caller's band edges; points whose band's network error exceeds the bar (or
+// that fall outside every band) are traced, the others take the network's
+// PSF.  The routing kernel also forms the network inputs of a chunk.
+constexpr int kMaxBands = 64;
+
+struct RouteArgs {
+    const double* points;            // [P][4] h_x, h_y, depth, slot
+    long long r0;
+    int n;                           // points in this chunk
+    int n_bands;
+    double edges[kMaxBands + 1];
+    int traced_band[kMaxBands];      // 1 where the band's error exceeds the bar
+    float lambda[SDIRT_MAX_LAMBDAS];
+    int n_lambda;
+    float* x;                        // [n][4] network inputs of the chunk
+    int* source;                     // [P] 0 network, 1 traced
+};
+
+__global__ void hybrid_route_kernel(const RouteArgs a) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n) return;
+    const long long q = a.r0 + t;
+    const double* p = a.points + 4 * q;
+    const double iv = 1.0 / p[2];
+    int traced = 1;
+    if (iv >= a.edges[0] && iv <= a.edges[a.n_bands]) {
+        int b = 0;
+        for (int k = 1; k < a.n_bands; ++k) b += iv >= a.edges[k];
+        traced = a.traced_band[b];
+    }
+    const int slot = (int)p[3];
+    a.source[q] = traced;
+    float* x = a.x + 4 * (size_t)t;
+    x[0] = (float)p[0];
+    x[1] = (float)p[1];
+    x[2] = (float)iv;
+    x[3] = (slot >= 0 && slot < a.n_lambda) ? a.lambda[slot] : 0.f;
+}
+
+int trace_dp_psf_impl(const sdirt_lens*, const sdirt_sensor*, const sdirt_psf_query*, void*,
+                      double*, hipStream_t, int, const int*);
+
+int psf_hybrid(const sdirt_mlp_desc* d, const float* params, const sdirt_lens* lens,
+               const sdirt_sensor* sensor, const sdirt_psf_query* query, int n_bands,
+               const double* band_edges, const double* band_error, double max_error,
+               float* psf_out, int* source_out, void* workspace, int ws_batch,
+               hipStream_t st) {
+    MlpDims m;
+    int rc = dims_of(d, &m);
+    if (rc) return rc;
+    if (!params || !lens || !sensor || !query || !band_edges || !band_error || !psf_out ||
+        !source_out || !workspace)
+        return SDIRT_EINVAL;
+    if (!query->points || query->n_points < 1 || !query->wavelengths) return SDIRT_EINVAL;
+    if (ws_batch < 64 || ws_batch % 64) return SDIRT_EINVAL;
+    if (n_bands < 1 || n_bands > kMaxBands || !std::isfinite(max_error) || max_error < 0)
+        return SDIRT_EINVAL;
+    for (int k = 0; k <= n_bands; ++k)
+        if (!std::isfinite(band_edges[k]) || (k > 0 && !(band_edges[k] > band_edges[k - 1])))
+            return SDIRT_EINVAL;
+    for (int k = 0; k < n_bands; ++k)
+        if (!std::isfinite(band_error[k])) return SDIRT_EINVAL;
+    if (query->n_wavelengths < 1 || query->n_wavelengths > SDIRT_MAX_LAMBDAS) return SDIRT_EINVAL;
+    // the two sources must agree on what a PSF is: a jointly sum-normalised
+    // float32 [2][ks][ks] block, the network's width-256 fused kernels
+    if (query->normalize != SDIRT_NORM_SUM || query->out_dtype != SDIRT_F32) return SDIRT_EUNSUPPORTED;
+    if (2 * query->ks * query->ks != m.n_out) return SDIRT_EINVAL;
+    if (m.width != 256) return SDIRT_EUNSUPPORTED;
+    RouteArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.points = query->points;
+    ra.n_bands = n_bands;
+    for (int k = 0; k <= n_bands; ++k) ra.edges[k] = band_edges[k];
+    for (int k = 0; k < n_bands; ++k) ra.traced_band[k] = band_error[k] > max_error ? 1 : 0;
+    ra.n_lambda = query->n_wavelengths;
+    for (int l = 0; l < ra.n_lambda; ++l) ra.lambda[l] = (float)query->wavelengths[l];
+    ra.source = source_out;
+    const MlpWs w = carve(m, ws_batch, (char*)workspace);
+    ra.x = w.xb;
+    const long long P = query->n_points;
+    // 1. routing and the network's PSF for every point (traced points are
+    //    overwritten below), chunk by chunk through the workspace
+    for (long long r0 = 0; r0 < P; r0 += ws_batch) {
+        const int nb = (int)std::min<long long>(ws_batch, P - r0);
+        ra.r0 = r0;
+        ra.n = nb;
+        hipLaunchKernelGGL(hybrid_route_kernel, dim3((nb + 255) / 256), dim3(256), 0, st, ra);
+        if ((rc = forward_fused(m, d, w, w.H[m.n_hidden], ws_batch, params, nb, w.xb,
+                                psf_out + r0 * m.n_out, SDIRT_F32, st, r0 == 0)))
+            return rc;
+    }
+    // 2. the tracer for the points routed to it (masked list-mode trace)
+    return trace_dp_psf_impl(lens, sensor, query, psf_out, nullptr, st, 0, source_out);
 }
 
 int mlp_render(const sdirt_mlp_desc* d, const float* params, const sdirt_mlp_render_desc* rd,

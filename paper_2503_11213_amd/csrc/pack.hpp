@@ -20,6 +20,7 @@ struct PointArgs {
     double depths[kMaxD];
     const double* points;        // list mode: device [P][4]
     double m_num, z_ep_ref;      // chief-ray magnification constants
+    const int* mask;             // device [P] or nullptr: trace only points with mask != 0
 };
 
 struct SampleArgs {

@@ -74,6 +74,9 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
     const int q = blockIdx.x / A.smp.chunks;
     const int chunk = blockIdx.x - q * A.smp.chunks;
     const int tid = threadIdx.x;
+    // masked mode: points outside the mask are left as they are (the whole
+    // workgroup leaves before its first barrier)
+    if (A.pts.mask && A.pts.mask[q] == 0) return;
     for (int i = tid; i < (det ? 4 : 2) * kk; i += kBlock) tile[i] = 0.0f;
 
     double hx, hy, depth;
@@ -229,9 +232,12 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
     }
 }
 
-// Joint normalisation of each point's [2][ks][ks] block (sum or max).
+// Joint normalisation of each point's [2][ks][ks] block (sum or max);
+// points outside a mask (if any) are left as they are.
 template <typename OutT>
-__global__ __launch_bounds__(kBlock) void normalize_kernel(OutT* out, int kk2, int mode) {
+__global__ __launch_bounds__(kBlock) void normalize_kernel(OutT* out, int kk2, int mode,
+                                                           const int* mask) {
+    if (mask && mask[blockIdx.x] == 0) return;
     __shared__ double red[kBlock / 64];
     OutT* p = out + (size_t)blockIdx.x * kk2;
     double acc = 0.0;
@@ -252,6 +258,14 @@ __global__ __launch_bounds__(kBlock) void normalize_kernel(OutT* out, int kk2, i
         const double inv = 1.0 / tot;
         for (int i = threadIdx.x; i < kk2; i += kBlock) p[i] = (OutT)((double)p[i] * inv);
     }
+}
+
+// Zero the [P][n_words] blocks of the points with mask != 0.
+__global__ void fill_zero_masked_kernel(uint32_t* p, int P, int n_words, const int* mask) {
+    const int q = blockIdx.x;
+    if (q >= P || mask[q] == 0) return;
+    uint32_t* b = p + (size_t)q * n_words;
+    for (int i = threadIdx.x; i < n_words; i += blockDim.x) b[i] = 0u;
 }
 
 __global__ void fill_zero_kernel(uint32_t* p, size_t n) {
@@ -337,7 +351,8 @@ static int chunks_for(int P, int n_rays) {
 
 int trace_dp_psf_impl(const sdirt_lens* lens, const sdirt_sensor* sensor,
                       const sdirt_psf_query* query, void* psf_out,
-                      double* stats_out, hipStream_t stream, int chunks_override) {
+                      double* stats_out, hipStream_t stream, int chunks_override,
+                      const int* mask) {
     if (!psf_out) return SDIRT_EINVAL;
     Resolved R;
     int rc = resolve_lens(lens, &R);
@@ -355,8 +370,21 @@ int trace_dp_psf_impl(const sdirt_lens* lens, const sdirt_sensor* sensor,
     const int n_rays = A.smp.nx * A.smp.ny;
     const int kk = query->ks * query->ks;
     const size_t elt = query->out_dtype == SDIRT_F64 ? 8 : 4;
-    if ((rc = launch_fill_zero(psf_out, (size_t)P * 2 * kk * elt, stream))) return rc;
-    if (stats_out && (rc = launch_fill_zero(stats_out, (size_t)P * 7 * 8, stream))) return rc;
+    A.pts.mask = mask;
+    if (mask) {
+        // only the masked points' blocks (and statistics) start from zero
+        if (P > 0) {
+            hipLaunchKernelGGL(fill_zero_masked_kernel, dim3(P), dim3(kBlock), 0, stream,
+                               (uint32_t*)psf_out, P, (int)(2 * kk * elt / 4), mask);
+            if (stats_out)
+                hipLaunchKernelGGL(fill_zero_masked_kernel, dim3(P), dim3(64), 0, stream,
+                                   (uint32_t*)stats_out, P, 14, mask);
+        }
+        if (hipGetLastError() != hipSuccess) return SDIRT_ELAUNCH;
+    } else {
+        if ((rc = launch_fill_zero(psf_out, (size_t)P * 2 * kk * elt, stream))) return rc;
+        if (stats_out && (rc = launch_fill_zero(stats_out, (size_t)P * 7 * 8, stream))) return rc;
+    }
     // deterministic mode: one workgroup per point, integer tile
     const int chunks = A.smp.det ? 1
                        : chunks_override > 0 ? std::min(chunks_override, n_rays) : chunks_for(P, n_rays);
@@ -376,10 +404,10 @@ int trace_dp_psf_impl(const sdirt_lens* lens, const sdirt_sensor* sensor,
     if (query->normalize != SDIRT_NORM_NONE) {
         if (query->out_dtype == SDIRT_F64)
             hipLaunchKernelGGL(normalize_kernel<double>, dim3(P), dim3(kBlock), 0, stream,
-                               (double*)psf_out, 2 * kk, query->normalize);
+                               (double*)psf_out, 2 * kk, query->normalize, mask);
         else
             hipLaunchKernelGGL(normalize_kernel<float>, dim3(P), dim3(kBlock), 0, stream,
-                               (float*)psf_out, 2 * kk, query->normalize);
+                               (float*)psf_out, 2 * kk, query->normalize, mask);
         if (hipGetLastError() != hipSuccess) return SDIRT_ELAUNCH;
     }
     return SDIRT_OK;

@@ -377,6 +377,32 @@ def mlp_forward_noalloc(desc, params, x, out_dtype=abi.F32, out=None):
     return out
 
 
+def psf_hybrid(desc, params, lens, sensor, query, points, band_edges, band_error, max_error,
+               workspace, ws_batch, out=None):
+    """PSFs [P][2][ks][ks] (float32) of list-mode points (device float64
+    [P][4]) from the network where its measured error per inverse-depth band
+    is at most max_error, ray traced elsewhere; returns (psf, source) with
+    source [P] int32 (0 network, 1 traced)."""
+    P = int(points.shape[0])
+    ks = int(query.ks)
+    _check_mlp(desc, params, workspace, ws_batch)
+    _expect(points, "points", torch.float64, 4 * P)
+    if out is None:
+        out = torch.empty((P, 2, ks, ks), dtype=torch.float32, device=points.device)
+    _expect(out, "out", torch.float32, P * 2 * ks * ks)
+    src = torch.empty((P,), dtype=torch.int32, device=points.device)
+    L, keep = make_lens(lens)
+    s = make_sensor(sensor)
+    q, keep2 = make_query(query, abi.F64, points)
+    edges, errs = _darr(band_edges), _darr(band_error)
+    rc = abi.lib().sdirt_psf_hybrid(C.byref(desc), _dptr(params), C.byref(L), C.byref(s),
+                                    C.byref(q), len(band_error), edges, errs, float(max_error),
+                                    _dptr(out), _dptr(src), _dptr(workspace), int(ws_batch),
+                                    _stream())
+    abi.check("sdirt_psf_hybrid", rc)
+    return out, src
+
+
 def mlp_render(desc, params, img, depth, wavelengths, pitch, workspace, ws_batch, out=None):
     """Surrogate render: img [N][C][H][W] f32 rendered with the network's PSF
     for every pixel and channel (depth [N][H][W] mm, wavelengths [C] um,
@@ -512,3 +538,25 @@ def mlp_load_checkpoint(path, device="cuda"):
                 "batch": int(meta["batch"])}
     return (desc, t["params"], t["m"], t["v"], int(meta["step"]), int(meta["seed"]),
             int(meta["total_steps"]), schedule)
+
+
+def mlp_save_weights(path, desc, params, meta=None):
+    """Trained network weights to a safetensors file: the float32 parameter
+    vector, the network description and free-form metadata (JSON)."""
+    from safetensors.torch import save_file
+    m = {"desc": json.dumps({n: getattr(desc, n) for n, _ in desc._fields_}),
+         "meta": json.dumps(meta or {})}
+    save_file({"params": params.detach().float().cpu().contiguous()}, path, metadata=m)
+
+
+def mlp_load_weights(path, device="cuda"):
+    """(desc, params, meta) from mlp_save_weights."""
+    from safetensors import safe_open
+    with safe_open(path, framework="pt") as f:
+        md = f.metadata()
+        params = f.get_tensor("params").to(device)
+    dd = json.loads(md["desc"])
+    desc = abi.MlpDesc()
+    for n, _ in abi.MlpDesc._fields_:
+        setattr(desc, n, dd[n])
+    return desc, params, json.loads(md["meta"])

@@ -25,9 +25,10 @@ import torch
 from . import sdirt, _abi as abi
 
 
-def trace_points(lens, sensor, query, pts, rays=None, chunk=65536):
+def trace_points(lens, sensor, query, pts, rays=None, chunk=65536, stats=False):
     """SUM-normalised traced PSFs [n][2 ks ks] (float32, device) at list-mode
-    points (device float64 [n][4])."""
+    points (device float64 [n][4]); with stats=True also the per-point
+    energy statistics [n][7] (before normalisation)."""
     import copy
     q = copy.copy(query)
     if rays is not None:
@@ -35,11 +36,42 @@ def trace_points(lens, sensor, query, pts, rays=None, chunk=65536):
     n = pts.shape[0]
     kk2 = 2 * q.ks * q.ks
     out = torch.empty((n, kk2), dtype=torch.float32, device=pts.device)
+    st = torch.empty((n, 7), dtype=torch.float64, device=pts.device) if stats else None
     for a in range(0, n, chunk):
         b = min(n, a + chunk)
         view = out[a:b].view(b - a, 2, q.ks, q.ks)
-        sdirt.trace_dp_psf(lens, sensor, q, points=pts[a:b].contiguous(), out=view, stats=False)
-    return out
+        _, s_ = sdirt.trace_dp_psf(lens, sensor, q, points=pts[a:b].contiguous(), out=view,
+                                   stats=stats)
+        if stats:
+            st[a:b] = s_
+    return (out, st) if stats else out
+
+
+def band_report(err, iv, hx, hy, in_window, x_half, y_half, iv_lo, iv_hi, n_bands=9):
+    """Mean and median energy L1 of the network per band of inverse depth and
+    per band of field radius, with the mean in-window energy fraction of the
+    reference there (below 1 where the blur disc spills out of the window)."""
+    import numpy as np
+    rep = {"inverse_depth": [], "field_radius": []}
+    edges = np.linspace(iv_lo, iv_hi, n_bands + 1)
+    for k in range(n_bands):
+        m = (iv >= edges[k]) & (iv <= edges[k + 1])
+        if m.any():
+            rep["inverse_depth"].append({
+                "iv_per_m": [float(edges[k] * 1e3), float(edges[k + 1] * 1e3)],
+                "points": int(m.sum()), "l1_mean": float(err[m].mean()),
+                "l1_median": float(np.median(err[m])),
+                "in_window": float(in_window[m].mean())})
+    rad = np.hypot(hx / x_half, hy / y_half) / np.sqrt(2.0)
+    redges = np.linspace(0.0, 1.0, 6)
+    for k in range(5):
+        m = (rad >= redges[k]) & (rad <= redges[k + 1])
+        if m.any():
+            rep["field_radius"].append({
+                "relative": [float(redges[k]), float(redges[k + 1])],
+                "points": int(m.sum()), "l1_mean": float(err[m].mean()),
+                "in_window": float(in_window[m].mean())})
+    return rep
 
 
 def energy_l1(pred, ref):
@@ -57,6 +89,7 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--reference-rays", type=int, default=8192)
     ap.add_argument("--loss", choices=["kl", "l2max"], default="kl")
+    ap.add_argument("--save", default=None, help="write the trained weights (safetensors)")
     args = ap.parse_args()
     dev = torch.device("cuda", 0)
     lens, sensor, query = configs.config4()
@@ -102,11 +135,22 @@ def main():
     # held-out error, against the tracer at more rays
     hpts, hx = configs.surrogate_points(args.heldout, seed=2)
     hpts_t = torch.from_numpy(hpts).to(dev)
-    reference = trace_points(lens, sensor, query, hpts_t, rays=args.reference_rays, chunk=4096)
+    reference, ref_st = trace_points(lens, sensor, query, hpts_t, rays=args.reference_rays,
+                                     chunk=4096, stats=True)
     hx_t = torch.from_numpy(hx).to(dev)
     ws_inf = sdirt.mlp_workspace(desc, 4096)
     pred = sdirt.mlp_forward(desc, params, hx_t, ws_inf, 4096)
     e_mlp = energy_l1(pred, reference)
+    if args.save:
+        sdirt.mlp_save_weights(args.save, desc, params,
+                               {"samples": args.samples, "steps": args.steps,
+                                "batch": args.batch, "lr": args.lr, "loss": args.loss,
+                                "heldout_energy_l1_mean": float(e_mlp.mean())})
+    st = ref_st.cpu().numpy()
+    kw = configs.config4_desc_kwargs()
+    rec["bands"] = band_report(e_mlp.cpu().numpy(), hx[:, 2].astype(np.float64), hx[:, 0],
+                               hx[:, 1], (st[:, 3] + st[:, 4]) / st[:, 0], kw["x_half"],
+                               kw["y_half"], kw["iv_lo"], kw["iv_hi"])
     kk2 = pred.shape[1]
     rec["heldout"] = {"points": args.heldout, "reference_rays": args.reference_rays ** 2,
                       "mlp_energy_l1_mean": float(e_mlp.mean()),

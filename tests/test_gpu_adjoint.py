@@ -1,5 +1,7 @@
 """GPU adjoint of the trace + splat against float64 central finite
 differences of the oracle's estimator (frozen framing), through the C ABI."""
+import copy
+
 import numpy as np
 import pytest
 import torch
@@ -95,3 +97,41 @@ def test_adjoint_config3_full_size_properties():
     psf2, _ = sdirt.trace_dp_psf(lens, s3, query)
     fd = ((G1 * (psf1 - psf2)).sum() / (2e-3 * sensor.sigmoid_k)).item()
     assert g1[-1].item() == pytest.approx(fd, rel=2e-3)
+
+
+def test_adjoint_config3_full_grid_matches_fd():
+    # the config-3 grid (8 fields x 8 depths x 3 wavelengths = 192 points,
+    # ks 41, tent splat) at 64 x 64 rays per point: the GPU adjoint against
+    # the oracle's per-ray central differences for curvatures, thicknesses,
+    # the sensor distance and the response slope
+    lens, sensor, query = configs.config3(rays=64)
+    S = len(lens.surfaces)
+    kinds = [s.kind for s in lens.surfaces]
+    params = [8 * s for s in (0, 2, 7, 9, 11)] + [8 * s + 1 for s in (0, 4, 10)] + \
+             [8 * (S - 1) + 1, 8 * S]
+    assert all(kinds[p // 8] != 2 for p in params if p < 8 * S and p % 8 == 0)
+    G = np.random.default_rng(13).normal(size=(query.n_points, 2, 41, 41)).astype(np.float32)
+    print("config-3 grid adjoint on the GPU", flush=True)
+    g_gpu = sdirt.trace_dp_psf_backward(lens, sensor, query, torch.from_numpy(G).cuda()).cpu().numpy()
+    est = A.FrozenEstimator(lens, sensor, query)
+    # step sizes from the landing sensitivity of a subset of the points
+    sub = copy.copy(query)
+    sub.fields, sub.depths = query.fields[::3], query.depths[::3]
+    est_sub = A.FrozenEstimator(lens, sensor, sub)
+    G64 = G.astype(np.float64)
+    fd = {}
+    for p in params:
+        if p == 8 * S:
+            h = 1.0
+        else:
+            sens = est_sub.landing_sensitivity(p, 1e-7 * max(abs(est_sub.theta0[p]), 1e-3))
+            h = 1e-6 / max(sens, 1e-12)
+        fd[p] = est.ray_fd_gradient(G64, p, h)
+        if p in params[:2]:
+            # the difference quotient has converged well below the bar
+            half = est.ray_fd_gradient(G64, p, h / 2)
+            assert abs(fd[p] - half) <= 1e-5 * max(abs(half), 1e-12), (p, fd[p], half)
+        print("param", p, "gpu %.9e fd %.9e" % (g_gpu[p], fd[p]), flush=True)
+    scale = max(abs(v) for v in fd.values())
+    for p, b in fd.items():
+        assert abs(g_gpu[p] - b) <= REL * max(abs(b), 1e-3 * scale), (p, g_gpu[p], b)

@@ -329,3 +329,50 @@ def test_bank_kernel_gradient(ks, two_d):
     err = np.max(np.abs(got - ref)) / np.abs(ref).max()
     print("bank kernel gradient max err / max", err)
     assert err <= 1e-5
+
+
+def test_bank_config5_full_batch_sampled_pixels():
+    # the benchmarked launch of the largest workload: 16 RGB 4032 x 3024
+    # images, 64 x 32 x 3 bank (ks 65), forward and image adjoint; sampled
+    # pixels of images 0 and 15 (corners, both sides of the mirror lines,
+    # random) against the oracle's per-pixel bank render and adjoint
+    from workloads import configs
+    lens, sensor, query = configs.config5(rays=8)
+    N, C, H, W, ks = 16, 3, sensor.height_px, sensor.width_px, query.ks
+    F, D, L, ps = len(query.fields), len(query.depths), 3, sensor.pitch
+    rng = np.random.default_rng(51)
+    bank = rng.uniform(0, 1, (F, D, L, 2, ks, ks)).astype(np.float32)
+    radii = [f[0] for f in query.fields]
+    iv = [1.0 / d for d in query.depths]
+    img = rng.uniform(0, 1, (N, C, H, W)).astype(np.float32)
+    dms = [scenes.depth_voronoi(H, W, 100.0, 5000.0, seed=200 + k) for k in range(4)]
+    dmap = np.stack([dms[k % 4] for k in range(N)])
+    loc = list(configs.LAMBDA_OF_RGB)
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps)
+    bt, dt = torch.from_numpy(bank).cuda(), torch.from_numpy(dmap).cuda()
+    print("config-5 batch: forward", flush=True)
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), bt, depth=dt)
+    cy, cx = (H - 1) // 2, (W - 1) // 2
+    pix = []
+    for n in (0, N - 1):
+        pix += [(n, 0, 0), (n, 0, W - 1), (n, H - 1, 0), (n, H - 1, W - 1),
+                (n, cy, cx), (n, cy + 1, cx + 1), (n, cy, cx + 1), (n, cy + 1, cx),
+                (n, 5, cx), (n, H - 3, cx + 1), (n, cy, 2), (n, cy + 1, W - 2)]
+        pix += [(n, int(rng.integers(H)), int(rng.integers(W))) for _ in range(12)]
+    got = np.stack([out[n, :, y, x].cpu().numpy() for (n, y, x) in pix])
+    del out
+    ref = R.render_bank_pixels(img, bank, dmap, radii, iv, loc, ps, pix)
+    err = np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max()))
+    print("config-5 forward max rel err %.2e" % err, flush=True)
+    assert err <= REL_TOL
+    print("config-5 batch: adjoint", flush=True)
+    g = rng.normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, bt, torch.from_numpy(g).cuda(), depth=dt)
+    got = np.stack([gi[n, :, y, x].cpu().numpy() for (n, y, x) in pix])
+    del gi
+    ref = R.render_bank_adjoint_pixels(g, bank, dmap, radii, iv, loc, ps, pix)
+    err = np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max()))
+    print("config-5 adjoint max rel err %.2e" % err, flush=True)
+    assert err <= REL_TOL

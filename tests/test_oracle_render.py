@@ -243,3 +243,22 @@ def test_bank_pixels_equal_the_bank_render_everywhere(H, W):
     fi, di, mx, my = R.bank_lookup(H, W, dmap[0], radii, iv, ps)
     assert {(a, b) for a, b in zip(mx.ravel(), my.ravel())} == {(False, False), (False, True),
                                                                 (True, False), (True, True)}
+
+
+@pytest.mark.parametrize("H,W", [(9, 12), (10, 11)])
+def test_bank_adjoint_pixels_equal_the_bank_adjoint_everywhere(H, W):
+    # the per-pixel image adjoint used for sampled full-size parity is the
+    # bank adjoint itself, border pixels (where clamped taps fold) included
+    N, C, ks, ps = 2, 2, 5, 0.01
+    rng = np.random.default_rng(32)
+    g = rng.normal(size=(N, 2 * C, H, W))
+    bank = rng.uniform(0, 1, (4, 3, 2, 2, ks, ks))
+    radii = [0.0, 0.02, 0.04, 0.06]
+    iv = [1 / 5000.0, 1 / 2000.0, 1 / 500.0]
+    dmap = rng.uniform(500, 5000, (N, H, W)).astype(np.float32)
+    loc = [1, 0]
+    full = R.render_bank_adjoint(g, bank, dmap, radii, iv, loc, ps)
+    pix = [(n, y, x) for n in range(N) for y in range(H) for x in range(W)]
+    got = R.render_bank_adjoint_pixels(g, bank, dmap, radii, iv, loc, ps, pix)
+    ref = np.stack([full[n, :, y, x] for (n, y, x) in pix])
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
