@@ -252,33 +252,15 @@ def extras(dev, stream):
                            "kernel_grad_hbm_frac": nbytes / tk / 1e6 / PEAK_HBM_GBS}
     del K, gK, gout, gi, o
     print("dense render done", file=sys.stderr, flush=True)
-    # 3. MLP inference vs tracing at ks 33 (12-surface lens, 512^2 rays)
-    lens, sensor, query = configs.config4()
-    pts, x = configs.surrogate_points(65536, seed=3)
-    pts_t = torch.from_numpy(pts).to(dev)
-    tq = torch.empty((65536, 2, 33, 33), device=dev)
-    tr = lambda: sdirt.trace_dp_psf(lens, sensor, query, points=pts_t, out=tq, stats=False)
-    tr()
-    t_trace = timed(tr, stream, 2)
-    desc = sdirt.make_mlp_desc(n_out=2 * 33 * 33, **configs.config4_desc_kwargs())
-    layers = scenes.mlp_init([64, 256, 256, 256, 256, 256, 2178], seed=0)
-    params = torch.from_numpy(np.concatenate([np.concatenate([Wt.ravel(), bt]) for Wt, bt in layers]).astype(np.float32)).to(dev)
-    nrow = 1 << 20
-    xb = torch.from_numpy(np.tile(x, (nrow // 65536, 1))).to(dev)
-    ob = torch.empty((nrow, 2178), dtype=torch.bfloat16, device=dev)
+    # 3. the trained surrogate (workloads/surrogate_ks33.safetensors, written by
+    #    the surrogate workflow: 200k traced PSFs, 20k steps) against tracing
+    #    at ks 33 on the 12-surface lens: its error on fresh points against
+    #    8192^2-ray traces, its speed against tracing at the ray count of the
+    #    same error, and the network with the tracer as fallback at <= 2 %
+    out["mlp_vs_trace"] = surrogate_vs_trace(dev, stream)
+    desc, params, _ = sdirt.mlp_load_weights(
+        os.path.join(ROOT, "workloads", "surrogate_ks33.safetensors"), device=dev)
     ws = sdirt.mlp_workspace(desc, 65536)
-    inf = lambda: sdirt.mlp_forward(desc, params, xb, ws, 65536, out_dtype=abi.BF16, out=ob)
-    inf()
-    t_mlp = timed(inf, stream, 2)
-    flop = nrow * 2.0 * (64 * 256 + 4 * 256 * 256 + 256 * 2178)
-    out["mlp_vs_trace"] = {"workload": "ks 33, 12-surface lens; trace 65536 PSFs x 512^2 rays; "
-                                       "MLP 2^20 PSFs, bf16 out",
-                           "trace_psfs_per_s": 65536 / (t_trace * 1e-3),
-                           "mlp_psfs_per_s": nrow / (t_mlp * 1e-3),
-                           "speedup": (nrow / t_mlp) / (65536 / t_trace),
-                           "mlp_tflops": flop / (t_mlp * 1e-3) / 1e12,
-                           "mlp_mfma_frac": flop / (t_mlp * 1e-3) / 2.5e15}
-    del xb, ob, tq
     # 3b. the surrogate workload end to end: per-pixel MLP PSFs (bf16, one per
     #     pixel and wavelength) for a batch of 8 images of 1680 x 1120 RGB,
     #     each image's dense map then rendered (24.6 GB per image)
@@ -398,6 +380,78 @@ def extras(dev, stream):
     out["config2"] = config2_step(dev, stream)
     print("12-surface lens done", file=sys.stderr, flush=True)
     return out
+
+
+def surrogate_vs_trace(dev, stream):
+    import copy
+    import numpy as np
+    import torch
+    from workloads import configs
+    from paper_2503_11213_amd import sdirt, _abi as abi
+    from paper_2503_11213_amd.surrogate import trace_points, energy_l1
+    desc, params, meta = sdirt.mlp_load_weights(
+        os.path.join(ROOT, "workloads", "surrogate_ks33.safetensors"), device=dev)
+    lens, sensor, query = configs.config4()
+    n_eval = 512
+    hp, hx = configs.surrogate_points(n_eval, seed=21)       # points the training never saw
+    hp_t, hx_t = torch.from_numpy(hp).to(dev), torch.from_numpy(hx).to(dev)
+    ref = trace_points(lens, sensor, query, hp_t, rays=8192, chunk=256)
+    ws = sdirt.mlp_workspace(desc, 4096)
+    e_net = float(energy_l1(sdirt.mlp_forward(desc, params, hx_t, ws, 4096), ref).mean())
+    ray_counts = (256, 512, 1024)
+    e_tr = {r: float(energy_l1(trace_points(lens, sensor, query, hp_t, rays=r), ref).mean())
+            for r in ray_counts}
+    # throughput: the network on 2^20 rows (bf16 out), tracing 16384 points
+    nrow = 1 << 20
+    _, xr = configs.surrogate_points(nrow, seed=22)
+    xr = torch.from_numpy(xr).to(dev)
+    ob = torch.empty((nrow, desc.n_out), dtype=torch.bfloat16, device=dev)
+    wsb = sdirt.mlp_workspace(desc, 65536)
+    inf = lambda: sdirt.mlp_forward(desc, params, xr, wsb, 65536, out_dtype=abi.BF16, out=ob)
+    inf()
+    t_net = timed(inf, stream, 3)
+    net_rate = nrow / (t_net * 1e-3)
+    tp, _ = configs.surrogate_points(16384, seed=23)
+    tp = torch.from_numpy(tp).to(dev)
+    tbuf = torch.empty((16384, 2 * 33 * 33), device=dev)
+    rate = {}
+    for r in ray_counts:
+        q = copy.copy(query)
+        q.rays_x = q.rays_y = r
+        f = lambda: sdirt.trace_dp_psf(lens, sensor, q, points=tp, out=tbuf.view(-1, 2, 33, 33),
+                                       stats=False)
+        f()
+        rate[r] = 16384 / (timed(f, stream, 2) * 1e-3)
+    matched = min([r for r in ray_counts if e_tr[r] <= e_net], default=None)
+    # the network with the tracer (1024^2 rays) as fallback, by the held-out
+    # error per inverse-depth band stored with the weights, bar 2 %
+    edges, errs = meta["band_edges_inv_mm"], meta["band_energy_l1"]
+    q1k = copy.copy(query)
+    q1k.rays_x = q1k.rays_y = 1024
+    ph, src = sdirt.psf_hybrid(desc, params, lens, sensor, q1k, hp_t, edges, errs, 0.02, ws, 4096)
+    e_h = float(energy_l1(ph.view(n_eval, -1), ref).mean())
+    hyb = lambda: sdirt.psf_hybrid(desc, params, lens, sensor, q1k, tp, edges, errs, 0.02, ws,
+                                   4096, out=tbuf.view(-1, 2, 33, 33))
+    _, src_t = hyb()
+    h_rate = 16384 / (timed(hyb, stream, 2) * 1e-3)
+    flop = nrow * 2.0 * (64 * 256 + 4 * 256 * 256 + 256 * 2178)
+    return {"workload": "ks 33, 12-surface lens; trained network (%s); %d fresh points against "
+                        "8192^2-ray traces; network rate on 2^20 rows (bf16 out), tracing and "
+                        "fallback rates on 16384 points" % (meta.get("loss", "kl"), n_eval),
+            "network_energy_l1": e_net,
+            "trace_energy_l1": {str(r): e for r, e in e_tr.items()},
+            "network_psfs_per_s": net_rate,
+            "trace_psfs_per_s": {str(r): v for r, v in rate.items()},
+            "trace_rays_at_network_error": matched,
+            "speedup_at_network_error": net_rate / rate[matched] if matched else None,
+            "mlp_tflops": flop / (t_net * 1e-3) / 1e12,
+            "mlp_mfma_frac": flop / (t_net * 1e-3) / 2.5e15,
+            "fallback": {"bar": 0.02, "tracer_rays": 1024 * 1024,
+                         "energy_l1": e_h, "traced_fraction": float(src.float().mean()),
+                         "traced_fraction_rate_points": float(src_t.float().mean()),
+                         "psfs_per_s": h_rate,
+                         "speedup_over_tracing_at_2pc": h_rate / rate[1024],
+                         "tracing_energy_l1_at_1024": e_tr[1024]}}
 
 
 def config2_step(dev, stream, reps=5):

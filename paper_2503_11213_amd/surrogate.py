@@ -141,16 +141,22 @@ def main():
     ws_inf = sdirt.mlp_workspace(desc, 4096)
     pred = sdirt.mlp_forward(desc, params, hx_t, ws_inf, 4096)
     e_mlp = energy_l1(pred, reference)
-    if args.save:
-        sdirt.mlp_save_weights(args.save, desc, params,
-                               {"samples": args.samples, "steps": args.steps,
-                                "batch": args.batch, "lr": args.lr, "loss": args.loss,
-                                "heldout_energy_l1_mean": float(e_mlp.mean())})
     st = ref_st.cpu().numpy()
     kw = configs.config4_desc_kwargs()
     rec["bands"] = band_report(e_mlp.cpu().numpy(), hx[:, 2].astype(np.float64), hx[:, 0],
                                hx[:, 1], (st[:, 3] + st[:, 4]) / st[:, 0], kw["x_half"],
                                kw["y_half"], kw["iv_lo"], kw["iv_hi"])
+    if args.save:
+        # the weights, with the held-out error per inverse-depth band (the
+        # table the network-with-tracer-fallback entry point routes by)
+        b = rec["bands"]["inverse_depth"]
+        sdirt.mlp_save_weights(args.save, desc, params, {
+            "samples": args.samples, "steps": args.steps, "batch": args.batch, "lr": args.lr,
+            "loss": args.loss, "heldout_energy_l1_mean": float(e_mlp.mean()),
+            "heldout_points": args.heldout, "reference_rays": args.reference_rays ** 2,
+            "band_edges_inv_mm": [x["iv_per_m"][0] * 1e-3 for x in b] + [b[-1]["iv_per_m"][1] * 1e-3],
+            "band_energy_l1": [x["l1_mean"] for x in b],
+            "band_points": [x["points"] for x in b]})
     kk2 = pred.shape[1]
     rec["heldout"] = {"points": args.heldout, "reference_rays": args.reference_rays ** 2,
                       "mlp_energy_l1_mean": float(e_mlp.mean()),

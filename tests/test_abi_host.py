@@ -240,3 +240,15 @@ def test_trainer_checkpoint_round_trip(tmp_path):
     assert sched == {"lr0": 1.5e-3, "lr_min": 2.5e-5, "batch": 1024}
     for name, _ in abi.MlpDesc._fields_:
         assert getattr(d2, name) == getattr(d, name), name
+
+
+def test_committed_surrogate_weights_load():
+    # the trained network bench.py times: its description, parameter count and
+    # the held-out error table the fallback routes by (host only)
+    desc, params, meta = sdirt.mlp_load_weights(
+        os.path.join(os.path.dirname(__file__), "..", "workloads", "surrogate_ks33.safetensors"),
+        device="cpu")
+    assert (desc.n_hidden, desc.width, desc.n_out, desc.n_freq) == (5, 256, 2178, 8)
+    assert params.numel() == sdirt.mlp_n_params(desc) == 839554
+    assert len(meta["band_edges_inv_mm"]) == len(meta["band_energy_l1"]) + 1
+    assert all(b > a for a, b in zip(meta["band_edges_inv_mm"], meta["band_edges_inv_mm"][1:]))
