@@ -32,7 +32,7 @@ struct LensArgs {
     double inv_c[kMaxS];        // 1/c for spheres with |c| >= 1e-6 per mm, else 0
     double tprev[kMaxS];        // distance from the previous vertex (0 for s=0)
     double semi2[kMaxS];        // squared clear semi-diameter
-    double asph[kMaxAsph][6];   // conic, a4, a6, a8, a10, a12
+    double asph[kMaxAsph][7];   // conic, a4, a6, a8, a10, a12, 1 / ((1 + conic) c) or 0
     double sensor_dist;         // last vertex -> sensor plane
 };
 
@@ -199,19 +199,24 @@ template <> __device__ inline float sqrt_pos<float>(float v) {
     return __builtin_amdgcn_sqrtf(v);
 }
 
-// Even-asphere surface constants, read once per surface.
+// Even-asphere surface constants, read once per surface.  inv_kc =
+// 1 / ((1 + k) c) when |(1 + k) c| >= 1e-3 per mm (host), else 0.
 template <typename T>
 struct Asph {
-    T c, kc2, a4, a6, a8, a10, a12;
+    T c, kc2, a4, a6, a8, a10, a12, inv_kc;
     __device__ Asph(const double* co, T cc)
         : c(cc), kc2((T(1) + (T)co[0]) * cc * cc), a4((T)co[1]), a6((T)co[2]), a8((T)co[3]),
-          a10((T)co[4]), a12((T)co[5]) {}
+          a10((T)co[4]), a12((T)co[5]), inv_kc((T)co[6]) {}
 };
 
 // Even-asphere sag and its derivative in rho = r^2; *ok is false where the
 // conic root is imaginary.  EXACT_D: derivative from the refined 1/sqrt;
 // otherwise from the raw hardware value (for Newton steps, whose
-// convergence a 5e-8 relative error in the slope does not spoil).
+// convergence a 5e-8 relative error in the slope does not spoil).  The conic
+// part c rho / (1 + q), q = sqrt(1 - (1 + k) c^2 rho), equals
+// (1 - q) / ((1 + k) c): with that reciprocal from the host it takes no
+// division (absolute error about eps / |(1 + k) c| <= 1.1e-13 mm at the
+// host's threshold); nearly parabolic or flat surfaces keep the quotient.
 template <typename T, bool EXACT_D>
 __device__ __forceinline__ void asphere_sag(const Asph<T>& S, T rho, T* sag, T* dsag, bool* ok) {
     const T arg = T(1) - S.kc2 * rho;
@@ -221,7 +226,9 @@ __device__ __forceinline__ void asphere_sag(const Asph<T>& S, T rho, T* sag, T* 
     const T s0 = a * y;
     const T q = fma(T(0.5) * y, fma(-s0, s0, a), s0);                 // sqrt(a)
     const T iq = EXACT_D ? y * fma(T(-0.5) * a * y, y, T(1.5)) : y;   // 1 / sqrt(a)
-    *sag = S.c * rho * rcp_t<T>(T(1) + q) +
+    const T conic = S.inv_kc != T(0) ? fma(-q, S.inv_kc, S.inv_kc)
+                                     : S.c * rho * rcp_t<T>(T(1) + q);
+    *sag = conic +
            rho * rho * (S.a4 + rho * (S.a6 + rho * (S.a8 + rho * (S.a10 + rho * S.a12))));
     *dsag = T(0.5) * S.c * iq +
             rho * (T(2) * S.a4 + rho * (T(3) * S.a6 + rho * (T(4) * S.a8 +

@@ -21,6 +21,9 @@ int pack_lens(const Resolved& R, LensArgs* A) {
             slot = nas;
             A->asph[nas][0] = R.conic[s];
             for (int m = 0; m < 5; ++m) A->asph[nas][m + 1] = R.asph[5 * s + m];
+            // reciprocal of (1 + k) c for the division-free conic sag
+            const double kc = (1.0 + R.conic[s]) * R.c[s];
+            A->asph[nas][6] = std::fabs(kc) >= 1e-3 ? 1.0 / kc : 0.0;
             ++nas;
         }
         A->code[s] = (R.kind[s] & 0x7f) | (A->inv_c[s] != 0.0 ? 0x80 : 0) |
