@@ -19,6 +19,7 @@ SPLAT_BOX, SPLAT_TENT = 0, 1
 NORM_NONE, NORM_SUM, NORM_MAX = 0, 1, 2
 F32, F64, BF16 = 0, 1, 2
 SRC_DENSE, SRC_BANK, SRC_BANK2D = 0, 1, 2
+BANK_FP32, BANK_SPLIT_BF16 = 0, 1
 LOSS_L2MAX, LOSS_KL = 0, 1
 MAX_SURFACES = 24
 
@@ -73,7 +74,8 @@ class RenderDesc(C.Structure):
                 ("field_radii", C.POINTER(C.c_double)),
                 ("inv_depths", C.POINTER(C.c_double)),
                 ("lambda_of_channel", C.c_int * 4), ("pitch", C.c_double),
-                ("bank_fields_y", C.c_int), ("field_y", C.POINTER(C.c_double))]
+                ("bank_fields_y", C.c_int), ("field_y", C.POINTER(C.c_double)),
+                ("bank_math", C.c_int)]
 
 
 class MlpDesc(C.Structure):

@@ -40,6 +40,7 @@ struct RenderArgs {
     int lam_of_c[4];
     int tiles_x, tiles_y;
     int use_fast;        // bank source: grouped kernels when ks allows
+    int split;           // bank source: split-bf16 matrix cores (forward)
     const float* img;
     const void* psf;
     const float* depth;
@@ -664,22 +665,198 @@ __device__ inline void bank_kgrad_chunk(const RenderArgs& A, int n, int c, int y
     }
 }
 
-// KGRAD: instead of the output, the gradient with respect to the bank
-// entries (see bank_kgrad_chunk); grad is the bank-shaped accumulator.
-template <int KS, bool KGRAD>
+// ---- split-bf16 forward ----------------------------------------------------
+//
+// The same entry-grouped chunks on the bf16 matrix cores: every float32
+// operand x is split into x_hi = bf16(x) and x_lo = bf16(x - x_hi), and a
+// product is taken as A_hi B_hi + A_hi B_lo + A_lo B_hi (the dropped
+// A_lo B_lo and the residuals of the splits are below 2^-16 of it), summed in
+// float32 by v_mfma_f32_16x16x32_bf16.  For one chunk, the contraction runs
+// over (kernel row i, window column p): 8 consecutive window columns of one
+// row form a k-group, P = the strip window rounded up to 8 columns, so a row
+// is G = P / 8 groups and R consecutive rows (R G a multiple of 4) make T =
+// R G / 4 k-steps of 32.  Lane (m, kg) of the A operand (m = (side, q) output
+// row, kg = k-group) needs 8 consecutive taps of the reversed kernel row
+// starting at 8 pg - q: each wave stages, per R rows, four copies of each
+// reversed row pair shifted by q mod 4 (hi and lo), so every lane reads its
+// 8 taps as two aligned 8-byte LDS reads; the B operand (image windows) is
+// read from hi and lo bf16 halos as aligned 16-byte LDS reads.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+
+template <int KS>
+struct SplitGeom {
+    static constexpr int P = ((KS + kStrip - 1 + 7) / 8) * 8;   // window columns per row
+    static constexpr int G = P / 8;                              // k-groups per row
+    static constexpr int R = (G % 4 == 0) ? 1 : ((G % 2 == 0) ? 2 : 4);   // rows per super-step
+    static constexpr int T = R * G / 4;                          // k-steps per super-step
+    static constexpr int NSS = (KS + R - 1) / R;                 // super-steps
+    static constexpr int PB = P + 4;                             // staged copy: index w = v + 4
+    static constexpr int RRW = KS + 24;                          // float32 reversed row, u at 8 + u
+    static constexpr int NCOPY = R * 2 * 4;                      // (row, side, shift) copies
+    static constexpr int STAGE = NCOPY * PB;                     // bf16 per hi (or lo) block
+    static constexpr int NPAIR = STAGE / 2;                      // bf16 pairs per block
+    static constexpr int NTAP = R * 2 * KS;                      // kernel taps per super-step
+    static constexpr int SCRATCH = STAGE + R * 2 * RRW;          // floats per wave
+    static constexpr int HWB = kGT - kStrip + P + 8;             // halo row stride (bf16)
+    static constexpr int HH = kGT + KS - 1;
+    static_assert((R * G) % 4 == 0, "whole k-steps per super-step");
+    static_assert(PB % 4 == 0 && HWB % 8 == 0, "aligned fragment reads");
+};
+
+__device__ inline void split_bf16(float v, __bf16* hi, __bf16* lo) {
+    const __bf16 h = (__bf16)v;
+    *hi = h;
+    *lo = (__bf16)(v - (float)h);
+}
+
+// One lane's share of a super-step's raw taps: element e = lane + 64 k of
+// [R rows][2 sides][KS] (reversed-row order u), read from the entry with its
+// mirrors applied; rows past the kernel read as zero.
+template <int KS>
+struct SplitTaps {
+    using S = SplitGeom<KS>;
+    static constexpr int NL = (S::NTAP + 63) / 64;
+    float v[NL];
+    __device__ void load(const float* __restrict__ entry, int i0, bool fx, bool fy, int lane) {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int e = lane + 64 * k;
+            const int r = e / (2 * KS), rem = e - r * 2 * KS;
+            const int side = rem >= KS, u = rem - side * KS;
+            const int i = i0 + r;
+            float x = 0.f;
+            if (e < S::NTAP && i < KS) {
+                const int ri = fy ? KS - 1 - i : i;
+                // output side s reads the stored side s, or 1 - s mirrored in x;
+                // reversed row: R_s[u] = K_s[i][KS - 1 - u]
+                x = fx ? entry[(size_t)(1 - side) * KS * KS + ri * KS + u]
+                       : entry[(size_t)side * KS * KS + ri * KS + KS - 1 - u];
+            }
+            v[k] = x;
+        }
+    }
+    __device__ void store(float* rr, int lane) const {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int e = lane + 64 * k;
+            if (e < S::NTAP) {
+                const int r = e / (2 * KS), rem = e - r * 2 * KS;
+                const int side = rem >= KS, u = rem - side * KS;
+                rr[(r * 2 + side) * S::RRW + 8 + u] = v[k];
+            }
+        }
+    }
+};
+
+// Shifted hi/lo copies of a super-step's reversed rows: copy (r, side, c)
+// holds C_c[w - 4] = R[w - 4 - c], zero outside the row, for w in [0, PB).
+template <int KS>
+__device__ inline void split_build_copies(const float* rr, uint32_t* st_hi, uint32_t* st_lo,
+                                          int lane) {
+    using S = SplitGeom<KS>;
+    for (int e = lane; e < S::NPAIR; e += 64) {
+        const int copy = e / (S::PB / 2), wp = e - copy * (S::PB / 2);
+        const int c = copy & 3, rs = copy >> 2;               // rs = r * 2 + side
+        const float* row = rr + rs * S::RRW + 8;
+        const int u = 2 * wp - 4 - c;                         // >= -7, < P: inside the margins
+        __bf16 h0, l0, h1, l1;
+        split_bf16(row[u], &h0, &l0);
+        split_bf16(row[u + 1], &h1, &l1);
+        st_hi[e] = (uint32_t)__builtin_bit_cast(uint16_t, h0) |
+                   ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+        st_lo[e] = (uint32_t)__builtin_bit_cast(uint16_t, l0) |
+                   ((uint32_t)__builtin_bit_cast(uint16_t, l1) << 16);
+    }
+}
+
+// Rows of one chunk on the split-bf16 path: NG groups of 16 strips.
+template <int KS, int NG>
+__device__ inline void bank_split_rows(const float* __restrict__ entry, bool fx, bool fy,
+                                       const __bf16* hhi, const __bf16* hlo, float* scratch,
+                                       int lane, const int (&bofs)[4], floatx4_t (&out)[4]) {
+    using S = SplitGeom<KS>;
+    uint32_t* st_hi = reinterpret_cast<uint32_t*>(scratch);
+    uint32_t* st_lo = st_hi + S::STAGE / 2;
+    float* rr = scratch + S::STAGE;
+    const int m = lane & 15, kg = lane >> 4;
+    const int side = m >> 3, q = m & 7;
+    const int c = q & 3;
+    const int wq = 4 - 4 * (q >> 2);                           // w offset of the lane's reads
+    floatx4_t acc[NG];
+#pragma unroll
+    for (int u = 0; u < NG; ++u) acc[u] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    SplitTaps<KS> taps;
+    taps.load(entry, 0, fx, fy, lane);
+    for (int ss = 0; ss < S::NSS; ++ss) {
+        taps.store(rr, lane);
+        if (ss + 1 < S::NSS) taps.load(entry, (ss + 1) * S::R, fx, fy, lane);
+        split_build_copies<KS>(rr, st_hi, st_lo, lane);
+        const __bf16* ahi = reinterpret_cast<const __bf16*>(st_hi);
+        const __bf16* alo = reinterpret_cast<const __bf16*>(st_lo);
+#pragma unroll
+        for (int t = 0; t < S::T; ++t) {
+            const int g = 4 * t + kg;                         // k-group of this lane
+            const int ir = g / S::G, pg = g - ir * S::G;      // row in the super-step, column group
+            const int aoff = ((ir * 2 + side) * 4 + c) * S::PB + 8 * pg + wq;
+            bf16x8_t a_hi, a_lo;
+            {
+                const bf16x4_t h0 = *reinterpret_cast<const bf16x4_t*>(ahi + aoff);
+                const bf16x4_t h1 = *reinterpret_cast<const bf16x4_t*>(ahi + aoff + 4);
+                const bf16x4_t l0 = *reinterpret_cast<const bf16x4_t*>(alo + aoff);
+                const bf16x4_t l1 = *reinterpret_cast<const bf16x4_t*>(alo + aoff + 4);
+                a_hi = bf16x8_t{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+                a_lo = bf16x8_t{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+            }
+            // rows past the kernel (the last super-step's padding) carry
+            // zero taps; their image rows are clamped into the halo so that
+            // the zero products stay finite
+            const int brow = -min(ss * S::R + ir, KS - 1) * S::HWB + 8 * pg;
+            bf16x8_t b_hi[NG], b_lo[NG];
+#pragma unroll
+            for (int u = 0; u < NG; ++u) {
+                b_hi[u] = *reinterpret_cast<const bf16x8_t*>(hhi + bofs[u] + brow);
+                b_lo[u] = *reinterpret_cast<const bf16x8_t*>(hlo + bofs[u] + brow);
+            }
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_hi[u], acc[u], 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_lo[u], acc[u], 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, b_hi[u], acc[u], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NG; ++u) out[u] = acc[u];
+}
+
+// MODE: kBankFwd (fp32 matrix cores), kBankKGrad (gradient with respect to
+// the bank entries, see bank_kgrad_chunk; grad is the bank-shaped
+// accumulator), kBankSplit (split-bf16 matrix cores).
+enum BankMode { kBankFwd = 0, kBankKGrad = 1, kBankSplit = 2 };
+
+template <int KS, int MODE>
 __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderArgs A,
                                                                  const float* __restrict__ bank,
                                                                  float* __restrict__ grad) {
+    constexpr bool KGRAD = MODE == kBankKGrad;
+    constexpr bool SPLIT = MODE == kBankSplit;
     using G = GroupGeom<KS>;
     using M = MfmaGeom<KS>;
-    extern __shared__ __align__(16) float halo[];        // [HH][HW]
+    using S = SplitGeom<KS>;
+    // [HH][HW] float32 image halo, or (split) [HH][HWB] bf16 hi then lo
+    extern __shared__ __align__(16) float halo[];
     __shared__ int items[kGMaxItems];                    // strip | mask << 9
     __shared__ int chunk_key[kGMaxChunks], chunk_pos[kGMaxChunks];
     __shared__ int red[kRBlock / 64];
     __shared__ int n_items, n_full, n_part, next_chunk;
-    // per wave: kernel-row staging (2 buffers x 2 sides), or for KGRAD the
-    // block and diagonal-sum scratch of bank_kgrad_chunk
-    constexpr int kWaveScratch = KGRAD ? KGradGeom<KS>::SCR : 4 * M::ROW;
+    // per wave: kernel-row staging (2 buffers x 2 sides), for KGRAD the
+    // block and diagonal-sum scratch of bank_kgrad_chunk, for the split path
+    // the shifted hi/lo row copies and the float32 reversed rows
+    constexpr int kWaveScratch = KGRAD ? KGradGeom<KS>::SCR : SPLIT ? S::SCRATCH : 4 * M::ROW;
     __shared__ __align__(16) float arows[kRBlock / 64][kWaveScratch];
     const int pad = (KS - 1) / 2;
     const int kk = KS * KS;
@@ -765,11 +942,22 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
         {
             const int lam = A.lam_of_c[c];
             const float* im = A.img + ((size_t)n * A.C + c) * A.H * A.W;
-            for (int e = tid; e < G::HH * G::HW; e += kRBlock) {
-                const int r = e / G::HW, q = e - r * G::HW;
-                const int yy = min(max(y0 - pad + r, 0), A.H - 1);
-                const int xx = min(max(x0 - pad + q, 0), A.W - 1);
-                halo[e] = im[(size_t)yy * A.W + xx];
+            if constexpr (SPLIT) {
+                __bf16* hhi = reinterpret_cast<__bf16*>(halo);
+                __bf16* hlo = hhi + S::HH * S::HWB;
+                for (int e = tid; e < S::HH * S::HWB; e += kRBlock) {
+                    const int r = e / S::HWB, q = e - r * S::HWB;
+                    const int yy = min(max(y0 - pad + r, 0), A.H - 1);
+                    const int xx = min(max(x0 - pad + q, 0), A.W - 1);
+                    split_bf16(im[(size_t)yy * A.W + xx], &hhi[e], &hlo[e]);
+                }
+            } else {
+                for (int e = tid; e < G::HH * G::HW; e += kRBlock) {
+                    const int r = e / G::HW, q = e - r * G::HW;
+                    const int yy = min(max(y0 - pad + r, 0), A.H - 1);
+                    const int xx = min(max(x0 - pad + q, 0), A.W - 1);
+                    halo[e] = im[(size_t)yy * A.W + xx];
+                }
             }
             __syncthreads();
             while (true) {
@@ -788,23 +976,43 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
                                          grad + ((size_t)fd * A.L + lam) * 2 * kk, halo, arow, lane);
                     continue;
                 }
-                // left output side reads the stored right kernel when mirrored
-                const float* kl = bank + ((size_t)fd * A.L + lam) * 2 * kk + (fxb ? kk : 0);
                 int its[4], bofs[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    its[u] = items[s0 + min(16 * u + (lane & 15), cnt - 1)];
-                    const int sid = its[u] & 511;
-                    bofs[u] = ((sid >> 3) + KS - 1) * G::HW + (sid & 7) * kStrip + M::TPG * (lane >> 4);
-                }
                 const int ng = (cnt + 15) >> 4;
-                const int rstep = fyb ? -KS : KS;
                 floatx4_t acc[4];
-                switch (ng) {
-                    case 1: bank_mfma_rows<KS, 1>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
-                    case 2: bank_mfma_rows<KS, 2>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
-                    case 3: bank_mfma_rows<KS, 3>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
-                    default: bank_mfma_rows<KS, 4>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
+                if constexpr (SPLIT) {
+                    const float* entry = bank + ((size_t)fd * A.L + lam) * 2 * kk;
+                    const __bf16* hhi = reinterpret_cast<const __bf16*>(halo);
+                    const __bf16* hlo = hhi + S::HH * S::HWB;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        its[u] = items[s0 + min(16 * u + (lane & 15), cnt - 1)];
+                        const int sid = its[u] & 511;
+                        // B operand of lane (strip, kg): halo row (strip row + KS - 1 - i),
+                        // columns 8 (strip column) + 8 pg + [0, 8)
+                        bofs[u] = ((sid >> 3) + KS - 1) * S::HWB + (sid & 7) * kStrip;
+                    }
+                    switch (ng) {
+                        case 1: bank_split_rows<KS, 1>(entry, fxb, fyb, hhi, hlo, arow, lane, bofs, acc); break;
+                        case 2: bank_split_rows<KS, 2>(entry, fxb, fyb, hhi, hlo, arow, lane, bofs, acc); break;
+                        case 3: bank_split_rows<KS, 3>(entry, fxb, fyb, hhi, hlo, arow, lane, bofs, acc); break;
+                        default: bank_split_rows<KS, 4>(entry, fxb, fyb, hhi, hlo, arow, lane, bofs, acc); break;
+                    }
+                } else {
+                    // left output side reads the stored right kernel when mirrored
+                    const float* kl = bank + ((size_t)fd * A.L + lam) * 2 * kk + (fxb ? kk : 0);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        its[u] = items[s0 + min(16 * u + (lane & 15), cnt - 1)];
+                        const int sid = its[u] & 511;
+                        bofs[u] = ((sid >> 3) + KS - 1) * G::HW + (sid & 7) * kStrip + M::TPG * (lane >> 4);
+                    }
+                    const int rstep = fyb ? -KS : KS;
+                    switch (ng) {
+                        case 1: bank_mfma_rows<KS, 1>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
+                        case 2: bank_mfma_rows<KS, 2>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
+                        case 3: bank_mfma_rows<KS, 3>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
+                        default: bank_mfma_rows<KS, 4>(kl, rstep, fxb, fyb, halo, arow, lane, bofs, acc); break;
+                    }
                 }
                 // lane holds outputs q = 4 (g & 1) + r of side g >> 1 of its strip
                 const int g = lane >> 4;
@@ -1123,13 +1331,21 @@ static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
         if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_bwd_kernel<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         hipLaunchKernelGGL(render_bank_bwd_kernel<KS>, grid, dim3(64), shm, st, A,
                            reinterpret_cast<const float*>(A.psf));
+    } else if (A.split) {
+        using S = SplitGeom<KS>;
+        const size_t shm = (size_t)2 * S::HH * S::HWB * sizeof(uint16_t);
+        const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
+        const dim3 grid((unsigned)((long long)A.C * A.N * tilesx * tilesy));
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS, kBankSplit>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL((render_bank_fast_kernel<KS, kBankSplit>), grid, dim3(kRBlock), shm, st, A,
+                           reinterpret_cast<const float*>(A.psf), (float*)nullptr);
     } else {
         using G = GroupGeom<KS>;
         const size_t shm = (size_t)G::HH * G::HW * sizeof(float);
         const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
         const dim3 grid((unsigned)((long long)A.C * A.N * tilesx * tilesy));
-        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL((render_bank_fast_kernel<KS, false>), grid, dim3(kRBlock), shm, st, A,
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS, kBankFwd>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL((render_bank_fast_kernel<KS, kBankFwd>), grid, dim3(kRBlock), shm, st, A,
                            reinterpret_cast<const float*>(A.psf), (float*)nullptr);
     }
     return true;
@@ -1141,8 +1357,8 @@ static void launch_bank_kgrad(const RenderArgs& A, float* grad, hipStream_t st) 
     const size_t shm = (size_t)G::HH * G::HW * sizeof(float);
     const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
     const dim3 grid((unsigned)((long long)A.C * A.N * tilesx * tilesy));
-    if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((render_bank_fast_kernel<KS, true>), grid, dim3(kRBlock), shm, st, A,
+    if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS, kBankKGrad>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((render_bank_fast_kernel<KS, kBankKGrad>), grid, dim3(kRBlock), shm, st, A,
                        (const float*)nullptr, grad);
 }
 
@@ -1265,6 +1481,9 @@ static int pack_render(const sdirt_render_desc* d, RenderArgs* A) {
             if (d->lambda_of_channel[c] < 0 || d->lambda_of_channel[c] >= A->L) return SDIRT_EINVAL;
             A->lam_of_c[c] = d->lambda_of_channel[c];
         }
+        if (d->bank_math != SDIRT_BANK_FP32 && d->bank_math != SDIRT_BANK_SPLIT_BF16)
+            return SDIRT_EINVAL;
+        A->split = d->bank_math == SDIRT_BANK_SPLIT_BF16;
     } else {
         return SDIRT_EINVAL;
     }

@@ -226,7 +226,8 @@ def trace_dp_psf_backward(lens, sensor, query, grad_psf, math=abi.F64):
 
 def make_render_desc(N, C_, H, W, ks, source=abi.SRC_DENSE, psf_channels=None,
                      psf_dtype=abi.F32, field_radii=None, inv_depths=None,
-                     bank_lambdas=1, lambda_of_channel=None, pitch=0.0, field_y=None):
+                     bank_lambdas=1, lambda_of_channel=None, pitch=0.0, field_y=None,
+                     bank_math=abi.BANK_FP32):
     """Render descriptor; for the banks, field_radii is the radial grid
     (SRC_BANK) or the x grid (SRC_BANK2D, with field_y the y grid)."""
     d = abi.RenderDesc()
@@ -234,6 +235,7 @@ def make_render_desc(N, C_, H, W, ks, source=abi.SRC_DENSE, psf_channels=None,
     d.source = int(source)
     d.psf_channels = int(psf_channels if psf_channels is not None else C_)
     d.psf_dtype = int(psf_dtype)
+    d.bank_math = int(bank_math)
     keep = []
     if source == abi.SRC_BANK2D:
         fy = _darr(field_y)

@@ -331,7 +331,8 @@ def test_bank_kernel_gradient(ks, two_d):
     assert err <= 1e-5
 
 
-def test_bank_config5_full_batch_sampled_pixels():
+@pytest.mark.parametrize("bank_math", [0, 1])
+def test_bank_config5_full_batch_sampled_pixels(bank_math):
     # the benchmarked launch of the largest workload: 16 RGB 4032 x 3024
     # images, 64 x 32 x 3 bank (ks 65), forward and image adjoint; sampled
     # pixels of images 0 and 15 (corners, both sides of the mirror lines,
@@ -350,9 +351,9 @@ def test_bank_config5_full_batch_sampled_pixels():
     loc = list(configs.LAMBDA_OF_RGB)
     desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
                                         field_radii=radii, inv_depths=iv, bank_lambdas=L,
-                                        lambda_of_channel=loc, pitch=ps)
+                                        lambda_of_channel=loc, pitch=ps, bank_math=bank_math)
     bt, dt = torch.from_numpy(bank).cuda(), torch.from_numpy(dmap).cuda()
-    print("config-5 batch: forward", flush=True)
+    print("config-5 batch: forward, bank_math %d" % bank_math, flush=True)
     out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), bt, depth=dt)
     cy, cx = (H - 1) // 2, (W - 1) // 2
     pix = []
@@ -376,3 +377,68 @@ def test_bank_config5_full_batch_sampled_pixels():
     err = np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max()))
     print("config-5 adjoint max rel err %.2e" % err, flush=True)
     assert err <= REL_TOL
+
+
+# ---- split-bf16 bank forward ------------------------------------------------
+# Each operand split into bf16 hi + lo, three matrix-core products summed in
+# float32: a product's relative error is below 2^-15 (the dropped lo * lo
+# term and the residual of each split), so the renders meet the same 1e-4
+# bar as the float32 path.
+
+@pytest.mark.parametrize("ks", [21, 31, 33, 41, 63, 65])
+def test_bank_split_bf16_forward(ks):
+    N, C, H, W, F, D, L, ps = 2, 3, 45, 150, 6, 5, 3, 0.01
+    img, bank, radii, iv, dmap = _bank_case(N, C, H, W, ks, F, D, L, ps, 9)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps,
+                                        bank_math=abi.BANK_SPLIT_BF16)
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), torch.from_numpy(bank).cuda(),
+                          depth=torch.from_numpy(dmap).cuda())
+    ref = R.render_bank(img, bank, dmap, radii, iv, loc, ps)
+    err = _rel(out.cpu().numpy(), ref)
+    print("split-bf16 ks %d rel err %.2e" % (ks, err))
+    assert err <= REL_TOL
+
+
+@pytest.mark.parametrize("ks", [33, 65])
+def test_bank2d_split_bf16_forward(ks):
+    N, C, H, W, Fx, Fy, D, L, ps = 2, 3, 45, 150, 5, 4, 4, 3, 0.01
+    img, bank, xs, ys, iv, dmap = _bank2d_case(N, C, H, W, ks, Fx, Fy, D, L, ps, 41, True)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK2D,
+                                        field_radii=xs, field_y=ys, inv_depths=iv,
+                                        bank_lambdas=L, lambda_of_channel=loc, pitch=ps,
+                                        bank_math=abi.BANK_SPLIT_BF16)
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), torch.from_numpy(bank).cuda(),
+                          depth=torch.from_numpy(dmap).cuda())
+    ref = R.render_bank2d(img, bank, dmap, xs, ys, iv, loc, ps)
+    assert _rel(out.cpu().numpy(), ref) <= REL_TOL
+
+
+def test_bank_split_bf16_entry_per_pixel_noise_and_delta_kernels():
+    # several batches per tile (white-noise depth), and delta kernels whose
+    # output must reproduce shifted image values to float32 accuracy
+    N, C, H, W, ks, F, D, L, ps = 1, 3, 130, 200, 21, 9, 24, 3, 0.01
+    rng = np.random.default_rng(31)
+    img = rng.uniform(0, 1, (N, C, H, W)).astype(np.float32)
+    bank = rng.uniform(0, 1, (F, D, L, 2, ks, ks)).astype(np.float32)
+    radii = np.linspace(0, np.hypot(W * ps / 2, H * ps / 2), F)
+    iv = np.linspace(1 / 5000.0, 1 / 500.0, D)
+    dmap = (1.0 / rng.uniform(1 / 5000.0, 1 / 500.0, (N, H, W))).astype(np.float32)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps,
+                                        bank_math=abi.BANK_SPLIT_BF16)
+    bt, dt = torch.from_numpy(bank).cuda(), torch.from_numpy(dmap).cuda()
+    out = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), bt, depth=dt)
+    assert _rel(out.cpu().numpy(), R.render_bank(img, bank, dmap, radii, iv, loc, ps)) <= REL_TOL
+    delta = np.zeros_like(bank)
+    delta[..., 0, 3, 17] = 1.0          # left: tap (3, 17); right: centre
+    delta[..., 1, 10, 10] = 1.0
+    o2 = sdirt.render_dp(desc, torch.from_numpy(img).cuda(), torch.from_numpy(delta).cuda(),
+                         depth=dt).cpu().numpy()
+    ref2 = R.render_bank(img, delta, dmap, radii, iv, loc, ps)
+    assert np.max(np.abs(o2 - ref2)) <= 2.0 ** -16 * np.abs(ref2).max()
