@@ -676,13 +676,21 @@ __device__ inline void bank_kgrad_chunk(const RenderArgs& A, int n, int c, int y
 // row form a k-group, P = the strip window rounded up to 8 columns, so a row
 // is G = P / 8 groups and R consecutive rows (R G a multiple of 4) make T =
 // R G / 4 k-steps of 32.  Lane (m, kg) of the A operand (m = (side, q) output
-// row, kg = k-group) needs 8 consecutive taps of the reversed kernel row
-// starting at 8 pg - q: each wave stages, per R rows, four copies of each
-// reversed row pair shifted by q mod 4 (hi and lo), so every lane reads its
-// 8 taps as two aligned 8-byte LDS reads; the B operand (image windows) is
-// read from hi and lo bf16 halos as aligned 16-byte LDS reads.
+// row, kg = k-group) needs the 8 taps of the reversed kernel row starting at
+// 8 pg - q.  Each wave stages, per R rows, the reversed rows of both sides
+// once, split into bf16 hi and lo rows between zero margins; a lane reads
+// the 5 dwords that hold its 8 taps and shifts them into place by the parity
+// of q with v_alignbit (the shift is fixed per lane).  The B operand (image
+// windows) is read from hi and lo bf16 halos as aligned 16-byte LDS reads.
+// Two accumulator chains per group (hi hi, and hi lo + lo hi) halve the
+// dependent MFMA sequence.  The halo rows carry no padding, so that the halo
+// (64 KB at ks 65) and the wave buffers fit two workgroups per CU.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+// LDS words written as bf16 halves and read as dwords: accesses through
+// these types may alias each other
+typedef uint32_t __attribute__((may_alias)) u32_alias;
+typedef uint16_t __attribute__((may_alias)) u16_alias;
 
 template <int KS>
 struct SplitGeom {
@@ -691,84 +699,68 @@ struct SplitGeom {
     static constexpr int R = (G % 4 == 0) ? 1 : ((G % 2 == 0) ? 2 : 4);   // rows per super-step
     static constexpr int T = R * G / 4;                          // k-steps per super-step
     static constexpr int NSS = (KS + R - 1) / R;                 // super-steps
-    static constexpr int PB = P + 4;                             // staged copy: index w = v + 4
-    static constexpr int RRW = KS + 24;                          // float32 reversed row, u at 8 + u
-    static constexpr int NCOPY = R * 2 * 4;                      // (row, side, shift) copies
-    static constexpr int STAGE = NCOPY * PB;                     // bf16 per hi (or lo) block
-    static constexpr int NPAIR = STAGE / 2;                      // bf16 pairs per block
+    static constexpr int MARG = 8;                               // zero margin before the taps
+    // staged row: taps at MARG + u; lane reads reach element P + 9
+    static constexpr int RWB = ((MARG + P + 2 + 7) / 8) * 8;
+    static constexpr int LO = R * 2 * RWB;                       // lo rows after the hi rows (bf16)
+    static constexpr int SCRATCH = LO;                           // floats per wave (hi + lo bf16)
     static constexpr int NTAP = R * 2 * KS;                      // kernel taps per super-step
-    static constexpr int SCRATCH = STAGE + R * 2 * RRW;          // floats per wave
-    static constexpr int HWB = kGT - kStrip + P + 8;             // halo row stride (bf16)
+    static constexpr int HW0 = kGT + KS - 1 > kGT - kStrip + P ? kGT + KS - 1 : kGT - kStrip + P;
+    static constexpr int HWB = ((HW0 + 7) / 8) * 8;              // halo row stride (bf16)
     static constexpr int HH = kGT + KS - 1;
     static_assert((R * G) % 4 == 0, "whole k-steps per super-step");
-    static_assert(PB % 4 == 0 && HWB % 8 == 0, "aligned fragment reads");
+    static_assert(RWB % 2 == 0 && LO % 2 == 0 && HWB % 8 == 0, "aligned fragment reads");
+    static_assert(MARG >= kStrip - 1 && RWB >= P + 10, "lane reads stay inside the staged row");
 };
 
-__device__ inline void split_bf16(float v, __bf16* hi, __bf16* lo) {
+__device__ inline uint32_t split_bf16_bits(float v) {
     const __bf16 h = (__bf16)v;
-    *hi = h;
-    *lo = (__bf16)(v - (float)h);
+    const __bf16 l = (__bf16)(v - (float)h);
+    return (uint32_t)__builtin_bit_cast(uint16_t, h) | ((uint32_t)__builtin_bit_cast(uint16_t, l) << 16);
 }
 
-// One lane's share of a super-step's raw taps: element e = lane + 64 k of
+// One lane's share of a super-step's taps: element e = lane + 64 k of
 // [R rows][2 sides][KS] (reversed-row order u), read from the entry with its
-// mirrors applied; rows past the kernel read as zero.
+// mirrors applied, and its place in the staged rows.  Offsets are those of
+// super-step 0; super-step ss moves R rows down the entry (up, when flipped
+// in y), and rows past the kernel read as zero.
 template <int KS>
 struct SplitTaps {
     using S = SplitGeom<KS>;
     static constexpr int NL = (S::NTAP + 63) / 64;
+    int src[NL], dst[NL], row[NL];
     float v[NL];
-    __device__ void load(const float* __restrict__ entry, int i0, bool fx, bool fy, int lane) {
+    __device__ void init(int lane, bool fx, bool fy) {
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             const int e = lane + 64 * k;
             const int r = e / (2 * KS), rem = e - r * 2 * KS;
             const int side = rem >= KS, u = rem - side * KS;
-            const int i = i0 + r;
-            float x = 0.f;
-            if (e < S::NTAP && i < KS) {
-                const int ri = fy ? KS - 1 - i : i;
-                // output side s reads the stored side s, or 1 - s mirrored in x;
-                // reversed row: R_s[u] = K_s[i][KS - 1 - u]
-                x = fx ? entry[(size_t)(1 - side) * KS * KS + ri * KS + u]
-                       : entry[(size_t)side * KS * KS + ri * KS + KS - 1 - u];
-            }
-            v[k] = x;
+            const int ri = fy ? KS - 1 - r : r;
+            // output side s reads the stored side s, or 1 - s mirrored in x;
+            // reversed row: R_s[u] = K_s[i][KS - 1 - u]
+            src[k] = fx ? (1 - side) * KS * KS + ri * KS + u : side * KS * KS + ri * KS + KS - 1 - u;
+            dst[k] = (r * 2 + side) * S::RWB + S::MARG + u;
+            row[k] = e < S::NTAP ? r : KS;
         }
     }
-    __device__ void store(float* rr, int lane) const {
+    __device__ void load(const float* __restrict__ entry, int ss, int rstep) {
+        const int lim = KS - ss * S::R;
+        const int ofs = ss * S::R * rstep;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) v[k] = row[k] < lim ? entry[src[k] + ofs] : 0.f;
+    }
+    __device__ void store(u16_alias* st) const {
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int e = lane + 64 * k;
-            if (e < S::NTAP) {
-                const int r = e / (2 * KS), rem = e - r * 2 * KS;
-                const int side = rem >= KS, u = rem - side * KS;
-                rr[(r * 2 + side) * S::RRW + 8 + u] = v[k];
+            if (64 * k + 64 <= S::NTAP || row[k] < KS) {            // e < NTAP
+                const uint32_t b = split_bf16_bits(v[k]);
+                st[dst[k]] = (uint16_t)b;
+                st[S::LO + dst[k]] = (uint16_t)(b >> 16);
             }
         }
     }
 };
-
-// Shifted hi/lo copies of a super-step's reversed rows: copy (r, side, c)
-// holds C_c[w - 4] = R[w - 4 - c], zero outside the row, for w in [0, PB).
-template <int KS>
-__device__ inline void split_build_copies(const float* rr, uint32_t* st_hi, uint32_t* st_lo,
-                                          int lane) {
-    using S = SplitGeom<KS>;
-    for (int e = lane; e < S::NPAIR; e += 64) {
-        const int copy = e / (S::PB / 2), wp = e - copy * (S::PB / 2);
-        const int c = copy & 3, rs = copy >> 2;               // rs = r * 2 + side
-        const float* row = rr + rs * S::RRW + 8;
-        const int u = 2 * wp - 4 - c;                         // >= -7, < P: inside the margins
-        __bf16 h0, l0, h1, l1;
-        split_bf16(row[u], &h0, &l0);
-        split_bf16(row[u + 1], &h1, &l1);
-        st_hi[e] = (uint32_t)__builtin_bit_cast(uint16_t, h0) |
-                   ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
-        st_lo[e] = (uint32_t)__builtin_bit_cast(uint16_t, l0) |
-                   ((uint32_t)__builtin_bit_cast(uint16_t, l1) << 16);
-    }
-}
 
 // Rows of one chunk on the split-bf16 path: NG groups of 16 strips.
 template <int KS, int NG>
@@ -776,42 +768,59 @@ __device__ inline void bank_split_rows(const float* __restrict__ entry, bool fx,
                                        const __bf16* hhi, const __bf16* hlo, float* scratch,
                                        int lane, const int (&bofs)[4], floatx4_t (&out)[4]) {
     using S = SplitGeom<KS>;
-    uint32_t* st_hi = reinterpret_cast<uint32_t*>(scratch);
-    uint32_t* st_lo = st_hi + S::STAGE / 2;
-    float* rr = scratch + S::STAGE;
+    u16_alias* st = reinterpret_cast<u16_alias*>(scratch);
+    const u32_alias* sw = reinterpret_cast<const u32_alias*>(scratch);
     const int m = lane & 15, kg = lane >> 4;
     const int side = m >> 3, q = m & 7;
-    const int c = q & 3;
-    const int wq = 4 - 4 * (q >> 2);                           // w offset of the lane's reads
-    floatx4_t acc[NG];
+    const uint32_t sh = (q & 1) * 16;
+    // per k-step: dword index of the lane's first A word, its row in the
+    // super-step and window column
+    int ad[S::T], irw[S::T], pcol[S::T];
 #pragma unroll
-    for (int u = 0; u < NG; ++u) acc[u] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < S::T; ++t) {
+        const int g = 4 * t + kg;
+        const int ir = g / S::G, pg = g - ir * S::G;
+        ad[t] = ((ir * 2 + side) * S::RWB + S::MARG + 8 * pg - q) >> 1;
+        irw[t] = ir;
+        pcol[t] = 8 * pg;
+    }
+    floatx4_t acc_h[NG], acc_l[NG];
+#pragma unroll
+    for (int u = 0; u < NG; ++u) {
+        acc_h[u] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        acc_l[u] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    const int rstep = fy ? -KS : KS;
     SplitTaps<KS> taps;
-    taps.load(entry, 0, fx, fy, lane);
+    taps.init(lane, fx, fy);
+    taps.load(entry, 0, rstep);
     for (int ss = 0; ss < S::NSS; ++ss) {
-        taps.store(rr, lane);
-        if (ss + 1 < S::NSS) taps.load(entry, (ss + 1) * S::R, fx, fy, lane);
-        split_build_copies<KS>(rr, st_hi, st_lo, lane);
-        const __bf16* ahi = reinterpret_cast<const __bf16*>(st_hi);
-        const __bf16* alo = reinterpret_cast<const __bf16*>(st_lo);
+        // the previous super-step's reads of the staged rows are issued
+        // before these writes (one wave: LDS accesses stay in order)
+        __asm__ volatile("" ::: "memory");
+        taps.store(st);
+        __asm__ volatile("" ::: "memory");
+        if (ss + 1 < S::NSS) taps.load(entry, ss + 1, rstep);
 #pragma unroll
         for (int t = 0; t < S::T; ++t) {
-            const int g = 4 * t + kg;                         // k-group of this lane
-            const int ir = g / S::G, pg = g - ir * S::G;      // row in the super-step, column group
-            const int aoff = ((ir * 2 + side) * 4 + c) * S::PB + 8 * pg + wq;
-            bf16x8_t a_hi, a_lo;
-            {
-                const bf16x4_t h0 = *reinterpret_cast<const bf16x4_t*>(ahi + aoff);
-                const bf16x4_t h1 = *reinterpret_cast<const bf16x4_t*>(ahi + aoff + 4);
-                const bf16x4_t l0 = *reinterpret_cast<const bf16x4_t*>(alo + aoff);
-                const bf16x4_t l1 = *reinterpret_cast<const bf16x4_t*>(alo + aoff + 4);
-                a_hi = bf16x8_t{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
-                a_lo = bf16x8_t{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+            uint32_t h[5], l[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                h[j] = sw[ad[t] + j];
+                l[j] = sw[S::LO / 2 + ad[t] + j];
             }
+            u32x4_t ah, al;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                ah[j] = __builtin_amdgcn_alignbit(h[j + 1], h[j], sh);
+                al[j] = __builtin_amdgcn_alignbit(l[j + 1], l[j], sh);
+            }
+            const bf16x8_t a_hi = __builtin_bit_cast(bf16x8_t, ah);
+            const bf16x8_t a_lo = __builtin_bit_cast(bf16x8_t, al);
             // rows past the kernel (the last super-step's padding) carry
             // zero taps; their image rows are clamped into the halo so that
             // the zero products stay finite
-            const int brow = -min(ss * S::R + ir, KS - 1) * S::HWB + 8 * pg;
+            const int brow = -min(ss * S::R + irw[t], KS - 1) * S::HWB + pcol[t];
             bf16x8_t b_hi[NG], b_lo[NG];
 #pragma unroll
             for (int u = 0; u < NG; ++u) {
@@ -819,18 +828,17 @@ __device__ inline void bank_split_rows(const float* __restrict__ entry, bool fx,
                 b_lo[u] = *reinterpret_cast<const bf16x8_t*>(hlo + bofs[u] + brow);
             }
 #pragma unroll
-            for (int u = 0; u < NG; ++u)
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_hi[u], acc[u], 0, 0, 0);
+            for (int u = 0; u < NG; ++u) {
+                acc_h[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_hi[u], acc_h[u], 0, 0, 0);
+                acc_l[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_lo[u], acc_l[u], 0, 0, 0);
+            }
 #pragma unroll
             for (int u = 0; u < NG; ++u)
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b_lo[u], acc[u], 0, 0, 0);
-#pragma unroll
-            for (int u = 0; u < NG; ++u)
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, b_hi[u], acc[u], 0, 0, 0);
+                acc_l[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, b_hi[u], acc_l[u], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int u = 0; u < NG; ++u) out[u] = acc[u];
+    for (int u = 0; u < NG; ++u) out[u] = acc_h[u] + acc_l[u];
 }
 
 // MODE: kBankFwd (fp32 matrix cores), kBankKGrad (gradient with respect to
@@ -839,7 +847,7 @@ __device__ inline void bank_split_rows(const float* __restrict__ entry, bool fx,
 enum BankMode { kBankFwd = 0, kBankKGrad = 1, kBankSplit = 2 };
 
 template <int KS, int MODE>
-__global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderArgs A,
+__global__ __launch_bounds__(kRBlock, 2) void render_bank_fast_kernel(const RenderArgs A,
                                                                  const float* __restrict__ bank,
                                                                  float* __restrict__ grad) {
     constexpr bool KGRAD = MODE == kBankKGrad;
@@ -943,13 +951,17 @@ __global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderA
             const int lam = A.lam_of_c[c];
             const float* im = A.img + ((size_t)n * A.C + c) * A.H * A.W;
             if constexpr (SPLIT) {
-                __bf16* hhi = reinterpret_cast<__bf16*>(halo);
-                __bf16* hlo = hhi + S::HH * S::HWB;
-                for (int e = tid; e < S::HH * S::HWB; e += kRBlock) {
-                    const int r = e / S::HWB, q = e - r * S::HWB;
+                u32_alias* hhi = reinterpret_cast<u32_alias*>(halo);
+                u32_alias* hlo = hhi + S::HH * S::HWB / 2;
+                for (int e = tid; e < S::HH * S::HWB / 2; e += kRBlock) {
+                    const int r = e / (S::HWB / 2), q = 2 * (e - r * (S::HWB / 2));
                     const int yy = min(max(y0 - pad + r, 0), A.H - 1);
-                    const int xx = min(max(x0 - pad + q, 0), A.W - 1);
-                    split_bf16(im[(size_t)yy * A.W + xx], &hhi[e], &hlo[e]);
+                    const int x0c = min(max(x0 - pad + q, 0), A.W - 1);
+                    const int x1c = min(max(x0 - pad + q + 1, 0), A.W - 1);
+                    const uint32_t b0 = split_bf16_bits(im[(size_t)yy * A.W + x0c]);
+                    const uint32_t b1 = split_bf16_bits(im[(size_t)yy * A.W + x1c]);
+                    hhi[e] = (b0 & 0xffffu) | (b1 << 16);
+                    hlo[e] = (b0 >> 16) | (b1 & 0xffff0000u);
                 }
             } else {
                 for (int e = tid; e < G::HH * G::HW; e += kRBlock) {
