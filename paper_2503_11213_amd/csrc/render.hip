@@ -706,8 +706,12 @@ struct SplitGeom {
     static constexpr int SCRATCH = LO;                           // floats per wave (hi + lo bf16)
     static constexpr int NTAP = R * 2 * KS;                      // kernel taps per super-step
     static constexpr int HW0 = kGT + KS - 1 > kGT - kStrip + P ? kGT + KS - 1 : kGT - kStrip + P;
-    static constexpr int HWB = ((HW0 + 7) / 8) * 8;              // halo row stride (bf16)
+    // halo rows of 128 bf16 (16 blocks of 8): odd rows keep their two
+    // halves swapped (column ^ 64), which puts the two strip rows of a
+    // typical group of 16 strips on different LDS banks
+    static constexpr int HWB = 128;
     static constexpr int HH = kGT + KS - 1;
+    static_assert(HW0 <= HWB, "strip windows inside the halo row");
     static_assert((R * G) % 4 == 0, "whole k-steps per super-step");
     static_assert(RWB % 2 == 0 && LO % 2 == 0 && HWB % 8 == 0, "aligned fragment reads");
     static_assert(MARG >= kStrip - 1 && RWB >= P + 10, "lane reads stay inside the staged row");
@@ -824,8 +828,11 @@ __device__ inline void bank_split_rows(const float* __restrict__ entry, bool fx,
             bf16x8_t b_hi[NG], b_lo[NG];
 #pragma unroll
             for (int u = 0; u < NG; ++u) {
-                b_hi[u] = *reinterpret_cast<const bf16x8_t*>(hhi + bofs[u] + brow);
-                b_lo[u] = *reinterpret_cast<const bf16x8_t*>(hlo + bofs[u] + brow);
+                // bit 7 of the element offset is the halo row's parity
+                int o = bofs[u] + brow;
+                o ^= (o >> 1) & 64;
+                b_hi[u] = *reinterpret_cast<const bf16x8_t*>(hhi + o);
+                b_lo[u] = *reinterpret_cast<const bf16x8_t*>(hlo + o);
             }
 #pragma unroll
             for (int u = 0; u < NG; ++u) {
@@ -960,8 +967,9 @@ __global__ __launch_bounds__(kRBlock, 2) void render_bank_fast_kernel(const Rend
                     const int x1c = min(max(x0 - pad + q + 1, 0), A.W - 1);
                     const uint32_t b0 = split_bf16_bits(im[(size_t)yy * A.W + x0c]);
                     const uint32_t b1 = split_bf16_bits(im[(size_t)yy * A.W + x1c]);
-                    hhi[e] = (b0 & 0xffffu) | (b1 << 16);
-                    hlo[e] = (b0 >> 16) | (b1 & 0xffff0000u);
+                    const int es = r * (S::HWB / 2) + ((q ^ ((r & 1) << 6)) >> 1);
+                    hhi[es] = (b0 & 0xffffu) | (b1 << 16);
+                    hlo[es] = (b0 >> 16) | (b1 & 0xffff0000u);
                 }
             } else {
                 for (int e = tid; e < G::HH * G::HW; e += kRBlock) {
