@@ -854,9 +854,8 @@ __device__ inline void bank_split_rows(const float* __restrict__ entry, bool fx,
 enum BankMode { kBankFwd = 0, kBankKGrad = 1, kBankSplit = 2 };
 
 template <int KS, int MODE>
-__global__ __launch_bounds__(kRBlock, 2) void render_bank_fast_kernel(const RenderArgs A,
-                                                                 const float* __restrict__ bank,
-                                                                 float* __restrict__ grad) {
+__device__ __forceinline__ void render_bank_fast_body(const RenderArgs A, const float* __restrict__ bank,
+                                                      float* __restrict__ grad) {
     constexpr bool KGRAD = MODE == kBankKGrad;
     constexpr bool SPLIT = MODE == kBankSplit;
     using G = GroupGeom<KS>;
@@ -1063,6 +1062,21 @@ __global__ __launch_bounds__(kRBlock, 2) void render_bank_fast_kernel(const Rend
             __syncthreads();
         }
     }
+}
+
+template <int KS, int MODE>
+__global__ __launch_bounds__(kRBlock) void render_bank_fast_kernel(const RenderArgs A,
+                                                                 const float* __restrict__ bank,
+                                                                 float* __restrict__ grad) {
+    render_bank_fast_body<KS, MODE>(A, bank, grad);
+}
+
+// The split-bf16 forward, compiled for two workgroups per CU (its LDS use is
+// sized for that).
+template <int KS>
+__global__ __launch_bounds__(kRBlock, 2) void render_bank_split_kernel(const RenderArgs A,
+                                                                     const float* __restrict__ bank) {
+    render_bank_fast_body<KS, kBankSplit>(A, bank, nullptr);
 }
 
 // Bank-source image adjoint on the matrix cores.  A one-wave workgroup owns
@@ -1342,9 +1356,366 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
     }
 }
 
+// ---- split-bf16 image adjoint ----------------------------------------------
+//
+// The bank adjoint scatters each output's gradient through its own entry's
+// kernel.  A workgroup owns a 64 x 64 pixel tile and an LDS float32 copy of
+// its halo gradient; entries are taken in batches, and for an entry a group
+// is a segment of 16 consecutive strip rows of one strip column (strips or
+// pixels outside the entry carry zero gradient).  For kernel row i, strip n
+// of a group adds D_i[n][p] = sum over (side, q) of g[n][(side, q)] *
+// K_side[i][KS - 1 - p + q] at halo row (strip row n + KS - 1 - i), column
+// 8 (strip column) + p, for the window columns p < P = 16 NB: a 16 x 16 x 16
+// product per block of 16 columns, taken as g_hi (K_hi + K_lo) on a
+// v_mfma_f32_16x16x32_bf16 (the K index holds (side, q) twice, once against
+// hi taps and once against lo taps) plus g_lo K_hi on a
+// v_mfma_f32_16x16x16_bf16 that reuses the first half of the same tap
+// fragment.  The halo row of (n, i) is fixed along n - i, so the gradient
+// operand's rows are rotated by one strip per kernel row (DPP row_ror): row
+// m holds strip (m + i) mod 16, and accumulator row m keeps adding into one
+// halo row until its strip index wraps, when that row's sum since its last
+// wrap (16 lanes of one register, less its value at that wrap) is added into
+// the LDS halo with ds_add_f32.  The accumulators are never cleared: only
+// the matrix cores write them, so every product accumulates in place.  Taps
+// are staged per kernel row as natural-order hi and lo rows between zero
+// margins; a lane reads its four taps as three dwords shifted into place by
+// v_alignbit.  Finally the halo is added onto the clamped image pixels with
+// global atomics.
+constexpr int kSBSlots = 8;                       // entries per batch
+constexpr int kSBGroups = 2;                      // segments per chunk
+constexpr int kSBChunks = kSBSlots * 32 / kSBGroups;
+
+template <int KS>
+struct SplitBwdGeom {
+    static constexpr int NB = (KS + kStrip - 1 + 15) / 16;      // 16-column blocks of the window
+    static constexpr int P = 16 * NB;
+    static constexpr int PW = KS + kStrip - 1;                   // window columns with taps
+    static constexpr int MARG = ((P - KS + 1) / 2) * 2;          // zero margin before the taps
+    static constexpr int RW = ((MARG + KS + 9 + 7) / 8) * 8;     // staged row (bf16)
+    static constexpr int LO = 2 * RW;                            // lo rows after the hi rows
+    static constexpr int SCRATCH = LO;                           // floats per wave
+    static constexpr int NTAP = 2 * KS;                          // taps of one kernel row
+    static constexpr int HH = kGT + KS - 1;
+    static constexpr int HWG = kGT + KS;                         // halo-gradient row stride (odd)
+    static_assert(MARG >= P - KS && RW >= MARG + KS + 9, "lane reads stay inside the staged row");
+    static_assert(kGT - kStrip + PW <= HWG - 1, "window columns inside the halo row");
+};
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+
+// One lane's share of staging one kernel row (both sides, natural tap order
+// v, mirrors applied): element e = lane + 64 k of [2 sides][KS].
+template <int KS>
+struct SplitRowTaps {
+    using S = SplitBwdGeom<KS>;
+    static constexpr int NL = (S::NTAP + 63) / 64;
+    int src[NL], dst[NL];
+    float v[NL];
+    __device__ void init(int lane, bool fx, bool fy) {
+        const int ri = fy ? KS - 1 : 0;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int e = min(lane + 64 * k, S::NTAP - 1);
+            const int side = e >= KS, u = e - side * KS;
+            // effective kernel K'_s[i][u]: the stored side s, or side 1 - s
+            // mirrored in x
+            src[k] = fx ? (1 - side) * KS * KS + ri * KS + KS - 1 - u : side * KS * KS + ri * KS + u;
+            dst[k] = side * S::RW + S::MARG + u;
+        }
+    }
+    __device__ void load(const float* __restrict__ entry, int ofs) {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) v[k] = entry[src[k] + ofs];
+    }
+    __device__ void store(u16_alias* st, int lane) const {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            if (64 * k + 64 <= S::NTAP || lane + 64 * k < S::NTAP) {
+                const uint32_t b = split_bf16_bits(v[k]);
+                st[dst[k]] = (uint16_t)b;
+                st[S::LO + dst[k]] = (uint16_t)(b >> 16);
+            }
+        }
+    }
+};
+
+__device__ inline uint32_t rot_row_left(uint32_t x) {
+    // lane l of each row of 16 takes lane (l + 1) mod 16 (DPP row_ror:15)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x12f, 0xf, 0xf, false);
+}
+
+// All kernel rows for NG groups (segments) of one entry.  ga / gl: the
+// lane's gradient fragments (x32: g_hi twice; x16: g_lo) of strip m = lane
+// % 16 at i = 0; hrow: the halo row of strip 0 at i = 0 (segment row + KS -
+// 1), hcol: the lane's halo column at block 0 (strip column + lane % 16).
+template <int KS, int NG>
+__device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool fx, bool fy,
+                                           float* hg, float* scratch, int lane,
+                                           u32x4_t (&ga)[kSBGroups], uint32_t (&gl)[kSBGroups][2],
+                                           const int (&hrow)[kSBGroups], const int (&hcol)[kSBGroups]) {
+    using S = SplitBwdGeom<KS>;
+    u16_alias* st = reinterpret_cast<u16_alias*>(scratch);
+    const u32_alias* sw = reinterpret_cast<const u32_alias*>(scratch);
+    const int pl = lane & 15, kg = lane >> 4;
+    const int side = kg >> 1, q0 = 4 * (kg & 1);
+    const int s0 = S::MARG + KS - 1 - pl + q0;                 // block 0, relative to the row
+    const uint32_t sh = (s0 & 1) * 16;
+    const int ad0 = (side * S::RW + s0) >> 1;                  // block b: ad0 - 8 b
+    // acc (x32 products) and acc2 (x16 products): running sums written only
+    // by the matrix cores, each an in-place chain of one instruction; prev:
+    // their total at each row's last flush, so that a flush adds
+    // acc + acc2 - prev, the sum since then
+    floatx4_t acc[NG][S::NB], acc2[NG][S::NB], prev[NG][S::NB];
+#pragma unroll
+    for (int u = 0; u < NG; ++u)
+#pragma unroll
+        for (int b = 0; b < S::NB; ++b) {
+            acc[u][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+            acc2[u][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+            prev[u][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        }
+    const int rstep = fy ? -KS : KS;
+    SplitRowTaps<KS> taps;
+    taps.init(lane, fx, fy);
+    taps.load(entry, 0);
+    for (int i = 0; i < KS; ++i) {
+        __asm__ volatile("" ::: "memory");
+        taps.store(st, lane);
+        __asm__ volatile("" ::: "memory");
+        if (i + 1 < KS) taps.load(entry, (i + 1) * rstep);
+        if (i > 0) {
+            // accumulator row m* = (16 - i) mod 16 finished its halo row
+            // (strip 15 at row i - 1): add it in
+            const int ms = (16 - (i & 15)) & 15;
+            const bool mine = kg == (ms >> 2);
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                if ((ms & 3) != jj) continue;
+#pragma unroll
+                for (int u = 0; u < NG; ++u) {
+                    const int rb = (hrow[u] + 16 - i) * S::HWG + hcol[u];
+#pragma unroll
+                    for (int b = 0; b < S::NB; ++b) {
+                        const float tot = acc[u][b][jj] + acc2[u][b][jj];
+                        if (mine && 16 * b + pl < S::PW) atomicAdd(&hg[rb + 16 * b], tot - prev[u][b][jj]);
+                        prev[u][b][jj] = mine ? tot : prev[u][b][jj];
+                    }
+                }
+            }
+            // gradient rows move up by one strip
+#pragma unroll
+            for (int u = 0; u < NG; ++u) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w) ga[u][w] = rot_row_left(ga[u][w]);
+                gl[u][0] = rot_row_left(gl[u][0]);
+                gl[u][1] = rot_row_left(gl[u][1]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < S::NB; ++b) {
+            uint32_t h[3], l[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                h[j] = sw[ad0 - 8 * b + j];
+                l[j] = sw[S::LO / 2 + ad0 - 8 * b + j];
+            }
+            const uint32_t h0 = __builtin_amdgcn_alignbit(h[1], h[0], sh);
+            const uint32_t h1 = __builtin_amdgcn_alignbit(h[2], h[1], sh);
+            const uint32_t l0 = __builtin_amdgcn_alignbit(l[1], l[0], sh);
+            const uint32_t l1 = __builtin_amdgcn_alignbit(l[2], l[1], sh);
+            const bf16x8_t t32 = __builtin_bit_cast(bf16x8_t, u32x4_t{h0, h1, l0, l1});
+            const short4_t t16 = __builtin_bit_cast(short4_t, uint2{h0, h1});
+#pragma unroll
+            for (int u = 0; u < NG; ++u) {
+                acc[u][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ga[u]), t32,
+                                                                    acc[u][b], 0, 0, 0);
+                acc2[u][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                    __builtin_bit_cast(short4_t, uint2{gl[u][0], gl[u][1]}), t16, acc2[u][b], 0, 0, 0);
+            }
+        }
+    }
+    // every accumulator row holds part of one halo row: strip
+    // n = (m + KS - 1) mod 16 at the last kernel row, halo row n
+#pragma unroll
+    for (int u = 0; u < NG; ++u)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int nn = (4 * kg + jj + KS - 1) & 15;
+            const int rb = (hrow[u] - (KS - 1) + nn) * S::HWG + hcol[u];
+#pragma unroll
+            for (int b = 0; b < S::NB; ++b)
+                if (16 * b + pl < S::PW)
+                    atomicAdd(&hg[rb + 16 * b], acc[u][b][jj] + acc2[u][b][jj] - prev[u][b][jj]);
+        }
+}
+
+template <int KS>
+__global__ __launch_bounds__(kRBlock, 2) void render_bank_split_bwd_kernel(const RenderArgs A,
+                                                                         const float* __restrict__ bank) {
+    using S = SplitBwdGeom<KS>;
+    extern __shared__ __align__(16) float hgrad[];                 // [HH][HWG]
+    __shared__ uint8_t pm[kSBSlots][kGStrips];                     // pixel masks per batch entry
+    __shared__ unsigned segm[kSBSlots];                            // segments holding the entry
+    __shared__ int slot_key[kSBSlots];
+    __shared__ int chunk_tab[kSBChunks];                           // slot | first << 4 | count << 10
+    __shared__ int red[kRBlock / 64];
+    __shared__ int n_chunks, next_chunk;
+    __shared__ __align__(16) float wscr[kRBlock / 64][S::SCRATCH];
+    const int kk = KS * KS;
+    const int pad = (KS - 1) / 2;
+    const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
+    const int nt = A.N * tilesx * tilesy;
+    const int c = blockIdx.x / nt;                                 // channel slowest
+    const int tile = blockIdx.x - c * nt;
+    const int n = tile / (tilesx * tilesy);
+    const int rem = tile - n * tilesx * tilesy;
+    const int y0 = (rem / tilesx) * kGT, x0 = (rem % tilesx) * kGT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float* scr = wscr[wave];
+    for (int e = lane; e < S::SCRATCH; e += 64) scr[e] = 0.f;    // margins stay zero
+    for (int e = tid; e < S::HH * S::HWG; e += kRBlock) hgrad[e] = 0.f;
+    int key[2][kStrip];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int sid = tid + h * kRBlock;
+        const int y = y0 + (sid >> 3), xs = x0 + (sid & 7) * kStrip;
+#pragma unroll
+        for (int q = 0; q < kStrip; ++q)
+            key[h][q] = (y < A.H && xs + q < A.W) ? bank_key(A, n, y, xs + q) : 0x7fffffff;
+    }
+    unsigned done = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < kStrip; ++q)
+            if (key[h][q] == 0x7fffffff) done |= 1u << (8 * h + q);
+    const int lam = A.lam_of_c[c];
+    const size_t plane = (size_t)A.C * A.H * A.W;
+    bool more = true;
+    while (more) {
+        // ---- list a batch of up to kSBSlots entries: pixel masks per strip
+        // and the 16-row segments that hold each entry
+        if (tid < kSBSlots) segm[tid] = 0u;
+        int ns = 0;
+        while (ns < kSBSlots) {
+            int mine = 0x7fffffff;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < kStrip; ++q)
+                    if (!(done & (1u << (8 * h + q)))) mine = min(mine, key[h][q]);
+            const int wm = wave_min_int(mine);
+            if (lane == 0) red[wave] = wm;
+            __syncthreads();
+            int k = red[0];
+#pragma unroll
+            for (int w = 1; w < kRBlock / 64; ++w) k = min(k, red[w]);
+            __syncthreads();
+            if (k == 0x7fffffff) { more = false; break; }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int sid = tid + h * kRBlock;
+                unsigned m = 0;
+#pragma unroll
+                for (int q = 0; q < kStrip; ++q)
+                    if (key[h][q] == k) m |= 1u << q;
+                pm[ns][sid] = (uint8_t)m;
+                if (m) {
+                    atomicOr(&segm[ns], 1u << ((sid & 7) + 8 * (sid >> 7)));
+                    done |= m << (8 * h);
+                }
+            }
+            if (tid == 0) slot_key[ns] = k;
+            ++ns;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int nc = 0;
+            for (int s2 = 0; s2 < ns; ++s2) {
+                const int cnt = __popc(segm[s2]);
+                for (int j0 = 0; j0 < cnt; j0 += kSBGroups)
+                    chunk_tab[nc++] = s2 | (j0 << 4) | (min(kSBGroups, cnt - j0) << 10);
+            }
+            n_chunks = nc;
+            next_chunk = 0;
+        }
+        __syncthreads();
+        const int nch = n_chunks;
+        while (true) {
+            int j = 0;
+            if (lane == 0) j = atomicAdd(&next_chunk, 1);
+            j = __builtin_amdgcn_readfirstlane(j);
+            if (j >= nch) break;
+            const int ct = __builtin_amdgcn_readfirstlane(chunk_tab[j]);
+            const int sl = ct & 15, first = (ct >> 4) & 63, cnt = ct >> 10;
+            const int k = __builtin_amdgcn_readfirstlane(slot_key[sl]);
+            unsigned bits = (unsigned)__builtin_amdgcn_readfirstlane((int)segm[sl]);
+            for (int t = 0; t < first; ++t) bits &= bits - 1u;
+            const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
+            const float* entry = bank + ((size_t)fd * A.L + lam) * 2 * kk;
+            const int pl = lane & 15, kg = lane >> 4;
+            const int side = kg >> 1, q0 = 4 * (kg & 1);
+            u32x4_t ga[kSBGroups];
+            uint32_t gl[kSBGroups][2];
+            int hrow[kSBGroups], hcol[kSBGroups];
+#pragma unroll
+            for (int u = 0; u < kSBGroups; ++u) {
+                const int seg = bits ? __builtin_ctz(bits) : 0;
+                if (u < cnt) bits &= bits - 1u;
+                const int sc = seg & 7, rs = seg >> 3;
+                const int tr = 16 * rs + pl;                           // tile strip row of row m = pl
+                const unsigned pmk = u < cnt ? pm[sl][tr * 8 + sc] : 0u;
+                const int y = min(y0 + tr, A.H - 1);
+                const size_t orow = (((size_t)n * 2 * A.C + c) * A.H + y) * A.W + side * plane;
+                uint32_t hb[4], lb[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int q = q0 + jj;
+                    const int xq = min(x0 + sc * kStrip + q, A.W - 1);
+                    float g = 0.f;
+                    if ((pmk >> q) & 1u) {
+                        g = A.gout[orow + xq];
+                        if (A.bank2d) g *= pass_weight(A, n, y, xq);
+                    }
+                    const uint32_t bb = split_bf16_bits(g);
+                    hb[jj] = bb & 0xffffu;
+                    lb[jj] = bb >> 16;
+                }
+                const uint32_t h01 = hb[0] | (hb[1] << 16), h23 = hb[2] | (hb[3] << 16);
+                ga[u] = u32x4_t{h01, h23, h01, h23};
+                gl[u][0] = lb[0] | (lb[1] << 16);
+                gl[u][1] = lb[2] | (lb[3] << 16);
+                hrow[u] = 16 * rs + KS - 1;
+                hcol[u] = sc * kStrip + pl;
+            }
+            if (cnt == 1) bank_split_bwd_rows<KS, 1>(entry, fxb, fyb, hgrad, scr, lane, ga, gl, hrow, hcol);
+            else bank_split_bwd_rows<KS, 2>(entry, fxb, fyb, hgrad, scr, lane, ga, gl, hrow, hcol);
+        }
+        __syncthreads();
+    }
+    // fold the tile's halo gradient onto the clamped image pixels
+    float* gi = A.gimg + ((size_t)n * A.C + c) * A.H * A.W;
+    for (int e = tid; e < S::HH * S::HWG; e += kRBlock) {
+        const int R = e / S::HWG, Cc = e - R * S::HWG;
+        const float v = hgrad[e];
+        if (v == 0.f || Cc >= kGT + KS - 1) continue;
+        const int yy = min(max(y0 - pad + R, 0), A.H - 1);
+        const int xx = min(max(x0 - pad + Cc, 0), A.W - 1);
+        atomicAdd(&gi[(size_t)yy * A.W + xx], v);
+    }
+}
+
 template <int KS, bool BWD>
 static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
-    if (BWD) {
+    if (BWD && A.split) {
+        using S = SplitBwdGeom<KS>;
+        const size_t shm = (size_t)S::HH * S::HWG * sizeof(float);
+        const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
+        const dim3 grid((unsigned)((long long)A.C * A.N * tilesx * tilesy));
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_split_bwd_kernel<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL(render_bank_split_bwd_kernel<KS>, grid, dim3(kRBlock), shm, st, A,
+                           reinterpret_cast<const float*>(A.psf));
+    } else if (BWD) {
         const size_t shm = (size_t)BandGeom<KS>::HH * BandGeom<KS>::HW * sizeof(float);
         const int bandsx = (A.W + kBW - 1) / kBW, bandsy = (A.H + kBR - 1) / kBR;
         const dim3 grid((unsigned)((long long)A.C * A.N * bandsx * bandsy));
@@ -1356,9 +1727,9 @@ static bool launch_bank_fast(const RenderArgs& A, hipStream_t st) {
         const size_t shm = (size_t)2 * S::HH * S::HWB * sizeof(uint16_t);
         const int tilesx = (A.W + kGT - 1) / kGT, tilesy = (A.H + kGT - 1) / kGT;
         const dim3 grid((unsigned)((long long)A.C * A.N * tilesx * tilesy));
-        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_fast_kernel<KS, kBankSplit>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL((render_bank_fast_kernel<KS, kBankSplit>), grid, dim3(kRBlock), shm, st, A,
-                           reinterpret_cast<const float*>(A.psf), (float*)nullptr);
+        if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_bank_split_kernel<KS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        hipLaunchKernelGGL(render_bank_split_kernel<KS>, grid, dim3(kRBlock), shm, st, A,
+                           reinterpret_cast<const float*>(A.psf));
     } else {
         using G = GroupGeom<KS>;
         const size_t shm = (size_t)G::HH * G::HW * sizeof(float);

@@ -442,3 +442,130 @@ def test_bank_split_bf16_entry_per_pixel_noise_and_delta_kernels():
                          depth=dt).cpu().numpy()
     ref2 = R.render_bank(img, delta, dmap, radii, iv, loc, ps)
     assert np.max(np.abs(o2 - ref2)) <= 2.0 ** -16 * np.abs(ref2).max()
+
+
+# ---- split-bf16 bank adjoint ------------------------------------------------
+# The image adjoint on the bf16 matrix cores: the gradient and the kernel
+# taps split into hi + lo, products g_hi K_hi + g_hi K_lo + g_lo K_hi summed
+# in float32.  Each product is off by at most 3 * 2^-18 of its magnitude (the
+# dropped lo * lo term and the two split residuals), so with gradients of
+# both signs the bound is element-wise against the adjoint of |g| with the
+# (nonnegative) kernels: |err| <= 2^-15 * (|g| adjoint |K|).  Relative to the
+# result itself the error can exceed 1e-4 where the sum cancels.
+
+SPLIT_BOUND = 2.0 ** -15
+
+
+def _split_bound(gi, ref, absref):
+    ratio = np.abs(gi - ref) / np.maximum(absref, 1e-7 * absref.max())
+    return float(ratio.max())
+
+@pytest.mark.parametrize("ks", [21, 31, 33, 41, 63, 65])
+def test_bank_split_bf16_adjoint(ks):
+    N, C, H, W, F, D, L, ps = 2, 3, 45, 150, 6, 5, 3, 0.01
+    img, bank, radii, iv, dmap = _bank_case(N, C, H, W, ks, F, D, L, ps, 9)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps,
+                                        bank_math=abi.BANK_SPLIT_BF16)
+    g = np.random.default_rng(10).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    print("split-bf16 adjoint ks %d" % ks, flush=True)
+    gi = sdirt.render_dp_backward(desc, torch.from_numpy(bank).cuda(), torch.from_numpy(g).cuda(),
+                                  depth=torch.from_numpy(dmap).cuda())
+    gref = R.render_bank_adjoint(g, bank, dmap, radii, iv, loc, ps)
+    gabs = R.render_bank_adjoint(np.abs(g), bank, dmap, radii, iv, loc, ps)
+    b = _split_bound(gi.cpu().numpy(), gref, gabs)
+    print("split-bf16 adjoint ks %d err / (|g| adjoint K) %.2e" % (ks, b))
+    assert b <= SPLIT_BOUND
+
+
+def test_bank_split_bf16_adjoint_smooth_depth_long_segments():
+    # few entries over large regions: full 16-row segments whose diagonals
+    # run through every kernel row, several tiles with ragged edges
+    N, C, H, W, ks, F, D, L, ps = 1, 3, 200, 270, 65, 3, 2, 3, 0.01
+    rng = np.random.default_rng(61)
+    bank = rng.uniform(0, 1, (F, D, L, 2, ks, ks)).astype(np.float32)
+    radii = np.linspace(0, np.hypot(W * ps / 2, H * ps / 2), F)
+    iv = np.array([1 / 3000.0, 1 / 1000.0])
+    dmap = np.where(np.arange(W)[None, None, :] < 150, 800.0, 4000.0) * np.ones((N, H, 1))
+    dmap = dmap.astype(np.float32)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps,
+                                        bank_math=abi.BANK_SPLIT_BF16)
+    g = rng.normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, torch.from_numpy(bank).cuda(), torch.from_numpy(g).cuda(),
+                                  depth=torch.from_numpy(dmap).cuda())
+    gref = R.render_bank_adjoint(g, bank, dmap, radii, iv, loc, ps)
+    gabs = R.render_bank_adjoint(np.abs(g), bank, dmap, radii, iv, loc, ps)
+    b = _split_bound(gi.cpu().numpy(), gref, gabs)
+    print("split-bf16 adjoint smooth depth err / (|g| adjoint K) %.2e" % b)
+    assert b <= SPLIT_BOUND
+
+
+@pytest.mark.parametrize("ks", [21, 65])
+def test_bank_split_bf16_adjoint_positive_gradient(ks):
+    # nonnegative upstream gradient: sums do not cancel and the relative
+    # bar of the float32 path applies element by element
+    N, C, H, W, F, D, L, ps = 2, 3, 45, 150, 6, 5, 3, 0.01
+    img, bank, radii, iv, dmap = _bank_case(N, C, H, W, ks, F, D, L, ps, 19)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps,
+                                        bank_math=abi.BANK_SPLIT_BF16)
+    g = np.random.default_rng(20).uniform(0, 1, (N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, torch.from_numpy(bank).cuda(), torch.from_numpy(g).cuda(),
+                                  depth=torch.from_numpy(dmap).cuda())
+    err = _rel(gi.cpu().numpy(), R.render_bank_adjoint(g, bank, dmap, radii, iv, loc, ps))
+    print("split-bf16 adjoint, positive gradient, ks %d rel err %.2e" % (ks, err))
+    assert err <= REL_TOL
+
+
+@pytest.mark.parametrize("ks,noise", [(21, False), (33, True), (65, False)])
+def test_bank2d_split_bf16_adjoint(ks, noise):
+    N, C, H, W, Fx, Fy, D, L, ps = 2, 3, 45, 150, 5, 4, 4, 3, 0.01
+    img, bank, xs, ys, iv, dmap = _bank2d_case(N, C, H, W, ks, Fx, Fy, D, L, ps, 41, noise)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK2D,
+                                        field_radii=xs, field_y=ys, inv_depths=iv,
+                                        bank_lambdas=L, lambda_of_channel=loc, pitch=ps,
+                                        bank_math=abi.BANK_SPLIT_BF16)
+    g = np.random.default_rng(42).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, torch.from_numpy(bank).cuda(), torch.from_numpy(g).cuda(),
+                                  depth=torch.from_numpy(dmap).cuda())
+    gref = R.render_bank2d_adjoint(g, bank, dmap, xs, ys, iv, loc, ps)
+    gabs = R.render_bank2d_adjoint(np.abs(g), bank, dmap, xs, ys, iv, loc, ps)
+    assert _split_bound(gi.cpu().numpy(), gref, gabs) <= SPLIT_BOUND
+
+
+def test_bank_split_bf16_adjoint_noise_and_delta_kernels():
+    # white-noise depth (many entries per tile: several batches of entries),
+    # and delta kernels, whose adjoint moves each output gradient to one
+    # image pixel and must match to float32 accuracy
+    N, C, H, W, ks, F, D, L, ps = 1, 3, 130, 200, 21, 9, 24, 3, 0.01
+    rng = np.random.default_rng(31)
+    bank = rng.uniform(0, 1, (F, D, L, 2, ks, ks)).astype(np.float32)
+    radii = np.linspace(0, np.hypot(W * ps / 2, H * ps / 2), F)
+    iv = np.linspace(1 / 5000.0, 1 / 500.0, D)
+    dmap = (1.0 / rng.uniform(1 / 5000.0, 1 / 500.0, (N, H, W))).astype(np.float32)
+    loc = [2, 1, 0]
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, source=abi.SRC_BANK,
+                                        field_radii=radii, inv_depths=iv, bank_lambdas=L,
+                                        lambda_of_channel=loc, pitch=ps,
+                                        bank_math=abi.BANK_SPLIT_BF16)
+    dt = torch.from_numpy(dmap).cuda()
+    g = rng.normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gi = sdirt.render_dp_backward(desc, torch.from_numpy(bank).cuda(), torch.from_numpy(g).cuda(), depth=dt)
+    gref = R.render_bank_adjoint(g, bank, dmap, radii, iv, loc, ps)
+    gabs = R.render_bank_adjoint(np.abs(g), bank, dmap, radii, iv, loc, ps)
+    assert _split_bound(gi.cpu().numpy(), gref, gabs) <= SPLIT_BOUND
+    delta = np.zeros_like(bank)
+    delta[..., 0, 3, 17] = 1.0
+    delta[..., 1, 10, 10] = 1.0
+    g2 = sdirt.render_dp_backward(desc, torch.from_numpy(delta).cuda(), torch.from_numpy(g).cuda(),
+                                  depth=dt).cpu().numpy()
+    ref2 = R.render_bank_adjoint(g, delta, dmap, radii, iv, loc, ps)
+    assert np.max(np.abs(g2 - ref2)) <= 2.0 ** -15 * np.abs(ref2).max()
