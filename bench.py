@@ -95,7 +95,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--pmc-target", default=None,
-                    choices=["calib", "trace", "trace_paper", "render", "render_bwd", "render_split", "dense",
+                    choices=["calib", "trace", "trace_paper", "render", "render_bwd", "render_split",
+                             "render_split_bwd", "dense",
                              "mlp_head"],
                     help="for counter runs: a 1 GiB device copy (calibration of the memory "
                          "counters), then one launch of the named kernel; prints nothing")
@@ -515,7 +516,8 @@ def pmc_target(name, dev):
       trace       the step's trace (16-surface aspheric lens, 6144 PSFs);
       trace_paper the paper's PSF map (RF50, 393,216 PSFs x 4096 rays);
       render, render_bwd  the step's bank render and image adjoint;
-      render_split  the step's bank render on the split-bf16 matrix cores;
+      render_split, render_split_bwd  the step's bank render and image
+                  adjoint on the split-bf16 matrix cores;
       dense       dense render of 512 x 512 RGB with a 41 x 41 f32 map;
       mlp_head    surrogate inference of 2^20 rows (ks 33, bf16 out)."""
     import ctypes as C
@@ -540,7 +542,7 @@ def pmc_target(name, dev):
         dmap = scenes.depth_uniform_inverse(H, W, 500.0, 20000.0, seed=100)
         pts = torch.from_numpy(configs.pixel_points(H, W, sensor.pitch, dmap)).to(dev)
         sdirt.trace_dp_psf(lens, sensor, query, points=pts, stats=False)
-    elif name in ("render", "render_bwd", "render_split"):
+    elif name in ("render", "render_bwd", "render_split", "render_split_bwd"):
         lens, sensor, query = configs.config5()
         bank, _ = sdirt.trace_dp_psf(lens, sensor, query, stats=False)
         H, W, N = sensor.height_px, sensor.width_px, 16
@@ -555,7 +557,7 @@ def pmc_target(name, dev):
                                             bank_lambdas=3,
                                             lambda_of_channel=list(configs.LAMBDA_OF_RGB),
                                             pitch=sensor.pitch,
-                                            bank_math=abi.BANK_SPLIT_BF16 if name == "render_split"
+                                            bank_math=abi.BANK_SPLIT_BF16 if "split" in name
                                             else abi.BANK_FP32)
         if name in ("render", "render_split"):
             sdirt.render_dp(desc, img, bank, depth=dmap)

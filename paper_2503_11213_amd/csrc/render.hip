@@ -1360,30 +1360,32 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
 //
 // The bank adjoint scatters each output's gradient through its own entry's
 // kernel.  A workgroup owns a 64 x 64 pixel tile and an LDS float32 copy of
-// its halo gradient; entries are taken in batches, and for an entry a group
-// is a segment of 16 consecutive strip rows of one strip column (strips or
-// pixels outside the entry carry zero gradient).  For kernel row i, strip n
-// of a group adds D_i[n][p] = sum over (side, q) of g[n][(side, q)] *
-// K_side[i][KS - 1 - p + q] at halo row (strip row n + KS - 1 - i), column
-// 8 (strip column) + p, for the window columns p < P = 16 NB: a 16 x 16 x 16
-// product per block of 16 columns, taken as g_hi (K_hi + K_lo) on a
-// v_mfma_f32_16x16x32_bf16 (the K index holds (side, q) twice, once against
-// hi taps and once against lo taps) plus g_lo K_hi on a
-// v_mfma_f32_16x16x16_bf16 that reuses the first half of the same tap
-// fragment.  The halo row of (n, i) is fixed along n - i, so the gradient
-// operand's rows are rotated by one strip per kernel row (DPP row_ror): row
-// m holds strip (m + i) mod 16, and accumulator row m keeps adding into one
-// halo row until its strip index wraps, when that row's sum since its last
-// wrap (16 lanes of one register, less its value at that wrap) is added into
-// the LDS halo with ds_add_f32.  The accumulators are never cleared: only
-// the matrix cores write them, so every product accumulates in place.  Taps
-// are staged per kernel row as natural-order hi and lo rows between zero
-// margins; a lane reads its four taps as three dwords shifted into place by
-// v_alignbit.  Finally the halo is added onto the clamped image pixels with
-// global atomics.
+// its halo gradient; entries are taken in batches, and for an entry the unit
+// of work is a segment of 16 consecutive strip rows of one strip column
+// (strips or pixels outside the entry carry zero gradient).  For kernel row
+// i, strip n of a segment adds D_i[n][p] = sum over (side, q) of
+// g[n][(side, q)] * K_side[i][KS - 1 - p + q] at halo row (strip row n +
+// KS - 1 - i), column 8 (strip column) + p, for the window columns p < P =
+// 16 NB: per block of 16 columns, two v_mfma_f32_16x16x32_bf16 on one tap
+// fragment (hi taps, then lo taps, along K): g_hi (K_hi + K_lo), and g_lo
+// K_hi with zeros against the lo half.  The halo row of (n, i) is fixed
+// along n - i, so the gradient operand's rows are rotated by one strip per
+// kernel row (DPP row_ror): row m holds strip (m + i) mod 16, and
+// accumulator row m keeps adding into one halo row until its strip index
+// wraps.  The row it finished continues, in the segment below, in that
+// segment's accumulator row m (which starts strip 0 at that kernel row), so
+// a run of vertically adjacent segments hands each finished row down the
+// run, and only the lowest segment adds its finished row (16 lanes of one
+// register) into the LDS halo with ds_add_f32.  The accumulators are never
+// cleared (only the matrix cores write them, so every product accumulates
+// in place, in one instruction type); a second set records each row's value
+// at its last wrap, less what it was handed.  Taps are staged per kernel row
+// as natural-order hi and lo rows between zero margins; a lane reads its four
+// taps as three dwords shifted into place by v_alignbit.  Finally the halo
+// is added onto the clamped image pixels with global atomics.
 constexpr int kSBSlots = 8;                       // entries per batch
-constexpr int kSBGroups = 2;                      // segments per chunk
-constexpr int kSBChunks = kSBSlots * 32 / kSBGroups;
+constexpr int kSBGroups = 4;                      // segments per run (a tile column)
+constexpr int kSBChunks = kSBSlots * 16;          // runs per batch (<= 2 per column)
 
 template <int KS>
 struct SplitBwdGeom {
@@ -1397,11 +1399,10 @@ struct SplitBwdGeom {
     static constexpr int NTAP = 2 * KS;                          // taps of one kernel row
     static constexpr int HH = kGT + KS - 1;
     static constexpr int HWG = kGT + KS;                         // halo-gradient row stride (odd)
+    static constexpr int NGMAX = NB >= 5 ? 2 : 4;                // segments per run (registers)
     static_assert(MARG >= P - KS && RW >= MARG + KS + 9, "lane reads stay inside the staged row");
     static_assert(kGT - kStrip + PW <= HWG - 1, "window columns inside the halo row");
 };
-
-typedef short short4_t __attribute__((ext_vector_type(4)));
 
 // One lane's share of staging one kernel row (both sides, natural tap order
 // v, mirrors applied): element e = lane + 64 k of [2 sides][KS].
@@ -1444,15 +1445,17 @@ __device__ inline uint32_t rot_row_left(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x12f, 0xf, 0xf, false);
 }
 
-// All kernel rows for NG groups (segments) of one entry.  ga / gl: the
-// lane's gradient fragments (x32: g_hi twice; x16: g_lo) of strip m = lane
-// % 16 at i = 0; hrow: the halo row of strip 0 at i = 0 (segment row + KS -
-// 1), hcol: the lane's halo column at block 0 (strip column + lane % 16).
+// All kernel rows for a run of NG vertically adjacent segments of one entry
+// (segment u at strip rows 16 (rs0 + u) ..).  ga / gl: the lane's x32
+// gradient fragments of strip m = lane % 16 of each segment at i = 0 (g_hi
+// twice; g_lo then zeros); hrow: the halo row of strip 0 of the top segment
+// at i = 0 (16 rs0 + KS - 1); hcol: the lane's halo column at block 0
+// (8 strip column + lane % 16).
 template <int KS, int NG>
 __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool fx, bool fy,
                                            float* hg, float* scratch, int lane,
-                                           u32x4_t (&ga)[kSBGroups], uint32_t (&gl)[kSBGroups][2],
-                                           const int (&hrow)[kSBGroups], const int (&hcol)[kSBGroups]) {
+                                           u32x4_t (&ga)[kSBGroups], u32x4_t (&gl)[kSBGroups],
+                                           int hrow, int hcol) {
     using S = SplitBwdGeom<KS>;
     u16_alias* st = reinterpret_cast<u16_alias*>(scratch);
     const u32_alias* sw = reinterpret_cast<const u32_alias*>(scratch);
@@ -1461,17 +1464,15 @@ __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool
     const int s0 = S::MARG + KS - 1 - pl + q0;                 // block 0, relative to the row
     const uint32_t sh = (s0 & 1) * 16;
     const int ad0 = (side * S::RW + s0) >> 1;                  // block b: ad0 - 8 b
-    // acc (x32 products) and acc2 (x16 products): running sums written only
-    // by the matrix cores, each an in-place chain of one instruction; prev:
-    // their total at each row's last flush, so that a flush adds
-    // acc + acc2 - prev, the sum since then
-    floatx4_t acc[NG][S::NB], acc2[NG][S::NB], prev[NG][S::NB];
+    // acc: running sums written only by the matrix cores; prev: each row's
+    // value at its last wrap, less the sum it was handed then, so that
+    // acc - prev is the row's halo total so far
+    floatx4_t acc[NG][S::NB], prev[NG][S::NB];
 #pragma unroll
     for (int u = 0; u < NG; ++u)
 #pragma unroll
         for (int b = 0; b < S::NB; ++b) {
             acc[u][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-            acc2[u][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
             prev[u][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
         }
     const int rstep = fy ? -KS : KS;
@@ -1484,22 +1485,25 @@ __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool
         __asm__ volatile("" ::: "memory");
         if (i + 1 < KS) taps.load(entry, (i + 1) * rstep);
         if (i > 0) {
-            // accumulator row m* = (16 - i) mod 16 finished its halo row
-            // (strip 15 at row i - 1): add it in
+            // accumulator row m* = (16 - i) mod 16 of every segment finished
+            // a halo row (strip 15 at row i - 1): each hands it to the
+            // segment below, the lowest adds it into the halo
             const int ms = (16 - (i & 15)) & 15;
             const bool mine = kg == (ms >> 2);
+            const int rb = (hrow + 16 * (NG - 1) + 16 - i) * S::HWG + hcol;
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 if ((ms & 3) != jj) continue;
 #pragma unroll
-                for (int u = 0; u < NG; ++u) {
-                    const int rb = (hrow[u] + 16 - i) * S::HWG + hcol[u];
+                for (int b = 0; b < S::NB; ++b) {
+                    float v[NG];
 #pragma unroll
-                    for (int b = 0; b < S::NB; ++b) {
-                        const float tot = acc[u][b][jj] + acc2[u][b][jj];
-                        if (mine && 16 * b + pl < S::PW) atomicAdd(&hg[rb + 16 * b], tot - prev[u][b][jj]);
-                        prev[u][b][jj] = mine ? tot : prev[u][b][jj];
-                    }
+                    for (int u = 0; u < NG; ++u) v[u] = acc[u][b][jj] - prev[u][b][jj];
+                    if (mine && 16 * b + pl < S::PW) atomicAdd(&hg[rb + 16 * b], v[NG - 1]);
+                    prev[0][b][jj] = mine ? acc[0][b][jj] : prev[0][b][jj];
+#pragma unroll
+                    for (int u = 1; u < NG; ++u)
+                        prev[u][b][jj] = mine ? acc[u][b][jj] - v[u - 1] : prev[u][b][jj];
                 }
             }
             // gradient rows move up by one strip
@@ -1524,28 +1528,27 @@ __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool
             const uint32_t l0 = __builtin_amdgcn_alignbit(l[1], l[0], sh);
             const uint32_t l1 = __builtin_amdgcn_alignbit(l[2], l[1], sh);
             const bf16x8_t t32 = __builtin_bit_cast(bf16x8_t, u32x4_t{h0, h1, l0, l1});
-            const short4_t t16 = __builtin_bit_cast(short4_t, uint2{h0, h1});
 #pragma unroll
             for (int u = 0; u < NG; ++u) {
                 acc[u][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ga[u]), t32,
                                                                     acc[u][b], 0, 0, 0);
-                acc2[u][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
-                    __builtin_bit_cast(short4_t, uint2{gl[u][0], gl[u][1]}), t16, acc2[u][b], 0, 0, 0);
+                acc[u][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, gl[u]), t32,
+                                                                    acc[u][b], 0, 0, 0);
             }
         }
     }
-    // every accumulator row holds part of one halo row: strip
-    // n = (m + KS - 1) mod 16 at the last kernel row, halo row n
+    // every accumulator row holds (part of) one halo row: strip
+    // n = (m + KS - 1) mod 16 of its segment at the last kernel row, halo row
+    // 16 (rs0 + u) + n
 #pragma unroll
     for (int u = 0; u < NG; ++u)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
             const int nn = (4 * kg + jj + KS - 1) & 15;
-            const int rb = (hrow[u] - (KS - 1) + nn) * S::HWG + hcol[u];
+            const int rb = (hrow - (KS - 1) + 16 * u + nn) * S::HWG + hcol;
 #pragma unroll
             for (int b = 0; b < S::NB; ++b)
-                if (16 * b + pl < S::PW)
-                    atomicAdd(&hg[rb + 16 * b], acc[u][b][jj] + acc2[u][b][jj] - prev[u][b][jj]);
+                if (16 * b + pl < S::PW) atomicAdd(&hg[rb + 16 * b], acc[u][b][jj] - prev[u][b][jj]);
         }
 }
 
@@ -1557,7 +1560,7 @@ __global__ __launch_bounds__(kRBlock, 2) void render_bank_split_bwd_kernel(const
     __shared__ uint8_t pm[kSBSlots][kGStrips];                     // pixel masks per batch entry
     __shared__ unsigned segm[kSBSlots];                            // segments holding the entry
     __shared__ int slot_key[kSBSlots];
-    __shared__ int chunk_tab[kSBChunks];                           // slot | first << 4 | count << 10
+    __shared__ int chunk_tab[kSBChunks];                           // slot | col << 4 | row << 7 | len << 9
     __shared__ int red[kRBlock / 64];
     __shared__ int n_chunks, next_chunk;
     __shared__ __align__(16) float wscr[kRBlock / 64][S::SCRATCH];
@@ -1631,10 +1634,19 @@ __global__ __launch_bounds__(kRBlock, 2) void render_bank_split_bwd_kernel(const
         __syncthreads();
         if (tid == 0) {
             int nc = 0;
+            // runs of vertically adjacent segments, column by column
             for (int s2 = 0; s2 < ns; ++s2) {
-                const int cnt = __popc(segm[s2]);
-                for (int j0 = 0; j0 < cnt; j0 += kSBGroups)
-                    chunk_tab[nc++] = s2 | (j0 << 4) | (min(kSBGroups, cnt - j0) << 10);
+                const unsigned bits = segm[s2];
+                for (int sc = 0; sc < kStrip; ++sc) {
+                    int rs = 0;
+                    while (rs < 4) {
+                        if (!((bits >> (8 * rs + sc)) & 1u)) { ++rs; continue; }
+                        int len = 1;
+                        while (rs + len < 4 && len < S::NGMAX && ((bits >> (8 * (rs + len) + sc)) & 1u)) ++len;
+                        chunk_tab[nc++] = s2 | (sc << 4) | (rs << 7) | (len << 9);
+                        rs += len;
+                    }
+                }
             }
             n_chunks = nc;
             next_chunk = 0;
@@ -1647,23 +1659,16 @@ __global__ __launch_bounds__(kRBlock, 2) void render_bank_split_bwd_kernel(const
             j = __builtin_amdgcn_readfirstlane(j);
             if (j >= nch) break;
             const int ct = __builtin_amdgcn_readfirstlane(chunk_tab[j]);
-            const int sl = ct & 15, first = (ct >> 4) & 63, cnt = ct >> 10;
+            const int sl = ct & 15, sc = (ct >> 4) & 7, rs0 = (ct >> 7) & 3, cnt = ct >> 9;
             const int k = __builtin_amdgcn_readfirstlane(slot_key[sl]);
-            unsigned bits = (unsigned)__builtin_amdgcn_readfirstlane((int)segm[sl]);
-            for (int t = 0; t < first; ++t) bits &= bits - 1u;
             const int fyb = k & 1, fxb = (k >> 1) & 1, fd = k >> 2;
             const float* entry = bank + ((size_t)fd * A.L + lam) * 2 * kk;
             const int pl = lane & 15, kg = lane >> 4;
             const int side = kg >> 1, q0 = 4 * (kg & 1);
-            u32x4_t ga[kSBGroups];
-            uint32_t gl[kSBGroups][2];
-            int hrow[kSBGroups], hcol[kSBGroups];
+            u32x4_t ga[kSBGroups], gl[kSBGroups];
 #pragma unroll
             for (int u = 0; u < kSBGroups; ++u) {
-                const int seg = bits ? __builtin_ctz(bits) : 0;
-                if (u < cnt) bits &= bits - 1u;
-                const int sc = seg & 7, rs = seg >> 3;
-                const int tr = 16 * rs + pl;                           // tile strip row of row m = pl
+                const int tr = 16 * min(rs0 + u, 3) + pl;              // tile strip row of row m = pl
                 const unsigned pmk = u < cnt ? pm[sl][tr * 8 + sc] : 0u;
                 const int y = min(y0 + tr, A.H - 1);
                 const size_t orow = (((size_t)n * 2 * A.C + c) * A.H + y) * A.W + side * plane;
@@ -1683,13 +1688,17 @@ __global__ __launch_bounds__(kRBlock, 2) void render_bank_split_bwd_kernel(const
                 }
                 const uint32_t h01 = hb[0] | (hb[1] << 16), h23 = hb[2] | (hb[3] << 16);
                 ga[u] = u32x4_t{h01, h23, h01, h23};
-                gl[u][0] = lb[0] | (lb[1] << 16);
-                gl[u][1] = lb[2] | (lb[3] << 16);
-                hrow[u] = 16 * rs + KS - 1;
-                hcol[u] = sc * kStrip + pl;
+                gl[u] = u32x4_t{lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16), 0u, 0u};
             }
-            if (cnt == 1) bank_split_bwd_rows<KS, 1>(entry, fxb, fyb, hgrad, scr, lane, ga, gl, hrow, hcol);
-            else bank_split_bwd_rows<KS, 2>(entry, fxb, fyb, hgrad, scr, lane, ga, gl, hrow, hcol);
+            const int hrow = 16 * rs0 + KS - 1, hcol = sc * kStrip + pl;
+            if (cnt == 1) {
+                bank_split_bwd_rows<KS, 1>(entry, fxb, fyb, hgrad, scr, lane, ga, gl, hrow, hcol);
+            } else if (cnt == 2 || S::NGMAX == 2) {
+                bank_split_bwd_rows<KS, 2>(entry, fxb, fyb, hgrad, scr, lane, ga, gl, hrow, hcol);
+            } else if constexpr (S::NGMAX == 4) {
+                if (cnt == 3) bank_split_bwd_rows<KS, 3>(entry, fxb, fyb, hgrad, scr, lane, ga, gl, hrow, hcol);
+                else bank_split_bwd_rows<KS, 4>(entry, fxb, fyb, hgrad, scr, lane, ga, gl, hrow, hcol);
+            }
         }
         __syncthreads();
     }
