@@ -1376,10 +1376,10 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
 // segment's accumulator row m (which starts strip 0 at that kernel row), so
 // a run of vertically adjacent segments hands each finished row down the
 // run, and only the lowest segment adds its finished row (16 lanes of one
-// register) into the LDS halo with ds_add_f32.  The accumulators are never
-// cleared (only the matrix cores write them, so every product accumulates
-// in place, in one instruction type); a second set records each row's value
-// at its last wrap, less what it was handed.  Taps are staged per kernel row
+// register) into the LDS halo with ds_add_f32; the rows above move down one
+// segment and the top one restarts from zero.  All products go through one
+// instruction type (an MFMA reading another type's result as its
+// accumulator has returned stale rows).  Taps are staged per kernel row
 // as natural-order hi and lo rows between zero margins; a lane reads its four
 // taps as three dwords shifted into place by v_alignbit.  Finally the halo
 // is added onto the clamped image pixels with global atomics.
@@ -1399,7 +1399,7 @@ struct SplitBwdGeom {
     static constexpr int NTAP = 2 * KS;                          // taps of one kernel row
     static constexpr int HH = kGT + KS - 1;
     static constexpr int HWG = kGT + KS;                         // halo-gradient row stride (odd)
-    static constexpr int NGMAX = NB >= 5 ? 2 : 4;                // segments per run (registers)
+    static constexpr int NGMAX = 4;                              // segments per run
     static_assert(MARG >= P - KS && RW >= MARG + KS + 9, "lane reads stay inside the staged row");
     static_assert(kGT - kStrip + PW <= HWG - 1, "window columns inside the halo row");
 };
@@ -1464,17 +1464,13 @@ __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool
     const int s0 = S::MARG + KS - 1 - pl + q0;                 // block 0, relative to the row
     const uint32_t sh = (s0 & 1) * 16;
     const int ad0 = (side * S::RW + s0) >> 1;                  // block b: ad0 - 8 b
-    // acc: running sums written only by the matrix cores; prev: each row's
-    // value at its last wrap, less the sum it was handed then, so that
-    // acc - prev is the row's halo total so far
-    floatx4_t acc[NG][S::NB], prev[NG][S::NB];
+    // acc: the running halo rows, one 16 x 16 block per segment and window
+    // block (row m of segment u: strip (m + i) mod 16's halo row)
+    floatx4_t acc[NG][S::NB];
 #pragma unroll
     for (int u = 0; u < NG; ++u)
 #pragma unroll
-        for (int b = 0; b < S::NB; ++b) {
-            acc[u][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-            prev[u][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int b = 0; b < S::NB; ++b) acc[u][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     const int rstep = fy ? -KS : KS;
     SplitRowTaps<KS> taps;
     taps.init(lane, fx, fy);
@@ -1486,8 +1482,9 @@ __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool
         if (i + 1 < KS) taps.load(entry, (i + 1) * rstep);
         if (i > 0) {
             // accumulator row m* = (16 - i) mod 16 of every segment finished
-            // a halo row (strip 15 at row i - 1): each hands it to the
-            // segment below, the lowest adds it into the halo
+            // a halo row (strip 15 at row i - 1), which the same row of the
+            // segment below continues: the lowest adds its row into the halo,
+            // the others move down one segment, the top one starts from zero
             const int ms = (16 - (i & 15)) & 15;
             const bool mine = kg == (ms >> 2);
             const int rb = (hrow + 16 * (NG - 1) + 16 - i) * S::HWG + hcol;
@@ -1496,14 +1493,10 @@ __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool
                 if ((ms & 3) != jj) continue;
 #pragma unroll
                 for (int b = 0; b < S::NB; ++b) {
-                    float v[NG];
+                    if (mine && 16 * b + pl < S::PW) atomicAdd(&hg[rb + 16 * b], acc[NG - 1][b][jj]);
 #pragma unroll
-                    for (int u = 0; u < NG; ++u) v[u] = acc[u][b][jj] - prev[u][b][jj];
-                    if (mine && 16 * b + pl < S::PW) atomicAdd(&hg[rb + 16 * b], v[NG - 1]);
-                    prev[0][b][jj] = mine ? acc[0][b][jj] : prev[0][b][jj];
-#pragma unroll
-                    for (int u = 1; u < NG; ++u)
-                        prev[u][b][jj] = mine ? acc[u][b][jj] - v[u - 1] : prev[u][b][jj];
+                    for (int u = NG - 1; u > 0; --u) acc[u][b][jj] = mine ? acc[u - 1][b][jj] : acc[u][b][jj];
+                    acc[0][b][jj] = mine ? 0.f : acc[0][b][jj];
                 }
             }
             // gradient rows move up by one strip
@@ -1548,7 +1541,7 @@ __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool
             const int rb = (hrow - (KS - 1) + 16 * u + nn) * S::HWG + hcol;
 #pragma unroll
             for (int b = 0; b < S::NB; ++b)
-                if (16 * b + pl < S::PW) atomicAdd(&hg[rb + 16 * b], acc[u][b][jj] - prev[u][b][jj]);
+                if (16 * b + pl < S::PW) atomicAdd(&hg[rb + 16 * b], acc[u][b][jj]);
         }
 }
 
