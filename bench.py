@@ -31,6 +31,9 @@ METRIC = ("rays·surfaces/s and DP PSFs/s; render Mpix/s; fwd+bwd vs fwd time; "
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+# three bf16 products per float32 product on the split path
+PEAK_SPLIT_BF16_TFLOPS = PEAK_BF16_MFMA_TFLOPS / 3
 
 # Algorithmic FLOPs of the float64 trace (add/mul = 1, fma = 2, div/sqrt/
 # rsqrt = 1), counted on the surfaces a ray reaches alive:
@@ -618,7 +621,7 @@ def main():
                                         field_radii=[f[0] for f in query.fields],
                                         inv_depths=[1.0 / d for d in query.depths],
                                         bank_lambdas=3, lambda_of_channel=list(configs.LAMBDA_OF_RGB),
-                                        pitch=sensor.pitch)
+                                        pitch=sensor.pitch, bank_math=abi.BANK_SPLIT_BF16)
     out = torch.empty((N, 6, H, W), dtype=torch.float32, device=dev)
     gimg = torch.empty((N, 3, H, W), dtype=torch.float32, device=dev)
 
@@ -697,13 +700,28 @@ def main():
                   "psfs_per_s": P / (ms_trace * 1e-3),
                   "in_window_energy_fraction": float((st[:, 3] + st[:, 4]).sum() / st[:, 0].sum()),
                   "transmitted_fraction": float(st[:, 2].sum() / st[:, 0].sum())},
-        "render": {"fwd_ms": ms_render, "bwd_ms": ms_rbwd,
+        "render": {"arithmetic": "split-bf16 matrix cores (hi*hi + hi*lo + lo*hi, float32 accumulation)",
+                   "fwd_ms": ms_render, "bwd_ms": ms_rbwd,
                    "fwd_mpix_per_s": npx / (ms_render * 1e-3) / 1e6,
                    "fwd_tflops": render_flop / (ms_render * 1e-3) / 1e12,
-                   "fwd_fp32_mfma_frac": render_flop / (ms_render * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                   "fwd_split_bf16_frac": render_flop / (ms_render * 1e-3) / 1e12 / PEAK_SPLIT_BF16_TFLOPS,
                    "bwd_tflops": render_flop / (ms_rbwd * 1e-3) / 1e12,
+                   "bwd_split_bf16_frac": render_flop / (ms_rbwd * 1e-3) / 1e12 / PEAK_SPLIT_BF16_TFLOPS,
                    "fwd_plus_bwd_over_fwd": (ms_render + ms_rbwd) / ms_render},
     }
+    # the same render on the float32 matrix cores, for comparison
+    desc32, keep32 = sdirt.make_render_desc(N, 3, H, W, ks, source=abi.SRC_BANK,
+                                            field_radii=[f[0] for f in query.fields],
+                                            inv_depths=[1.0 / d for d in query.depths],
+                                            bank_lambdas=3, lambda_of_channel=list(configs.LAMBDA_OF_RGB),
+                                            pitch=sensor.pitch, bank_math=abi.BANK_FP32)
+    sdirt.render_dp(desc32, img, bank, depth=dmap, out=out)
+    sdirt.render_dp_backward(desc32, bank, gout, depth=dmap, grad_img=gimg)
+    t32f = timed(lambda: sdirt.render_dp(desc32, img, bank, depth=dmap, out=out), stream, 2)
+    t32b = timed(lambda: sdirt.render_dp_backward(desc32, bank, gout, depth=dmap, grad_img=gimg), stream, 2)
+    line["render"]["fp32_mfma"] = {"fwd_ms": t32f, "bwd_ms": t32b,
+                                   "fwd_frac": render_flop / (t32f * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                                   "bwd_frac": render_flop / (t32b * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS}
     del img, dmap, gout, out, gimg
     torch.cuda.empty_cache()
     if not args.no_extras:
