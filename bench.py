@@ -474,7 +474,7 @@ def config2_step(dev, stream, reps=5):
                                         field_radii=[f[0] for f in query.fields],
                                         inv_depths=[1.0 / d for d in query.depths],
                                         bank_lambdas=3, lambda_of_channel=list(configs.LAMBDA_OF_RGB),
-                                        pitch=ps)
+                                        pitch=ps, bank_math=abi.BANK_SPLIT_BF16)
     P = query.n_points
     bank = torch.empty((P, 2, query.ks, query.ks), dtype=torch.float32, device=dev)
     out = torch.empty((1, 6, H, W), dtype=torch.float32, device=dev)

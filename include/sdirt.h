@@ -261,16 +261,19 @@ typedef struct {
     int bank_fields_y;           /* BANK2D: Fy                             */
     const double* field_y;       /* BANK2D: host [Fy], strictly increasing */
     int bank_math;               /* banks: SDIRT_BANK_FP32 (default) or
-                                    SDIRT_BANK_SPLIT_BF16 (forward only)    */
+                                    SDIRT_BANK_SPLIT_BF16                   */
 } sdirt_render_desc;
 
-/* Arithmetic of the bank render forward (SDIRT_SRC_BANK / BANK2D at the
- * matrix-core window sizes; Supplement S1.3's per-pixel convolution):
- * SDIRT_BANK_FP32 multiplies float32 kernels and image values on the fp32
- * matrix cores; SDIRT_BANK_SPLIT_BF16 splits each into bf16 hi + lo parts and
- * sums the three products hi*hi + hi*lo + lo*hi on the bf16 matrix cores
- * with float32 accumulation (relative error of a product below 2^-15).  The
- * adjoint and the kernel gradient use the float32 path in either case. */
+/* Arithmetic of the bank render and its image adjoint (SDIRT_SRC_BANK /
+ * BANK2D at the matrix-core window sizes ks = 21, 31, 33, 41, 63, 65;
+ * Supplement S1.3's per-pixel convolution): SDIRT_BANK_FP32 multiplies
+ * float32 kernels and image values (or output gradients) on the fp32 matrix
+ * cores; SDIRT_BANK_SPLIT_BF16 splits each into bf16 hi + lo parts and sums
+ * the three products hi*hi + hi*lo + lo*hi on the bf16 matrix cores with
+ * float32 accumulation (a product's error is below 3 * 2^-18 of its
+ * magnitude; a sum's error is bounded by that fraction of the sum of the
+ * products' magnitudes).  The gradient with respect to the bank, and every
+ * other window size, use float32 arithmetic in either case. */
 enum { SDIRT_BANK_FP32 = 0, SDIRT_BANK_SPLIT_BF16 = 1 };
 
 /* img device [N][C][H][W] f32; depth device [N][H][W] f32 (BANK only, may

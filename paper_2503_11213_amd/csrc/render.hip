@@ -40,7 +40,7 @@ struct RenderArgs {
     int lam_of_c[4];
     int tiles_x, tiles_y;
     int use_fast;        // bank source: grouped kernels when ks allows
-    int split;           // bank source: split-bf16 matrix cores (forward)
+    int split;           // bank source: split-bf16 matrix cores (render and image adjoint)
     const float* img;
     const void* psf;
     const float* depth;
