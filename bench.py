@@ -99,7 +99,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--pmc-target", default=None,
-                    choices=["calib", "trace", "trace_paper", "render", "render_bwd", "render_split",
+                    choices=["calib", "trace", "trace_paper", "trace_bwd", "render", "render_bwd",
+                             "render_split",
                              "render_split_bwd", "dense",
                              "mlp_head"],
                     help="for counter runs: a 1 GiB device copy (calibration of the memory "
@@ -519,6 +520,8 @@ def pmc_target(name, dev):
                   (8.39e9 float64 FMAs);
       trace       the step's trace (16-surface aspheric lens, 6144 PSFs);
       trace_paper the paper's PSF map (RF50, 393,216 PSFs x 4096 rays);
+      trace_bwd   the adjoint of the trace (12-surface lens, 192 PSFs x
+                  256^2 rays, ks 41, tent splat), after its forward;
       render, render_bwd  the step's bank render and image adjoint;
       render_split, render_split_bwd  the step's bank render and image
                   adjoint on the split-bf16 matrix cores;
@@ -541,6 +544,12 @@ def pmc_target(name, dev):
     elif name == "trace":
         lens, sensor, query = configs.config5()
         sdirt.trace_dp_psf(lens, sensor, query, stats=False)
+    elif name == "trace_bwd":
+        lens, sensor, query = configs.config3()
+        psf, _ = sdirt.trace_dp_psf(lens, sensor, query, stats=False)
+        g = torch.from_numpy(np.random.default_rng(5).standard_normal(tuple(psf.shape))
+                             .astype(np.float32)).to(dev)
+        sdirt.trace_dp_psf_backward(lens, sensor, query, g)
     elif name == "trace_paper":
         lens, sensor, query, (H, W) = configs.paper_psf_map()
         dmap = scenes.depth_uniform_inverse(H, W, 500.0, 20000.0, seed=100)

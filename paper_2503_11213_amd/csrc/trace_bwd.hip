@@ -74,6 +74,30 @@ __device__ inline double wave_sum_d(double v) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Row sums of two per-lane values at once: on return the even lanes of
+// each row of 16 hold the row's sum of a, the odd lanes its sum of b.  The
+// first step exchanges a and b within each lane pair (an even lane keeps
+// a and receives its odd neighbour's a, and the reverse for b), so the
+// three remaining steps carry one value per lane instead of two.
+__device__ inline double row_sum_pair(double a, double b, int lane) {
+    const bool odd = lane & 1;
+    double t = (odd ? b : a) + dpp_move<0xb1>(odd ? a : b);   // quad_perm [1, 0, 3, 2]
+    t += dpp_move<0x4e>(t);     // quad_perm [2, 3, 0, 1]
+    t += dpp_move<0x124>(t);    // row_ror:4
+    t += dpp_move<0x128>(t);    // row_ror:8
+    return t;
+}
+
+// Adds the wave's sums of a and b into LDS: lanes 0, 16, 32 and 48 add
+// their row's sum of a at g[ia] if ua, lanes 1, 17, 33 and 49 their row's
+// sum of b at g[ib] if ub.
+__device__ inline void lds_add_pair(double* g, double a, int ia, bool ua, double b, int ib, bool ub,
+                                    int lane) {
+    const double t = row_sum_pair(a, b, lane);
+    const bool odd = lane & 1;
+    if ((lane & 14) == 0 && (odd ? ub : ua) && t != 0.0) atomicAdd(&g[odd ? ib : ia], t);
+}
+
 // Adjoint of vector Snell refraction d' = mu d + g N, g = sqrt(K) - mu cosI,
 // K = 1 - mu^2 (1 - cosI^2), cosI = d . N.  Adds to db and nb.
 __device__ __forceinline__ void refract_bwd(double mu, const double d[3], const double n[3],
@@ -127,6 +151,7 @@ __device__ __forceinline__ SagD sag_derivs(const double* co, double c, double rh
 // refracted direction).  Writes the adjoint of `in` to `ib` and the
 // parameter adjoints [c, t_{s-1}, k, a4..a12] to pg (t_{s-1} at index 1 is
 // the thickness of the previous surface).
+template <bool GENERAL>
 __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu, const St& in,
                                    const St& ob, St& ib, double pg[kPerSurf]) {
     for (int k = 0; k < kPerSurf; ++k) pg[k] = 0.0;
@@ -150,7 +175,7 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
         sq = sqrt_t<double>(disc);
         den = G + sq;
         D = F * rcp_d(den);
-    } else if (kind == SDIRT_ASPHERE) {
+    } else if (GENERAL && kind == SDIRT_ASPHERE) {
         const double kk = co[0];
         const double FF = c * (x1 * x1 + y1 * y1);
         const double GG = dz - c * (x1 * dx + y1 * dy);
@@ -171,7 +196,7 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
             if (fabs(step) < 1e-12 * (1.0 + fabs(D))) break;
         }
     }
-    if (kind == SDIRT_SPHERE || kind == SDIRT_ASPHERE) {
+    if (kind == SDIRT_SPHERE || (GENERAL && kind == SDIRT_ASPHERE)) {
         xh = x1 + D * dx;
         yh = y1 + D * dy;
         zh = D * dz;
@@ -189,7 +214,7 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
         double nb[3] = {0.0, 0.0, 0.0};
         refract_bwd(mu, d, n, odb, db, nb);
         zhb = 0.0;
-    } else if (kind == SDIRT_IDEAL) {
+    } else if (GENERAL && kind == SDIRT_IDEAL) {
         const double tx = dx / dz - xh * c, ty = dy / dz - yh * c;
         const double inv = 1.0 / sqrt(tx * tx + ty * ty + 1.0);
         const double ab = odb[0] * tx + odb[1] * ty + odb[2];
@@ -232,7 +257,7 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
         x1b += Fb * 2.0 * c * x1; y1b += Fb * 2.0 * c * y1;
         pg[0] += Fb * (x1 * x1 + y1 * y1);
         xhb = x1b; yhb = y1b;     // now adjoints of x1, y1
-    } else {   // ASPHERE
+    } else if (GENERAL) {   // ASPHERE
         const double rho = xh * xh + yh * yh;
         const SagD S = sag_derivs(co, c, rho);
         const double nrm = sqrt(4.0 * rho * S.s1 * S.s1 + 1.0);
@@ -433,26 +458,23 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             St ib{0, 0, 0, 0, 0, 0};
             if (live) {
                 const St in = path_get(path, s, lane);
-                surface_bwd(A.lens, s, mu[s], in, ob, ib, pg);
+                surface_bwd<GENERAL>(A.lens, s, mu[s], in, ob, ib, pg);
                 ob = ib;
             } else {
                 for (int k = 0; k < kPerSurf; ++k) pg[k] = 0.0;
             }
             const int kind = kind_of(A.lens, s);
-            // c (sphere/asphere), t_{s-1} (s > 0), conic and a's (asphere)
-            if (kind == SDIRT_SPHERE || kind == SDIRT_ASPHERE) {
-                const double v = wave_sum_d(pg[0]);
-                if (lane == 0 && v != 0.0) atomicAdd(&gsh[kPerSurf * s + 0], v);
-            }
-            if (s > 0) {
-                const double v = wave_sum_d(pg[1]);
-                if (lane == 0 && v != 0.0) atomicAdd(&gsh[kPerSurf * (s - 1) + 1], v);
-            }
-            if (kind == SDIRT_ASPHERE) {
-                for (int k = 2; k < kPerSurf; ++k) {
-                    const double v = wave_sum_d(pg[k]);
-                    if (lane == 0 && v != 0.0) atomicAdd(&gsh[kPerSurf * s + k], v);
-                }
+            // c (sphere/asphere) with t_{s-1} (s > 0), then conic and the
+            // a's (asphere) in pairs
+            const bool has_c = kind == SDIRT_SPHERE || (GENERAL && kind == SDIRT_ASPHERE);
+            if (has_c || s > 0)
+                lds_add_pair(gsh, pg[0], kPerSurf * s, has_c, pg[1], kPerSurf * (s - 1) + 1, s > 0,
+                             lane);
+            if (GENERAL && kind == SDIRT_ASPHERE) {
+#pragma unroll
+                for (int k = 2; k < kPerSurf; k += 2)
+                    lds_add_pair(gsh, pg[k], kPerSurf * s + k, true, pg[k + 1], kPerSurf * s + k + 1,
+                                 true, lane);
             }
         }
     }
