@@ -6,14 +6,15 @@
 // every hidden layer run with the bf16 activations [64][256] in LDS (double
 // buffer), wave w computing output columns [64 w, 64 w + 64); the last
 // activations go to a chunk buffer in HBM (512 B per row).
-// Head: the softmax output layer (2 ks^2 columns, tiles of 64) of 64 rows,
-// two workgroups per compute unit.  Pass 1 computes each tile's logits and
-// keeps a running (max, sum of 2^z) per row and lane; the lanes of a row and
-// then the four waves merge them; pass 2 recomputes the tiles and writes
-// 2^(z - max - log2 sum) (bf16 or float32).  Recomputing doubles the output
-// layer's matrix work but keeps the float32 logits out of HBM.
+// Head: the softmax output layer (2 ks^2 columns, tiles of 64) of 256 rows,
+// each wave holding its 64 rows' activations in registers while the weight
+// tiles stream through LDS, two workgroups per compute unit.  Pass 1
+// computes each tile's logits and keeps a running (max, sum of 2^z) per row
+// and lane; the lanes of a row merge them; pass 2 recomputes the tiles and
+// writes 2^(z - max - log2 sum) (bf16 or float32).  Recomputing doubles the
+// output layer's matrix work but keeps the float32 logits out of HBM.
 // Weights are read in matrix-core fragment order (one 1 KB contiguous piece
-// per B fragment), two k-steps ahead of use.
+// per fragment).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -205,125 +206,139 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_trunk_kernel(const FusedArgs
     }
 }
 
-// Head products of one 64-column output tile t, transposed: acc[i][j]
-// holds C[column 16 j + 4 (l / 16) + r][row 16 i + l % 16], so lane l owns
-// rows 16 i + l % 16 and, in each column block j, four consecutive
-// columns.  A operands: weight fragments (fragment order, as in frag_mma)
-// held for all eight k-steps: on entry ring holds, or has in flight, tile
-// t's; each k-step's slot is refilled, as soon as its products are issued,
-// with the same k-step of tile tn (the wave's next tile, if tn >= 0).  All
-// of the next tile's weight loads are thus issued before this tile's
-// output stores, so that waiting for them never waits for those stores
-// (loads and stores share one in-order counter).  B operands: hidden rows
-// from LDS.
-__device__ inline void head_prefetch(const bf16_t* WF, int t, bf16x8_t (&ring)[8][4], int lane) {
-    constexpr int KS = kFWidth / 32;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) ring[ks][j] = load_frag(WF, KS, 4 * t + j, ks, lane);
-}
+// ---- head ---------------------------------------------------------------------
+// The softmax output layer (n_out = 2 ks^2 columns, tiles of 64) of 256 rows
+// per workgroup; wave w owns rows [64 w, 64 w + 64) and holds their hidden
+// activations in registers, as matrix-core B operands, for the whole kernel.
+// The weight tiles (32 KB each, fragment order) stream through a two-slot
+// LDS ring: each is copied once per workgroup by direct global-to-LDS loads
+// (a quarter per wave) while the waves work on the other slot, and read by
+// all four waves, so that a weight byte fetched from L2 serves 256 rows per
+// pass.  (Read by each wave from L2 for its own 64 rows, the weights kept
+// the vector-memory unit 71 % busy and the matrix cores 31 %.)  Tile t's 64
+// biases come along into a small LDS slot.  A tile is taken in two halves of
+// 32 columns, which keeps the accumulators at 32 registers beside the 128 of
+// the hidden rows, within the 256 of a wave at two workgroups per compute
+// unit.
+// Transposed products (weights as the A operand): acc[i][j] holds
+// C[column 16 j + 4 (l / 16) + r][row 16 i + l % 16] of a half, so lane l
+// owns rows 16 i + l % 16 and, in each column block j, four consecutive
+// columns; the softmax statistics take 4 registers per quantity and the
+// four lanes of a row merge theirs with two exchanges (no cross-wave step).
+// Pass 1 keeps a running (reference, sum of 2^z) per row and lane; pass 2
+// recomputes each tile and writes 2^(z - M - log2 S).  Two workgroups per
+// compute unit: one's softmax runs while the other's products keep the
+// matrix cores busy.
+constexpr int kHRows = 256;                     // rows per workgroup
+constexpr int kHJ = 2;                          // 16-column blocks per half tile
+constexpr int kHCols = 32 * kHJ;                // columns per tile (two halves)
+constexpr int kHTile = kHCols * kFWidth;        // bf16 elements per weight tile (32 KB)
 
-__device__ inline void head_tile_mma(const bf16_t* Hs, const bf16_t* WF, int t, int tn,
-                                     bf16x8_t (&ring)[8][4], floatx4_t (&acc)[4][4], int lane) {
-    constexpr int KS = kFWidth / 32;
-    const int r16 = lane & 15, kg = (lane >> 4) * 8;
-    const bf16_t* hp = Hs + r16 * kFStride + kg;
-    // the hidden rows are the same for every tile: keep the compiler from
-    // hoisting their reads out of the tile loop (128 registers)
-    asm volatile("" ::: "memory");
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        bf16x8_t h[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            h[i] = *reinterpret_cast<const bf16x8_t*>(hp + 16 * i * kFStride + 32 * ks);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    ring[ks][j], h[i],
-                    ks == 0 ? floatx4_t{0.f, 0.f, 0.f, 0.f} : acc[i][j], 0, 0, 0);
-        if (tn >= 0) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) ring[ks][j] = load_frag(WF, KS, 4 * tn + j, ks, lane);
-        }
-    }
-}
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-// Head: the softmax output layer of 64 rows of the chunk, from the trunk's
-// activations.  Two passes over the output tiles (the logits are recomputed
-// rather than stored); two workgroups share a compute unit.  In the
-// transposed tile layout a lane holds 4 rows x 16 columns of a tile, so the
-// softmax statistics take 4 registers per quantity and the output leaves
-// in runs of four consecutive columns per lane.
 template <bool BF16>
 __global__ __launch_bounds__(kFThreads, 2) void mlp_head_kernel(const FusedArgs A, long long r_begin,
                                                               long long r_end, const bf16_t* hin) {
-    __shared__ bf16_t Hs[kFRows * kFStride];
-    __shared__ float stat_m[4][kFRows], stat_s[4][kFRows];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r16 = lane & 15, g4 = (lane >> 4) * 4;
-    const long long row0 = r_begin + (long long)blockIdx.x * kFRows;
-    const int Lo = A.n_hidden;
-    const bf16_t* Wo = A.W[Lo];
-    const float* bo = A.params + A.b_off[Lo];
-    const int ntile = (A.n_out + 63) / 64;
-    bf16x8_t ring[8][4];
-    if (wave < ntile) head_prefetch(Wo, wave, ring, lane);
-    for (int e = tid; e < kFRows * (kFWidth / 8); e += kFThreads) {
-        const int row = e / (kFWidth / 8), c8 = e % (kFWidth / 8);
-        const bf16x8_t zero = {};
-        *reinterpret_cast<bf16x8_t*>(Hs + row * kFStride + 8 * c8) =
-            row0 + row < r_end
-                ? *reinterpret_cast<const bf16x8_t*>(hin + (size_t)(row0 - r_begin + row) * kFWidth + 8 * c8)
-                : zero;
-    }
-    __syncthreads();
-    floatx4_t acc[4][4];
-    // ---- output layer: pass 1, running reference / sum per row ---------------
-    // Logits are carried in base 2 (z log2 e) so that every exponential is
-    // one v_exp_f32; -1e30 stands for "no column yet" (finite, so no
-    // special cases: its exponentials vanish).  m[i], the reference of row
-    // 16 i + l % 16's running sum s[i] = sum 2^(z - m[i]), is kept at or
-    // above every logit of the row seen so far and raised (to kSlack above
-    // the new maximum) only when a logit passes it, so that between raises a
-    // tile costs one exponential per logit and no rescaling; the terms stay
-    // in (0, 1] and far from underflow.
+    // the two ring slots are separate arrays, so that the compiler can see
+    // that a copy into one slot does not feed reads of the other
+    __shared__ __align__(16) bf16_t wt0[kHTile], wt1[kHTile];
+    __shared__ __align__(16) float bt0[kHCols], bt1[kHCols];
+    constexpr int KS = kFWidth / 32;
     constexpr float kL2E = 1.4426950408889634f;
     constexpr float kNone = -1e30f;
     constexpr float kSlack = 32.f;
-    float m[4], s[4];
+    typedef typename std::conditional<BF16, __bf16, float>::type OutT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g4 = (lane >> 4) * 4, kg = (lane >> 4) * 8;
+    const long long row0 = r_begin + (long long)blockIdx.x * kHRows + 64 * wave;
+    const int Lo = A.n_hidden;
+    const bf16_t* Wo = A.W[Lo];
+    const float* bo = A.params + A.b_off[Lo];
+    const int n_out = A.n_out;
+    const int ntile = (n_out + kHCols - 1) / kHCols;
+    OutT* outp = reinterpret_cast<OutT*>(A.out);
+    // whole 4-byte words per four columns: bf16 pairs need an even row pitch
+    const bool words = !BF16 || (n_out & 1) == 0;
+
+    // copy of tile t into a ring slot: wave w takes fragments w, w + 4, ...
+    // (each 64 lanes x 16 B); wave 0 also the tile's biases, the lanes past
+    // the last column reading the last bias (their logits are masked)
+    auto fetch = [&](int t, bf16_t* w, float* b) __attribute__((always_inline)) {
+        const bf16_t* src = Wo + (size_t)t * kHTile + lane * 8;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { m[i] = kNone; s[i] = 0.f; }
-    for (int t = wave; t < ntile; t += 4) {
-        // the last tile of this pass prefetches the first of the next
-        head_tile_mma(Hs, Wo, t, t + 4 < ntile ? t + 4 : wave, ring, acc, lane);
-        float bl[4][4];
+        for (int f = wave; f < 2 * kHJ * KS; f += 4)
+            __builtin_amdgcn_global_load_lds(src + f * 512, (lds_ptr_t)(w + f * 512), 16, 0, 0);
+        if (wave == 0)
+            __builtin_amdgcn_global_load_lds(bo + min(kHCols * t + lane, n_out - 1), (lds_ptr_t)b, 4, 0, 0);
+    };
+    fetch(0, wt0, bt0);
+    bf16x8_t h[4][KS];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 4; ++i) {
+        const long long gr = row0 + 16 * i + r16;
+        const bf16_t* hp = hin + (size_t)(gr - r_begin) * kFWidth + kg;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int n = 64 * t + 16 * j + g4 + r;
-                bl[j][r] = n < A.n_out ? bo[n] * kL2E : kNone;
-            }
+        for (int ks = 0; ks < KS; ++ks) h[i][ks] = gr < r_end ? load_b8(hp + 32 * ks) : bf16x8_t{};
+    }
+    floatx4_t acc[4][kHJ];
+    // products of half `half` of the tile in slot w
+    auto products = [&](const bf16_t* w, int half) __attribute__((always_inline)) {
+        const bf16_t* wb = w + lane * 8 + half * kHJ * KS * 512;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            // one k-step's fragments at a time (the scheduler would
+            // otherwise hoist all the reads)
+            __builtin_amdgcn_sched_barrier(0);
+            bf16x8_t a[kHJ];
+#pragma unroll
+            for (int j = 0; j < kHJ; ++j) a[j] = *reinterpret_cast<const bf16x8_t*>(wb + (j * KS + ks) * 512);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < kHJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        a[j], h[i][ks], ks == 0 ? floatx4_t{0.f, 0.f, 0.f, 0.f} : acc[i][j], 0, 0, 0);
+        }
+    };
+    // biases of this lane's four columns in block j of a half, times log2 e;
+    // `none` past n_out
+    auto biases = [&](const float* b, int col0, int j, float none) __attribute__((always_inline)) {
+        const floatx4_t v = *reinterpret_cast<const floatx4_t*>(b + (col0 % kHCols) + 16 * j + g4);
+        floatx4_t bl;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bl[r] = col0 + 16 * j + g4 + r < n_out ? v[r] * kL2E : none;
+        return bl;
+    };
+    // Pass 1.  Logits are carried in base 2 (z log2 e) so that every
+    // exponential is one v_exp_f32; -1e30 stands for "no column yet"
+    // (finite, so no special cases: its exponentials vanish).  m[i], the
+    // reference of row 16 i + l % 16's running sum s[i] = sum 2^(z - m[i]),
+    // is kept at or above every logit of the row seen so far and raised (to
+    // kSlack above the new maximum) only when a logit passes it, so that
+    // between raises a half costs one exponential per logit and no
+    // rescaling; the terms stay in (0, 1] and far from underflow.
+    float m[4], s[4], mls[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { m[i] = kNone; s[i] = 0.f; mls[i] = 1e30f; }
+    auto stats = [&](const float* b, int col0) __attribute__((always_inline)) {
         bool raise = false;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < kHJ; ++j) {
+            const floatx4_t bl = biases(b, col0, j, kNone);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl[j][r]);
+                    acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl[r]);
                     raise |= acc[i][j][r] > m[i];
                 }
+        }
         if (__ballot(raise)) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 float zm = kNone;
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < kHJ; ++j)
                     zm = fmaxf(zm, fmaxf(fmaxf(acc[i][j][0], acc[i][j][1]), fmaxf(acc[i][j][2], acc[i][j][3])));
                 const float mn = fmaxf(m[i], zm + kSlack);
                 s[i] *= __builtin_amdgcn_exp2f(m[i] - mn);
@@ -334,92 +349,110 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_head_kernel(const FusedArgs 
         for (int i = 0; i < 4; ++i) {
             float a = 0.f;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < kHJ; ++j)
                 a += (__builtin_amdgcn_exp2f(acc[i][j][0] - m[i]) + __builtin_amdgcn_exp2f(acc[i][j][1] - m[i])) +
                      (__builtin_amdgcn_exp2f(acc[i][j][2] - m[i]) + __builtin_amdgcn_exp2f(acc[i][j][3] - m[i]));
             s[i] += a;
         }
-    }
-    // merge over the 4 lanes holding the same rows, then over the 4 waves
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int o = 16; o < 64; o <<= 1) {
-            const float m2 = __shfl_xor(m[i], o, 64);
-            const float s2 = __shfl_xor(s[i], o, 64);
-            const float mn = fmaxf(m[i], m2);
-            s[i] = s[i] * __builtin_amdgcn_exp2f(m[i] - mn) + s2 * __builtin_amdgcn_exp2f(m2 - mn);
-            m[i] = mn;
-        }
-    }
-    if (lane < 16) {
+    };
+    // merge over the 4 lanes holding the same rows; per row M + log2(S), so
+    // that p = 2^(z - M - log2 S)
+    auto merge = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            stat_m[wave][16 * i + r16] = m[i];
-            stat_s[wave][16 * i + r16] = s[i];
-        }
-    }
-    __syncthreads();
-    // per row: M + log2(S), so that p = 2^(z - M - log2 S)
-    float mls[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = 16 * i + r16;
-        float mm = stat_m[0][row], ss = stat_s[0][row];
-        for (int w = 1; w < 4; ++w) {
-            const float m2 = stat_m[w][row], s2 = stat_s[w][row];
-            const float mn = fmaxf(mm, m2);
-            ss = ss * __builtin_amdgcn_exp2f(mm - mn) + s2 * __builtin_amdgcn_exp2f(m2 - mn);
-            mm = mn;
-        }
-        mls[i] = ss > 0.f ? mm + __builtin_amdgcn_logf(ss) : 1e30f;
-    }
-    // ---- pass 2: recompute and write probabilities ---------------------------
-    // each lane writes four consecutive columns per block: two 4-byte words
-    // of bf16 pairs (the row pitch keeps words aligned when n_out is even),
-    // or four floats
-    typedef typename std::conditional<BF16, __bf16, float>::type OutT;
-    OutT* outp = reinterpret_cast<OutT*>(A.out);
-    const bool words = !BF16 || (A.n_out & 1) == 0;
-    for (int t = wave; t < ntile; t += 4) {
-        head_tile_mma(Hs, Wo, t, t + 4 < ntile ? t + 4 : -1, ring, acc, lane);
-        float bl[4][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int n = 64 * t + 16 * j + g4 + r;
-                bl[j][r] = n < A.n_out ? bo[n] * kL2E : 0.f;
+            for (int o = 16; o < 64; o <<= 1) {
+                const float m2 = __shfl_xor(m[i], o, 64);
+                const float s2 = __shfl_xor(s[i], o, 64);
+                const float mn = fmaxf(m[i], m2);
+                s[i] = s[i] * __builtin_amdgcn_exp2f(m[i] - mn) + s2 * __builtin_amdgcn_exp2f(m2 - mn);
+                m[i] = mn;
             }
+            mls[i] = s[i] > 0.f ? m[i] + __builtin_amdgcn_logf(s[i]) : 1e30f;
+        }
+    };
+    // Pass 2: the probabilities of a half as output words (bf16 pairs or
+    // float bits), then their stores (each lane writes four consecutive
+    // columns per block)
+    uint32_t pw[4][kHJ][4];
+    auto probs = [&](const float* b, int col0) __attribute__((always_inline)) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const long long gr = row0 + 16 * i + r16;
-            if (gr >= r_end) continue;
-            OutT* rowp = outp + gr * A.n_out + 64 * t + g4;
+        for (int j = 0; j < kHJ; ++j) {
+            const floatx4_t bl = biases(b, col0, j, 0.f);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int i = 0; i < 4; ++i) {
                 float p[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    p[r] = __builtin_amdgcn_exp2f(fmaf(acc[i][j][r], kL2E, bl[j][r]) - mls[i]);
-                const int n0 = 64 * t + 16 * j + g4;
-                OutT* q = rowp + 16 * j;
-                if (words && n0 + 3 < A.n_out) {
-                    if (BF16) {
-                        uint32_t* w = reinterpret_cast<uint32_t*>(q);
-                        w[0] = (uint32_t)f2bf_rne(p[0]) | ((uint32_t)f2bf_rne(p[1]) << 16);
-                        w[1] = (uint32_t)f2bf_rne(p[2]) | ((uint32_t)f2bf_rne(p[3]) << 16);
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) q[r] = (OutT)p[r];
-                    }
+                    p[r] = __builtin_amdgcn_exp2f(fmaf(acc[i][j][r], kL2E, bl[r]) - mls[i]);
+                if (BF16) {
+                    pw[i][j][0] = (uint32_t)f2bf_rne(p[0]) | ((uint32_t)f2bf_rne(p[1]) << 16);
+                    pw[i][j][1] = (uint32_t)f2bf_rne(p[2]) | ((uint32_t)f2bf_rne(p[3]) << 16);
                 } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (n0 + r < A.n_out) q[r] = (OutT)p[r];
+                    for (int r = 0; r < 4; ++r) pw[i][j][r] = __builtin_bit_cast(uint32_t, p[r]);
                 }
             }
         }
+    };
+    auto store = [&](int col0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < kHJ; ++j) {
+            const int n0 = col0 + 16 * j + g4;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long gr = row0 + 16 * i + r16;
+                if (gr >= r_end) continue;
+                OutT* q = outp + gr * n_out + n0;
+                if (words && n0 + 3 < n_out) {
+                    uint32_t* w = reinterpret_cast<uint32_t*>(q);
+#pragma unroll
+                    for (int e = 0; e < (BF16 ? 2 : 4); ++e) w[e] = pw[i][j][e];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        if (n0 + r >= n_out) continue;
+                        if constexpr (BF16)
+                            reinterpret_cast<uint16_t*>(q)[r] = (uint16_t)(pw[i][j][r >> 1] >> (16 * (r & 1)));
+                        else
+                            reinterpret_cast<uint32_t*>(q)[r] = pw[i][j][r];
+                    }
+                }
+            }
+        }
+    };
+    // Step k of the 2 ntile steps (pass 1 over the tiles, then pass 2)
+    // reads slot k & 1.  It starts when this wave's copies are done
+    // (vector-memory count 0, which also covers earlier output stores) and
+    // all waves are past step k - 1; it then starts the copy of step k + 1's
+    // tile into the other slot (which step k - 1 read) and takes the two
+    // halves of its own tile.  The slot is a compile-time choice, so that
+    // the reads of one slot need not wait for the copy into the other.
+    auto step = [&](int k, auto slot) __attribute__((always_inline)) {
+        constexpr int SL = decltype(slot)::value;
+        const bf16_t* w = SL ? wt1 : wt0;
+        const float* b = SL ? bt1 : bt0;
+        __builtin_amdgcn_s_waitcnt(0x0f70);          // vmcnt(0)
+        __syncthreads();
+        if (k + 1 < 2 * ntile) fetch((k + 1) % ntile, SL ? wt0 : wt1, SL ? bt0 : bt1);
+        const bool pass1 = k < ntile;
+        const int t = pass1 ? k : k - ntile;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int col0 = kHCols * t + 32 * half;
+            products(w, half);
+            if (pass1) {
+                stats(b, col0);
+            } else {
+                probs(b, col0);
+                store(col0);
+            }
+        }
+        if (k == ntile - 1) merge();
+    };
+    for (int k = 0; k < 2 * ntile; k += 2) {
+        step(k, std::integral_constant<int, 0>());
+        step(k + 1, std::integral_constant<int, 1>());
     }
 }
 
@@ -429,14 +462,15 @@ int launch_mlp_fused(const FusedArgs& A, bf16_t* hbuf, long long chunk, hipStrea
     for (long long r0 = 0; r0 < A.n_rows; r0 += chunk) {
         const long long r1 = std::min(A.n_rows, r0 + chunk);
         const long long blocks = (r1 - r0 + kFRows - 1) / kFRows;
+        const long long hblocks = (r1 - r0 + kHRows - 1) / kHRows;
         if (blocks > 0x7fffffffLL) return SDIRT_EUNSUPPORTED;
         hipLaunchKernelGGL(mlp_trunk_kernel, dim3((unsigned)blocks), dim3(kFThreads), 0, st, A, r0, r1, hbuf);
         if (A.out_bf16)
-            hipLaunchKernelGGL(mlp_head_kernel<true>, dim3((unsigned)blocks), dim3(kFThreads), 0, st, A, r0, r1,
-                               (const bf16_t*)hbuf);
+            hipLaunchKernelGGL(mlp_head_kernel<true>, dim3((unsigned)hblocks), dim3(kFThreads), 0, st, A, r0,
+                               r1, (const bf16_t*)hbuf);
         else
-            hipLaunchKernelGGL(mlp_head_kernel<false>, dim3((unsigned)blocks), dim3(kFThreads), 0, st, A, r0, r1,
-                               (const bf16_t*)hbuf);
+            hipLaunchKernelGGL(mlp_head_kernel<false>, dim3((unsigned)hblocks), dim3(kFThreads), 0, st, A, r0,
+                               r1, (const bf16_t*)hbuf);
     }
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
 }
