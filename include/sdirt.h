@@ -346,9 +346,11 @@ int sdirt_mlp_n_params(const sdirt_mlp_desc* desc, long long* n_params);
 int sdirt_mlp_workspace_size(const sdirt_mlp_desc* desc, int batch, size_t* bytes);
 
 /* Inference of n_rows inputs x (device [n_rows][4]: h_x, h_y, 1/d, lambda)
- * into out (device [n_rows][n_out], SDIRT_F32 or SDIRT_BF16), processed in
- * chunks of ws_batch rows with a workspace sized for ws_batch (chunks of
- * 16384 rows or more keep every compute unit busy). */
+ * into out (device [n_rows][n_out], SDIRT_F32 or SDIRT_BF16) with a
+ * workspace sized for ws_batch rows.  Width-256 networks run fused, in
+ * chunks of as many rows as the workspace's activation area holds (512 B
+ * per row; a workspace for 65536 rows holds over 10^6); other widths in
+ * chunks of ws_batch rows. */
 int sdirt_mlp_forward(const sdirt_mlp_desc* desc, const float* params,
                       long long n_rows, const float* x, void* out, int out_dtype,
                       void* workspace, int ws_batch, void* stream);

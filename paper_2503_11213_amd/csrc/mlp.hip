@@ -674,9 +674,15 @@ int mlp_forward(const sdirt_mlp_desc* d, const float* params, long long n_rows, 
     if (ws_batch < 64 || ws_batch % 64) return SDIRT_EINVAL;
     if (out_dtype != SDIRT_F32 && out_dtype != SDIRT_BF16) return SDIRT_EUNSUPPORTED;
     const MlpWs w = carve(m, ws_batch, (char*)workspace);
-    if (m.width == 256)
-        return forward_fused(m, d, w, w.H[m.n_hidden], ws_batch, params, n_rows, x, out,
-                             out_dtype, st);
+    if (m.width == 256) {
+        // The fused path needs only the fragment-ordered weights and one
+        // chunk of last hidden activations (512 B per row): the workspace
+        // from the first activation buffer to its end holds the largest
+        // chunk that fits, in whole 256-row workgroups of the output layer.
+        const size_t avail = w.bytes - (size_t)((char*)w.H[0] - (char*)workspace);
+        const long long chunk = (long long)(avail / (m.width * sizeof(bf16_t))) / 256 * 256;
+        return forward_fused(m, d, w, w.H[0], chunk, params, n_rows, x, out, out_dtype, st);
+    }
     cast_all(m, w, params, st);
     const size_t esz = out_dtype == SDIRT_BF16 ? 2 : 4;
     for (long long r0 = 0; r0 < n_rows; r0 += ws_batch) {
