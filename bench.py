@@ -59,6 +59,11 @@ TRACE_COUNTS = {
     "config2": {"alive": [1.0, 1.0, 1.0, 0.9998, 0.9998, 0.9998, 0.9998, 0.9929, 0.9929,
                           0.9929, 0.9928, 0.9928, 0.9928],
                 "newton_per_ray": 0.0},
+    # the paper's PSF map (RF50, microlens DP pixels): 12 x 8 pixel
+    # positions x 8 depths, all counted (tests/flop_counts.py)
+    "paper_map": {"alive": [1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 0.979, 0.979, 0.978, 0.9762, 0.9762,
+                            0.9762],
+                  "newton_per_ray": 5.083},
 }
 
 
@@ -338,10 +343,16 @@ def extras(dev, stream):
     inf = lambda: sdirt.mlp_forward(mdesc, params, xi, ws, 65536, out=mo)
     inf()
     t_inf = timed(inf, stream, 3)
+    c = TRACE_COUNTS["paper_map"]
+    flop_map = H * W * query.n_rays * trace_flop_per_ray([s_.kind for s_ in lens.surfaces],
+                                                         c["alive"], c["newton_per_ray"])
     out["paper_psf_map"] = {
         "workload": "RF50 (Table S1) F/4, focus 1 m, 512x768 px over 24x36 mm, microlens DP "
                     "model, ks 21, 4096 rays/PSF, 393216 PSFs, depth uniform in 1/d 0.5-20 m",
         "trace_map_s": t_map * 1e-3, "paper_trace_map_s": 801.544,
+        "trace_flop_per_ray": flop_map / (H * W * query.n_rays),
+        "trace_tflops": flop_map / (t_map * 1e-3) / 1e12,
+        "trace_fp64_frac": flop_map / (t_map * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
         "mlp_map_s": t_inf * 1e-3, "paper_mlp_map_s": 0.395,
         "render_s": t_r * 1e-3, "paper_render_s": 0.2,
         "paper_hardware": "i7-12700K + RTX 3090 (Sec. 5.1)"}

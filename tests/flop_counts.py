@@ -44,12 +44,13 @@ def sample_points(query, per_axis=(8, 4)):
             for d in range(0, D, max(1, D // per_axis[1])) for l in range(L)]
 
 
-def count(lens, query):
-    """(alive fraction per surface, Newton iterations per launched ray)."""
+def count(lens, query, per_axis=(8, 4)):
+    """(alive fraction per surface, Newton iterations per launched ray) over
+    the sample of per_axis[0] fields x per_axis[1] depths x all wavelengths."""
     P = optics.Prepared(lens)
     S = len(lens.surfaces)
     n, alive, its = 0, np.zeros(S), 0.0
-    for p in sample_points(query):
+    for p in sample_points(query, per_axis):
         e, d = opsf.bundle(P, query, *p)
         log = {}
         tr.trace(P, query.wavelengths[p[2]], e, d, log=log)
@@ -61,9 +62,30 @@ def count(lens, query):
     return alive / n, its / n
 
 
+def paper_map_sample():
+    """The paper's PSF-map workload (one PSF per pixel, list mode) as a grid
+    sample for count(): 12 x 8 pixel positions over the sensor and 8 depths
+    (all 768 points counted: per_axis=(96, 8))
+    uniform in 1/d over the map's 0.5-20 m (its depth map draws each pixel's
+    depth independently from that distribution), at the workload's 64 x 64
+    rays per PSF."""
+    import copy
+    from workloads import configs
+    lens, sensor, query, (H, W) = configs.paper_psf_map()
+    q = copy.copy(query)
+    xs = (np.linspace(0.0, W - 1, 12) - (W - 1) / 2.0) * sensor.pitch
+    ys = (np.linspace(0.0, H - 1, 8) - (H - 1) / 2.0) * sensor.pitch
+    q.fields = [(float(x), float(y)) for y in ys for x in xs]
+    q.depths = list(1.0 / np.linspace(1.0 / 500.0, 1.0 / 20000.0, 8))
+    return lens, q
+
+
 if __name__ == "__main__":
     from workloads import configs
     for name, fn in (("config5", configs.config5), ("config2", configs.config2)):
         lens, sensor, query = fn(rays=64)
         a, it = count(lens, query)
         print(name, [round(float(v), 4) for v in a], round(float(it), 3))
+    lens, q = paper_map_sample()
+    a, it = count(lens, q, per_axis=(96, 8))
+    print("paper_map", [round(float(v), 4) for v in a], round(float(it), 3))

@@ -5,14 +5,18 @@ import numpy as np
 import pytest
 
 import bench
-from flop_counts import count
+from flop_counts import count, paper_map_sample
 from workloads import configs
 
 
-@pytest.mark.parametrize("name", ["config5", "config2"])
+@pytest.mark.parametrize("name", ["config5", "config2", "paper_map"])
 def test_trace_counts_match_the_oracle(name):
-    lens, sensor, query = getattr(configs, name)(rays=64)
-    alive, newton = count(lens, query)
+    if name == "paper_map":
+        lens, query = paper_map_sample()
+        alive, newton = count(lens, query, per_axis=(96, 8))
+    else:
+        lens, sensor, query = getattr(configs, name)(rays=64)
+        alive, newton = count(lens, query)
     c = bench.TRACE_COUNTS[name]
     assert len(c["alive"]) == len(lens.surfaces)
     assert np.allclose(alive, c["alive"], atol=1e-4)
