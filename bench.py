@@ -117,6 +117,7 @@ def timed(fn, stream, reps):
     import torch
     s = torch.cuda.Event(enable_timing=True)
     e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     s.record(stream)
     for _ in range(reps):
         fn()
