@@ -422,8 +422,9 @@ int sdirt_psf_hybrid(const sdirt_mlp_desc* desc, const float* params,
  * The network must have width 256 and n_out = 2 ks ks (odd ks <= 65).
  * img device [N][C][H][W] f32, depth device [N][H][W] f32, out device
  * [N][2C][H][W] f32 (overwritten); workspace as for sdirt_mlp_forward with
- * ws_batch rows (a multiple of 64; rows are processed 64 pixels, one 8 x 8
- * tile of one channel, at a time). */
+ * ws_batch rows (a multiple of 64).  Rows are pixels, 64 per 8 x 8 tile of
+ * one channel, processed in chunks of as many rows as the workspace's
+ * activation area holds (512 B per row). */
 typedef struct {
     int N, C, H, W;          /* images, channels (1..4), rows, columns      */
     int ks;                  /* PSF window (n_out = 2 ks ks)                 */

@@ -890,7 +890,11 @@ int mlp_render(const sdirt_mlp_desc* d, const float* params, const sdirt_mlp_ren
     f.pitch = (float)rd->pitch;
     for (int c = 0; c < rd->C; ++c) f.lam[c] = (float)rd->wavelength[c];
     f.n_rows = (long long)rd->N * rd->C * f.tiles_x * f.tiles_y * 64;
-    return launch_mlp_render(f, w.H[m.n_hidden], ws_batch, st);
+    // as in the fused inference: one chunk of last hidden activations, as
+    // large as the workspace past the weights holds, in 256-row workgroups
+    const size_t avail = w.bytes - (size_t)((char*)w.H[0] - (char*)workspace);
+    const long long chunk = (long long)(avail / (m.width * sizeof(bf16_t))) / 256 * 256;
+    return launch_mlp_render(f, w.H[0], chunk, st);
 }
 
 int mlp_backward(const sdirt_mlp_desc* d, const float* params, int batch, const float* x,

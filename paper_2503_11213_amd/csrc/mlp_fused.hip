@@ -475,189 +475,236 @@ int launch_mlp_fused(const FusedArgs& A, bf16_t* hbuf, long long chunk, hipStrea
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;
 }
 
-// Fused surrogate render: the softmax layer of the 64 rows of one 8 x 8
-// pixel tile of one channel, reduced against the tile's image windows in the
-// same pass instead of being written out.  With the column k of a row taken
-// as (side s, tap (i, j)) and w_k the image value under that tap (clamped
-// image, staged in LDS), the row's outputs are
+// Fused surrogate render: the softmax layer of the pixel rows, reduced
+// against each pixel's image window in the same pass instead of being
+// written out.  With the column k of a row taken as (side s, tap (i, j)) and
+// w_k the image value under that tap (clamped image), the row's outputs are
 //     out_s = sum_{k in side s} 2^(z_k - M) w_k / sum_k 2^(z_k - M),
-// so one pass keeps per row and lane a running max M, the sum S and the two
-// weighted sums (all rescaled together when M rises).
+// so one pass keeps per row a running reference M, the sum S and the two
+// weighted sums (all rescaled together when M rises).  A workgroup takes 256
+// rows, wave w one 8 x 8 pixel tile of one channel (rows [64 w, 64 w + 64)),
+// with the tile's clamped (8 + ks - 1)^2 image halo in LDS and its hidden
+// activations in registers; the weight tiles of 32 columns (16 KB) stream
+// through a two-slot LDS ring as in the inference head, each copied once per
+// workgroup and read by all four waves.  Transposed products: lane l holds
+// rows 16 i + l % 16 and, per column block j, four consecutive columns, so
+// the running state takes 4 registers per quantity and the four lanes of a
+// row merge theirs at the end.
+constexpr int kRHCols = 32;                      // columns per render-head weight tile
+constexpr int kRHTile = kRHCols * kFWidth;       // bf16 elements per tile (16 KB)
+
 __global__ __launch_bounds__(kFThreads, 2) void mlp_render_head_kernel(const FusedArgs A,
                                                                      long long r_begin,
                                                                      long long r_end,
                                                                      const bf16_t* hin) {
-    __shared__ bf16_t Hs[kFRows * kFStride];
-    __shared__ float stat[4][kFRows][4];                 // per wave: M, S, a_left, a_right
-    extern __shared__ float halo[];                      // [8 + ks - 1]^2 image values
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r16 = lane & 15, g4 = (lane >> 4) * 4;
-    const long long row0 = r_begin + (long long)blockIdx.x * kFRows;
-    const PixelRow pr = pixel_row(A, row0);              // the tile (row0 is its pixel 0)
-    const int ks = A.ks, kk = ks * ks, pad = (ks - 1) / 2, hh = 8 + ks - 1;
-    for (int e = tid; e < kFRows * (kFWidth / 8); e += kFThreads) {
-        const int row = e / (kFWidth / 8), c8 = e % (kFWidth / 8);
-        const bf16x8_t zero = {};
-        *reinterpret_cast<bf16x8_t*>(Hs + row * kFStride + 8 * c8) =
-            row0 + row < r_end
-                ? *reinterpret_cast<const bf16x8_t*>(hin + (size_t)(row0 - r_begin + row) * kFWidth + 8 * c8)
-                : zero;
-    }
-    const float* im = A.img + ((size_t)pr.n * A.img_c + pr.c) * A.img_h * A.img_w;
-    for (int e = tid; e < hh * hh; e += kFThreads) {
-        const int r = e / hh, q = e - r * hh;
-        const int yy = min(max(pr.y0 - pad + r, 0), A.img_h - 1);
-        const int xx = min(max(pr.x0 - pad + q, 0), A.img_w - 1);
-        halo[e] = im[(size_t)yy * A.img_w + xx];
-    }
-    __syncthreads();
-    // the lane's rows 16 i + g4 + r are pixels (row / 8, row % 8); tap (i, j)
-    // of output pixel (py, px) reads halo[py + 2 pad - i][px + 2 pad - j]
-    int hb[16];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = 16 * i + g4 + r;
-            hb[4 * i + r] = ((row >> 3) + 2 * pad) * hh + (row & 7) + 2 * pad;
-        }
+    __shared__ __align__(16) bf16_t wt0[kRHTile], wt1[kRHTile];
+    __shared__ __align__(16) float bt0[64], bt1[64];
+    extern __shared__ float halos[];                     // [4 waves][(8 + ks - 1)^2]
+    constexpr int KS = kFWidth / 32;
     constexpr float kL2E = 1.4426950408889634f;
     constexpr float kNone = -1e30f;
     constexpr float kSlack = 32.f;
+    // wave-uniform values in scalar registers
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r16 = lane & 15, g4 = (lane >> 4) * 4, kg = (lane >> 4) * 8;
+    const long long row0 = r_begin + (long long)blockIdx.x * kHRows + 64 * wave;
+    const bool active = row0 < r_end;                    // the wave has a tile
+    const int ks = A.ks, kk = ks * ks, pad = (ks - 1) / 2, hh = 8 + ks - 1;
+    const float inv_ks = 1.f / (float)ks;
     const int Lo = A.n_hidden;
     const bf16_t* Wo = A.W[Lo];
     const float* bo = A.params + A.b_off[Lo];
-    const int ntile = (A.n_out + 63) / 64;
-    floatx4_t acc[4][4];
-    float m[16], s[16], al[16], ar[16];
+    const int n_out = A.n_out;
+    const int ntile = (n_out + kRHCols - 1) / kRHCols;
+    auto fetch = [&](int t, bf16_t* w, float* b) __attribute__((always_inline)) {
+        const bf16_t* src = Wo + (size_t)t * kRHTile + lane * 8;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) { m[k] = kNone; s[k] = 0.f; al[k] = 0.f; ar[k] = 0.f; }
-    for (int t = wave; t < ntile; t += 4) {
-        frag_mma(Hs, Wo, kFWidth / 32, 64 * t, acc);
-        float bl[4], right[4];
-        int coff[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = 64 * t + 16 * j + r16;
-            const bool valid = n < A.n_out;
-            bl[j] = valid ? bo[n] * kL2E : kNone;
-            const int side = n >= kk;
-            const int tap = valid ? n - side * kk : 0;
-            const int ti = tap / ks;
-            coff[j] = ti * hh + (tap - ti * ks);
-            right[j] = side ? 1.f : 0.f;
+        for (int f = wave; f < 2 * KS; f += 4)
+            __builtin_amdgcn_global_load_lds(src + f * 512, (lds_ptr_t)(w + f * 512), 16, 0, 0);
+        if (wave == 0)
+            __builtin_amdgcn_global_load_lds(bo + min(kRHCols * t + lane, n_out - 1), (lds_ptr_t)b, 4,
+                                             0, 0);
+    };
+    fetch(0, wt0, bt0);
+    const PixelRow pr = pixel_row(A, active ? row0 : r_begin);   // the wave's tile
+    float* halo = halos + wave * hh * hh;
+    if (active) {
+        const float* im = A.img + ((size_t)pr.n * A.img_c + pr.c) * A.img_h * A.img_w;
+        for (int e = lane; e < hh * hh; e += 64) {
+            const int r = e / hh, q = e - r * hh;
+            const int yy = min(max(pr.y0 - pad + r, 0), A.img_h - 1);
+            const int xx = min(max(pr.x0 - pad + q, 0), A.img_w - 1);
+            halo[e] = im[(size_t)yy * A.img_w + xx];
         }
-        // the reference m[k] is raised only when a logit passes it (to
-        // kSlack above the new maximum), as in the inference head
+    }
+    bf16x8_t h[4][KS];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const long long gr = row0 + 16 * i + r16;
+        const bf16_t* hp = hin + (size_t)(gr - r_begin) * kFWidth + kg;
+#pragma unroll
+        for (int ks8 = 0; ks8 < KS; ++ks8) h[i][ks8] = gr < r_end ? load_b8(hp + 32 * ks8) : bf16x8_t{};
+    }
+    // the lane's row 16 i + l % 16 is pixel (row / 8, row % 8) of the tile;
+    // tap (ti, tj) of that pixel reads halo[py + 2 pad - ti][px + 2 pad - tj],
+    // i.e. hb[i] - (ti hh + tj) = hb[i] - (tap + 7 ti), as hh - ks = 7
+    int hb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = 16 * i + r16;
+        hb[i] = ((row >> 3) + 2 * pad) * hh + (row & 7) + 2 * pad;
+    }
+    floatx4_t acc[4][2];
+    auto products = [&](const bf16_t* w) __attribute__((always_inline)) {
+        const bf16_t* wb = w + lane * 8;
+#pragma unroll
+        for (int k8 = 0; k8 < KS; ++k8) {
+            __builtin_amdgcn_sched_barrier(0);
+            bf16x8_t a[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) a[j] = *reinterpret_cast<const bf16x8_t*>(wb + (j * KS + k8) * 512);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        a[j], h[i][k8], k8 == 0 ? floatx4_t{0.f, 0.f, 0.f, 0.f} : acc[i][j], 0, 0, 0);
+        }
+    };
+    float m[4], s[4], al[4], ar[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { m[i] = kNone; s[i] = 0.f; al[i] = 0.f; ar[i] = 0.f; }
+    // one tile: logits in base 2 with the bias, the lazily raised reference
+    // (as in the inference head), then the terms 2^(z - M) into S and, times
+    // the image value under the column's tap, into the side's sum
+    auto reduce = [&](const float* b, int t) __attribute__((always_inline)) {
+        int coff[2][4];
         bool raise = false;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl[j]);
-                    raise |= acc[i][j][r] > m[4 * i + r];
-                }
-        if (__ballot(raise)) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int k = 4 * i + r;
-                    const float zm = fmaxf(fmaxf(acc[i][0][r], acc[i][1][r]), fmaxf(acc[i][2][r], acc[i][3][r]));
-                    const float mn = fmaxf(m[k], zm + kSlack);
-                    const float sc = __builtin_amdgcn_exp2f(m[k] - mn);
-                    s[k] *= sc; al[k] *= sc; ar[k] *= sc;
-                    m[k] = mn;
-                }
-        }
-        // outputs [0, ks^2) are the left kernel's taps, [ks^2, 2 ks^2) the
-        // right's: a tile wholly inside one of them (every tile but the one
-        // that holds output ks^2 - 1 and ks^2) adds its weighted terms to
-        // that kernel's sum alone
-        const int side0 = 64 * t >= kk, side1 = 64 * t + 63 >= kk;
-        if (side0 == side1) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int k = 4 * i + r;
-                    float es = 0.f, ews = 0.f;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const float e = __builtin_amdgcn_exp2f(acc[i][j][r] - m[k]);
-                        es += e;
-                        ews = fmaf(e, halo[hb[k] - coff[j]], ews);
-                    }
-                    s[k] += es;
-                    if (side0) ar[k] += ews;
-                    else al[k] += ews;
-                }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int k = 4 * i + r;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const float e = __builtin_amdgcn_exp2f(acc[i][j][r] - m[k]);
-                        const float ew = e * halo[hb[k] - coff[j]];
-                        s[k] += e;
-                        al[k] = fmaf(ew, 1.f - right[j], al[k]);
-                        ar[k] = fmaf(ew, right[j], ar[k]);
-                    }
-                }
-        }
-    }
-    // merge over the 16 lanes holding the same rows, then over the 4 waves
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-            const float m2 = __shfl_xor(m[k], o, 64);
-            const float s2 = __shfl_xor(s[k], o, 64);
-            const float l2 = __shfl_xor(al[k], o, 64);
-            const float q2 = __shfl_xor(ar[k], o, 64);
-            const float mn = fmaxf(m[k], m2);
-            const float f1 = __builtin_amdgcn_exp2f(m[k] - mn), f2 = __builtin_amdgcn_exp2f(m2 - mn);
-            s[k] = s[k] * f1 + s2 * f2;
-            al[k] = al[k] * f1 + l2 * f2;
-            ar[k] = ar[k] * f1 + q2 * f2;
-            m[k] = mn;
-        }
-    }
-    if (r16 == 0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const floatx4_t v = *reinterpret_cast<const floatx4_t*>(b + 16 * j + g4);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                float* st = stat[wave][16 * i + g4 + r];
-                const int k = 4 * i + r;
-                st[0] = m[k]; st[1] = s[k]; st[2] = al[k]; st[3] = ar[k];
+                const int n = kRHCols * t + 16 * j + g4 + r;
+                const bool valid = n < n_out;
+                const float bl = valid ? v[r] * kL2E : kNone;
+                const int tap = valid ? n - (n >= kk ? kk : 0) : 0;
+                const int ti = (int)(((float)tap + 0.5f) * inv_ks);
+                coff[j][r] = tap + 7 * ti;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl);
+                    raise |= acc[i][j][r] > m[i];
+                }
             }
-    }
-    __syncthreads();
-    if (tid < kFRows) {
-        const int row = tid;
-        float mm = stat[0][row][0], ss = stat[0][row][1], ll = stat[0][row][2], qq = stat[0][row][3];
-        for (int w = 1; w < 4; ++w) {
-            const float m2 = stat[w][row][0];
-            const float mn = fmaxf(mm, m2);
-            const float f1 = __builtin_amdgcn_exp2f(mm - mn), f2 = __builtin_amdgcn_exp2f(m2 - mn);
-            ss = ss * f1 + stat[w][row][1] * f2;
-            ll = ll * f1 + stat[w][row][2] * f2;
-            qq = qq * f1 + stat[w][row][3] * f2;
-            mm = mn;
         }
-        const int y = pr.y0 + (row >> 3), x = pr.x0 + (row & 7);
-        if (row0 + row < r_end && y < A.img_h && x < A.img_w) {
-            const float inv = 1.f / ss;
-            const size_t plane = (size_t)A.img_h * A.img_w;
-            float* o = A.rout + ((size_t)pr.n * 2 * A.img_c + pr.c) * plane + (size_t)y * A.img_w + x;
-            o[0] = ll * inv;
-            o[(size_t)A.img_c * plane] = qq * inv;
+        if (__ballot(raise)) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float zm = kNone;
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    zm = fmaxf(zm, fmaxf(fmaxf(acc[i][j][0], acc[i][j][1]), fmaxf(acc[i][j][2], acc[i][j][3])));
+                const float mn = fmaxf(m[i], zm + kSlack);
+                const float sc = __builtin_amdgcn_exp2f(m[i] - mn);
+                s[i] *= sc; al[i] *= sc; ar[i] *= sc;
+                m[i] = mn;
+            }
+        }
+        // outputs [0, ks^2) are the left kernel's taps, [ks^2, 2 ks^2) the
+        // right's: a tile wholly inside one of them (all but the one that
+        // holds columns ks^2 - 1 and ks^2) adds its weighted terms to that
+        // side's sum; that one tile also sums its right columns apart
+        const int c0 = kRHCols * t;
+        float ews[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float es = 0.f;
+            ews[i] = 0.f;
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float e = __builtin_amdgcn_exp2f(acc[i][j][r] - m[i]);
+                    es += e;
+                    ews[i] = fmaf(e, halo[hb[i] - coff[j][r]], ews[i]);
+                }
+            s[i] += es;
+        }
+        // the right side's part of each row's weighted sum: all of it, none,
+        // or (the one straddling tile) its right columns summed apart; the
+        // updates are arithmetic selects, so both sums stay in registers
+        const bool straddle = c0 < kk && c0 + kRHCols > kk;
+        float er[4] = {0.f, 0.f, 0.f, 0.f};
+        if (straddle) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float e = __builtin_amdgcn_exp2f(acc[i][j][r] - m[i]);
+                        er[i] = fmaf(c0 + 16 * j + g4 + r >= kk ? e : 0.f, halo[hb[i] - coff[j][r]], er[i]);
+                    }
+        }
+        const bool rs = c0 >= kk;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float rp = straddle ? er[i] : (rs ? ews[i] : 0.f);
+            ar[i] += rp;
+            al[i] += ews[i] - rp;
+        }
+    };
+
+    // tile steps as in the inference head: wait for this wave's copies and
+    // the other waves, start the next tile's copy into the other slot, then
+    // the products and the reduction of this one
+    auto step = [&](int t, auto slot) __attribute__((always_inline)) {
+        constexpr int SL = decltype(slot)::value;
+        __builtin_amdgcn_s_waitcnt(0x0f70);          // vmcnt(0)
+        __syncthreads();
+        if (t + 1 < ntile) fetch(t + 1, SL ? wt0 : wt1, SL ? bt0 : bt1);
+        if (active) {
+            products(SL ? wt1 : wt0);
+            reduce(SL ? bt1 : bt0, t);
+        }
+    };
+    int t = 0;
+    for (; t + 1 < ntile; t += 2) {
+        step(t, std::integral_constant<int, 0>());
+        step(t + 1, std::integral_constant<int, 1>());
+    }
+    if (t < ntile) step(t, std::integral_constant<int, 0>());
+    if (!active) return;
+    // merge over the 4 lanes holding the same rows
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int o = 16; o < 64; o <<= 1) {
+            const float m2 = __shfl_xor(m[i], o, 64);
+            const float s2 = __shfl_xor(s[i], o, 64);
+            const float l2 = __shfl_xor(al[i], o, 64);
+            const float q2 = __shfl_xor(ar[i], o, 64);
+            const float mn = fmaxf(m[i], m2);
+            const float f1 = __builtin_amdgcn_exp2f(m[i] - mn), f2 = __builtin_amdgcn_exp2f(m2 - mn);
+            s[i] = s[i] * f1 + s2 * f2;
+            al[i] = al[i] * f1 + l2 * f2;
+            ar[i] = ar[i] * f1 + q2 * f2;
+            m[i] = mn;
+        }
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * i + r16;
+            const int y = pr.y0 + (row >> 3), x = pr.x0 + (row & 7);
+            if (row0 + row < r_end && y < A.img_h && x < A.img_w) {
+                const float inv = 1.f / s[i];
+                const size_t plane = (size_t)A.img_h * A.img_w;
+                float* o = A.rout + ((size_t)pr.n * 2 * A.img_c + pr.c) * plane + (size_t)y * A.img_w + x;
+                o[0] = al[i] * inv;
+                o[(size_t)A.img_c * plane] = ar[i] * inv;
+            }
         }
     }
 }
@@ -666,13 +713,17 @@ int launch_mlp_render(const FusedArgs& A, bf16_t* hbuf, long long chunk, hipStre
     if (A.n_rows <= 0) return SDIRT_OK;
     if (chunk < kFRows || chunk % kFRows) return SDIRT_EINVAL;
     const int hh = 8 + A.ks - 1;
-    const size_t shm = (size_t)hh * hh * sizeof(float);
+    const size_t shm = (size_t)4 * hh * hh * sizeof(float);
+    if (shm + 2 * (kRHTile * sizeof(bf16_t) + 64 * sizeof(float)) > 160 * 1024) return SDIRT_EUNSUPPORTED;
+    (void)hipFuncSetAttribute((const void*)mlp_render_head_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
     for (long long r0 = 0; r0 < A.n_rows; r0 += chunk) {
         const long long r1 = std::min(A.n_rows, r0 + chunk);
         const long long blocks = (r1 - r0 + kFRows - 1) / kFRows;
+        const long long hblocks = (r1 - r0 + kHRows - 1) / kHRows;
         if (blocks > 0x7fffffffLL) return SDIRT_EUNSUPPORTED;
         hipLaunchKernelGGL(mlp_trunk_kernel, dim3((unsigned)blocks), dim3(kFThreads), 0, st, A, r0, r1, hbuf);
-        hipLaunchKernelGGL(mlp_render_head_kernel, dim3((unsigned)blocks), dim3(kFThreads), shm, st, A, r0,
+        hipLaunchKernelGGL(mlp_render_head_kernel, dim3((unsigned)hblocks), dim3(kFThreads), shm, st, A, r0,
                            r1, (const bf16_t*)hbuf);
     }
     return hipGetLastError() == hipSuccess ? SDIRT_OK : SDIRT_ELAUNCH;

@@ -294,8 +294,9 @@ def test_fused_forward_output_widths(n_out):
 
 
 def test_inference_full_size_sampled_rows():
-    # the benchmarked launch: 2^20 rows in 65536-row chunks, ks 33, bf16
-    # out; sampled rows (chunk edges among them) against the bf16 mirror,
+    # the benchmarked launch: 2^20 rows with a workspace for 65536 (one
+    # chunk of activations), ks 33, bf16 out; sampled rows (the 256-row
+    # workgroup edges at 65536 among them) against the bf16 mirror,
     # and every row's probabilities summing to one
     from workloads import configs
     n, chunk, n_out = 1 << 20, 65536, 2 * 33 * 33
@@ -322,7 +323,7 @@ def test_inference_full_size_sampled_rows():
                                           (5, 1, 1, 9, 8, 64)])
 def test_surrogate_render_matches_oracle(ks, N, C, H, W, ws):
     # per-pixel network PSFs consumed by the renderer in one pass; ragged
-    # 8 x 8 tiles, several workspace chunks, one and three channels
+    # 8 x 8 tiles, workgroups with idle waves, one and three channels
     widths = [64, 256, 256, 256, 256, 256, 2 * ks * ks]
     layers, flat = _params(widths, 3)
     rng = np.random.default_rng(4)
@@ -349,9 +350,9 @@ def test_surrogate_render_matches_oracle(ks, N, C, H, W, ws):
 
 @pytest.mark.parametrize("chunk", [65536, 262144])
 def test_surrogate_render_full_size_sampled_pixels(chunk):
-    # 1680 x 1120 RGB, ks 33 (5,644,800 pixel rows): 65536-row chunks, and
-    # the benchmarked launch of 262144-row chunks (21 full chunks and a
-    # 139,776-row tail)
+    # 1680 x 1120 RGB, ks 33 (5,644,800 pixel rows): with a workspace for
+    # 65536 rows (2.8 GB) the activations go in two chunks, with the
+    # benchmarked one for 262144 rows in one
     ks, N, C, H, W, ps = 33, 1, 3, 1120, 1680, 0.00536
     widths = [64, 256, 256, 256, 256, 256, 2 * ks * ks]
     layers, flat = _params(widths, 5)
