@@ -107,7 +107,7 @@ def parse():
                     choices=["calib", "trace", "trace_paper", "trace_bwd", "render", "render_bwd",
                              "render_split",
                              "render_split_bwd", "dense",
-                             "mlp_head"],
+                             "mlp_head", "mlp_render"],
                     help="for counter runs: a 1 GiB device copy (calibration of the memory "
                          "counters), then one launch of the named kernel; prints nothing")
     return ap.parse_args()
@@ -538,7 +538,9 @@ def pmc_target(name, dev):
       render_split, render_split_bwd  the step's bank render and image
                   adjoint on the split-bf16 matrix cores;
       dense       dense render of 512 x 512 RGB with a 41 x 41 f32 map;
-      mlp_head    surrogate inference of 2^20 rows (ks 33, bf16 out)."""
+      mlp_head    surrogate inference of 2^20 rows (ks 33, bf16 out);
+      mlp_render  fused surrogate render of one 1680 x 1120 RGB image (ks 33,
+                  trained weights)."""
     import ctypes as C
     import numpy as np
     import torch
@@ -604,6 +606,15 @@ def pmc_target(name, dev):
         ws = sdirt.mlp_workspace(desc, 1 << 20)
         sdirt.mlp_forward(desc, params, torch.from_numpy(x).to(dev), ws, 1 << 20,
                           out_dtype=abi.BF16)
+    elif name == "mlp_render":
+        desc, params, _ = sdirt.mlp_load_weights(
+            os.path.join(ROOT, "workloads", "surrogate_ks33.safetensors"), device=dev)
+        H4, W4, ps4 = 1120, 1680, 0.00536
+        img = torch.from_numpy(scenes.aif_blobs(H4, W4, 3, n_blobs=2000, seed=0)[None]).to(dev)
+        dm = torch.from_numpy(scenes.depth_voronoi(H4, W4, 500.0, 5000.0, seed=100)[None]).to(dev)
+        lam_rgb = [configs.RGB_LAMBDAS[i] for i in configs.LAMBDA_OF_RGB]
+        ws = sdirt.mlp_workspace(desc, 262144)
+        sdirt.mlp_render(desc, params, img, dm, lam_rgb, ps4, ws, 262144)
     torch.cuda.synchronize()
 
 
