@@ -235,6 +235,7 @@ constexpr int kHCols = 32 * kHJ;                // columns per tile (two halves)
 constexpr int kHTile = kHCols * kFWidth;        // bf16 elements per weight tile (32 KB)
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(3))) const float lds_cfloat_t;
 
 template <bool BF16>
 __global__ __launch_bounds__(kFThreads, 2) void mlp_head_kernel(const FusedArgs A, long long r_begin,
@@ -548,12 +549,18 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_render_head_kernel(const Fus
     // the lane's row 16 i + l % 16 is pixel (row / 8, row % 8) of the tile;
     // tap (ti, tj) of that pixel reads halo[py + 2 pad - ti][px + 2 pad - tj],
     // i.e. hb[i] - (ti hh + tj) = hb[i] - (tap + 7 ti), as hh - ks = 7
-    int hb[4];
+    // (as LDS byte addresses, so that a read's address is one subtraction:
+    // hb4[i] - coff4)
+    const unsigned hbase = (unsigned)(size_t)(lds_cfloat_t*)halos;
+    unsigned hb4[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int row = 16 * i + r16;
-        hb[i] = ((row >> 3) + 2 * pad) * hh + (row & 7) + 2 * pad;
+        hb4[i] = hbase + 4u * (wave * hh * hh + ((row >> 3) + 2 * pad) * hh + (row & 7) + 2 * pad);
     }
+    auto halo_at = [&](int i, int cb) __attribute__((always_inline)) {
+        return *(lds_cfloat_t*)(size_t)(hb4[i] - (unsigned)cb);
+    };
     floatx4_t acc[4][2];
     auto products = [&](const bf16_t* w) __attribute__((always_inline)) {
         const bf16_t* wb = w + lane * 8;
@@ -578,8 +585,7 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_render_head_kernel(const Fus
     // (as in the inference head), then the terms 2^(z - M) into S and, times
     // the image value under the column's tap, into the side's sum
     auto reduce = [&](const float* b, int t) __attribute__((always_inline)) {
-        int coff[2][4];
-        bool raise = false;
+        int coff4[2][4];                 // byte offsets of the columns' taps
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const floatx4_t v = *reinterpret_cast<const floatx4_t*>(b + 16 * j + g4);
@@ -590,22 +596,25 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_render_head_kernel(const Fus
                 const float bl = valid ? v[r] * kL2E : kNone;
                 const int tap = valid ? n - (n >= kk ? kk : 0) : 0;
                 const int ti = (int)(((float)tap + 0.5f) * inv_ks);
-                coff[j][r] = tap + 7 * ti;
+                coff4[j][r] = 4 * (tap + 7 * ti);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl);
-                    raise |= acc[i][j][r] > m[i];
-                }
+                for (int i = 0; i < 4; ++i) acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl);
             }
+        }
+        // each row's largest logit of the tile, compared once with its
+        // reference
+        float zm[4];
+        bool raise = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            zm[i] = fmaxf(fmaxf(fmaxf(acc[i][0][0], acc[i][0][1]), fmaxf(acc[i][0][2], acc[i][0][3])),
+                          fmaxf(fmaxf(acc[i][1][0], acc[i][1][1]), fmaxf(acc[i][1][2], acc[i][1][3])));
+            raise |= zm[i] > m[i];
         }
         if (__ballot(raise)) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float zm = kNone;
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    zm = fmaxf(zm, fmaxf(fmaxf(acc[i][j][0], acc[i][j][1]), fmaxf(acc[i][j][2], acc[i][j][3])));
-                const float mn = fmaxf(m[i], zm + kSlack);
+                const float mn = fmaxf(m[i], zm[i] + kSlack);
                 const float sc = __builtin_amdgcn_exp2f(m[i] - mn);
                 s[i] *= sc; al[i] *= sc; ar[i] *= sc;
                 m[i] = mn;
@@ -627,7 +636,7 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_render_head_kernel(const Fus
                 for (int r = 0; r < 4; ++r) {
                     const float e = __builtin_amdgcn_exp2f(acc[i][j][r] - m[i]);
                     es += e;
-                    ews[i] = fmaf(e, halo[hb[i] - coff[j][r]], ews[i]);
+                    ews[i] = fmaf(e, halo_at(i, coff4[j][r]), ews[i]);
                 }
             s[i] += es;
         }
@@ -644,7 +653,7 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_render_head_kernel(const Fus
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const float e = __builtin_amdgcn_exp2f(acc[i][j][r] - m[i]);
-                        er[i] = fmaf(c0 + 16 * j + g4 + r >= kk ? e : 0.f, halo[hb[i] - coff[j][r]], er[i]);
+                        er[i] = fmaf(c0 + 16 * j + g4 + r >= kk ? e : 0.f, halo_at(i, coff4[j][r]), er[i]);
                     }
         }
         const bool rs = c0 >= kk;
