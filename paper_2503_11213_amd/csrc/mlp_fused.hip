@@ -322,26 +322,30 @@ __global__ __launch_bounds__(kFThreads, 2) void mlp_head_kernel(const FusedArgs 
 #pragma unroll
     for (int i = 0; i < 4; ++i) { m[i] = kNone; s[i] = 0.f; mls[i] = 1e30f; }
     auto stats = [&](const float* b, int col0) __attribute__((always_inline)) {
-        bool raise = false;
 #pragma unroll
         for (int j = 0; j < kHJ; ++j) {
             const floatx4_t bl = biases(b, col0, j, kNone);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl[r]);
-                    raise |= acc[i][j][r] > m[i];
-                }
+                for (int r = 0; r < 4; ++r) acc[i][j][r] = fmaf(acc[i][j][r], kL2E, bl[r]);
+        }
+        // each row's largest logit of the half, compared once with its
+        // reference
+        float zm[4];
+        bool raise = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            zm[i] = kNone;
+#pragma unroll
+            for (int j = 0; j < kHJ; ++j)
+                zm[i] = fmaxf(zm[i], fmaxf(fmaxf(acc[i][j][0], acc[i][j][1]), fmaxf(acc[i][j][2], acc[i][j][3])));
+            raise |= zm[i] > m[i];
         }
         if (__ballot(raise)) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float zm = kNone;
-#pragma unroll
-                for (int j = 0; j < kHJ; ++j)
-                    zm = fmaxf(zm, fmaxf(fmaxf(acc[i][j][0], acc[i][j][1]), fmaxf(acc[i][j][2], acc[i][j][3])));
-                const float mn = fmaxf(m[i], zm + kSlack);
+                const float mn = fmaxf(m[i], zm[i] + kSlack);
                 s[i] *= __builtin_amdgcn_exp2f(m[i] - mn);
                 m[i] = mn;
             }
