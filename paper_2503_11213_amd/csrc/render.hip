@@ -1367,8 +1367,9 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
 // g[n][(side, q)] * K_side[i][KS - 1 - p + q] at halo row (strip row n +
 // KS - 1 - i), column 8 (strip column) + p, for the window columns p < P =
 // 16 NB: per block of 16 columns, two v_mfma_f32_16x16x32_bf16 on one tap
-// fragment (hi taps, then lo taps, along K): g_hi (K_hi + K_lo), and g_lo
-// K_hi with zeros against the lo half.  The halo row of (n, i) is fixed
+// fragment (each tap's hi and lo parts side by side along K): g_hi, repeated
+// against both parts, gives g_hi (K_hi + K_lo), and g_lo with zeros against
+// the lo parts g_lo K_hi.  The halo row of (n, i) is fixed
 // along n - i, so the gradient operand's rows are rotated by one strip per
 // kernel row (DPP row_ror): row m holds strip (m + i) mod 16, and
 // accumulator row m keeps adding into one halo row until its strip index
@@ -1379,10 +1380,10 @@ __global__ __launch_bounds__(64) void render_bank_bwd_kernel(const RenderArgs A,
 // register) into the LDS halo with ds_add_f32; the rows above move down one
 // segment and the top one restarts from zero.  All products go through one
 // instruction type (an MFMA reading another type's result as its
-// accumulator has returned stale rows).  Taps are staged per kernel row
-// as natural-order hi and lo rows between zero margins; a lane reads its four
-// taps as three dwords shifted into place by v_alignbit.  Finally the halo
-// is added onto the clamped image pixels with global atomics.
+// accumulator has returned stale rows).  Taps are staged per kernel row in
+// natural order between zero margins, one dword per tap (hi | lo << 16), so
+// a lane reads its four taps as four whole dwords.  Finally the halo is
+// added onto the clamped image pixels with global atomics.
 constexpr int kSBSlots = 8;                       // entries per batch
 constexpr int kSBGroups = 4;                      // segments per run (a tile column)
 constexpr int kSBChunks = kSBSlots * 16;          // runs per batch (<= 2 per column)
@@ -1393,9 +1394,8 @@ struct SplitBwdGeom {
     static constexpr int P = 16 * NB;
     static constexpr int PW = KS + kStrip - 1;                   // window columns with taps
     static constexpr int MARG = ((P - KS + 1) / 2) * 2;          // zero margin before the taps
-    static constexpr int RW = ((MARG + KS + 9 + 7) / 8) * 8;     // staged row (bf16)
-    static constexpr int LO = 2 * RW;                            // lo rows after the hi rows
-    static constexpr int SCRATCH = LO;                           // floats per wave
+    static constexpr int RW = ((MARG + KS + 9 + 7) / 8) * 8;     // staged row (taps)
+    static constexpr int SCRATCH = 2 * RW;                       // dwords per wave (two sides)
     static constexpr int NTAP = 2 * KS;                          // taps of one kernel row
     static constexpr int HH = kGT + KS - 1;
     static constexpr int HWG = kGT + KS;                         // halo-gradient row stride (odd)
@@ -1428,15 +1428,11 @@ struct SplitRowTaps {
 #pragma unroll
         for (int k = 0; k < NL; ++k) v[k] = entry[src[k] + ofs];
     }
-    __device__ void store(u16_alias* st, int lane) const {
+    // one dword per tap: its bf16 high part, then its low part
+    __device__ void store(u32_alias* st, int lane) const {
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            if (64 * k + 64 <= S::NTAP || lane + 64 * k < S::NTAP) {
-                const uint32_t b = split_bf16_bits(v[k]);
-                st[dst[k]] = (uint16_t)b;
-                st[S::LO + dst[k]] = (uint16_t)(b >> 16);
-            }
-        }
+        for (int k = 0; k < NL; ++k)
+            if (64 * k + 64 <= S::NTAP || lane + 64 * k < S::NTAP) st[dst[k]] = split_bf16_bits(v[k]);
     }
 };
 
@@ -1457,13 +1453,11 @@ __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool
                                            u32x4_t (&ga)[kSBGroups], u32x4_t (&gl)[kSBGroups],
                                            int hrow, int hcol) {
     using S = SplitBwdGeom<KS>;
-    u16_alias* st = reinterpret_cast<u16_alias*>(scratch);
-    const u32_alias* sw = reinterpret_cast<const u32_alias*>(scratch);
+    u32_alias* sw = reinterpret_cast<u32_alias*>(scratch);
     const int pl = lane & 15, kg = lane >> 4;
     const int side = kg >> 1, q0 = 4 * (kg & 1);
-    const int s0 = S::MARG + KS - 1 - pl + q0;                 // block 0, relative to the row
-    const uint32_t sh = (s0 & 1) * 16;
-    const int ad0 = (side * S::RW + s0) >> 1;                  // block b: ad0 - 8 b
+    // the lane's four taps of block b: dwords ad0 - 16 b .. + 3
+    const int ad0 = side * S::RW + S::MARG + KS - 1 - pl + q0;
     // acc: the running halo rows, one 16 x 16 block per segment and window
     // block (row m of segment u: strip (m + i) mod 16's halo row)
     floatx4_t acc[NG][S::NB];
@@ -1477,7 +1471,7 @@ __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool
     taps.load(entry, 0);
     for (int i = 0; i < KS; ++i) {
         __asm__ volatile("" ::: "memory");
-        taps.store(st, lane);
+        taps.store(sw, lane);
         __asm__ volatile("" ::: "memory");
         if (i + 1 < KS) taps.load(entry, (i + 1) * rstep);
         if (i > 0) {
@@ -1510,22 +1504,18 @@ __device__ inline void bank_split_bwd_rows(const float* __restrict__ entry, bool
         }
 #pragma unroll
         for (int b = 0; b < S::NB; ++b) {
-            uint32_t h[3], l[3];
+            u32x4_t tw;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                h[j] = sw[ad0 - 8 * b + j];
-                l[j] = sw[S::LO / 2 + ad0 - 8 * b + j];
-            }
-            const uint32_t h0 = __builtin_amdgcn_alignbit(h[1], h[0], sh);
-            const uint32_t h1 = __builtin_amdgcn_alignbit(h[2], h[1], sh);
-            const uint32_t l0 = __builtin_amdgcn_alignbit(l[1], l[0], sh);
-            const uint32_t l1 = __builtin_amdgcn_alignbit(l[2], l[1], sh);
-            const bf16x8_t t32 = __builtin_bit_cast(bf16x8_t, u32x4_t{h0, h1, l0, l1});
+            for (int j = 0; j < 4; ++j) tw[j] = sw[ad0 - 16 * b + j];
+            const bf16x8_t t32 = __builtin_bit_cast(bf16x8_t, tw);
 #pragma unroll
             for (int u = 0; u < NG; ++u) {
+                // g_lo kept as two packed dwords; spread to one per tap here
+                const u32x4_t glw = u32x4_t{gl[u][0] & 0xffffu, gl[u][0] >> 16, gl[u][1] & 0xffffu,
+                                            gl[u][1] >> 16};
                 acc[u][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ga[u]), t32,
                                                                     acc[u][b], 0, 0, 0);
-                acc[u][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, gl[u]), t32,
+                acc[u][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, glw), t32,
                                                                     acc[u][b], 0, 0, 0);
             }
         }
@@ -1679,8 +1669,9 @@ __global__ __launch_bounds__(kRBlock, 2) void render_bank_split_bwd_kernel(const
                     hb[jj] = bb & 0xffffu;
                     lb[jj] = bb >> 16;
                 }
-                const uint32_t h01 = hb[0] | (hb[1] << 16), h23 = hb[2] | (hb[3] << 16);
-                ga[u] = u32x4_t{h01, h23, h01, h23};
+                // k pairs (tap j high, tap j low): g_hi against both, g_lo
+                // against the high part only
+                ga[u] = u32x4_t{hb[0] * 0x10001u, hb[1] * 0x10001u, hb[2] * 0x10001u, hb[3] * 0x10001u};
                 gl[u] = u32x4_t{lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16), 0u, 0u};
             }
             const int hrow = 16 * rs0 + KS - 1, hcol = sc * kStrip + pl;
