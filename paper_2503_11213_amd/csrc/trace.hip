@@ -30,6 +30,13 @@ struct SplatArgs {
 static_assert(sizeof(SplatArgs) <= 4000, "kernel arguments too large");
 
 constexpr int kBlock = 256;
+// The trace-and-splat workgroup: eight waves (two per SIMD) sharing one LDS
+// splat tile, with registers capped for six waves per SIMD, so that three
+// workgroups (24 waves) fit per compute unit even at the 33.8 KB tile of
+// ks 65 (with 256 lanes and no cap the tile limited a compute unit to 16
+// waves; 370 -> 351 ms on the 16-surface lens at ks 65).
+constexpr int kTBlock = 512;
+constexpr int kTWavesPerSimd = 6;
 
 
 __device__ inline float wave_sum(float v) {
@@ -61,13 +68,13 @@ __device__ inline unsigned long long fixed_weight(float w) {
 }
 
 template <typename T, int SPLAT, int DP, typename OutT, bool GENERAL>
-__global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) {
+__global__ __launch_bounds__(kTBlock, kTWavesPerSimd) void trace_splat_kernel(const SplatArgs A) {
     // [2][ks][ks] float32 sums, or (deterministic mode) 64-bit integer sums
     // of weights in units of 2^-32
     extern __shared__ float tile[];
     unsigned long long* tile_q = reinterpret_cast<unsigned long long*>(tile);
     const bool det = A.smp.det != 0;
-    __shared__ float red[kBlock / 64][8];
+    __shared__ float red[kTBlock / 64][8];
     const int ks = A.sen.ks;
     const int kk = ks * ks;
     const int pad = (ks - 1) / 2;
@@ -77,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
     // masked mode: points outside the mask are left as they are (the whole
     // workgroup leaves before its first barrier)
     if (A.pts.mask && A.pts.mask[q] == 0) return;
-    for (int i = tid; i < (det ? 4 : 2) * kk; i += kBlock) tile[i] = 0.0f;
+    for (int i = tid; i < (det ? 4 : 2) * kk; i += kTBlock) tile[i] = 0.0f;
 
     double hx, hy, depth;
     int slot;
@@ -99,14 +106,14 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
     __syncthreads();
 
     // grid cell (ci, cj) of ray r = cj nx + ci, advanced at the top of each
-    // pass by the loop stride kBlock = step_j nx + step_i with one carry
+    // pass by the loop stride kTBlock = step_j nx + step_i with one carry
     // (0 <= ci < nx); it starts one stride before the first ray
-    const int step_j = kBlock / nx, step_i = kBlock - step_j * nx;
+    const int step_j = kTBlock / nx, step_i = kTBlock - step_j * nx;
     int cj = (int)(((uint64_t)(uint32_t)(r0 + tid) * A.smp.div_magic) >> A.smp.div_shift);
     int ci = r0 + tid - cj * nx - step_i;
     cj -= step_j;
     if (ci < 0) { ci += nx; --cj; }
-    for (int r = r0 + tid; r < r1 && slot_ok; r += kBlock) {
+    for (int r = r0 + tid; r < r1 && slot_ok; r += kTBlock) {
         ci += step_i;
         cj += step_j;
         if (ci >= nx) { ci -= nx; ++cj; }
@@ -212,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
     __syncthreads();
     if (tid == 0 && A.stats && slot_ok) {
         double tot[6] = {0, 0, 0, 0, 0, 0};
-        for (int w = 0; w < kBlock / 64; ++w)
+        for (int w = 0; w < kTBlock / 64; ++w)
             for (int k = 0; k < 6; ++k) tot[k] += red[w][k];
         double* st = A.stats + 7 * (size_t)q;
         atomicAdd(&st[0], (double)max(r1 - r0, 0));
@@ -222,11 +229,11 @@ __global__ __launch_bounds__(kBlock) void trace_splat_kernel(const SplatArgs A) 
     OutT* out = reinterpret_cast<OutT*>(A.out) + (size_t)q * 2 * kk;
     if (det) {
         // the point's only workgroup: exact sums, one store per element
-        for (int i = tid; i < 2 * kk; i += kBlock)
+        for (int i = tid; i < 2 * kk; i += kTBlock)
             out[i] = (OutT)((double)tile_q[i] * (1.0 / 4294967296.0));
         return;
     }
-    for (int i = tid; i < 2 * kk; i += kBlock) {
+    for (int i = tid; i < 2 * kk; i += kTBlock) {
         const float v = tile[i];
         if (v != 0.0f) atomicAdd(&out[i], (OutT)v);
     }
@@ -323,7 +330,7 @@ static void launch_splat(const SplatArgs& A, dim3 grid, size_t shm, hipStream_t 
     auto k = general ? trace_splat_kernel<T, SPLAT, DP, OutT, true>
                   : trace_splat_kernel<T, SPLAT, DP, OutT, false>;
     if (shm > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k, grid, dim3(kBlock), shm, st, A);
+    hipLaunchKernelGGL(k, grid, dim3(kTBlock), shm, st, A);
 }
 
 template <typename T, typename OutT>
