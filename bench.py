@@ -83,8 +83,8 @@ TRACE_SOURCES = ("paper_2503_11213_amd/csrc/device_common.hpp",
                  "paper_2503_11213_amd/csrc/trace.hip",
                  "paper_2503_11213_amd/csrc/pack.hpp",
                  "paper_2503_11213_amd/csrc/pack.cpp")
-TRACE_TRAFFIC = {"sources_sha256": "fb7d2ac468a38af5a29e18317cad150da02a5f4e61160c0a75f24f69c48038d9",
-                 "bytes": 1.956530e8}    # FETCH 2.048e5 B + WRITE 1.954e8 B
+TRACE_TRAFFIC = {"sources_sha256": "448ec8dd6014b6b5286534025a40d909b85a6b344c90c3b3e332e9b88414107a",
+                 "bytes": 2.082422e8}    # FETCH 6.503e6 B + WRITE 2.017e8 B
 
 
 def sources_digest():
@@ -104,7 +104,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--pmc-target", default=None,
-                    choices=["calib", "trace", "trace_paper", "trace_bwd", "render", "render_bwd",
+                    choices=["calib", "trace", "trace_c2", "trace_paper", "trace_bwd", "render",
+                             "render_bwd",
                              "render_split",
                              "render_split_bwd", "dense",
                              "mlp_head", "mlp_render"],
@@ -534,6 +535,7 @@ def pmc_target(name, dev):
       calib       sdirt_calib_fma64, 2^20 threads x 1000 iterations
                   (8.39e9 float64 FMAs);
       trace       the step's trace (16-surface aspheric lens, 6144 PSFs);
+      trace_c2    the 12-surface lens trace (1536 PSFs x 512^2 rays, ks 63);
       trace_paper the paper's PSF map (RF50, 393,216 PSFs x 4096 rays);
       trace_bwd   the adjoint of the trace (12-surface lens, 192 PSFs x
                   256^2 rays, ks 41, tent splat), after its forward;
@@ -560,6 +562,9 @@ def pmc_target(name, dev):
             C.c_void_p(torch.cuda.current_stream().cuda_stream)))
     elif name == "trace":
         lens, sensor, query = configs.config5()
+        sdirt.trace_dp_psf(lens, sensor, query, stats=False)
+    elif name == "trace_c2":
+        lens, sensor, query = configs.config2()
         sdirt.trace_dp_psf(lens, sensor, query, stats=False)
     elif name == "trace_bwd":
         lens, sensor, query = configs.config3()
