@@ -199,17 +199,59 @@ template <> __device__ inline float sqrt_pos<float>(float v) {
     return __builtin_amdgcn_sqrtf(v);
 }
 
-// Even-asphere surface constants, read once per surface.  inv_kc =
-// 1 / ((1 + k) c) when |(1 + k) c| >= 1e-3 per mm (host), else 0.
-template <typename T>
-struct Asph {
-    T c, kc2, a4, a6, a8, a10, a12, inv_kc;
-    __device__ Asph(const double* co, T cc)
-        : c(cc), kc2((T(1) + (T)co[0]) * cc * cc), a4((T)co[1]), a6((T)co[2]), a8((T)co[3]),
-          a10((T)co[4]), a12((T)co[5]), inv_kc((T)co[6]) {}
+// Constants of the trace that depend only on the prescription and the
+// wavelength, staged once per workgroup in LDS: float64 has no scalar ALU,
+// so evaluated in the per-ray loop they cost vector instructions on every
+// surface of every ray.  Per surface m^2 and 1 - m^2 (m the index ratio, the
+// latter as fma(-m, m, 1)); per asphere slot (1 + k) c^2, a12 and the
+// coefficients 4 a4, 6 a6, 8 a8, 10 a10, 12 a12 of twice the sag's slope.
+struct TraceConsts {
+    double sm[kMaxS][2];
+    double as[kMaxAsph][8];
 };
 
-// Even-asphere sag and its derivative in rho = r^2; *ok is false where the
+// Fill the table (threads tid < S each take one surface); the caller
+// synchronises the workgroup before the first read.
+__device__ inline void stage_trace_consts(const LensArgs& L, const double* mu, TraceConsts* tc,
+                                          int tid) {
+    if (tid >= L.S) return;
+    const double m = mu[tid];
+    tc->sm[tid][0] = m * m;
+    tc->sm[tid][1] = fma(-m, m, 1.0);
+    const int code = L.code[tid];
+    if ((code & 0x7f) == SDIRT_ASPHERE) {
+        const double* co = L.asph[code >> 8];
+        const double c = L.c[tid];
+        double* a = tc->as[code >> 8];
+        a[0] = (1.0 + co[0]) * c * c;
+        a[1] = co[5];
+        a[2] = 4.0 * co[1];
+        a[3] = 6.0 * co[2];
+        a[4] = 8.0 * co[3];
+        a[5] = 10.0 * co[4];
+        a[6] = 12.0 * co[5];
+        a[7] = 0.0;
+    }
+}
+
+// Even-asphere surface constants, read once per surface.  inv_kc =
+// 1 / ((1 + k) c) when |(1 + k) c| >= 1e-3 per mm (host), else 0; d4 .. d12
+// = 4 a4 .. 12 a12 are the coefficients of twice the slope.
+template <typename T>
+struct Asph {
+    T c, kc2, a4, a6, a8, a10, a12, inv_kc, d4, d6, d8, d10, d12;
+    __device__ Asph(const double* co, T cc)
+        : c(cc), kc2((T(1) + (T)co[0]) * cc * cc), a4((T)co[1]), a6((T)co[2]), a8((T)co[3]),
+          a10((T)co[4]), a12((T)co[5]), inv_kc((T)co[6]), d4(T(4) * a4), d6(T(6) * a6),
+          d8(T(8) * a8), d10(T(10) * a10), d12(T(12) * a12) {}
+    // the derived constants from a staged table row (TraceConsts::as)
+    __device__ Asph(const double* co, T cc, const double* t)
+        : c(cc), kc2((T)t[0]), a4((T)co[1]), a6((T)co[2]), a8((T)co[3]), a10((T)co[4]),
+          a12((T)t[1]), inv_kc((T)co[6]), d4((T)t[2]), d6((T)t[3]), d8((T)t[4]), d10((T)t[5]),
+          d12((T)t[6]) {}
+};
+
+// Even-asphere sag and twice its derivative in rho = r^2; *ok is false where the
 // conic root is imaginary.  EXACT_D: derivative from the refined 1/sqrt;
 // otherwise from the raw hardware value (for Newton steps, whose
 // convergence a 5e-8 relative error in the slope does not spoil).  The conic
@@ -218,7 +260,7 @@ struct Asph {
 // division (absolute error about eps / |(1 + k) c| <= 1.1e-13 mm at the
 // host's threshold); nearly parabolic or flat surfaces keep the quotient.
 template <typename T, bool EXACT_D>
-__device__ __forceinline__ void asphere_sag(const Asph<T>& S, T rho, T* sag, T* dsag, bool* ok) {
+__device__ __forceinline__ void asphere_sag(const Asph<T>& S, T rho, T* sag, T* dsag2, bool* ok) {
     const T arg = T(1) - S.kc2 * rho;
     *ok = arg >= T(0);
     const T a = fmax(arg, T(1e-30));
@@ -230,23 +272,25 @@ __device__ __forceinline__ void asphere_sag(const Asph<T>& S, T rho, T* sag, T* 
                                      : S.c * rho * rcp_t<T>(T(1) + q);
     *sag = conic +
            rho * rho * (S.a4 + rho * (S.a6 + rho * (S.a8 + rho * (S.a10 + rho * S.a12))));
-    *dsag = T(0.5) * S.c * iq +
-            rho * (T(2) * S.a4 + rho * (T(3) * S.a6 + rho * (T(4) * S.a8 +
-                   rho * (T(5) * S.a10 + rho * T(6) * S.a12))));
+    *dsag2 = S.c * iq + rho * (S.d4 + rho * (S.d6 + rho * (S.d8 + rho * (S.d10 + rho * S.d12))));
 }
 
 // Vector Snell refraction at the unit normal n (pointing along +z) with
 // index ratio m = n_before / n_after.  Returns K = cos^2 of the refracted
 // angle; K < 0 is total internal reflection, which the caller records.
 template <typename T>
-__device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m) {
+__device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m, T m2) {
     const T cosI = r.dx * nx + r.dy * ny + r.dz * nz;
-    const T K = T(1) - m * m * (T(1) - cosI * cosI);
+    const T K = T(1) - m2 * (T(1) - cosI * cosI);
     const T g = sqrt_live<T>(K) - m * cosI;
     r.dx = m * r.dx + g * nx;
     r.dy = m * r.dy + g * ny;
     r.dz = m * r.dz + g * nz;
     return K;
+}
+template <typename T>
+__device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m) {
+    return refract<T>(r, nx, ny, nz, m, m * m);
 }
 
 // Sequential trace of one ray through surfaces [0, S): on return r holds
@@ -267,10 +311,12 @@ __device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m) {
 // (the quadratic's root is then the plane transfer) and a stop has index
 // ratio 1 (the refraction then leaves the direction unchanged), so every
 // surface but the aperture stop takes the sphere path, without per-surface
-// branches; the aperture stop is a plane transfer and a clip.
-template <typename T, typename Rec, bool EXACT = true, bool GENERAL = true>
+// branches; the aperture stop is a plane transfer and a clip.  TC: the
+// derived constants come from the workgroup's staged table tc (same values,
+// bit for bit, as computing them here).
+template <typename T, typename Rec, bool EXACT = true, bool GENERAL = true, bool TC = false>
 __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
-                                Rec rec) {
+                                Rec rec, const TraceConsts* tc = nullptr) {
     int status = kAlive;
     bool alive = true;
 #define SDIRT_FAIL(cond, code)                                   \
@@ -303,8 +349,9 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         SDIRT_FAIL(rho2 > semi2, kClip);
         // vector Snell with cos^2 I = disc: K = 1 - m^2 (1 - disc)
         const T m = (T)mu[s];
-        const T m2 = m * m;
-        const T K = fma(m2, disc, T(1) - m2);
+        const T m2 = TC ? (T)tc->sm[s][0] : m * m;
+        const T om2 = TC ? (T)tc->sm[s][1] : fma(-m, m, T(1));
+        const T K = fma(m2, disc, om2);
         // total internal reflection, or an exit ray along the surface
         SDIRT_FAIL(!(K > T(0)), kTir);
         const T g = sqrt_pos<T>(K) - m * cosI;
@@ -358,7 +405,7 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
             r.z = T(0);
             if (kind == SDIRT_ASPHERE) {
                 const double* co = L.asph[code >> 8];
-                const Asph<T> S(co, c);
+                const Asph<T> S = TC ? Asph<T>(co, c, tc->as[code >> 8]) : Asph<T>(co, c);
                 const T k = (T)co[0];
                 const T F = c * (r.x * r.x + r.y * r.y);
                 const T G = r.dz - c * (r.x * r.dx + r.y * r.dy);
@@ -378,12 +425,12 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
                 for (int it = 0; it < 50 && !conv && !bad; ++it) {
                     const T xr = r.x + delta * r.dx;
                     const T yr = r.y + delta * r.dy;
-                    T sag, dsag;
+                    T sag, dsag2;
                     bool ok;
-                    asphere_sag<T, false>(S, xr * xr + yr * yr, &sag, &dsag, &ok);
+                    asphere_sag<T, false>(S, xr * xr + yr * yr, &sag, &dsag2, &ok);
                     if (!ok) { bad = true; break; }
                     const T f = delta * r.dz - sag;
-                    const T fp = r.dz - dsag * T(2) * (xr * r.dx + yr * r.dy);
+                    const T fp = r.dz - dsag2 * (xr * r.dx + yr * r.dy);
                     const T step = f * rcp_raw<T>(fp);
                     delta -= step;
                     const T as = fabs(step), sc = T(1) + fabs(delta);
@@ -397,19 +444,22 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
                 r.z = delta * r.dz;
                 const T r2 = r.x * r.x + r.y * r.y;
                 SDIRT_FAIL(r2 > semi2, kClip);
-                T sag, dsag;
+                T sag, dsag2;
                 bool ok;
-                asphere_sag<T, true>(S, r2, &sag, &dsag, &ok);
-                T nx = T(-2) * r.x * dsag, ny = T(-2) * r.y * dsag;
+                asphere_sag<T, true>(S, r2, &sag, &dsag2, &ok);
+                T nx = -r.x * dsag2, ny = -r.y * dsag2;
                 const T inv = rsqrt_t<T>(nx * nx + ny * ny + T(1));
-                const T K = refract<T>(r, nx * inv, ny * inv, inv, (T)mu[s]);
+                const T m = (T)mu[s];
+                const T K = refract<T>(r, nx * inv, ny * inv, inv, m,
+                                       TC ? (T)tc->sm[s][0] : m * m);
                 SDIRT_FAIL(K < T(0), kTir);
             } else {
                 SDIRT_FAIL(r.x * r.x + r.y * r.y > semi2, kClip);
                 if (kind == SDIRT_PLANE) {
                     // normal (0, 0, 1): the refracted dz is sqrt(K)
                     const T m = (T)mu[s];
-                    const T K = T(1) - m * m * (T(1) - r.dz * r.dz);
+                    const T m2 = TC ? (T)tc->sm[s][0] : m * m;
+                    const T K = T(1) - m2 * (T(1) - r.dz * r.dz);
                     SDIRT_FAIL(K < T(0), kTir);
                     r.dx *= m;
                     r.dy *= m;

@@ -75,6 +75,7 @@ __global__ __launch_bounds__(kTBlock, kTWavesPerSimd) void trace_splat_kernel(co
     unsigned long long* tile_q = reinterpret_cast<unsigned long long*>(tile);
     const bool det = A.smp.det != 0;
     __shared__ float red[kTBlock / 64][8];
+    __shared__ TraceConsts tc;
     const int ks = A.sen.ks;
     const int kk = ks * ks;
     const int pad = (ks - 1) / 2;
@@ -95,6 +96,7 @@ __global__ __launch_bounds__(kTBlock, kTWavesPerSimd) void trace_splat_kernel(co
     const double px = hx / m, py = hy / m, pz = -depth;
     const double zep = A.lam.z_ep[slot], rep = A.lam.rho_ep[slot];
     const double* mu = A.lam.mu[slot];
+    if (GENERAL) stage_trace_consts(A.lens, mu, &tc, tid);
     const uint32_t key = point_key(A.smp.seed, (uint32_t)q);
     const double ps = A.sen.ps, inv_ps = 1.0 / ps;
     const int nx = A.smp.nx;
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(kTBlock, kTWavesPerSimd) void trace_splat_kernel(co
         double ddx = ex - px, ddy = ey - py, ddz = zep - pz;
         const double inv = rsqrt_t<double>(ddx * ddx + ddy * ddy + ddz * ddz);
         Ray<T> ray{(T)ex, (T)ey, (T)zep, (T)(ddx * inv), (T)(ddy * inv), (T)(ddz * inv)};
-        const int st = trace_ray<T, NoRec, false, GENERAL>(A.lens, mu, ray, NoRec());
+        const int st = trace_ray<T, NoRec, false, GENERAL, GENERAL>(A.lens, mu, ray, NoRec(), &tc);
         if (st != kAlive) { e_vig += 1.f; continue; }
         e_tr += 1.f;
         const double wu = ((double)ray.x - hx) * inv_ps + pad;

@@ -185,12 +185,12 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
         const Asph<double> SA(co, c);
         for (int it = 0; it < 50; ++it) {
             const double xr = x1 + D * dx, yr = y1 + D * dy;
-            double sag, dsag;
+            double sag, dsag2;
             bool ok;
-            asphere_sag<double, true>(SA, xr * xr + yr * yr, &sag, &dsag, &ok);
+            asphere_sag<double, true>(SA, xr * xr + yr * yr, &sag, &dsag2, &ok);
             if (!ok) break;
             const double f = D * dz - sag;
-            const double fp = dz - dsag * 2.0 * (xr * dx + yr * dy);
+            const double fp = dz - dsag2 * (xr * dx + yr * dy);
             const double step = f / fp;
             D -= step;
             if (fabs(step) < 1e-12 * (1.0 + fabs(D))) break;
