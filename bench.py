@@ -83,8 +83,8 @@ TRACE_SOURCES = ("paper_2503_11213_amd/csrc/device_common.hpp",
                  "paper_2503_11213_amd/csrc/trace.hip",
                  "paper_2503_11213_amd/csrc/pack.hpp",
                  "paper_2503_11213_amd/csrc/pack.cpp")
-TRACE_TRAFFIC = {"sources_sha256": "448ec8dd6014b6b5286534025a40d909b85a6b344c90c3b3e332e9b88414107a",
-                 "bytes": 2.082422e8}    # FETCH 6.503e6 B + WRITE 2.017e8 B
+TRACE_TRAFFIC = {"sources_sha256": "775d81ed81b858861e3c87db7b54c4405a6fc544493360deb1e9acf09e53e322",
+                 "bytes": 2.557886e8}    # FETCH 9.633e6 B + WRITE 2.4616e8 B
 
 
 def sources_digest():
