@@ -306,7 +306,9 @@ __device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m) {
 // vertex plane.
 // EXACT: report the first failure's code (ray-level debugging); otherwise
 // only whether the ray survived (kAlive or kMiss), which keeps the
-// bookkeeping in scalar lane masks.  GENERAL = false is for prescriptions of
+// bookkeeping in scalar lane masks, and in the general surface loop a wave
+// leaves after the surface where its last ray was lost (rec is then not
+// called for the surfaces after it).  GENERAL = false is for prescriptions of
 // spheres, planes and stops only: a flat surface is a sphere of curvature 0
 // (the quadratic's root is then the plane transfer) and a stop has index
 // ratio 1 (the refraction then leaves the direction unchanged), so every
@@ -474,6 +476,9 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
             }
         }
         rec(s, r);
+        // a wave whose rays are all lost leaves (vignetting loses whole
+        // stretches of the pupil, so this is the common way to lose rays)
+        if (!EXACT && !__any(alive)) return kMiss;
     }
     // to the sensor plane
     r.z -= (T)L.sensor_dist;
