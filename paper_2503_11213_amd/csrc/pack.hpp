@@ -32,6 +32,13 @@ struct SampleArgs {
     uint64_t div_magic;              // r / nx == (r * div_magic) >> div_shift
     uint32_t div_shift;
     int det;                         // fixed-point tiles, one workgroup per point
+    // tile order (nx, ny multiples of 8 and chunks of whole 64-ray tiles):
+    // ray r takes cell (8 (t mod nx/8) + r mod 8, 8 (t div nx/8) + (r div 8)
+    // mod 8) of the pupil grid, t = r div 64, so a wave's 64 rays sample one
+    // 8 x 8 patch of the pupil instead of a 64-cell stretch of one row
+    int tile8;
+    uint32_t tdiv_shift;             // t / (nx / 8) == (t * tdiv_magic) >> tdiv_shift
+    uint64_t tdiv_magic;
 };
 
 // Multiplier and shift for exact unsigned division by d of every n < 2^30.

@@ -107,22 +107,36 @@ __global__ __launch_bounds__(kTBlock, kTWavesPerSimd) void trace_splat_kernel(co
     float e_vig = 0.f, e_tr = 0.f, e_l = 0.f, e_r = 0.f, e_miss = 0.f, e_out = 0.f;
     __syncthreads();
 
-    // grid cell (ci, cj) of ray r = cj nx + ci, advanced at the top of each
-    // pass by the loop stride kTBlock = step_j nx + step_i with one carry
-    // (0 <= ci < nx); it starts one stride before the first ray
+    // grid cell (ci, cj) of ray r.  Tile order (every grid of our workloads):
+    // a wave's 64 rays sample one 8 x 8 patch of the pupil, so vignetting,
+    // which cuts the pupil along curves, more often loses whole waves (which
+    // then leave the surface loop); the jitter is keyed by the cell, so the
+    // rays are those of row order.  Row order: r = cj nx + ci, advanced at
+    // the top of each pass by the loop stride kTBlock = step_j nx + step_i
+    // with one carry (0 <= ci < nx), starting one stride before the first ray.
     const int step_j = kTBlock / nx, step_i = kTBlock - step_j * nx;
     int cj = (int)(((uint64_t)(uint32_t)(r0 + tid) * A.smp.div_magic) >> A.smp.div_shift);
     int ci = r0 + tid - cj * nx - step_i;
     cj -= step_j;
     if (ci < 0) { ci += nx; --cj; }
+    const bool tile8 = A.smp.tile8 != 0;
     for (int r = r0 + tid; r < r1 && slot_ok; r += kTBlock) {
-        ci += step_i;
-        cj += step_j;
-        if (ci >= nx) { ci -= nx; ++cj; }
+        uint32_t cell = (uint32_t)r;
+        if (tile8) {
+            const uint32_t t = (uint32_t)r >> 6;
+            const uint32_t ty = (uint32_t)(((uint64_t)t * A.smp.tdiv_magic) >> A.smp.tdiv_shift);
+            ci = (int)(((t - ty * (uint32_t)(nx >> 3)) << 3) | ((uint32_t)r & 7u));
+            cj = (int)((ty << 3) | (((uint32_t)r >> 3) & 7u));
+            cell = (uint32_t)(cj * nx + ci);
+        } else {
+            ci += step_i;
+            cj += step_j;
+            if (ci >= nx) { ci -= nx; ++cj; }
+        }
         double x1 = 0.5, x2 = 0.5;
         if (A.smp.jitter) {
-            x1 = jitter01(key, (uint32_t)r, 0u);
-            x2 = jitter01(key, (uint32_t)r, 1u);
+            x1 = jitter01(key, cell, 0u);
+            x2 = jitter01(key, cell, 1u);
         }
         const double a = -1.0 + (ci + x1) * two_nx;
         const double b = -1.0 + (cj + x2) * two_ny;
@@ -399,6 +413,12 @@ int trace_dp_psf_impl(const sdirt_lens* lens, const sdirt_sensor* sensor,
                        : chunks_override > 0 ? std::min(chunks_override, n_rays) : chunks_for(P, n_rays);
     A.smp.chunks = chunks;
     A.smp.rays_per_chunk = (n_rays + chunks - 1) / chunks;
+    if (A.smp.nx % 8 == 0 && A.smp.ny % 8 == 0) {
+        // whole 8 x 8 tiles per chunk (the last chunks may be short or empty)
+        A.smp.rays_per_chunk = (A.smp.rays_per_chunk + 63) / 64 * 64;
+        A.smp.tile8 = 1;
+        div_magic_for((uint32_t)(A.smp.nx / 8), &A.smp.tdiv_magic, &A.smp.tdiv_shift);
+    }
     const dim3 grid((unsigned)((long long)chunks * P));
     const size_t shm = (size_t)2 * kk * (A.smp.det ? sizeof(unsigned long long) : sizeof(float));
     const bool f64math = query->math == SDIRT_F64;
