@@ -318,29 +318,55 @@ __device__ __forceinline__ void surface_bwd(const LensArgs& L, int s, double mu,
 }
 
 // The state entering every surface, kept in LDS as float32 (structure of
-// arrays: entry (s, k) of lane l at [(5 s + k) * 64 + l], conflict-free):
-// x, y, z, dx, dy; dz is the positive root of |d| = 1 (a live ray always
-// travels toward +z), which saves a sixth of the LDS and so raises the
-// number of resident workgroups.
-constexpr int kPathVals = 5;
+// arrays: entry (s, k) of lane l at [(NV s + k) * 64 + l], conflict-free):
+// x, y, dx, dy and (spheres-and-planes instance) z.  dz is the positive root
+// of |d| = 1 (a live ray always travels toward +z).  The general instance,
+// whose registers allow more resident waves than its LDS does, rebuilds z
+// from the surface the ray left instead of storing it (the hit of surface
+// s - 1 in its vertex frame: 0 on planes, stops and ideal lenses, the
+// sphere's or the asphere's sag at the stored (x, y); the ray start lies on
+// the entrance-pupil plane): ten workgroups per CU instead of eight on a
+// 12-surface lens.
+template <bool GENERAL>
 struct PathRec {
+    static constexpr int NV = GENERAL ? 4 : 5;
     float* v;
     int lane;
     __device__ void operator()(int s, const Ray<double>& r) const {
-        float* o = v + kPathVals * (s + 1) * 64 + lane;
-        o[0] = (float)r.x; o[64] = (float)r.y; o[128] = (float)r.z;
-        o[192] = (float)r.dx; o[256] = (float)r.dy;
+        float* o = v + NV * (s + 1) * 64 + lane;
+        o[0] = (float)r.x; o[64] = (float)r.y;
+        o[128] = (float)r.dx; o[192] = (float)r.dy;
+        if (!GENERAL) o[256] = (float)r.z;
     }
 };
 
+template <bool GENERAL>
 __device__ inline void path_put(float* v, int s, int lane, const Ray<double>& r) {
-    PathRec{v, lane}(s - 1, r);
+    PathRec<GENERAL>{v, lane}(s - 1, r);
 }
 
-__device__ inline St path_get(const float* v, int s, int lane) {
-    const float* o = v + kPathVals * s * 64 + lane;
-    const double dx = o[192], dy = o[256];
-    return St{o[0], o[64], o[128], dx, dy, sqrt_t<double>(1.0 - dx * dx - dy * dy)};
+template <bool GENERAL>
+__device__ inline St path_get(const LensArgs& L, const float* v, int s, int lane, double zep) {
+    const float* o = v + PathRec<GENERAL>::NV * s * 64 + lane;
+    const double x = o[0], y = o[64], dx = o[128], dy = o[192];
+    double z = GENERAL ? zep : (double)o[256];
+    if (GENERAL && s > 0) {
+        const int kind = kind_of(L, s - 1);
+        const double c = L.c[s - 1];
+        const double rho = x * x + y * y;
+        z = 0.0;
+        if (kind == SDIRT_SPHERE) {
+            // the root near the vertex of c (rho + z^2) - 2 z = 0
+            z = c * rho * rcp_d(1.0 + sqrt_t<double>(1.0 - c * c * rho));
+        } else if (kind == SDIRT_ASPHERE) {
+            const Asph<double> SA(L.asph[aslot_of(L, s - 1)], c);
+            double sag, dsag2;
+            bool ok;
+            asphere_sag<double, false>(SA, rho, &sag, &dsag2, &ok);
+            z = sag;
+        }
+    }
+    return St{x, y, z, dx, dy, sqrt_t<double>(1.0 - dx * dx - dy * dy)};
 }
 
 // GENERAL = false: spheres, planes and stops only (the forward re-trace then
@@ -348,7 +374,7 @@ __device__ inline St path_get(const float* v, int s, int lane) {
 template <bool GENERAL>
 __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
     __shared__ double gsh[kPerSurf * kMaxS + 1];
-    extern __shared__ float path[];     // [(S + 1) * kPathVals][64]
+    extern __shared__ float path[];     // [(S + 1) * NV][64]
     const int S = A.lens.S;
     const int np = kPerSurf * S + 1;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -396,8 +422,9 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             const double ddx = ex - px, ddy = ey - py, ddz = zep - pz;
             const double inv = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
             ray = Ray<double>{ex, ey, zep, ddx * inv, ddy * inv, ddz * inv};
-            path_put(path, 0, lane, ray);
-            const int st = trace_ray<double, PathRec, false, GENERAL>(A.lens, mu, ray, PathRec{path, lane});
+            path_put<GENERAL>(path, 0, lane, ray);
+            const int st = trace_ray<double, PathRec<GENERAL>, false, GENERAL>(A.lens, mu, ray,
+                                                                             PathRec<GENERAL>{path, lane});
             live = st == kAlive;
         }
         // ---- splat adjoint: dL/dO, dL/dD, dL/dk -----------------------
@@ -432,7 +459,7 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             const double sxb = glr * sig1 * ksig;
             const double r3 = rr * rr * rr;
             // sensor plane: O = p + tau d, tau = -(z - t_S) / dz (ray holds O)
-            const St pl = path_get(path, S, lane);
+            const St pl = path_get<GENERAL>(A.lens, path, S, lane, zep);
             const double pz0 = pl.z;
             const double pdx = pl.dx, pdy = pl.dy, pdz = pl.dz;
             const double z1 = pz0 - A.lens.sensor_dist;
@@ -457,7 +484,7 @@ __global__ __launch_bounds__(kBBlock) void trace_bwd_kernel(const BwdArgs A) {
             double pg[kPerSurf];
             St ib{0, 0, 0, 0, 0, 0};
             if (live) {
-                const St in = path_get(path, s, lane);
+                const St in = path_get<GENERAL>(A.lens, path, s, lane, zep);
                 surface_bwd<GENERAL>(A.lens, s, mu[s], in, ob, ib, pg);
                 ob = ib;
             } else {
@@ -511,10 +538,11 @@ int trace_backward_impl(const sdirt_lens* lens, const sdirt_sensor* sensor,
     int chunks = std::max(1, std::min((16384 + P - 1) / P, n_rays / (kBBlock * 4)));
     A.smp.chunks = chunks;
     A.smp.rays_per_chunk = (n_rays + chunks - 1) / chunks;
-    const size_t shm = (size_t)(R.S + 1) * kPathVals * kBBlock * sizeof(float);
     bool general = false;
     for (int s = 0; s < R.S; ++s)
         general = general || R.kind[s] == SDIRT_ASPHERE || R.kind[s] == SDIRT_IDEAL;
+    const int nv = general ? PathRec<true>::NV : PathRec<false>::NV;
+    const size_t shm = (size_t)(R.S + 1) * nv * kBBlock * sizeof(float);
     hipLaunchKernelGGL(general ? trace_bwd_kernel<true> : trace_bwd_kernel<false>,
                        dim3((unsigned)((long long)chunks * P)),
                        dim3(kBBlock), shm, stream, A);
