@@ -249,6 +249,12 @@ __global__ __launch_bounds__(kTBlock, kTWavesPerSimd) void trace_splat_kernel(co
             out[i] = (OutT)((double)tile_q[i] * (1.0 / 4294967296.0));
         return;
     }
+    if (A.smp.chunks == 1) {
+        // the point's only workgroup: plain stores (the host skips the
+        // output's zero fill)
+        for (int i = tid; i < 2 * kk; i += kTBlock) out[i] = (OutT)tile[i];
+        return;
+    }
     for (int i = tid; i < 2 * kk; i += kTBlock) {
         const float v = tile[i];
         if (v != 0.0f) atomicAdd(&out[i], (OutT)v);
@@ -394,23 +400,27 @@ int trace_dp_psf_impl(const sdirt_lens* lens, const sdirt_sensor* sensor,
     const int kk = query->ks * query->ks;
     const size_t elt = query->out_dtype == SDIRT_F64 ? 8 : 4;
     A.pts.mask = mask;
+    // deterministic mode: one workgroup per point, integer tile
+    const int chunks = A.smp.det ? 1
+                       : chunks_override > 0 ? std::min(chunks_override, n_rays) : chunks_for(P, n_rays);
+    // with one workgroup per point the kernel stores every output element
+    // itself; otherwise the chunks add into a zeroed output
+    const bool fill = chunks > 1;
     if (mask) {
         // only the masked points' blocks (and statistics) start from zero
         if (P > 0) {
-            hipLaunchKernelGGL(fill_zero_masked_kernel, dim3(P), dim3(kBlock), 0, stream,
-                               (uint32_t*)psf_out, P, (int)(2 * kk * elt / 4), mask);
+            if (fill)
+                hipLaunchKernelGGL(fill_zero_masked_kernel, dim3(P), dim3(kBlock), 0, stream,
+                                   (uint32_t*)psf_out, P, (int)(2 * kk * elt / 4), mask);
             if (stats_out)
                 hipLaunchKernelGGL(fill_zero_masked_kernel, dim3(P), dim3(64), 0, stream,
                                    (uint32_t*)stats_out, P, 14, mask);
         }
         if (hipGetLastError() != hipSuccess) return SDIRT_ELAUNCH;
     } else {
-        if ((rc = launch_fill_zero(psf_out, (size_t)P * 2 * kk * elt, stream))) return rc;
+        if (fill && (rc = launch_fill_zero(psf_out, (size_t)P * 2 * kk * elt, stream))) return rc;
         if (stats_out && (rc = launch_fill_zero(stats_out, (size_t)P * 7 * 8, stream))) return rc;
     }
-    // deterministic mode: one workgroup per point, integer tile
-    const int chunks = A.smp.det ? 1
-                       : chunks_override > 0 ? std::min(chunks_override, n_rays) : chunks_for(P, n_rays);
     A.smp.chunks = chunks;
     A.smp.rays_per_chunk = (n_rays + chunks - 1) / chunks;
     if (A.smp.nx % 8 == 0 && A.smp.ny % 8 == 0) {
