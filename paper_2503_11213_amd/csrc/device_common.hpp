@@ -275,24 +275,6 @@ __device__ __forceinline__ void asphere_sag(const Asph<T>& S, T rho, T* sag, T* 
     *dsag2 = S.c * iq + rho * (S.d4 + rho * (S.d6 + rho * (S.d8 + rho * (S.d10 + rho * S.d12))));
 }
 
-// Vector Snell refraction at the unit normal n (pointing along +z) with
-// index ratio m = n_before / n_after.  Returns K = cos^2 of the refracted
-// angle; K < 0 is total internal reflection, which the caller records.
-template <typename T>
-__device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m, T m2) {
-    const T cosI = r.dx * nx + r.dy * ny + r.dz * nz;
-    const T K = T(1) - m2 * (T(1) - cosI * cosI);
-    const T g = sqrt_live<T>(K) - m * cosI;
-    r.dx = m * r.dx + g * nx;
-    r.dy = m * r.dy + g * ny;
-    r.dz = m * r.dz + g * nz;
-    return K;
-}
-template <typename T>
-__device__ __forceinline__ T refract(Ray<T>& r, T nx, T ny, T nz, T m) {
-    return refract<T>(r, nx, ny, nz, m, m * m);
-}
-
 // Sequential trace of one ray through surfaces [0, S): on return r holds
 // the vertex-local state after the last surface.  `rec(s, r)` is called
 // after each surface (hit point + refracted direction).
@@ -449,12 +431,20 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
                 T sag, dsag2;
                 bool ok;
                 asphere_sag<T, true>(S, r2, &sag, &dsag2, &ok);
-                T nx = -r.x * dsag2, ny = -r.y * dsag2;
-                const T inv = rsqrt_t<T>(nx * nx + ny * ny + T(1));
+                // vector Snell at the normal n (-x s', -y s', 1) / |n|, s' =
+                // dsag2 (|n|^2 = 1 + r2 s'^2), with the scale applied to the
+                // dot product and to the refracted term instead of to n
+                const T nx = -r.x * dsag2, ny = -r.y * dsag2;
+                const T inv = rsqrt_t<T>(fma(r2, dsag2 * dsag2, T(1)));
                 const T m = (T)mu[s];
-                const T K = refract<T>(r, nx * inv, ny * inv, inv, m,
-                                       TC ? (T)tc->sm[s][0] : m * m);
+                const T m2 = TC ? (T)tc->sm[s][0] : m * m;
+                const T cosI = fma(r.dx, nx, fma(r.dy, ny, r.dz)) * inv;
+                const T K = T(1) - m2 * (T(1) - cosI * cosI);
                 SDIRT_FAIL(K < T(0), kTir);
+                const T gi = (sqrt_live<T>(K) - m * cosI) * inv;
+                r.dx = fma(gi, nx, m * r.dx);
+                r.dy = fma(gi, ny, m * r.dy);
+                r.dz = fma(m, r.dz, gi);
             } else {
                 SDIRT_FAIL(r.x * r.x + r.y * r.y > semi2, kClip);
                 if (kind == SDIRT_PLANE) {
