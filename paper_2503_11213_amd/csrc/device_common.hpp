@@ -372,6 +372,9 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         }
         for (; s0 < L.S; ++s0) surf(s0);
     }
+    // x^2 + y^2 of the current point, left by every surface at its hit (a
+    // transfer along z keeps it)
+    T hrho2 = r.x * r.x + r.y * r.y;
     for (int s = s0; GENERAL && s < L.S; ++s) {
         const int code = L.code[s];
         const int kind = code & 0x7f;
@@ -380,8 +383,7 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         r.z -= (T)L.tprev[s];
         SDIRT_FAIL(!(r.dz > T(0)), kInvalid);
         if (kind == SDIRT_SPHERE) {
-            T rho2 = r.x * r.x + r.y * r.y;
-            sphere(s, code, c, semi2, rho2);
+            sphere(s, code, c, semi2, hrho2);
         } else {
             const T tau = -r.z * rcp_t<T>(r.dz);
             r.x += tau * r.dx;
@@ -427,6 +429,7 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
                 r.y += delta * r.dy;
                 r.z = delta * r.dz;
                 const T r2 = r.x * r.x + r.y * r.y;
+                hrho2 = r2;
                 SDIRT_FAIL(r2 > semi2, kClip);
                 T sag, dsag2;
                 bool ok;
@@ -446,7 +449,8 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
                 r.dy = fma(gi, ny, m * r.dy);
                 r.dz = fma(m, r.dz, gi);
             } else {
-                SDIRT_FAIL(r.x * r.x + r.y * r.y > semi2, kClip);
+                hrho2 = r.x * r.x + r.y * r.y;
+                SDIRT_FAIL(hrho2 > semi2, kClip);
                 if (kind == SDIRT_PLANE) {
                     // normal (0, 0, 1): the refracted dz is sqrt(K)
                     const T m = (T)mu[s];
