@@ -21,7 +21,8 @@ enum RayStatus : int { kAlive = 0, kMiss = 1, kClip = 2, kTir = 3,
                        kNewton = 4, kInvalid = 5 };
 
 // Prescription as kernel arguments: read with scalar loads in the hot loop.
-// code[s] = kind | 0x80 if inv_c[s] holds 1/c | (asphere slot << 8) (slot -1
+// code[s] = kind | 0x40 if an asphere's 1 / ((1 + k) c) is nonzero | 0x80 if
+// inv_c[s] holds 1/c | (asphere slot << 8) (slot -1
 // when not an asphere); a 32-bit word so that it is fetched by a scalar load
 // and tested with scalar instructions.
 struct LensArgs {
@@ -36,7 +37,7 @@ struct LensArgs {
     double sensor_dist;         // last vertex -> sensor plane
 };
 
-__device__ __host__ inline int kind_of(const LensArgs& L, int s) { return L.code[s] & 0x7f; }
+__device__ __host__ inline int kind_of(const LensArgs& L, int s) { return L.code[s] & 0x3f; }
 __device__ __host__ inline int aslot_of(const LensArgs& L, int s) { return L.code[s] >> 8; }
 
 // Per-wavelength data: index ratios and entrance pupil.
@@ -203,8 +204,9 @@ template <> __device__ inline float sqrt_pos<float>(float v) {
 // wavelength, staged once per workgroup in LDS: float64 has no scalar ALU,
 // so evaluated in the per-ray loop they cost vector instructions on every
 // surface of every ray.  Per surface m^2 and 1 - m^2 (m the index ratio, the
-// latter as fma(-m, m, 1)); per asphere slot (1 + k) c^2, a12 and the
-// coefficients 4 a4, 6 a6, 8 a8, 10 a10, 12 a12 of twice the sag's slope.
+// latter as fma(-m, m, 1)); per asphere slot (1 + k) c^2, a12, the
+// coefficients 4 a4, 6 a6, 8 a8, 10 a10, 12 a12 of twice the sag's slope
+// and k c.
 struct TraceConsts {
     double sm[kMaxS][2];
     double as[kMaxAsph][8];
@@ -219,7 +221,7 @@ __device__ inline void stage_trace_consts(const LensArgs& L, const double* mu, T
     tc->sm[tid][0] = m * m;
     tc->sm[tid][1] = fma(-m, m, 1.0);
     const int code = L.code[tid];
-    if ((code & 0x7f) == SDIRT_ASPHERE) {
+    if ((code & 0x3f) == SDIRT_ASPHERE) {
         const double* co = L.asph[code >> 8];
         const double c = L.c[tid];
         double* a = tc->as[code >> 8];
@@ -230,7 +232,7 @@ __device__ inline void stage_trace_consts(const LensArgs& L, const double* mu, T
         a[4] = 8.0 * co[3];
         a[5] = 10.0 * co[4];
         a[6] = 12.0 * co[5];
-        a[7] = 0.0;
+        a[7] = co[0] * c;
     }
 }
 
@@ -240,15 +242,17 @@ __device__ inline void stage_trace_consts(const LensArgs& L, const double* mu, T
 template <typename T>
 struct Asph {
     T c, kc2, a4, a6, a8, a10, a12, inv_kc, d4, d6, d8, d10, d12;
+    bool iv;    // inv_kc != 0
     __device__ Asph(const double* co, T cc)
         : c(cc), kc2((T(1) + (T)co[0]) * cc * cc), a4((T)co[1]), a6((T)co[2]), a8((T)co[3]),
           a10((T)co[4]), a12((T)co[5]), inv_kc((T)co[6]), d4(T(4) * a4), d6(T(6) * a6),
-          d8(T(8) * a8), d10(T(10) * a10), d12(T(12) * a12) {}
-    // the derived constants from a staged table row (TraceConsts::as)
-    __device__ Asph(const double* co, T cc, const double* t)
+          d8(T(8) * a8), d10(T(10) * a10), d12(T(12) * a12), iv(co[6] != 0.0) {}
+    // the derived constants from a staged table row (TraceConsts::as) and
+    // the surface code's flag for a nonzero inv_kc
+    __device__ Asph(const double* co, T cc, const double* t, bool iv_)
         : c(cc), kc2((T)t[0]), a4((T)co[1]), a6((T)co[2]), a8((T)co[3]), a10((T)co[4]),
           a12((T)t[1]), inv_kc((T)co[6]), d4((T)t[2]), d6((T)t[3]), d8((T)t[4]), d10((T)t[5]),
-          d12((T)t[6]) {}
+          d12((T)t[6]), iv(iv_) {}
 };
 
 // Even-asphere sag and twice its derivative in rho = r^2; *ok is false where the
@@ -268,7 +272,7 @@ __device__ __forceinline__ void asphere_sag(const Asph<T>& S, T rho, T* sag, T* 
     const T s0 = a * y;
     const T q = fma(T(0.5) * y, fma(-s0, s0, a), s0);                 // sqrt(a)
     const T iq = EXACT_D ? y * fma(T(-0.5) * a * y, y, T(1.5)) : y;   // 1 / sqrt(a)
-    const T conic = S.inv_kc != T(0) ? fma(-q, S.inv_kc, S.inv_kc)
+    const T conic = S.iv ? fma(-q, S.inv_kc, S.inv_kc)
                                      : S.c * rho * rcp_t<T>(T(1) + q);
     *sag = conic +
            rho * rho * (S.a4 + rho * (S.a6 + rho * (S.a8 + rho * (S.a10 + rho * S.a12))));
@@ -358,7 +362,7 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
         };
         const int stop = L.stop;
         for (; s0 < stop; ++s0) surf(s0);
-        if (s0 < L.S && (L.code[s0] & 0x7f) == SDIRT_STOP) {
+        if (s0 < L.S && (L.code[s0] & 0x3f) == SDIRT_STOP) {
             r.z -= (T)L.tprev[s0];
             SDIRT_FAIL(!(r.dz > T(0)), kInvalid);
             const T tau = -r.z * rcp_t<T>(r.dz);
@@ -377,7 +381,7 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
     T hrho2 = r.x * r.x + r.y * r.y;
     for (int s = s0; GENERAL && s < L.S; ++s) {
         const int code = L.code[s];
-        const int kind = code & 0x7f;
+        const int kind = code & 0x3f;
         const T c = (T)L.c[s];
         const T semi2 = (T)L.semi2[s];
         r.z -= (T)L.tprev[s];
@@ -391,11 +395,13 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
             r.z = T(0);
             if (kind == SDIRT_ASPHERE) {
                 const double* co = L.asph[code >> 8];
-                const Asph<T> S = TC ? Asph<T>(co, c, tc->as[code >> 8]) : Asph<T>(co, c);
-                const T k = (T)co[0];
+                const Asph<T> S = TC ? Asph<T>(co, c, tc->as[code >> 8], (code & 0x40) != 0)
+                                     : Asph<T>(co, c);
                 const T F = c * (r.x * r.x + r.y * r.y);
                 const T G = r.dz - c * (r.x * r.dx + r.y * r.dy);
-                const T a = c * (T(1) + k * r.dz * r.dz);
+                // c (1 + k dz^2), with k c from the staged table
+                const T a = TC ? fma((T)tc->as[code >> 8][7], r.dz * r.dz, c)
+                               : c * (T(1) + (T)co[0] * r.dz * r.dz);
                 const T disc = G * G - a * F;
                 T delta = disc >= T(0) ? F * rcp_t<T>(G + sqrt_t<T>(disc)) : T(0);
                 // Converged when the step is below the tolerance, or (float64)

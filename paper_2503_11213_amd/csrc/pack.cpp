@@ -26,7 +26,8 @@ int pack_lens(const Resolved& R, LensArgs* A) {
             A->asph[nas][6] = std::fabs(kc) >= 1e-3 ? 1.0 / kc : 0.0;
             ++nas;
         }
-        A->code[s] = (R.kind[s] & 0x7f) | (A->inv_c[s] != 0.0 ? 0x80 : 0) |
+        A->code[s] = (R.kind[s] & 0x3f) | (A->inv_c[s] != 0.0 ? 0x80 : 0) |
+                     (slot >= 0 && A->asph[slot][6] != 0.0 ? 0x40 : 0) |
                      (int)((unsigned)slot << 8);
     }
     A->sensor_dist = R.sensor_distance;
