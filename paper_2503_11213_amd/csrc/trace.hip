@@ -120,13 +120,16 @@ __global__ __launch_bounds__(kTBlock, kTWavesPerSimd) void trace_splat_kernel(co
     cj -= step_j;
     if (ci < 0) { ci += nx; --cj; }
     const bool tile8 = A.smp.tile8 != 0;
+    const uint32_t lx = (uint32_t)tid & 7u, ly = ((uint32_t)tid >> 3) & 7u;   // cell in the tile
     for (int r = r0 + tid; r < r1 && slot_ok; r += kTBlock) {
         uint32_t cell = (uint32_t)r;
         if (tile8) {
-            const uint32_t t = (uint32_t)r >> 6;
+            // the wave's tile: chunks start on whole tiles, so r >> 6 is the
+            // same on every lane of a wave (scalar arithmetic)
+            const uint32_t t = __builtin_amdgcn_readfirstlane((uint32_t)r >> 6);
             const uint32_t ty = (uint32_t)(((uint64_t)t * A.smp.tdiv_magic) >> A.smp.tdiv_shift);
-            ci = (int)(((t - ty * (uint32_t)(nx >> 3)) << 3) | ((uint32_t)r & 7u));
-            cj = (int)((ty << 3) | (((uint32_t)r >> 3) & 7u));
+            ci = (int)(((t - ty * (uint32_t)(nx >> 3)) << 3) | lx);
+            cj = (int)((ty << 3) | ly);
             cell = (uint32_t)(cj * nx + ci);
         } else {
             ci += step_i;
