@@ -83,7 +83,7 @@ TRACE_SOURCES = ("paper_2503_11213_amd/csrc/device_common.hpp",
                  "paper_2503_11213_amd/csrc/trace.hip",
                  "paper_2503_11213_amd/csrc/pack.hpp",
                  "paper_2503_11213_amd/csrc/pack.cpp")
-TRACE_TRAFFIC = {"sources_sha256": "04047fb3a85e15d36235b682215414784a7fcae9b12fc0b0b3649a1dff578435",
+TRACE_TRAFFIC = {"sources_sha256": "c9a6a065e89b7361d7de23577d420a156174a7b1388c9bbc3357b1aca7d387a3",
                  "bytes": 2.546416e8}    # FETCH 9.647e6 B + WRITE 2.4499e8 B
 
 

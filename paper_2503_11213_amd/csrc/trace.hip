@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kTBlock, kTWavesPerSimd) void trace_splat_kernel(co
     float e_vig = 0.f, e_tr = 0.f, e_l = 0.f, e_r = 0.f, e_miss = 0.f, e_out = 0.f;
     __syncthreads();
 
-    // grid cell (ci, cj) of ray r.  Tile order (every grid of our workloads):
+    // grid cell (ci, cj) of ray r.  Tile order (nx and ny multiples of 8):
     // a wave's 64 rays sample one 8 x 8 patch of the pupil, so vignetting,
     // which cuts the pupil along curves, more often loses whole waves (which
     // then leave the surface loop); the jitter is keyed by the cell, so the
