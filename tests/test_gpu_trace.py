@@ -253,6 +253,24 @@ def test_chunking_does_not_change_result():
     assert torch.equal(sa[:, :3], sb[:, :3])
 
 
+@pytest.mark.parametrize("out_f64", [False, True])
+def test_single_chunk_writes_every_element(out_f64):
+    # with one workgroup per point the kernel stores the whole tile and the
+    # output is not zero-filled first: a buffer full of NaN must come back
+    # finite and equal to the (zero-filled, atomically summed) 5-chunk result
+    lens, sensor, query = configs.config5(rays=40)
+    query.out_f64 = out_f64
+    dt = torch.float64 if out_f64 else torch.float32
+    shape = (query.n_points, 2, query.ks, query.ks)
+    out = torch.full(shape, float("nan"), dtype=dt, device="cuda")
+    a, sa = sdirt.trace_dp_psf(lens, sensor, query, chunks=1, out=out)
+    b, sb = sdirt.trace_dp_psf(lens, sensor, query, chunks=5)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(a).all())
+    assert torch.allclose(a, b, rtol=1e-5, atol=1e-4)
+    assert torch.equal(sa[:, :3], sb[:, :3])
+
+
 def test_paper_psf_map_sampled_pixels():
     # the per-pixel map of the paper's workload (RF50 F/4, microlens DP
     # model, ks 21, 4096 rays): list-mode points at sampled pixels against
