@@ -403,17 +403,19 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
                 const T a = TC ? fma((T)tc->as[code >> 8][7], r.dz * r.dz, c)
                                : c * (T(1) + (T)co[0] * r.dz * r.dz);
                 const T disc = G * G - a * F;
-                T delta = disc >= T(0) ? F * rcp_t<T>(G + sqrt_t<T>(disc)) : T(0);
+                T delta = disc >= T(0) ? F * rcp_t<T>(G + sqrt_live<T>(disc)) : T(0);
                 // Converged when the step is below the tolerance, or (float64)
                 // below 1e-7 mm while shrinking more than 1000-fold on the
                 // previous one: Newton is then in its quadratic regime and the
                 // next step would be under r^2 |step| < 1e-13 mm (r the ratio),
-                // so that step is skipped.
+                // so that step is skipped.  The tests are evaluated as
+                // |step| - tol |delta| < tol (one fma each), and prev holds
+                // 1e-3 times the previous |step|.
                 // a ray already lost (bookkeeping mode) takes no Newton
                 // step: its state is never used, and its iterations, which
                 // need not converge, would hold the whole wave
                 bool conv = !alive, bad = false;
-                T prev = T(1e30);
+                T prev = T(1e27);
                 for (int it = 0; it < 50 && !conv && !bad; ++it) {
                     const T xr = r.x + delta * r.dx;
                     const T yr = r.y + delta * r.dy;
@@ -425,10 +427,11 @@ __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ra
                     const T fp = r.dz - dsag2 * (xr * r.dx + yr * r.dy);
                     const T step = f * rcp_raw<T>(fp);
                     delta -= step;
-                    const T as = fabs(step), sc = T(1) + fabs(delta);
-                    conv = as < tol_newton<T>() * sc ||
-                           (sizeof(T) == sizeof(double) && as < T(1e-7) * sc && as < T(1e-3) * prev);
-                    prev = as;
+                    const T as = fabs(step), ad = fabs(delta);
+                    conv = fma(-tol_newton<T>(), ad, as) < tol_newton<T>() ||
+                           (sizeof(T) == sizeof(double) && fma(T(-1e-7), ad, as) < T(1e-7) &&
+                            as < prev);
+                    prev = T(1e-3) * as;
                 }
                 SDIRT_FAIL(!conv || bad, kNewton);
                 r.x += delta * r.dx;
