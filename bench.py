@@ -83,7 +83,7 @@ TRACE_SOURCES = ("paper_2503_11213_amd/csrc/device_common.hpp",
                  "paper_2503_11213_amd/csrc/trace.hip",
                  "paper_2503_11213_amd/csrc/pack.hpp",
                  "paper_2503_11213_amd/csrc/pack.cpp")
-TRACE_TRAFFIC = {"sources_sha256": "ecc51d7ab7eebb88acb2e3363c19d73aa138636f5708a85b73b79b4763d23fb3",
+TRACE_TRAFFIC = {"sources_sha256": "c268f48ee4b5955ec676ca7f5660fd2a7b0f8862440f38ee56f6a5c0343b227e",
                  "bytes": 2.542562e8}    # FETCH 9.645e6 B + WRITE 2.4461e8 B
 
 

@@ -300,8 +300,9 @@ __device__ __forceinline__ void asphere_sag(const Asph<T>& S, T rho, T* sag, T* 
 // ratio 1 (the refraction then leaves the direction unchanged), so every
 // surface but the aperture stop takes the sphere path, without per-surface
 // branches; the aperture stop is a plane transfer and a clip.  TC: the
-// derived constants come from the workgroup's staged table tc (same values,
-// bit for bit, as computing them here).
+// derived constants come from the workgroup's staged table tc (the values
+// computed here, bit for bit; only the asphere's base-conic start is
+// evaluated differently, as one fma with k c).
 template <typename T, typename Rec, bool EXACT = true, bool GENERAL = true, bool TC = false>
 __device__ __forceinline__ int trace_ray(const LensArgs& L, const double* mu, Ray<T>& r,
                                 Rec rec, const TraceConsts* tc = nullptr) {
