@@ -542,7 +542,8 @@ def pmc_target(name, dev):
       render, render_bwd  the step's bank render and image adjoint;
       render_split, render_split_bwd  the step's bank render and image
                   adjoint on the split-bf16 matrix cores;
-      dense       dense render of 512 x 512 RGB with a 41 x 41 f32 map;
+      dense       dense render of 512 x 512 RGB with a 41 x 41 f32 map,
+                  its image adjoint and its kernel-map gradient;
       mlp_head    surrogate inference of 2^20 rows (ks 33, bf16 out);
       mlp_render  fused surrogate render of one 1680 x 1120 RGB image (ks 33,
                   trained weights)."""
@@ -605,6 +606,9 @@ def pmc_target(name, dev):
         img = torch.rand((N, C_, H, W), device=dev)
         desc, keep = sdirt.make_render_desc(N, C_, H, W, ks)
         sdirt.render_dp(desc, img, K)
+        gout = torch.randn((N, 2 * C_, H, W), device=dev)
+        sdirt.render_dp_backward(desc, K, gout)
+        sdirt.render_dp_psf_backward(desc, img, gout, grad_psf=torch.empty_like(K))
     elif name == "mlp_head":
         desc = sdirt.make_mlp_desc(n_out=2 * 33 * 33, **configs.config4_desc_kwargs())
         layers = scenes.mlp_init([64, 256, 256, 256, 256, 256, 2178], seed=0)

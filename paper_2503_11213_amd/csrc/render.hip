@@ -135,20 +135,32 @@ __device__ inline void stage_halo(const RenderArgs& A, int n, int y0, int x0,
     }
 }
 
+// A workgroup of the forward owns a band of rows of a tile: bands smaller
+// than the tile make many more workgroups than the chip holds at once, so
+// the last of them leave little of it idle, while each band stages its own
+// image halo (from the caches: the image is small next to the kernels).
+// Measured best: one row for float32 per-channel kernels, four otherwise.
+template <int MODE, bool BF16>
+constexpr int fwd_rows() { return (MODE == kModeDense && !BF16) ? 1 : 4; }
+
 template <int NC, int MODE, bool BF16>
 __global__ __launch_bounds__(kRBlock) void render_fwd_kernel(const RenderArgs A) {
+    constexpr int kFwdRows = fwd_rows<MODE, BF16>();
     extern __shared__ float halo[];
     const int ks = A.ks, kk = ks * ks;
-    const int hh = kTH + ks - 1, hw = kTW + ks - 1;
-    const int tile = blockIdx.x;
+    const int hh = kFwdRows + ks - 1, hw = kTW + ks - 1;
+    constexpr int kBands = kTH / kFwdRows;
+    const int tile = blockIdx.x / kBands;
+    const int band = blockIdx.x - tile * kBands;
     const int n = tile / (A.tiles_x * A.tiles_y);
     const int rem = tile - n * A.tiles_x * A.tiles_y;
-    const int y0 = (rem / A.tiles_x) * kTH, x0 = (rem % A.tiles_x) * kTW;
+    const int y0 = (rem / A.tiles_x) * kTH + band * kFwdRows, x0 = (rem % A.tiles_x) * kTW;
+    if (y0 >= A.H) return;
     stage_halo(A, n, y0, x0, halo, hh, hw);
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int di = 64 / ks, dj = 64 % ks;
-    for (int p = wave; p < kTH * kTW; p += kWaves) {
+    for (int p = wave; p < kFwdRows * kTW; p += kWaves) {
         const int y = y0 + p / kTW, x = x0 + p % kTW;
         if (y >= A.H || x >= A.W) continue;
         PixelKernel<NC, BF16> pk;
@@ -290,24 +302,32 @@ __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A)
 
 // Gradient with respect to a dense per-pixel kernel map: for each pixel,
 // grad_K[c'][s][i][j] = sum over the channels c reading kernel c' of
-// grad_out[s C + c] * img[c][clamp(y + pad - i)][clamp(x + pad - j)].  The
-// tile's image halo is staged in LDS; one wave writes one pixel's 2 Cp ks^2
-// values with contiguous lanes (an HBM-bound stream, like the forward).
+// grad_out[s C + c] * img[c][clamp(y + pad - i)][clamp(x + pad - j)].  A
+// workgroup owns a band of rows of a tile (as the forward does; measured
+// best: one row for per-channel kernels, two for shared ones), whose image
+// halo is staged in LDS; one wave writes one pixel's 2 Cp ks^2 values with
+// contiguous lanes (an HBM-bound stream, like the forward).
+template <bool SHARED> constexpr int grad_rows() { return SHARED ? 2 : 1; }
+
 template <int NC, bool SHARED, bool BF16>
 __global__ __launch_bounds__(kRBlock) void render_psf_grad_kernel(const RenderArgs A, void* grad) {
     typedef typename PsfT<BF16>::type T;
+    constexpr int kGradRows = grad_rows<SHARED>();
     extern __shared__ float halo[];
     const int ks = A.ks, kk = ks * ks;
-    const int hh = kTH + ks - 1, hw = kTW + ks - 1;
-    const int tile = blockIdx.x;
+    const int hh = kGradRows + ks - 1, hw = kTW + ks - 1;
+    constexpr int kBands = kTH / kGradRows;
+    const int tile = blockIdx.x / kBands;
+    const int band = blockIdx.x - tile * kBands;
     const int n = tile / (A.tiles_x * A.tiles_y);
     const int rem = tile - n * A.tiles_x * A.tiles_y;
-    const int y0 = (rem / A.tiles_x) * kTH, x0 = (rem % A.tiles_x) * kTW;
+    const int y0 = (rem / A.tiles_x) * kTH + band * kGradRows, x0 = (rem % A.tiles_x) * kTW;
+    if (y0 >= A.H) return;
     stage_halo(A, n, y0, x0, halo, hh, hw);
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     T* gk = reinterpret_cast<T*>(grad);
-    for (int p = wave; p < kTH * kTW; p += kWaves) {
+    for (int p = wave; p < kGradRows * kTW; p += kWaves) {
         const int y = y0 + p / kTW, x = x0 + p % kTW;
         if (y >= A.H || x >= A.W) continue;
         float g[2][NC];
@@ -1879,14 +1899,16 @@ static int pack_render(const sdirt_render_desc* d, RenderArgs* A) {
 
 template <int NC, bool BWD, int MODE, bool BF16>
 static void launch_render3(const RenderArgs& A, hipStream_t st) {
-    const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
-    const size_t shm = (size_t)NC * hh * hw * sizeof(float);
-    const dim3 grid((unsigned)((long long)A.N * A.tiles_x * A.tiles_y));
+    const long long tiles = (long long)A.N * A.tiles_x * A.tiles_y;
     if (BWD) {
-        hipLaunchKernelGGL((render_bwd_kernel<NC, MODE, BF16>), grid, dim3(kRBlock), 0, st, A);
+        hipLaunchKernelGGL((render_bwd_kernel<NC, MODE, BF16>), dim3((unsigned)tiles), dim3(kRBlock), 0, st, A);
     } else {
+        constexpr int kFwdRows = fwd_rows<MODE, BF16>();
+        const int hh = kFwdRows + A.ks - 1, hw = kTW + A.ks - 1;
+        const size_t shm = (size_t)NC * hh * hw * sizeof(float);
         if (shm > 65536) (void)hipFuncSetAttribute((const void*)render_fwd_kernel<NC, MODE, BF16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        hipLaunchKernelGGL((render_fwd_kernel<NC, MODE, BF16>), grid, dim3(kRBlock), shm, st, A);
+        hipLaunchKernelGGL((render_fwd_kernel<NC, MODE, BF16>), dim3((unsigned)(tiles * (kTH / kFwdRows))),
+                           dim3(kRBlock), shm, st, A);
     }
 }
 
@@ -1947,11 +1969,11 @@ int render_backward_impl(const sdirt_render_desc* desc, const void* psf,
 
 template <int NC>
 static void launch_psf_grad(const RenderArgs& A, void* grad, hipStream_t st) {
-    const int hh = kTH + A.ks - 1, hw = kTW + A.ks - 1;
-    const size_t shm = (size_t)NC * hh * hw * sizeof(float);
-    const dim3 grid((unsigned)((long long)A.N * A.tiles_x * A.tiles_y));
 #define SDIRT_PSFG(SH, BF)                                                                   \
     do {                                                                                     \
+        const int hh = grad_rows<SH>() + A.ks - 1, hw = kTW + A.ks - 1;                      \
+        const size_t shm = (size_t)NC * hh * hw * sizeof(float);                            \
+        const dim3 grid((unsigned)((long long)A.N * A.tiles_x * A.tiles_y * (kTH / grad_rows<SH>()))); \
         auto k = render_psf_grad_kernel<NC, SH, BF>;                                         \
         if (shm > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); \
         hipLaunchKernelGGL(k, grid, dim3(kRBlock), shm, st, A, grad);                        \
