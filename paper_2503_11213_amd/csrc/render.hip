@@ -224,6 +224,7 @@ __global__ __launch_bounds__(kRBlock) void render_fwd_kernel(const RenderArgs A)
 // accumulated halo is folded onto the clamped image pixels with global
 // atomics (neighbouring tiles overlap there).
 constexpr int kGPer = 10;  // halo positions per thread per pass
+constexpr int kBwdSync = 8;  // output pixels between workgroup barriers
 
 template <int NC, int MODE, bool BF16>
 __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A) {
@@ -246,6 +247,10 @@ __global__ __launch_bounds__(kRBlock) void render_bwd_kernel(const RenderArgs A)
             for (int c = 0; c < NC; ++c) acc[k][c] = 0.f;
         }
         for (int p = 0; p < kTH * kTW; ++p) {
+            // keep the waves within a few pixels of each other, so that a
+            // pixel's kernel lines are still in L2 when the last wave reads
+            // them (2.24 -> 2.18 ms on a 512^2 RGB, 41^2 map)
+            if (p && p % kBwdSync == 0) __syncthreads();
             const int y = y0 + p / kTW, x = x0 + p % kTW;
             if (y >= A.H || x >= A.W) continue;
             PixelKernel<NC, BF16> pk;
