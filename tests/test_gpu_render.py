@@ -58,6 +58,38 @@ def test_dense_bf16_kernels():
     assert _rel(gi.cpu().numpy(), R.render_dense_adjoint(g, K)) <= REL_TOL
 
 
+@pytest.mark.parametrize("shape", [(1, 3, 1, 13, 5, 3), (1, 2, 9, 1, 3, 1),
+                                   (2, 3, 12, 11, 7, 3), (1, 1, 3, 17, 9, 1)])
+@pytest.mark.parametrize("bf16", [False, True])
+def test_dense_thin_images_and_partial_bands(shape, bf16):
+    # one-row and one-column images, and heights that end inside a band of the
+    # 8 x 8 tile (the forward and the kernel-map gradient give a workgroup one
+    # to four rows of a tile): forward, image adjoint and kernel-map gradient
+    N, C, H, W, ks, Cp = shape
+    img, K = _dense(N, C, H, W, ks, Cp, 5, bf16=bf16)
+    desc, keep = sdirt.make_render_desc(N, C, H, W, ks, psf_channels=Cp,
+                                        psf_dtype=abi.BF16 if bf16 else abi.F32)
+    Kt = torch.from_numpy(K).cuda()
+    if bf16:
+        Kt = Kt.to(torch.bfloat16)
+    it = torch.from_numpy(img).cuda()
+    out = sdirt.render_dp(desc, it, Kt)
+    assert _rel(out.cpu().numpy(), R.render_dense(img, K)) <= REL_TOL
+    g = np.random.default_rng(6).normal(size=(N, 2 * C, H, W)).astype(np.float32)
+    gt = torch.from_numpy(g).cuda()
+    gi = sdirt.render_dp_backward(desc, Kt, gt)
+    assert _rel(gi.cpu().numpy(), R.render_dense_adjoint(g, K)) <= REL_TOL
+    gk = sdirt.render_dp_psf_backward(desc, it, gt).float().cpu().numpy()
+    ref = R.render_dense_psf_adjoint(img, g, Cp, ks)
+    assert gk.shape == ref.shape
+    if bf16:
+        # the float32 value rounded once to nearest even: within half a bf16
+        # ulp (2^-9 relative) of the exact one, plus float32 rounding
+        assert np.all(np.abs(gk - ref) <= 2.0 ** -8 * np.abs(ref))
+    else:
+        assert np.max(np.abs(gk - ref)) <= 1e-6 * np.abs(ref).max()
+
+
 def _bank_case(N, C, H, W, ks, F, D, L, ps, seed):
     rng = np.random.default_rng(seed)
     img = rng.uniform(0, 1, (N, C, H, W)).astype(np.float32)
