@@ -281,7 +281,9 @@ enum { SDIRT_BANK_FP32 = 0, SDIRT_BANK_SPLIT_BF16 = 1 };
  * dense source, and the radial bank at window sizes other than those of
  * the matrix-core path, stage C (ks + 7)^2 image floats per 8 x 8 pixel
  * tile in LDS: SDIRT_EUNSUPPORTED when that exceeds 160 KB (ks > 109 at
- * C = 3; every ks <= SDIRT_MAX_KS fits at C = 1). */
+ * C = 3; every ks <= SDIRT_MAX_KS fits at C = 1).  All render calls
+ * return SDIRT_EUNSUPPORTED when 8 N ceil(H / 8) ceil(W / 8) exceeds
+ * 2^32 - 1 (the launch grid of the dense kernels). */
 int sdirt_render_dp(const sdirt_render_desc* desc, const float* img,
                     const void* psf, const float* depth, float* out,
                     void* stream);

@@ -1899,6 +1899,8 @@ static int pack_render(const sdirt_render_desc* d, RenderArgs* A) {
     A->use_fast = 1;
     A->tiles_x = (d->W + kTW - 1) / kTW;
     A->tiles_y = (d->H + kTH - 1) / kTH;
+    // the dense kernels launch up to one workgroup per row of every 8 x 8 tile
+    if ((long long)d->N * A->tiles_x * A->tiles_y * kTH > 0xffffffffLL) return SDIRT_EUNSUPPORTED;
     return SDIRT_OK;
 }
 

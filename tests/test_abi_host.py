@@ -149,6 +149,13 @@ def test_invalid_render_descs_are_rejected():
     assert call(d) == abi.EINVAL
     assert lib.sdirt_render_dp(C.byref(d), C.c_void_p(0), C.c_void_p(0), C.c_void_p(0),
                                C.c_void_p(0), C.c_void_p(0)) == abi.EINVAL
+    # 8 N ceil(H / 8) ceil(W / 8) past 2^32 - 1 (the dense kernels' grid):
+    # rejected before any launch
+    d, k = sdirt.make_render_desc(4096, 3, 4096, 4096, 5)
+    assert call(d) == abi.EUNSUPPORTED
+    assert lib.sdirt_render_dp_psf_backward(C.byref(d), C.c_void_p(0x1000), C.c_void_p(0),
+                                            C.c_void_p(0x1000), C.c_void_p(0x1000),
+                                            C.c_void_p(0)) == abi.EUNSUPPORTED
 
 
 def test_n_params():
